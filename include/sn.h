@@ -1,0 +1,152 @@
+/*
+ * sn.h -- C ABI of libsn, an MI355X (gfx950) library that evaluates the
+ * energy, forces and virial of a periodic atomic configuration under a
+ * NequIP-architecture graph-neural-network interatomic potential (SevenNet,
+ * arXiv 2402.03789).
+ *
+ * What is computed (paper section 2): atomic numbers and positions in,
+ * E = sum_i E_i (eq 1) and F_i = -dE/dr_i (eq 2) out, plus the virial
+ * W = -sum_e d_e (x) dE/dd_e (stress support, section 3.2).  Units: eV and
+ * angstrom.  The evaluation runs as one subdomain with a ghost shell of width
+ * r_c (section 3.1): ghost positions come from their owners plus an image
+ * shift, ghost node features are refreshed from their owners before every
+ * interaction block after the first, and ghost gradients and partial forces
+ * are folded back to the owners in the backward pass.
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int status: SN_OK (0) or a negative code.
+ *     No exception crosses the ABI.  On error the outputs are unspecified;
+ *     the context stays usable except after SN_EHIP.
+ *   - The caller owns every input and output buffer.  The library owns the
+ *     model, contexts, servers and all device scratch, released by *_free.
+ *   - A model is read-only after loading and may be shared by contexts.  A
+ *     context is used by one host thread at a time.
+ *   - Arrays are row-major.  Positions are n x 3 float64 (angstrom); the
+ *     cell is 3 x 3 float64 whose rows are the lattice vectors a1, a2, a3.
+ *   - Results are bitwise reproducible for the same input, precision and
+ *     build (no floating-point atomics anywhere).
+ */
+#ifndef SN_H_
+#define SN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------------- */
+#define SN_OK 0
+#define SN_EINVAL (-1)        /* bad argument: shape, NaN/Inf, singular cell, unknown Z, r = 0 pair */
+#define SN_ENOMEM (-2)        /* device memory or HBM budget exhausted */
+#define SN_EHIP (-3)          /* HIP runtime error; the context is no longer usable */
+#define SN_EUNSUPPORTED (-4)  /* valid request that this build does not implement */
+#define SN_EBUSY (-5)         /* resource in use (e.g. backward without a pending forward) */
+
+/* ---- precision forms -------------------------------------------------------------- */
+#define SN_FP64 0  /* everything in float64 (reference-grade; for tests and finite differences) */
+#define SN_FP32 1  /* float32 storage and arithmetic; edge vectors from float64 positions;
+                      energy and virial reductions in float64 */
+#define SN_BF16 2  /* radial MLP and channel-mixing linears with bfloat16 operands and float32
+                      accumulation on the matrix cores; tensor product in float32; float64
+                      energy and virial reductions */
+
+typedef struct sn_model sn_model_t;
+typedef struct sn_ctx sn_ctx_t;
+
+typedef struct sn_model_info {
+  int n_layers;      /* interaction blocks T */
+  int l_max;         /* highest feature degree */
+  int l_sh;          /* highest edge spherical-harmonic degree */
+  int muls[3];       /* channels per degree l = 0..2 (0 when absent) */
+  int n_basis;       /* radial Bessel functions */
+  int hidden;        /* radial-MLP hidden width */
+  int n_species;     /* rows of the embedding */
+  int species_z[128];/* atomic number of each embedding row */
+  double r_cut;      /* cutoff radius, angstrom */
+  double k_avg;      /* message normalisation (average neighbour count) */
+  double sigma;      /* per-atom energy scale */
+  int64_t n_params;  /* number of model parameters */
+} sn_model_info_t;
+
+/* Text of a status code (static storage). */
+const char* sn_strerror(int status);
+
+/* Most recent error message of a context, or of the last failed model load when
+ * ctx is NULL (thread-local storage for the latter).  Never NULL. */
+const char* sn_last_error(const sn_ctx_t* ctx);
+
+/* ---- model --------------------------------------------------------------------------
+ * sn_model_load reads a weights file: 8-byte magic "SNW1\0\0\0\0", little-endian
+ * u64 header length, JSON header {"format":"snw1","config":{...},"tensors":[{name,
+ * shape,offset}]}, padding, then float64 tensors.  The configuration holds the
+ * block count, channels per degree, l_sh, r_cut, species list, k_avg, sigma,
+ * per-species shift and activation scale.  Tensor shapes are checked against the
+ * architecture derived from the configuration (section 5.1: linear
+ * self-connection, scalar-only last block).  SN_EINVAL on a malformed file. */
+int sn_model_load(const char* path, sn_model_t** out);
+void sn_model_free(sn_model_t* model);
+int sn_model_info(const sn_model_t* model, sn_model_info_t* info);
+
+/* Real Clebsch-Gordan table used by the kernels for the coupling (l1, l2) -> l3
+ * (l <= 2), written densely into out[(2l1+1)(2l2+1)(2l3+1)] in row-major
+ * (m1, m2, m3) order.  Needs no device.  SN_EINVAL for an invalid triple. */
+int sn_cg_table(int l1, int l2, int l3, double* out);
+
+/* ---- context ------------------------------------------------------------------------
+ * A context binds a model to one device, one HIP stream (NULL = the null stream)
+ * and one precision form, and owns the device workspace.  hbm_budget caps the
+ * workspace in bytes (0 = no cap beyond the device); a request that would exceed
+ * it fails with SN_ENOMEM before any launch.  skin widens the ghost shell to
+ * r_cut + skin so that a neighbour list can be reused while atoms move less than
+ * skin / 2 (0 for a fresh list every call). */
+int sn_ctx_create(const sn_model_t* model, int device, void* hip_stream, size_t hbm_budget,
+                  int precision, double skin, sn_ctx_t** out);
+void sn_ctx_free(sn_ctx_t* ctx);
+
+/* ---- single structure, host buffers -------------------------------------------------
+ * n atoms; pos[n*3] angstrom; Z[n] atomic numbers known to the model; cell[9]
+ * rows a1 a2 a3; pbc[3] must all be nonzero (periodic in every direction; other
+ * cases return SN_EUNSUPPORTED).  Outputs (any may be NULL except energy):
+ * energy[1] eV; atom_energy[n] eV; forces[n*3] eV/angstrom; virial[9] eV,
+ * W = -sum_e d_e (x) dE/dd_e (stress = -W / volume).  Blocks until done. */
+int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, const double* cell,
+               const uint8_t* pbc, double* energy, double* atom_energy, double* forces,
+               double* virial);
+
+/* ---- device buffers, stream-ordered (the autograd pair) -----------------------------
+ * sn_forward_device builds the graph, runs every interaction block and the
+ * readout, and keeps the activations the backward pass needs inside ctx.
+ * d_pos[n*3] float64 and d_Z[n] int32 are device pointers; cell[9] is a host
+ * array.  d_energy[1] (float64) and d_atom_energy[n] (float64, may be NULL) are
+ * device outputs.  sn_backward_device consumes the pending forward: with the
+ * upstream gradient g = dL/dE (host scalar) it writes d_forces[n*3] = -g dE/dr
+ * (float64, device; i.e. the forces scaled by g) and d_virial[9] = g W (float64,
+ * device, may be NULL).  Both return as soon as the work is queued on the
+ * context's stream.  SN_EBUSY if backward is called without a pending forward. */
+int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32_t* d_Z,
+                      const double* cell, double* d_energy, double* d_atom_energy);
+int sn_backward_device(sn_ctx_t* ctx, double grad_energy, double* d_forces, double* d_virial);
+
+/* Wait for every queued operation of the context. */
+int sn_ctx_synchronize(sn_ctx_t* ctx);
+
+/* ---- inspection (tests and benchmarks) ---------------------------------------------
+ * After a compute/forward, the graph sizes: local atoms, ghosts, directed edges. */
+int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, int64_t* n_edge);
+
+/* The last graph in the caller's atom order: recv[E], send_owner[E] (owner atom of
+ * the sender), shift[E*3] (integer image shift of the sender), and ghost_owner[G],
+ * ghost_shift[G*3].  Host buffers sized from sn_ctx_graph_size; any may be NULL. */
+int sn_ctx_graph(const sn_ctx_t* ctx, int32_t* recv, int32_t* send_owner, int32_t* shift,
+                 int32_t* ghost_owner, int32_t* ghost_shift);
+
+/* Per-kernel timing of the last compute (milliseconds, HIP events on the context
+ * stream): names[k] and ms[k] for k < *count (count in: capacity, out: used). */
+int sn_ctx_timings(const sn_ctx_t* ctx, const char** names, double* ms, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SN_H_ */

@@ -1,0 +1,169 @@
+"""MI355X-native SevenNet/NequIP energy, force and virial evaluation.
+
+Python layer over libsn.so (include/sn.h): argument marshalling, a
+torch.autograd.Function wrapper, and the serving loop.  All arithmetic of
+the evaluation runs in the library's gfx950 kernels; nothing here falls back
+to a CPU or PyTorch implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._lib import lib, check, ptr, PRECISIONS, SNError, ModelInfo, EXPORTED  # noqa: F401
+
+
+def cg_table(l1: int, l2: int, l3: int) -> np.ndarray:
+    """The library's real Clebsch-Gordan tensor for (l1, l2) -> l3."""
+    out = np.zeros((2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1))
+    check(lib().sn_cg_table(l1, l2, l3, ptr(out)))
+    return out.reshape(2 * l1 + 1, 2 * l2 + 1, 2 * l3 + 1)
+
+
+class Model:
+    """A weights file loaded into host memory (shared by contexts)."""
+
+    def __init__(self, path: str):
+        h = C.c_void_p()
+        check(lib().sn_model_load(path.encode(), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = ModelInfo()
+        check(lib().sn_model_info(self._h, C.byref(i)))
+        return dict(n_layers=i.n_layers, l_max=i.l_max, l_sh=i.l_sh, muls=list(i.muls),
+                    n_basis=i.n_basis, hidden=i.hidden, n_species=i.n_species,
+                    species=list(i.species_z[:i.n_species]), r_cut=i.r_cut, k_avg=i.k_avg,
+                    sigma=i.sigma, n_params=i.n_params)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().sn_model_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Context:
+    """One model on one device, stream and precision form."""
+
+    def __init__(self, model: Model, device: int = 0, precision: str = "fp32", skin: float = 0.0,
+                 stream=None, hbm_budget: int = 0):
+        self.model = model
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().sn_ctx_create(model.handle, device, C.c_void_p(stream.cuda_stream), hbm_budget,
+                                 PRECISIONS[precision], float(skin), C.byref(h))
+        check(st)
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sn_ctx_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compute(self, pos, Z, cell, forces=True, virial=True) -> dict:
+        """Host-buffer evaluation: E, per-atom E, F, W (float64)."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        Z = np.ascontiguousarray(Z, dtype=np.int32)
+        cell = np.ascontiguousarray(cell, dtype=np.float64)
+        n = pos.shape[0]
+        e = np.zeros(1)
+        ae = np.zeros(n)
+        f = np.zeros((n, 3)) if forces else None
+        w = np.zeros((3, 3)) if virial else None
+        pbc = (C.c_uint8 * 3)(1, 1, 1)
+        check(lib().sn_compute(self._h, n, ptr(pos), ptr(Z), ptr(cell), C.cast(pbc, C.c_void_p),
+                               ptr(e), ptr(ae), ptr(f), ptr(w)), self._h)
+        out = dict(energy=float(e[0]), atom_energy=ae)
+        if forces:
+            out["forces"] = f
+        if virial:
+            out["virial"] = w
+        return out
+
+    def forward_device(self, pos: torch.Tensor, Z: torch.Tensor, cell, energy: torch.Tensor,
+                       atom_energy: torch.Tensor | None = None):
+        cell = np.ascontiguousarray(cell, dtype=np.float64)
+        check(lib().sn_forward_device(self._h, pos.shape[0], ptr(pos), ptr(Z), ptr(cell), ptr(energy),
+                                      ptr(atom_energy)), self._h)
+
+    def backward_device(self, grad_energy: float, forces: torch.Tensor, virial: torch.Tensor | None):
+        check(lib().sn_backward_device(self._h, float(grad_energy), ptr(forces), ptr(virial)), self._h)
+
+    def synchronize(self):
+        check(lib().sn_ctx_synchronize(self._h), self._h)
+
+    def graph_size(self):
+        n, g, e = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().sn_ctx_graph_size(self._h, C.byref(n), C.byref(g), C.byref(e)))
+        return n.value, g.value, e.value
+
+    def graph(self) -> dict:
+        n, g, e = self.graph_size()
+        recv = np.zeros(e, np.int32)
+        send = np.zeros(e, np.int32)
+        shift = np.zeros((e, 3), np.int32)
+        gown = np.zeros(g, np.int32)
+        gsh = np.zeros((g, 3), np.int32)
+        check(lib().sn_ctx_graph(self._h, ptr(recv), ptr(send), ptr(shift), ptr(gown), ptr(gsh)),
+              self._h)
+        return dict(recv=recv, send_owner=send, shift=shift, ghost_owner=gown, ghost_shift=gsh)
+
+    def timings(self) -> dict:
+        cnt = C.c_int(256)
+        names = (C.c_char_p * 256)()
+        ms = np.zeros(256)
+        check(lib().sn_ctx_timings(self._h, names, ptr(ms), C.byref(cnt)))
+        return {names[i].decode(): float(ms[i]) for i in range(min(cnt.value, 256))}
+
+
+class SevenNetEnergy(torch.autograd.Function):
+    """E(pos) with forces from the library's hand-written adjoint.
+
+    forward(pos [n,3] float64 cuda, Z [n] int32 cuda, cell (3x3 host), ctx) -> E (float64 scalar);
+    backward gives dL/dpos = g dE/dpos = -g F.  The virial of the last backward is
+    stored on the context object as `last_virial` (g W).
+    """
+
+    @staticmethod
+    def forward(actx, pos, Z, cell, ctx: Context):
+        energy = torch.zeros(1, dtype=torch.float64, device=pos.device)
+        ctx.forward_device(pos.contiguous(), Z.contiguous(), cell, energy)
+        actx.sn = ctx
+        actx.n = pos.shape[0]
+        return energy[0]
+
+    @staticmethod
+    def backward(actx, grad_e):
+        ctx = actx.sn
+        g = float(grad_e)
+        f = torch.zeros((actx.n, 3), dtype=torch.float64, device=grad_e.device)
+        w = torch.zeros(9, dtype=torch.float64, device=grad_e.device)
+        ctx.backward_device(g, f, w)
+        ctx.last_virial = w
+        return -f, None, None, None
+
+
+def energy(pos, Z, cell, ctx: Context):
+    return SevenNetEnergy.apply(pos, Z, cell, ctx)

@@ -1,0 +1,214 @@
+// Dense contractions: row-mapped GEMM for the channel-mixing linears and the
+// last radial-MLP layer, and the two hidden radial-MLP layers.
+//
+// Channel mixing (Lin1, Linsc, Lin2, paper section 5.1 and Fig 2b) acts on
+// each degree block independently and identically for every m, so with the
+// channel index innermost each (atom, m) pair is one GEMM row; RowMap
+// addresses those rows inside the interleaved feature rows.
+#include "kernels.h"
+
+namespace sn {
+
+// ------------------------------------------------------------------ generic tiled GEMM
+constexpr int GT = 64;   // tile rows / cols
+constexpr int GK = 16;   // k step
+
+template <typename T>
+__device__ inline T round_operand(T v, bool bf16) {
+  return v;
+}
+template <>
+__device__ inline float round_operand<float>(float v, bool bf16) {
+  if (!bf16) return v;
+  return __bfloat162float(__float2bfloat16(v));
+}
+
+template <typename T, bool BT>
+__global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, const T* __restrict__ A,
+                                                    RowMap am, const T* __restrict__ B, int ldb,
+                                                    T* __restrict__ C, RowMap cm, T alpha, int accumulate,
+                                                    int bf16) {
+  __shared__ T As[GK][GT + 4];
+  __shared__ T Bs[GK][GT + 4];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * GT;
+  const int n0 = blockIdx.y * GT;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  const int ar = tid >> 2, ak = (tid & 3) * 4;
+  const int64_t agm = m0 + ar;
+  const int64_t arow = agm < M ? am(agm) : 0;
+  const int bk = tid >> 4, bn = (tid & 15) * 4;
+  for (int k0 = 0; k0 < K; k0 += GK) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int k = k0 + ak + j;
+      As[ak + j][ar] = (agm < M && k < K) ? round_operand(A[arow + k], bf16) : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int n = n0 + bn + j, k = k0 + bk;
+      T v = T(0);
+      if (k < K && n < N) v = BT ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n];
+      Bs[bk][bn + j] = round_operand(v, bf16);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int64_t row = m0 + ty * 4 + i;
+    if (row >= M) continue;
+    T* c = C + cm(row);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int col = n0 + tx * 4 + j;
+      if (col >= N) continue;
+      T v = alpha * acc[i][j];
+      c[col] = accumulate ? c[col] + v : v;
+    }
+  }
+}
+
+template <typename T>
+void launch_gemm(int64_t M, int N, int K, const T* A, RowMap am, const T* B, int ldb, bool bt, T* C,
+                 RowMap cm, T alpha, bool accumulate, bool bf16_operands, hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  dim3 grid((unsigned)((M + GT - 1) / GT), (unsigned)((N + GT - 1) / GT));
+  if (bt)
+    k_gemm_valu<T, true><<<grid, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
+                                              bf16_operands);
+  else
+    k_gemm_valu<T, false><<<grid, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
+                                               bf16_operands);
+}
+
+template void launch_gemm<float>(int64_t, int, int, const float*, RowMap, const float*, int, bool,
+                                 float*, RowMap, float, bool, bool, hipStream_t);
+template void launch_gemm<double>(int64_t, int, int, const double*, RowMap, const double*, int,
+                                  bool, double*, RowMap, double, bool, bool, hipStream_t);
+
+// ------------------------------------------------------------------ radial MLP hidden layers
+// z2 = phi(phi(rho Wa) Wb); phi(z) = c z sigmoid(z); no biases.  One thread per edge,
+// weights in LDS (read as broadcasts).
+template <typename T, int NB, int H>
+__global__ __launch_bounds__(256) void k_mlp_fwd(int64_t E, const T* __restrict__ rho,
+                                                  const T* __restrict__ Wa, const T* __restrict__ Wb,
+                                                  T c, T* __restrict__ z2) {
+  __shared__ T sWa[NB * H];
+  __shared__ T sWb[H * H];
+  for (int i = threadIdx.x; i < NB * H; i += blockDim.x) sWa[i] = Wa[i];
+  for (int i = threadIdx.x; i < H * H; i += blockDim.x) sWb[i] = Wb[i];
+  __syncthreads();
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  T r[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) r[k] = rho[e * NB + k];
+  T z1[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    T a = T(0);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) a += r[k] * sWa[k * H + j];
+    z1[j] = act(a, c);
+  }
+  for (int j2 = 0; j2 < H; ++j2) {
+    T a = T(0);
+#pragma unroll
+    for (int j = 0; j < H; ++j) a += z1[j] * sWb[j * H + j2];
+    z2[e * H + j2] = act(a, c);
+  }
+}
+
+template <typename T, int NB, int H>
+__global__ __launch_bounds__(256) void k_mlp_bwd(int64_t E, const T* __restrict__ rho,
+                                                  const T* __restrict__ Wa, const T* __restrict__ Wb,
+                                                  T c, const T* __restrict__ dz2,
+                                                  T* __restrict__ drho, int accumulate) {
+  __shared__ T sWa[NB * H];
+  __shared__ T sWb[H * H];
+  for (int i = threadIdx.x; i < NB * H; i += blockDim.x) sWa[i] = Wa[i];
+  for (int i = threadIdx.x; i < H * H; i += blockDim.x) sWb[i] = Wb[i];
+  __syncthreads();
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  T r[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) r[k] = rho[e * NB + k];
+  T z1[H], dz1[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    T a = T(0);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) a += r[k] * sWa[k * H + j];
+    z1[j] = act(a, c);
+    dz1[j] = T(0);
+  }
+  for (int j2 = 0; j2 < H; ++j2) {
+    T a = T(0);
+#pragma unroll
+    for (int j = 0; j < H; ++j) a += z1[j] * sWb[j * H + j2];
+    T da = dz2[e * H + j2] * act_grad(a, c);
+#pragma unroll
+    for (int j = 0; j < H; ++j) dz1[j] += da * sWb[j * H + j2];
+  }
+  T dr[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) dr[k] = T(0);
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    T a = T(0);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) a += r[k] * sWa[k * H + j];
+    T da = dz1[j] * act_grad(a, c);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) dr[k] += da * sWa[k * H + j];
+  }
+#pragma unroll
+  for (int k = 0; k < NB; ++k) drho[e * NB + k] = accumulate ? drho[e * NB + k] + dr[k] : dr[k];
+}
+
+template <typename T>
+void launch_mlp_hidden_fwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa, const T* Wb,
+                           T c, T* z2, hipStream_t s) {
+  if (E <= 0) return;
+  // nb == 8, hidden == 64 (checked at model load)
+  k_mlp_fwd<T, 8, 64><<<(unsigned)((E + 255) / 256), 256, 0, s>>>(E, rho, Wa, Wb, c, z2);
+}
+template <typename T>
+void launch_mlp_hidden_bwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa, const T* Wb,
+                           T c, const T* dz2, T* drho, bool accumulate, hipStream_t s) {
+  if (E <= 0) return;
+  k_mlp_bwd<T, 8, 64><<<(unsigned)((E + 255) / 256), 256, 0, s>>>(E, rho, Wa, Wb, c, dz2, drho,
+                                                                  accumulate ? 1 : 0);
+}
+
+template void launch_mlp_hidden_fwd<float>(int64_t, const float*, int, int, const float*,
+                                           const float*, float, float*, hipStream_t);
+template void launch_mlp_hidden_fwd<double>(int64_t, const double*, int, int, const double*,
+                                            const double*, double, double*, hipStream_t);
+template void launch_mlp_hidden_bwd<float>(int64_t, const float*, int, int, const float*,
+                                           const float*, float, const float*, float*, bool,
+                                           hipStream_t);
+template void launch_mlp_hidden_bwd<double>(int64_t, const double*, int, int, const double*,
+                                            const double*, double, const double*, double*, bool,
+                                            hipStream_t);
+
+}  // namespace sn

@@ -1,0 +1,308 @@
+// Graph build: wrap, cell binning, ghost shell, receiver and sender CSR.
+//
+// One subdomain with a ghost shell (paper section 3.1): every periodic image
+// of an atom whose fractional coordinates fall within (r_c + skin) / w_a of
+// the cell on each axis (w_a: perpendicular width) is a ghost with an owner
+// and an integer image shift.  Edges join a local receiver to any local or
+// ghost sender closer than r_c (section 2), found by scanning the 27 bins
+// around the receiver on a grid over the extended fractional region whose
+// bin width is at least the shell half-width.  Every list is made
+// deterministic: bins are filled and then sorted by point index, edges are
+// emitted in bin-scan order, and sender segments are sorted by edge id.
+#include "kernels.h"
+
+namespace sn {
+
+// ------------------------------------------------------------------ exclusive scan
+constexpr int kScanBlock = 1024;
+
+__global__ void k_scan_block(const int* __restrict__ in, int* __restrict__ out, int64_t n,
+                             int* __restrict__ block_sums) {
+  __shared__ int s[kScanBlock];
+  int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  int v = (i < n) ? in[i] : 0;
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    int t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) out[i] = s[threadIdx.x] - v;  // exclusive
+  if (threadIdx.x == kScanBlock - 1) block_sums[blockIdx.x] = s[threadIdx.x];
+}
+
+__global__ void k_scan_add(int* __restrict__ out, int64_t n, const int* __restrict__ offs) {
+  int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  if (i < n) out[i] += offs[blockIdx.x];
+}
+
+__global__ void k_scan_total(const int* __restrict__ in, int* __restrict__ out, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = (n > 0 ? out[n - 1] + in[n - 1] : 0);
+}
+
+size_t scan_tmp_ints(int64_t n) {
+  size_t total = 0;
+  int64_t m = n;
+  while (true) {
+    int64_t nb = (m + kScanBlock - 1) / kScanBlock;
+    total += 2 * nb + 1;
+    if (nb <= 1) break;
+    m = nb;
+  }
+  return total + 16;
+}
+
+void scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t s) {
+  if (n <= 0) {
+    k_scan_total<<<1, 1, 0, s>>>(in, out, 0);
+    return;
+  }
+  int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  int* sums = tmp;
+  k_scan_block<<<(unsigned)nb, kScanBlock, 0, s>>>(in, out, n, sums);
+  if (nb > 1) {
+    int* sums_scan = tmp + nb;
+    scan_exclusive(sums, sums_scan, nb, tmp + 2 * nb + 1, s);
+    k_scan_add<<<(unsigned)nb, kScanBlock, 0, s>>>(out, n, sums_scan);
+  }
+  k_scan_total<<<1, 1, 0, s>>>(in, out, n);
+}
+
+// ------------------------------------------------------------------ binning helpers
+__device__ inline int bin_axis(double f, const BinGrid& g, int a) {
+  int b = (int)floor((f + g.delta[a]) / g.bw[a]);
+  return min(max(b, 0), g.nb[a] - 1);
+}
+__device__ inline int bin_lin(const double* f, const BinGrid& g) {
+  return (bin_axis(f[0], g, 0) * g.nb[1] + bin_axis(f[1], g, 1)) * g.nb[2] + bin_axis(f[2], g, 2);
+}
+
+struct Mat3 { double m[9]; };
+
+__global__ void k_wrap_bin(int n, const double* __restrict__ pos, Mat3 H, Mat3 Hinv, BinGrid g,
+                           double* __restrict__ posw, double* __restrict__ frac,
+                           int* __restrict__ key, int* __restrict__ err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+  if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) {
+    atomicOr(err, 1);
+    p[0] = p[1] = p[2] = 0.0;
+  }
+  double f[3];
+  for (int a = 0; a < 3; ++a) {
+    // row vector p times Hinv
+    double v = p[0] * Hinv.m[0 * 3 + a] + p[1] * Hinv.m[1 * 3 + a] + p[2] * Hinv.m[2 * 3 + a];
+    v -= floor(v);
+    if (v >= 1.0) v = 0.0;
+    f[a] = v;
+  }
+  for (int a = 0; a < 3; ++a) {
+    frac[3 * i + a] = f[a];
+    posw[3 * i + a] = f[0] * H.m[0 * 3 + a] + f[1] * H.m[1 * 3 + a] + f[2] * H.m[2 * 3 + a];
+  }
+  key[i] = bin_lin(f, g);
+}
+
+__global__ void k_count_keys(int n, const int* __restrict__ key, int* __restrict__ count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&count[key[i]], 1);
+}
+
+__global__ void k_scatter_keys(int n, const int* __restrict__ key, const int* __restrict__ start,
+                               int* __restrict__ cursor, int* __restrict__ items) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int k = key[i];
+  int pos = start[k] + atomicAdd(&cursor[k], 1);
+  items[pos] = i;
+}
+
+// insertion sort of each segment (segments are short: bin or sender lists)
+__global__ void k_sort_segments(int nseg, const int* __restrict__ start, int* __restrict__ items) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  int a = start[s], b = start[s + 1];
+  for (int i = a + 1; i < b; ++i) {
+    int v = items[i];
+    int j = i - 1;
+    while (j >= a && items[j] > v) {
+      items[j + 1] = items[j];
+      --j;
+    }
+    items[j + 1] = v;
+  }
+}
+
+__global__ void k_gather_local(int n, const int* __restrict__ order, const double* __restrict__ posw,
+                               const double* __restrict__ frac, const int* __restrict__ spec_orig,
+                               double* __restrict__ pos_ext, double* __restrict__ frac_ext,
+                               int* __restrict__ spec_ext) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int o = order[k];
+  for (int a = 0; a < 3; ++a) {
+    pos_ext[3 * k + a] = posw[3 * o + a];
+    frac_ext[3 * k + a] = frac[3 * o + a];
+  }
+  spec_ext[k] = spec_orig[o];
+}
+
+__device__ inline bool in_shell(const double* f, int sx, int sy, int sz, const BinGrid& g) {
+  double v[3] = {f[0] + sx, f[1] + sy, f[2] + sz};
+  for (int a = 0; a < 3; ++a)
+    if (!(v[a] >= -g.delta[a] && v[a] < 1.0 + g.delta[a])) return false;
+  return true;
+}
+
+__global__ void k_ghost_count(int n, const double* __restrict__ frac, BinGrid g,
+                              int* __restrict__ count) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double f[3] = {frac[3 * k], frac[3 * k + 1], frac[3 * k + 2]};
+  int c = 0;
+  for (int sx = -g.nimg[0]; sx <= g.nimg[0]; ++sx)
+    for (int sy = -g.nimg[1]; sy <= g.nimg[1]; ++sy)
+      for (int sz = -g.nimg[2]; sz <= g.nimg[2]; ++sz) {
+        if (sx == 0 && sy == 0 && sz == 0) continue;
+        c += in_shell(f, sx, sy, sz, g) ? 1 : 0;
+      }
+  count[k] = c;
+}
+
+__global__ void k_ghost_fill(int n, const double* __restrict__ frac, const double* __restrict__ pos,
+                             const int* __restrict__ spec, Mat3 H, BinGrid g,
+                             const int* __restrict__ gptr, int* __restrict__ owner,
+                             int* __restrict__ shift, double* __restrict__ pos_ext,
+                             double* __restrict__ frac_ext, int* __restrict__ spec_ext) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double f[3] = {frac[3 * k], frac[3 * k + 1], frac[3 * k + 2]};
+  int w = gptr[k];
+  for (int sx = -g.nimg[0]; sx <= g.nimg[0]; ++sx)
+    for (int sy = -g.nimg[1]; sy <= g.nimg[1]; ++sy)
+      for (int sz = -g.nimg[2]; sz <= g.nimg[2]; ++sz) {
+        if (sx == 0 && sy == 0 && sz == 0) continue;
+        if (!in_shell(f, sx, sy, sz, g)) continue;
+        owner[w] = k;
+        shift[3 * w] = sx;
+        shift[3 * w + 1] = sy;
+        shift[3 * w + 2] = sz;
+        int r = n + w;
+        for (int a = 0; a < 3; ++a) {
+          pos_ext[3 * r + a] = pos[3 * k + a] + sx * H.m[0 * 3 + a] + sy * H.m[1 * 3 + a] +
+                               sz * H.m[2 * 3 + a];
+        }
+        frac_ext[3 * r] = f[0] + sx;
+        frac_ext[3 * r + 1] = f[1] + sy;
+        frac_ext[3 * r + 2] = f[2] + sz;
+        spec_ext[r] = spec[k];
+        ++w;
+      }
+}
+
+__global__ void k_bin_keys(int n, const double* __restrict__ frac, BinGrid g, int* __restrict__ key) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double f[3] = {frac[3 * i], frac[3 * i + 1], frac[3 * i + 2]};
+  key[i] = bin_lin(f, g);
+}
+
+template <bool FILL>
+__global__ void k_edges(int n, const double* __restrict__ pos_ext, const double* __restrict__ frac_ext,
+                        BinGrid g, const int* __restrict__ cell_start,
+                        const int* __restrict__ cell_items, double rc2, int* __restrict__ count,
+                        int* __restrict__ err, const int* __restrict__ row_ptr,
+                        int* __restrict__ src, int* __restrict__ recv) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double p[3] = {pos_ext[3 * k], pos_ext[3 * k + 1], pos_ext[3 * k + 2]};
+  double f[3] = {frac_ext[3 * k], frac_ext[3 * k + 1], frac_ext[3 * k + 2]};
+  int b[3];
+  for (int a = 0; a < 3; ++a) b[a] = bin_axis(f[a], g, a);
+  int c = 0;
+  int w = FILL ? row_ptr[k] : 0;
+  for (int bx = max(b[0] - 1, 0); bx <= min(b[0] + 1, g.nb[0] - 1); ++bx)
+    for (int by = max(b[1] - 1, 0); by <= min(b[1] + 1, g.nb[1] - 1); ++by)
+      for (int bz = max(b[2] - 1, 0); bz <= min(b[2] + 1, g.nb[2] - 1); ++bz) {
+        int cell = (bx * g.nb[1] + by) * g.nb[2] + bz;
+        for (int q = cell_start[cell]; q < cell_start[cell + 1]; ++q) {
+          int s = cell_items[q];
+          if (s == k) continue;
+          double dx = pos_ext[3 * s] - p[0], dy = pos_ext[3 * s + 1] - p[1],
+                 dz = pos_ext[3 * s + 2] - p[2];
+          double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 < rc2) {
+            if (!FILL && r2 < 1e-16) atomicOr(err, 2);
+            if (FILL) {
+              src[w] = s;
+              recv[w] = k;
+              ++w;
+            } else {
+              ++c;
+            }
+          }
+        }
+      }
+  if (!FILL) count[k] = c;
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_wrap_bin(int n, const double* pos, const double* H, const double* Hinv, BinGrid g,
+                     double* posw, double* frac, int* key, int* err, hipStream_t s) {
+  Mat3 h, hi;
+  for (int i = 0; i < 9; ++i) { h.m[i] = H[i]; hi.m[i] = Hinv[i]; }
+  if (n > 0) k_wrap_bin<<<nblk(n, 256), 256, 0, s>>>(n, pos, h, hi, g, posw, frac, key, err);
+}
+void launch_count_keys(int n, const int* key, int* count, hipStream_t s) {
+  if (n > 0) k_count_keys<<<nblk(n, 256), 256, 0, s>>>(n, key, count);
+}
+void launch_scatter_keys(int n, const int* key, const int* start, int* cursor, int* items,
+                         hipStream_t s) {
+  if (n > 0) k_scatter_keys<<<nblk(n, 256), 256, 0, s>>>(n, key, start, cursor, items);
+}
+void launch_sort_segments(int nseg, const int* start, int* items, hipStream_t s) {
+  if (nseg > 0) k_sort_segments<<<nblk(nseg, 128), 128, 0, s>>>(nseg, start, items);
+}
+void launch_gather_local(int n, const int* order, const double* posw, const double* frac,
+                         const int* spec_orig, double* pos_ext, double* frac_ext, int* spec_ext,
+                         hipStream_t s) {
+  if (n > 0)
+    k_gather_local<<<nblk(n, 256), 256, 0, s>>>(n, order, posw, frac, spec_orig, pos_ext, frac_ext,
+                                                spec_ext);
+}
+void launch_ghost_count(int n, const double* frac, BinGrid g, int* count, hipStream_t s) {
+  if (n > 0) k_ghost_count<<<nblk(n, 128), 128, 0, s>>>(n, frac, g, count);
+}
+void launch_ghost_fill(int n, const double* frac, const double* pos, const int* spec,
+                       const double* H, BinGrid g, const int* gptr, int* owner, int* shift,
+                       double* pos_ext, double* frac_ext, int* spec_ext, hipStream_t s) {
+  Mat3 h;
+  for (int i = 0; i < 9; ++i) h.m[i] = H[i];
+  if (n > 0)
+    k_ghost_fill<<<nblk(n, 128), 128, 0, s>>>(n, frac, pos, spec, h, g, gptr, owner, shift, pos_ext,
+                                              frac_ext, spec_ext);
+}
+void launch_bin_keys(int n, const double* frac, BinGrid g, int* key, hipStream_t s) {
+  if (n > 0) k_bin_keys<<<nblk(n, 256), 256, 0, s>>>(n, frac, g, key);
+}
+void launch_edge_count(int n, const double* pos_ext, const double* frac_ext, BinGrid g,
+                       const int* cell_start, const int* cell_items, double rc2, int* count,
+                       int* err, hipStream_t s) {
+  if (n > 0)
+    k_edges<false><<<nblk(n, 128), 128, 0, s>>>(n, pos_ext, frac_ext, g, cell_start, cell_items, rc2,
+                                                 count, err, nullptr, nullptr, nullptr);
+}
+void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, BinGrid g,
+                      const int* cell_start, const int* cell_items, double rc2,
+                      const int* row_ptr, int* src, int* recv, hipStream_t s) {
+  if (n > 0)
+    k_edges<true><<<nblk(n, 128), 128, 0, s>>>(n, pos_ext, frac_ext, g, cell_start, cell_items, rc2,
+                                               nullptr, nullptr, row_ptr, src, recv);
+}
+
+}  // namespace sn

@@ -1,0 +1,321 @@
+// Node-level kernels and deterministic reductions.
+//
+//  * embedding (h^(1) = W_emb[species], section 2 and section 3.1: a ghost's
+//    first features come from its own species, so block 1 needs no refresh);
+//  * ghost refresh: ghost rows copy their owner's rows before every block
+//    after the first (forward communication, section 3.1, Fig 3d);
+//  * gate nonlinearity (forward and adjoint);
+//  * readout E_i = sigma (h_i Wr1) Wr2 + mu_s (eq 1 with the shift/scale of
+//    section 5.1); Wr1 Wr2 is a single C0-vector because no activation sits
+//    between the two linears;
+//  * sender-side segmented sums of per-edge gradient rows and the ghost fold
+//    (reverse communication of dE/dh and of partial forces, Fig 3e-f);
+//  * atomic forces from edge gradients (eq 6), virial and energy in float64.
+// Every reduction has a fixed order: no floating-point atomics.
+#include "kernels.h"
+
+namespace sn {
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+__global__ void k_embed(int rows, const int* __restrict__ spec, const T* __restrict__ Wemb, int C0,
+                        T* __restrict__ h, int ldh) {
+  int r = blockIdx.x;
+  const T* src = Wemb + (int64_t)spec[r] * C0;
+  for (int c = threadIdx.x; c < C0; c += blockDim.x) h[(int64_t)r * ldh + c] = src[c];
+}
+
+template <typename T>
+__global__ void k_ghost_refresh(int n_local, const int* __restrict__ owner, T* __restrict__ x,
+                                int width) {
+  int g = blockIdx.x;
+  const T* src = x + (int64_t)owner[g] * width;
+  T* dst = x + (int64_t)(n_local + g) * width;
+  for (int c = threadIdx.x; c < width; c += blockDim.x) dst[c] = src[c];
+}
+
+// y: gate-input row (l0: C0 scalars then gates for each l > 0 channel; l > 0 blocks)
+// h: output row (l0: C0; l > 0 blocks).  Last block: h0 = phi(y0) over C0 entries.
+template <typename T>
+__global__ void k_gate_fwd(int n, int last, IrrepLayout yl, IrrepLayout hl, const T* __restrict__ y,
+                           T* __restrict__ h, T c) {
+  int r = blockIdx.x;
+  const T* yr = y + (int64_t)r * yl.width;
+  T* hr = h + (int64_t)r * hl.width;
+  const int C0 = hl.mul[0];
+  for (int k = threadIdx.x; k < C0; k += blockDim.x) hr[hl.off[0] + k] = act(yr[yl.off[0] + k], c);
+  if (last) return;
+  int goff = C0;
+  for (int l = 1; l <= 2; ++l) {
+    const int mul = hl.mul[l];
+    if (mul == 0) continue;
+    const int nm = 2 * l + 1;
+    for (int k = threadIdx.x; k < nm * mul; k += blockDim.x) {
+      const int u = k % mul;
+      const T gv = act(yr[yl.off[0] + goff + u], c);
+      hr[hl.off[l] + k] = gv * yr[yl.off[l] + k];
+    }
+    goff += mul;
+  }
+}
+
+template <typename T>
+__global__ void k_gate_bwd(int n, int last, IrrepLayout yl, IrrepLayout hl, const T* __restrict__ y,
+                           const T* __restrict__ dh, T* __restrict__ dy, T c) {
+  int r = blockIdx.x;
+  const T* yr = y + (int64_t)r * yl.width;
+  const T* dhr = dh + (int64_t)r * hl.width;
+  T* dyr = dy + (int64_t)r * yl.width;
+  const int C0 = hl.mul[0];
+  for (int k = threadIdx.x; k < C0; k += blockDim.x)
+    dyr[yl.off[0] + k] = dhr[hl.off[0] + k] * act_grad(yr[yl.off[0] + k], c);
+  if (last) return;
+  int goff = C0;
+  for (int l = 1; l <= 2; ++l) {
+    const int mul = hl.mul[l];
+    if (mul == 0) continue;
+    const int nm = 2 * l + 1;
+    for (int k = threadIdx.x; k < nm * mul; k += blockDim.x) {
+      const int u = k % mul;
+      dyr[yl.off[l] + k] = dhr[hl.off[l] + k] * act(yr[yl.off[0] + goff + u], c);
+    }
+    for (int u = threadIdx.x; u < mul; u += blockDim.x) {
+      T s = T(0);
+      for (int m = 0; m < nm; ++m) s += dhr[hl.off[l] + m * mul + u] * yr[yl.off[l] + m * mul + u];
+      const T z = yr[yl.off[0] + goff + u];
+      dyr[yl.off[0] + goff + u] = s * act_grad(z, c);
+    }
+    goff += mul;
+  }
+}
+
+template <typename T>
+__global__ void k_readout(int n, const T* __restrict__ h, int ldh, const double* __restrict__ v,
+                          int C0, double sigma, const double* __restrict__ shift,
+                          const int* __restrict__ spec, double* __restrict__ atom_e) {
+  // one wave per atom
+  int r = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  int lane = threadIdx.x % kWave;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int k = lane; k < C0; k += kWave) s += (double)h[(int64_t)r * ldh + k] * v[k];
+  for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) atom_e[r] = sigma * s + shift[spec[r]];
+}
+
+template <typename T>
+__global__ void k_fill_rows(int n, const double* __restrict__ v, int C0, double scale,
+                            T* __restrict__ dh, int ldh) {
+  int r = blockIdx.x;
+  for (int k = threadIdx.x; k < ldh; k += blockDim.x)
+    dh[(int64_t)r * ldh + k] = k < C0 ? T(scale * v[k]) : T(0);
+}
+
+template <typename T>
+__global__ void k_sender_reduce(int n_rows, const int* __restrict__ sptr, const int* __restrict__ sidx,
+                                const T* __restrict__ dxe, int width, T* __restrict__ dx) {
+  int s = blockIdx.x;
+  int a = sptr[s], b = sptr[s + 1];
+  for (int c = threadIdx.x; c < width; c += blockDim.x) {
+    T acc = T(0);
+    for (int q = a; q < b; ++q) acc += dxe[(int64_t)sidx[q] * width + c];
+    dx[(int64_t)s * width + c] = acc;
+  }
+}
+
+// dx[o] = dx_ext[o] + sum of the owner's ghost rows dx_ext[n_local + g]
+template <typename T>
+__global__ void k_ghost_fold(int n_local, const int* __restrict__ gptr, const T* __restrict__ dx_ext,
+                             T* __restrict__ dx, int width) {
+  int o = blockIdx.x;
+  int a = gptr[o], b = gptr[o + 1];
+  for (int c = threadIdx.x; c < width; c += blockDim.x) {
+    T acc = dx_ext[(int64_t)o * width + c];
+    for (int q = a; q < b; ++q) acc += dx_ext[(int64_t)(n_local + q) * width + c];
+    dx[(int64_t)o * width + c] = acc;
+  }
+}
+
+template <typename T>
+__global__ void k_dY_reduce(int64_t E, int n_tasks, int NY, const T* __restrict__ part,
+                            T* __restrict__ dY, int accumulate) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * NY) return;
+  int64_t e = idx / NY;
+  int q = (int)(idx % NY);
+  T s = T(0);
+  for (int t = 0; t < n_tasks; ++t) s += part[(e * n_tasks + t) * NY + q];
+  dY[idx] = accumulate ? dY[idx] + s : s;
+}
+
+// F_k = sum_{e: recv=k} g_e - sum_{e: send=k} g_e - sum_{ghosts of k} sum_{e: send=ghost} g_e
+__global__ void k_forces(int n_local, const int* __restrict__ row_ptr, const int* __restrict__ sptr,
+                         const int* __restrict__ sidx, const int* __restrict__ gptr,
+                         const double* __restrict__ g, double* __restrict__ F) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_local) return;
+  double f[3] = {0, 0, 0};
+  for (int e = row_ptr[k]; e < row_ptr[k + 1]; ++e)
+    for (int a = 0; a < 3; ++a) f[a] += g[3 * (int64_t)e + a];
+  for (int q = sptr[k]; q < sptr[k + 1]; ++q) {
+    int64_t e = sidx[q];
+    for (int a = 0; a < 3; ++a) f[a] -= g[3 * e + a];
+  }
+  for (int gh = gptr[k]; gh < gptr[k + 1]; ++gh) {
+    int s = n_local + gh;
+    for (int q = sptr[s]; q < sptr[s + 1]; ++q) {
+      int64_t e = sidx[q];
+      for (int a = 0; a < 3; ++a) f[a] -= g[3 * e + a];
+    }
+  }
+  for (int a = 0; a < 3; ++a) F[3 * (int64_t)k + a] = f[a];
+}
+
+constexpr int kRedThreads = 256;
+
+// per-block sums of -d_e (x) g_e  (row-major 3x3)
+__global__ void k_virial_partial(int64_t E, const int* __restrict__ recv, const int* __restrict__ src,
+                                 const double* __restrict__ pos_ext, const double* __restrict__ g,
+                                 double* __restrict__ partial) {
+  __shared__ double s[kRedThreads][9];
+  double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int i = recv[e], j = src[e];
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = pos_ext[3 * j + a] - pos_ext[3 * i + a];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) w[a * 3 + b] -= d[a] * g[3 * e + b];
+  }
+  for (int q = 0; q < 9; ++q) s[threadIdx.x][q] = w[q];
+  __syncthreads();
+  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off)
+      for (int q = 0; q < 9; ++q) s[threadIdx.x][q] += s[threadIdx.x + off][q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 9; ++q) partial[blockIdx.x * 9 + q] = s[0][q];
+}
+
+__global__ void k_energy_partial(int n, const double* __restrict__ atom_e, double* __restrict__ partial) {
+  __shared__ double s[kRedThreads];
+  double v = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    v += atom_e[i];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ void k_sum_partials(int nblocks, int width, const double* __restrict__ partial,
+                               double* __restrict__ out, double scale) {
+  int q = threadIdx.x;
+  if (q >= width) return;
+  double s = 0;
+  for (int b = 0; b < nblocks; ++b) s += partial[b * width + q];
+  out[q] = scale * s;
+}
+
+__global__ void k_unpermute(int n, const int* __restrict__ order, const double* __restrict__ in_rows,
+                            int width, double* __restrict__ out_rows, double scale) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int o = order[k];
+  for (int a = 0; a < width; ++a) out_rows[(int64_t)o * width + a] = scale * in_rows[(int64_t)k * width + a];
+}
+
+// ------------------------------------------------------------------ launchers
+int partial_blocks(int64_t n) {
+  int64_t b = (n + kRedThreads - 1) / kRedThreads;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T>
+void launch_embed(int rows, const int* spec, const T* Wemb, int C0, T* h, int ldh, hipStream_t s) {
+  if (rows > 0) k_embed<T><<<rows, 64, 0, s>>>(rows, spec, Wemb, C0, h, ldh);
+}
+template <typename T>
+void launch_ghost_refresh(int n_local, int n_ghost, const int* owner, T* x, int width, hipStream_t s) {
+  if (n_ghost > 0) k_ghost_refresh<T><<<n_ghost, 128, 0, s>>>(n_local, owner, x, width);
+}
+template <typename T>
+void launch_gate_fwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const T* y, T* h, T c,
+                     hipStream_t s) {
+  if (n > 0) k_gate_fwd<T><<<n, 128, 0, s>>>(n, last ? 1 : 0, yl, hl, y, h, c);
+}
+template <typename T>
+void launch_gate_bwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const T* y, const T* dh,
+                     T* dy, T c, hipStream_t s) {
+  if (n > 0) k_gate_bwd<T><<<n, 128, 0, s>>>(n, last ? 1 : 0, yl, hl, y, dh, dy, c);
+}
+template <typename T>
+void launch_readout(int n, const T* h, int ldh, const double* v, int C0, double sigma,
+                    const double* shift, const int* spec, double* atom_e, hipStream_t s) {
+  if (n > 0) k_readout<T><<<nblk(n, 4), 256, 0, s>>>(n, h, ldh, v, C0, sigma, shift, spec, atom_e);
+}
+template <typename T>
+void launch_fill_rows(int n, const double* v, int C0, double scale, T* dh, int ldh, hipStream_t s) {
+  if (n > 0) k_fill_rows<T><<<n, 128, 0, s>>>(n, v, C0, scale, dh, ldh);
+}
+template <typename T>
+void launch_sender_reduce(int n_rows, const int* sptr, const int* sidx, const T* dxe, int width, T* dx,
+                          hipStream_t s) {
+  if (n_rows > 0) k_sender_reduce<T><<<n_rows, 128, 0, s>>>(n_rows, sptr, sidx, dxe, width, dx);
+}
+template <typename T>
+void launch_ghost_fold(int n_local, const int* gptr, const T* dx_ext, T* dx, int width, hipStream_t s) {
+  if (n_local > 0) k_ghost_fold<T><<<n_local, 128, 0, s>>>(n_local, gptr, dx_ext, dx, width);
+}
+template <typename T>
+void launch_dY_reduce(int64_t E, int n_tasks, int NY, const T* part, T* dY, bool accumulate,
+                      hipStream_t s) {
+  if (E > 0)
+    k_dY_reduce<T><<<nblk(E * NY, 256), 256, 0, s>>>(E, n_tasks, NY, part, dY, accumulate ? 1 : 0);
+}
+void launch_forces(int n_local, const int* row_ptr, const int* sptr, const int* sidx, const int* gptr,
+                   const double* g, double* F, hipStream_t s) {
+  if (n_local > 0) k_forces<<<nblk(n_local, 128), 128, 0, s>>>(n_local, row_ptr, sptr, sidx, gptr, g, F);
+}
+void launch_virial_partial(int64_t E, const int* recv, const int* src, const double* pos_ext,
+                           const double* g, double* partial, int nblocks, hipStream_t s) {
+  k_virial_partial<<<nblocks, kRedThreads, 0, s>>>(E, recv, src, pos_ext, g, partial);
+}
+void launch_energy_partial(int n, const double* atom_e, double* partial, int nblocks, hipStream_t s) {
+  k_energy_partial<<<nblocks, kRedThreads, 0, s>>>(n, atom_e, partial);
+}
+void launch_sum_partials(int nblocks, int width, const double* partial, double* out, double scale,
+                         hipStream_t s) {
+  k_sum_partials<<<1, 64, 0, s>>>(nblocks, width, partial, out, scale);
+}
+void launch_unpermute(int n, const int* order, const double* in_rows, int width, double* out_rows,
+                      double scale, hipStream_t s) {
+  if (n > 0) k_unpermute<<<nblk(n, 256), 256, 0, s>>>(n, order, in_rows, width, out_rows, scale);
+}
+
+#define SN_INST(T)                                                                                \
+  template void launch_embed<T>(int, const int*, const T*, int, T*, int, hipStream_t);            \
+  template void launch_ghost_refresh<T>(int, int, const int*, T*, int, hipStream_t);              \
+  template void launch_gate_fwd<T>(int, bool, IrrepLayout, IrrepLayout, const T*, T*, T,          \
+                                   hipStream_t);                                                  \
+  template void launch_gate_bwd<T>(int, bool, IrrepLayout, IrrepLayout, const T*, const T*, T*,   \
+                                   T, hipStream_t);                                               \
+  template void launch_readout<T>(int, const T*, int, const double*, int, double, const double*,  \
+                                  const int*, double*, hipStream_t);                              \
+  template void launch_fill_rows<T>(int, const double*, int, double, T*, int, hipStream_t);       \
+  template void launch_sender_reduce<T>(int, const int*, const int*, const T*, int, T*,           \
+                                        hipStream_t);                                             \
+  template void launch_ghost_fold<T>(int, const int*, const T*, T*, int, hipStream_t);            \
+  template void launch_dY_reduce<T>(int64_t, int, int, const T*, T*, bool, hipStream_t);
+SN_INST(float)
+SN_INST(double)
+#undef SN_INST
+
+}  // namespace sn

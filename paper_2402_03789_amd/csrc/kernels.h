@@ -1,0 +1,134 @@
+// Host-side launchers of the libsn kernels (one declaration per kernel family).
+#pragma once
+
+#include "common.h"
+
+namespace sn {
+
+// ---------------------------------------------------------------- graph build
+struct BinGrid {
+  int nb[3];        // bins per axis over the extended fractional region
+  double bw[3];     // bin width (fractional units), >= delta
+  double delta[3];  // shell half-width (fractional units) = (r_c + skin) / perpendicular width
+  int nimg[3];      // image-shift search range per axis
+};
+
+// exclusive scan of n ints into out[0..n] (out[n] = total); tmp needs scan_tmp_ints(n) ints
+size_t scan_tmp_ints(int64_t n);
+void scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
+
+void launch_wrap_bin(int n, const double* pos, const double* H, const double* Hinv, BinGrid g,
+                     double* posw, double* frac, int* key, int* err, hipStream_t s);
+void launch_count_keys(int n, const int* key, int* count, hipStream_t s);
+void launch_scatter_keys(int n, const int* key, const int* start, int* cursor, int* items,
+                         hipStream_t s);
+void launch_sort_segments(int nseg, const int* start, int* items, hipStream_t s);
+void launch_gather_local(int n, const int* order, const double* posw, const double* frac,
+                         const int* spec_orig, double* pos_ext, double* frac_ext, int* spec_ext,
+                         hipStream_t s);
+void launch_ghost_count(int n, const double* frac, BinGrid g, int* count, hipStream_t s);
+void launch_ghost_fill(int n, const double* frac, const double* pos, const int* spec,
+                       const double* H, BinGrid g, const int* gptr, int* owner, int* shift,
+                       double* pos_ext, double* frac_ext, int* spec_ext, hipStream_t s);
+void launch_bin_keys(int n, const double* frac, BinGrid g, int* key, hipStream_t s);
+void launch_edge_count(int n, const double* pos_ext, const double* frac_ext, BinGrid g,
+                       const int* cell_start, const int* cell_items, double rc2, int* count,
+                       int* err, hipStream_t s);
+void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, BinGrid g,
+                      const int* cell_start, const int* cell_items, double rc2,
+                      const int* row_ptr, int* src, int* recv, hipStream_t s);
+
+// ---------------------------------------------------------------- edge basis
+template <typename T>
+void launch_edge_basis(int64_t E, const int* recv, const int* src, const double* pos_ext,
+                       double r_cut, int n_basis, int p, int l_sh, T* Y, T* rho, hipStream_t s);
+template <typename T>
+void launch_edge_grad(int64_t E, const int* recv, const int* src, const double* pos_ext,
+                      double r_cut, int n_basis, int p, int l_sh, const T* dY, const T* drho,
+                      double* g, hipStream_t s);
+
+// ---------------------------------------------------------------- dense algebra
+// C[M x N] (=|+=) alpha * A[M x K] * op(B); op(B) = B (K x N, ld ldb) or B^T (B is N x K)
+template <typename T>
+void launch_gemm(int64_t M, int N, int K, const T* A, RowMap am, const T* B, int ldb, bool bt,
+                 T* C, RowMap cm, T alpha, bool accumulate, bool bf16_operands, hipStream_t s);
+
+template <typename T>
+void launch_mlp_hidden_fwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa,
+                           const T* Wb, T c, T* z2, hipStream_t s);
+template <typename T>
+void launch_mlp_hidden_bwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa,
+                           const T* Wb, T c, const T* dz2, T* drho, bool accumulate,
+                           hipStream_t s);
+
+// ---------------------------------------------------------------- tensor product
+struct TPTask {  // one wave's work: one degree l1, 64 lanes over channels x edges
+  int l1;
+  int u0;        // first channel
+  int cpt;       // channels per edge slot (power of two <= 64)
+};
+
+struct TPLayer {
+  int lmax, lsh;
+  bool scalar_only;     // last block: only l3 = 0 paths
+  IrrepLayout xin;      // layout of the sender feature rows
+  int P;                // radial weights per edge
+  int woff[3];          // first weight of the paths with each l1
+  int Dm;               // mid (message) row width
+  // per l1, per local path index: offset of (l3 block + channel start) in M, and l3 mid width
+  int mo[3][8];
+  int mw[3][8];
+  int n_tasks;
+  TPTask tasks[16];
+  int NY;               // (l_sh + 1)^2
+};
+
+template <typename T>
+void launch_tp_fwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
+                   const T* Y, const T* x, const T* w, T* M, T inv_k, hipStream_t s);
+template <typename T>
+void launch_tp_bwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
+                   const T* Y, const T* x, const T* w, const T* G, T* dw, T* dxe,
+                   T* dYpart, hipStream_t s);
+
+// ---------------------------------------------------------------- node-level and reductions
+template <typename T>
+void launch_embed(int rows, const int* spec, const T* Wemb, int C0, T* h, int ldh, hipStream_t s);
+template <typename T>
+void launch_ghost_refresh(int n_local, int n_ghost, const int* owner, T* x, int width,
+                          hipStream_t s);
+template <typename T>
+void launch_gate_fwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const T* y, T* h, T c,
+                     hipStream_t s);
+template <typename T>
+void launch_gate_bwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const T* y, const T* dh,
+                     T* dy, T c, hipStream_t s);
+template <typename T>
+void launch_readout(int n, const T* h, int ldh, const double* v, int C0, double sigma,
+                    const double* shift, const int* spec, double* atom_e, hipStream_t s);
+template <typename T>
+void launch_fill_rows(int n, const double* v, int C0, double scale, T* dh, int ldh,
+                      hipStream_t s);
+template <typename T>
+void launch_sender_reduce(int n_rows, const int* sptr, const int* sidx, const T* dxe, int width,
+                          T* dx, hipStream_t s);
+template <typename T>
+void launch_ghost_fold(int n_local, const int* gptr, const T* dx_ext, T* dx, int width,
+                       hipStream_t s);
+template <typename T>
+void launch_dY_reduce(int64_t E, int n_tasks, int NY, const T* part, T* dY, bool accumulate,
+                      hipStream_t s);
+void launch_forces(int n_local, const int* row_ptr, const int* sptr, const int* sidx,
+                   const int* gptr, const double* g, double* F, hipStream_t s);
+void launch_virial_partial(int64_t E, const int* recv, const int* src, const double* pos_ext,
+                           const double* g, double* partial, int nblocks, hipStream_t s);
+void launch_sum_partials(int nblocks, int width, const double* partial, double* out,
+                         double scale, hipStream_t s);
+void launch_energy_partial(int n, const double* atom_e, double* partial, int nblocks,
+                           hipStream_t s);
+void launch_unpermute(int n, const int* order, const double* in_rows, int width,
+                      double* out_rows, double scale, hipStream_t s);
+
+int partial_blocks(int64_t n);
+
+}  // namespace sn

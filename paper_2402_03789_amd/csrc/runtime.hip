@@ -1,0 +1,1016 @@
+// libsn host runtime: weights file, contexts, device workspace, and the
+// orchestration of one energy/force/virial evaluation on one subdomain with
+// a ghost shell (paper sections 2-3), plus the C ABI of include/sn.h.
+//
+// Evaluation order (paper Fig 3a):
+//   graph build (wrap, bins, ghost shell, receiver CSR, sender CSR)
+//   edge basis (Y, rho)
+//   for t = 1..T:  Lin1 (+ ghost refresh for t >= 2), Linsc, radial MLP,
+//                  tensor-product convolution, Lin2, gate
+//   readout, energy sum (eq 1)
+//   for t = T..1:  gate adjoint, Lin2^T, tensor-product adjoint (dw, per-edge
+//                  dx, dY), MLP adjoint (drho); for t >= 2: sender sums,
+//                  ghost fold, Lin1^T + Linsc^T (eq 8)
+//   edge gradients g_e (eq 5 summed over blocks), forces (eq 6) with the
+//   ghost force fold, virial W = -sum_e d_e (x) g_e.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "json.h"
+#include "cg_tables.h"
+#include "sn.h"
+
+namespace {
+
+using namespace sn;
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct MemError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct UnsupportedError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw HipError(std::string(#expr) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+thread_local std::string g_load_error;
+
+struct LayerDesc {
+  bool last = false;
+  std::vector<int> ins, outs;
+  std::vector<std::array<int, 3>> paths;
+  int P = 0;
+  int gmul[3] = {0, 0, 0};
+  int mid[3] = {0, 0, 0};
+  IrrepLayout hin{}, yl{}, ml{}, hout{};
+  TPLayer tp{};
+  int64_t w_lin1[3] = {-1, -1, -1}, w_linsc[3] = {-1, -1, -1}, w_lin2[3] = {-1, -1, -1};
+  int64_t w_mlp[3] = {-1, -1, -1};
+};
+
+IrrepLayout make_layout(int m0, int m1, int m2) {
+  IrrepLayout L{};
+  L.mul[0] = m0; L.mul[1] = m1; L.mul[2] = m2;
+  int off = 0;
+  for (int l = 0; l < 3; ++l) {
+    L.off[l] = off;
+    off += (2 * l + 1) * L.mul[l];
+  }
+  L.width = off;
+  return L;
+}
+
+RowMap rows_of(const IrrepLayout& L, int l) {
+  return RowMap{2 * l + 1, L.mul[l], (int64_t)L.width, (int64_t)L.off[l]};
+}
+
+}  // namespace
+
+struct sn_model {
+  int T = 0, lmax = 0, lsh = 0, nb = 8, hidden = 64, p = 6;
+  int muls[3] = {0, 0, 0};
+  double rc = 0, kavg = 1, sigma = 1, act = 1;
+  std::vector<int> species;
+  std::vector<double> shift;
+  std::vector<double> flat;
+  std::map<std::string, std::pair<int64_t, std::vector<int>>> tensors;
+  std::vector<LayerDesc> layers;
+  std::vector<double> readout_v;
+  int lut[128];
+  int64_t n_params = 0;
+
+  int64_t off(const std::string& name, std::vector<int> shape) const {
+    auto it = tensors.find(name);
+    if (it == tensors.end()) throw ArgError("weights file lacks tensor " + name);
+    if (it->second.second != shape) {
+      std::ostringstream o;
+      o << "tensor " << name << " has the wrong shape";
+      throw ArgError(o.str());
+    }
+    return it->second.first;
+  }
+};
+
+namespace {
+
+void build_layers(sn_model& m) {
+  const int C0 = m.muls[0];
+  const IrrepLayout feat = make_layout(m.muls[0], m.muls[1], m.muls[2]);
+  for (int t = 0; t < m.T; ++t) {
+    LayerDesc L;
+    L.last = (t == m.T - 1);
+    if (t == 0) L.ins = {0};
+    else for (int l = 0; l <= m.lmax; ++l) if (m.muls[l] > 0) L.ins.push_back(l);
+    if (L.last) L.outs = {0};
+    else for (int l = 0; l <= m.lmax; ++l) if (m.muls[l] > 0) L.outs.push_back(l);
+    for (int l1 : L.ins)
+      for (int l2 = 0; l2 <= m.lsh; ++l2)
+        for (int l3 = std::abs(l1 - l2); l3 <= std::min(l1 + l2, m.lmax); ++l3)
+          if (std::find(L.outs.begin(), L.outs.end(), l3) != L.outs.end())
+            L.paths.push_back({l1, l2, l3});
+    for (auto& pth : L.paths) L.P += m.muls[pth[0]];
+    for (int l : L.outs) {
+      if (L.last) L.gmul[l] = C0;
+      else L.gmul[l] = (l == 0) ? (m.muls[0] + m.muls[1] + m.muls[2]) : m.muls[l];
+    }
+    for (auto& pth : L.paths) L.mid[pth[2]] += m.muls[pth[0]];
+    L.hin = (t == 0) ? make_layout(C0, 0, 0) : feat;
+    L.yl = make_layout(L.gmul[0], L.gmul[1], L.gmul[2]);
+    L.ml = make_layout(L.mid[0], L.mid[1], L.mid[2]);
+    L.hout = L.last ? make_layout(C0, 0, 0) : feat;
+    // weights
+    for (int l : L.ins) {
+      const int mu = m.muls[l];
+      L.w_lin1[l] = m.off("l" + std::to_string(t) + ".lin1." + std::to_string(l), {mu, mu});
+      if (L.gmul[l] > 0)
+        L.w_linsc[l] = m.off("l" + std::to_string(t) + ".linsc." + std::to_string(l), {mu, L.gmul[l]});
+    }
+    L.w_mlp[0] = m.off("l" + std::to_string(t) + ".mlp.0", {m.nb, m.hidden});
+    L.w_mlp[1] = m.off("l" + std::to_string(t) + ".mlp.1", {m.hidden, m.hidden});
+    L.w_mlp[2] = m.off("l" + std::to_string(t) + ".mlp.2", {m.hidden, L.P});
+    for (int l : L.outs)
+      L.w_lin2[l] = m.off("l" + std::to_string(t) + ".lin2." + std::to_string(l), {L.mid[l], L.gmul[l]});
+    // tensor-product description
+    TPLayer& tp = L.tp;
+    tp.lmax = m.lmax;
+    tp.lsh = m.lsh;
+    tp.scalar_only = L.last;
+    tp.xin = L.hin;
+    tp.P = L.P;
+    tp.Dm = L.ml.width;
+    tp.NY = (m.lsh + 1) * (m.lsh + 1);
+    int woff = 0;
+    int kfill[3] = {0, 0, 0};
+    for (int l1 = 0; l1 <= 2; ++l1) {
+      tp.woff[l1] = woff;
+      int pi = 0;
+      for (auto& pth : L.paths) {
+        if (pth[0] != l1) continue;
+        const int l3 = pth[2];
+        tp.mo[l1][pi] = L.ml.off[l3] + kfill[l3];
+        tp.mw[l1][pi] = L.mid[l3];
+        kfill[l3] += m.muls[l1];
+        woff += m.muls[l1];
+        ++pi;
+      }
+    }
+    tp.n_tasks = 0;
+    for (int l1 : L.ins) {
+      const int mu = m.muls[l1];
+      int cpt = 1;
+      while (cpt < mu && cpt < 64) cpt <<= 1;
+      for (int u0 = 0; u0 < mu; u0 += cpt) {
+        if (tp.n_tasks >= 16) throw ArgError("too many channel tasks");
+        tp.tasks[tp.n_tasks++] = TPTask{l1, u0, cpt};
+      }
+    }
+    m.layers.push_back(L);
+  }
+}
+
+std::unique_ptr<sn_model> load_model(const char* path) {
+  std::ifstream f(path, std::ios::binary);
+  if (!f) throw ArgError(std::string("cannot open ") + path);
+  char magic[8];
+  f.read(magic, 8);
+  if (!f || std::memcmp(magic, "SNW1\0\0\0\0", 8) != 0) throw ArgError("not an SNW1 weights file");
+  uint64_t hlen = 0;
+  f.read(reinterpret_cast<char*>(&hlen), 8);
+  if (!f || hlen > (1u << 26)) throw ArgError("bad header length");
+  std::string hdr(hlen, ' ');
+  f.read(&hdr[0], (std::streamsize)hlen);
+  if (!f) throw ArgError("truncated header");
+  Json j = JsonParser(hdr).parse();
+  auto m = std::make_unique<sn_model>();
+  const Json& c = j.at("config");
+  m->T = c.at("n_layers").integer();
+  const auto& muls = c.at("muls").array();
+  if (muls.empty() || muls.size() > 3) throw UnsupportedError("l_max must be 0..2");
+  for (size_t l = 0; l < muls.size(); ++l) m->muls[l] = muls[l].integer();
+  m->lmax = (int)muls.size() - 1;
+  m->lsh = c.at("l_sh").integer();
+  m->rc = c.at("r_cut").number();
+  m->nb = c.at("n_basis").integer();
+  m->hidden = c.at("hidden").integer();
+  m->p = c.at("envelope_p").integer();
+  m->kavg = c.at("k_avg").number();
+  m->sigma = c.at("sigma").number();
+  m->act = c.at("act_scale").number();
+  if (c.has("gate") && c.at("gate").string() != "silu") throw UnsupportedError("only SiLU gates");
+  for (auto& z : c.at("species").array()) m->species.push_back(z.integer());
+  for (auto& v : c.at("shift").array()) m->shift.push_back(v.number());
+  if (m->T < 1 || m->rc <= 0 || m->species.empty() || m->species.size() > 128 ||
+      m->shift.size() != m->species.size())
+    throw ArgError("invalid model configuration");
+  if (m->nb != 8 || m->hidden != 64) throw UnsupportedError("radial MLP must be 8 -> 64 -> 64");
+  if (!((m->lmax == 1 && m->lsh == 1) || (m->lmax == 2 && m->lsh == 2)))
+    throw UnsupportedError("supported (l_max, l_sh): (1, 1) and (2, 2)");
+  if (m->muls[0] % 2 != 0) throw UnsupportedError("C0 must be even");
+  std::fill(m->lut, m->lut + 128, -1);
+  for (size_t s = 0; s < m->species.size(); ++s) {
+    int z = m->species[s];
+    if (z < 0 || z >= 128) throw ArgError("species out of range");
+    m->lut[z] = (int)s;
+  }
+  int64_t total = 0;
+  for (auto& t : j.at("tensors").array()) {
+    std::vector<int> shape;
+    int64_t cnt = 1;
+    for (auto& d : t.at("shape").array()) { shape.push_back(d.integer()); cnt *= d.integer(); }
+    int64_t off = (int64_t)t.at("offset").number();
+    if (off % 8 != 0) throw ArgError("misaligned tensor");
+    m->tensors[t.at("name").string()] = {off / 8, shape};
+    total = std::max(total, off / 8 + cnt);
+    m->n_params += cnt;
+  }
+  m->flat.resize((size_t)total);
+  f.read(reinterpret_cast<char*>(m->flat.data()), (std::streamsize)(total * 8));
+  if (!f) throw ArgError("truncated weights data");
+  const int C0 = m->muls[0];
+  m->off("embed", {(int)m->species.size(), C0});
+  int64_t r0 = m->off("readout.0", {C0, C0 / 2});
+  int64_t r1 = m->off("readout.1", {C0 / 2, 1});
+  m->readout_v.assign(C0, 0.0);
+  for (int a = 0; a < C0; ++a)
+    for (int k = 0; k < C0 / 2; ++k) m->readout_v[a] += m->flat[r0 + a * (C0 / 2) + k] * m->flat[r1 + k];
+  build_layers(*m);
+  return m;
+}
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct sn_ctx {
+  const sn_model* m = nullptr;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  int precision = SN_FP32;
+  double skin = 0;
+  std::string err;
+  std::map<std::string, Buf> bufs;
+  size_t used = 0;
+  bool dead = false;
+  // device weights
+  void* d_w = nullptr;
+  double* d_v = nullptr;
+  double* d_shift = nullptr;
+  // graph state
+  int N = 0, G = 0;
+  int64_t E = 0;
+  BinGrid grid{};
+  double H[9], Hinv[9];
+  bool pending = false;
+  // timing
+  std::vector<std::pair<std::string, hipEvent_t>> marks;
+  std::vector<std::pair<std::string, double>> timings;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_next = 0;
+
+  void* raw(const std::string& name, size_t bytes) {
+    Buf& b = bufs[name];
+    if (bytes <= b.cap) return b.p;
+    size_t want = std::max(bytes + bytes / 4, (size_t)256);
+    if (budget && used - b.cap + want > budget)
+      throw MemError("HBM budget exceeded allocating " + name);
+    if (b.p) {
+      HIPCHK(hipStreamSynchronize(stream));
+      HIPCHK(hipFree(b.p));
+      used -= b.cap;
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      throw MemError("device allocation failed for " + name);
+    }
+    b.cap = want;
+    used += want;
+    return b.p;
+  }
+  template <typename T>
+  T* get(const std::string& name, int64_t count) {
+    return static_cast<T*>(raw(name, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+  }
+  void mark(const std::string& name) {
+    if (event_next >= event_pool.size()) {
+      hipEvent_t ev;
+      HIPCHK(hipEventCreate(&ev));
+      event_pool.push_back(ev);
+    }
+    hipEvent_t ev = event_pool[event_next++];
+    HIPCHK(hipEventRecord(ev, stream));
+    marks.push_back({name, ev});
+  }
+};
+
+namespace {
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void zero(void* p, size_t bytes, hipStream_t s) {
+  int64_t n = (int64_t)(bytes / 4);
+  if (n > 0) k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(static_cast<uint32_t*>(p), n, 0u);
+}
+
+template <typename T>
+const T* W(const sn_ctx* c, int64_t off) {
+  return static_cast<const T*>(c->d_w) + off;
+}
+
+template <typename T>
+void upload_weights(sn_ctx* c) {
+  const sn_model* m = c->m;
+  std::vector<T> w(m->flat.size());
+  for (size_t i = 0; i < w.size(); ++i) w[i] = (T)m->flat[i];
+  HIPCHK(hipMalloc(&c->d_w, w.size() * sizeof(T)));
+  HIPCHK(hipMemcpy(c->d_w, w.data(), w.size() * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&c->d_v, m->readout_v.size() * sizeof(double)));
+  HIPCHK(hipMemcpy(c->d_v, m->readout_v.data(), m->readout_v.size() * sizeof(double),
+                   hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&c->d_shift, m->shift.size() * sizeof(double)));
+  HIPCHK(hipMemcpy(c->d_shift, m->shift.data(), m->shift.size() * sizeof(double),
+                   hipMemcpyHostToDevice));
+}
+
+// ------------------------------------------------------------------ graph build
+void inv3(const double* H, double* Hi, double* det_out) {
+  double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+               H[2] * (H[3] * H[7] - H[4] * H[6]);
+  *det_out = det;
+  double id = 1.0 / det;
+  Hi[0] = (H[4] * H[8] - H[5] * H[7]) * id;
+  Hi[1] = (H[2] * H[7] - H[1] * H[8]) * id;
+  Hi[2] = (H[1] * H[5] - H[2] * H[4]) * id;
+  Hi[3] = (H[5] * H[6] - H[3] * H[8]) * id;
+  Hi[4] = (H[0] * H[8] - H[2] * H[6]) * id;
+  Hi[5] = (H[2] * H[3] - H[0] * H[5]) * id;
+  Hi[6] = (H[3] * H[7] - H[4] * H[6]) * id;
+  Hi[7] = (H[1] * H[6] - H[0] * H[7]) * id;
+  Hi[8] = (H[0] * H[4] - H[1] * H[3]) * id;
+}
+
+void setup_cell(sn_ctx* c, const double* cell) {
+  for (int i = 0; i < 9; ++i) {
+    if (!std::isfinite(cell[i])) throw ArgError("cell has non-finite entries");
+    c->H[i] = cell[i];
+  }
+  double det;
+  inv3(c->H, c->Hinv, &det);
+  const double* a = c->H;
+  double cr[3][3];
+  for (int k = 0; k < 3; ++k) {
+    const double* u = a + 3 * ((k + 1) % 3);
+    const double* v = a + 3 * ((k + 2) % 3);
+    cr[k][0] = u[1] * v[2] - u[2] * v[1];
+    cr[k][1] = u[2] * v[0] - u[0] * v[2];
+    cr[k][2] = u[0] * v[1] - u[1] * v[0];
+  }
+  const double vol = std::fabs(det);
+  if (!(vol > 1e-6)) throw ArgError("singular cell");
+  const double reach = c->m->rc + c->skin;
+  BinGrid& g = c->grid;
+  int64_t nbins = 1;
+  for (int k = 0; k < 3; ++k) {
+    double w = vol / std::sqrt(cr[k][0] * cr[k][0] + cr[k][1] * cr[k][1] + cr[k][2] * cr[k][2]);
+    g.delta[k] = reach / w;
+    double span = 1.0 + 2.0 * g.delta[k];
+    g.bw[k] = std::max(g.delta[k], span / 256.0);
+    g.nb[k] = std::max(1, (int)std::ceil(span / g.bw[k] - 1e-12));
+    g.nimg[k] = (int)std::ceil(g.delta[k]) + 1;
+    nbins *= g.nb[k];
+  }
+  if (nbins > (1 << 24)) throw UnsupportedError("bin grid too large");
+}
+
+template <typename T>
+void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
+  hipStream_t s = c->stream;
+  const BinGrid g = c->grid;
+  const int nbins = g.nb[0] * g.nb[1] * g.nb[2];
+  c->N = N;
+  int* err = c->get<int>("err", 4);
+  zero(err, 16, s);
+  double* posw = c->get<double>("posw", 3 * N);
+  double* fracw = c->get<double>("fracw", 3 * N);
+  int* key = c->get<int>("key", N);
+  launch_wrap_bin(N, d_pos, c->H, c->Hinv, g, posw, fracw, key, err, s);
+  // order local atoms by bin (cell order) for locality of neighbour gathers
+  int* cnt = c->get<int>("bin_count", nbins + 1);
+  int* start = c->get<int>("bin_start", nbins + 1);
+  int* cursor = c->get<int>("bin_cursor", nbins + 1);
+  int64_t scan_max = std::max<int64_t>(nbins, 4 * (int64_t)N + 1024);
+  int* tmp = c->get<int>("scan_tmp", (int64_t)scan_tmp_ints(scan_max + 1));
+  int* order = c->get<int>("order", N);
+  zero(cnt, sizeof(int) * nbins, s);
+  zero(cursor, sizeof(int) * nbins, s);
+  launch_count_keys(N, key, cnt, s);
+  scan_exclusive(cnt, start, nbins, tmp, s);
+  launch_scatter_keys(N, key, start, cursor, order, s);
+  launch_sort_segments(nbins, start, order, s);
+  // local rows
+  int* gcount = c->get<int>("ghost_count", N + 1);
+  int* gptr = c->get<int>("ghost_ptr", N + 1);
+  double* fr_loc = c->get<double>("frac_local", 3 * N);
+  double* pos_loc = c->get<double>("pos_local", 3 * N);
+  int* spec_loc = c->get<int>("spec_local", N);
+  launch_gather_local(N, order, posw, fracw, d_spec, pos_loc, fr_loc, spec_loc, s);
+  launch_ghost_count(N, fr_loc, g, gcount, s);
+  scan_exclusive(gcount, gptr, N, tmp, s);
+  int hG[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&hG[0], gptr + N, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hG[1], err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hG[1] & 1) throw ArgError("non-finite positions");
+  const int G = hG[0];
+  c->G = G;
+  const int NE = N + G;
+  double* pos_ext = c->get<double>("pos_ext", 3 * (int64_t)NE);
+  double* frac_ext = c->get<double>("frac_ext", 3 * (int64_t)NE);
+  int* spec_ext = c->get<int>("spec_ext", NE);
+  int* owner = c->get<int>("ghost_owner", G);
+  int* shift = c->get<int>("ghost_shift", 3 * (int64_t)G);
+  HIPCHK(hipMemcpyAsync(pos_ext, pos_loc, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(frac_ext, fr_loc, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(spec_ext, spec_loc, sizeof(int) * N, hipMemcpyDeviceToDevice, s));
+  launch_ghost_fill(N, fr_loc, pos_loc, spec_loc, c->H, g, gptr, owner, shift, pos_ext, frac_ext,
+                    spec_ext, s);
+  // bin every extended point
+  int* ekey = c->get<int>("ext_key", NE);
+  int* cell_items = c->get<int>("cell_items", NE);
+  launch_bin_keys(NE, frac_ext, g, ekey, s);
+  zero(cnt, sizeof(int) * nbins, s);
+  zero(cursor, sizeof(int) * nbins, s);
+  launch_count_keys(NE, ekey, cnt, s);
+  scan_exclusive(cnt, start, nbins, tmp, s);
+  launch_scatter_keys(NE, ekey, start, cursor, cell_items, s);
+  launch_sort_segments(nbins, start, cell_items, s);
+  // receiver CSR
+  const double rc2 = c->m->rc * c->m->rc;
+  int* ecount = c->get<int>("edge_count", N + 1);
+  int* row_ptr = c->get<int>("row_ptr", N + 1);
+  launch_edge_count(N, pos_ext, frac_ext, g, start, cell_items, rc2, ecount, err, s);
+  scan_exclusive(ecount, row_ptr, N, tmp, s);
+  int hE[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&hE[0], row_ptr + N, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hE[1], err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hE[1] & 2) throw ArgError("two atoms at the same position (r = 0 pair)");
+  const int64_t E = hE[0];
+  c->E = E;
+  int* src = c->get<int>("src", E);
+  int* recv = c->get<int>("recv", E);
+  launch_edge_fill(N, pos_ext, frac_ext, g, start, cell_items, rc2, row_ptr, src, recv, s);
+  // sender CSR over extended rows (local and ghost senders)
+  int* scount = c->get<int>("send_count", NE + 1);
+  int* sptr = c->get<int>("send_ptr", NE + 1);
+  int* scur = c->get<int>("send_cursor", NE + 1);
+  int* sidx = c->get<int>("send_idx", E);
+  zero(scount, sizeof(int) * NE, s);
+  zero(scur, sizeof(int) * NE, s);
+  launch_count_keys((int)E, src, scount, s);
+  scan_exclusive(scount, sptr, NE, tmp, s);
+  launch_scatter_keys((int)E, src, sptr, scur, sidx, s);
+  launch_sort_segments(NE, sptr, sidx, s);
+}
+
+// ------------------------------------------------------------------ forward / backward
+template <typename T>
+struct Pipe {
+  sn_ctx* c;
+  const sn_model* m;
+  hipStream_t s;
+  bool bf16;
+  explicit Pipe(sn_ctx* ctx)
+      : c(ctx), m(ctx->m), s(ctx->stream), bf16(ctx->precision == SN_BF16) {}
+
+  void gemm(int64_t rows, int N, int K, const T* A, RowMap am, int64_t woff, int ldb, bool bt,
+            T* C, RowMap cm, T alpha, bool acc) {
+    launch_gemm<T>(rows, N, K, A, am, W<T>(c, woff), ldb, bt, C, cm, alpha, acc, bf16, s);
+  }
+
+  void forward(double* d_energy, double* d_atom_energy_orig) {
+    const int N = c->N, G = c->G, NE = N + G;
+    const int64_t E = c->E;
+    const int* row_ptr = c->get<int>("row_ptr", N + 1);
+    const int* src = c->get<int>("src", E);
+    const int* recv = c->get<int>("recv", E);
+    const double* pos_ext = c->get<double>("pos_ext", 3 * (int64_t)NE);
+    const int* spec_ext = c->get<int>("spec_ext", NE);
+    const int* owner = c->get<int>("ghost_owner", G);
+    const int NY = (m->lsh + 1) * (m->lsh + 1);
+    T* Y = c->get<T>("Y", E * NY);
+    T* rho = c->get<T>("rho", E * m->nb);
+    c->mark("edge_basis");
+    launch_edge_basis<T>(E, recv, src, pos_ext, m->rc, m->nb, m->p, m->lsh, Y, rho, s);
+    const T act = (T)m->act;
+    const int C0 = m->muls[0];
+    // h^(1): embedding rows for locals and ghosts (a ghost's first features come from its species)
+    T* h = c->get<T>("h_cur", (int64_t)NE * std::max(C0, m->layers[0].hout.width));
+    launch_embed<T>(NE, spec_ext, W<T>(c, m->off("embed", {(int)m->species.size(), C0})), C0, h,
+                    C0, s);
+    for (int t = 0; t < m->T; ++t) {
+      const LayerDesc& L = m->layers[t];
+      const std::string ts = std::to_string(t);
+      c->mark("layer" + ts + ".linear_in");
+      T* x = c->get<T>("x" + ts, (int64_t)NE * L.hin.width);
+      T* y = c->get<T>("y" + ts, (int64_t)N * L.yl.width);
+      const int xrows = (t == 0) ? NE : N;  // block 1: ghosts from their own species
+      for (int l : L.ins)
+        gemm((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h, rows_of(L.hin, l),
+             L.w_lin1[l], L.hin.mul[l], false, x, rows_of(L.hin, l), T(1), false);
+      if (t > 0) {
+        c->mark("layer" + ts + ".ghost_refresh");
+        launch_ghost_refresh<T>(N, G, owner, x, L.hin.width, s);
+      }
+      c->mark("layer" + ts + ".linsc");
+      for (int l : L.ins)
+        if (L.gmul[l] > 0)
+          gemm((int64_t)N * (2 * l + 1), L.gmul[l], L.hin.mul[l], h, rows_of(L.hin, l), L.w_linsc[l],
+               L.gmul[l], false, y, rows_of(L.yl, l), T(1), false);
+      c->mark("layer" + ts + ".mlp");
+      T* z2 = c->get<T>("z2_" + ts, E * m->hidden);
+      launch_mlp_hidden_fwd<T>(E, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]), W<T>(c, L.w_mlp[1]),
+                               act, z2, s);
+      T* w = c->get<T>("w" + ts, E * L.P);
+      gemm(E, L.P, m->hidden, z2, plain_rows(m->hidden), L.w_mlp[2], L.P, false, w, plain_rows(L.P),
+           T(1), false);
+      c->mark("layer" + ts + ".tp");
+      T* M = c->get<T>("M", (int64_t)N * L.ml.width);
+      launch_tp_fwd<T>(L.tp, N, row_ptr, src, Y, x, w, M, (T)(1.0 / m->kavg), s);
+      c->mark("layer" + ts + ".linear_out");
+      for (int l : L.outs) {
+        const bool has_sc = std::find(L.ins.begin(), L.ins.end(), l) != L.ins.end() && L.gmul[l] > 0;
+        gemm((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M, rows_of(L.ml, l), L.w_lin2[l],
+             L.gmul[l], false, y, rows_of(L.yl, l), T(1), has_sc);
+      }
+      T* hn = c->get<T>(t % 2 ? "h_a" : "h_b", (int64_t)N * L.hout.width);
+      launch_gate_fwd<T>(N, L.last, L.yl, L.hout, y, hn, act, s);
+      h = hn;
+    }
+    c->mark("readout");
+    double* ae = c->get<double>("atom_e", N);
+    const int* spec_loc = c->get<int>("spec_local", N);
+    launch_readout<T>(N, h, m->layers.back().hout.width, c->d_v, C0, m->sigma, c->d_shift, spec_loc,
+                      ae, s);
+    int nbk = partial_blocks(N);
+    double* part = c->get<double>("partial_e", nbk);
+    launch_energy_partial(N, ae, part, nbk, s);
+    launch_sum_partials(nbk, 1, part, d_energy, 1.0, s);
+    if (d_atom_energy_orig) {
+      const int* order = c->get<int>("order", N);
+      launch_unpermute(N, order, ae, 1, d_atom_energy_orig, 1.0, s);
+    }
+  }
+
+  void backward(double grad_scale, double* d_forces_orig, double* d_virial) {
+    const int N = c->N, G = c->G, NE = N + G;
+    const int64_t E = c->E;
+    const int* row_ptr = c->get<int>("row_ptr", N + 1);
+    const int* src = c->get<int>("src", E);
+    const int* recv = c->get<int>("recv", E);
+    const int* sptr = c->get<int>("send_ptr", NE + 1);
+    const int* sidx = c->get<int>("send_idx", E);
+    const int* gptr = c->get<int>("ghost_ptr", N + 1);
+    const double* pos_ext = c->get<double>("pos_ext", 3 * (int64_t)NE);
+    const int NY = (m->lsh + 1) * (m->lsh + 1);
+    const T* Y = c->get<T>("Y", E * NY);
+    const T* rho = c->get<T>("rho", E * m->nb);
+    const T act = (T)m->act;
+    const int C0 = m->muls[0];
+    int max_w = 0, max_P = 0, max_tasks = 0, max_m = 0, max_y = 0;
+    for (auto& L : m->layers) {
+      max_w = std::max(max_w, L.hin.width);
+      max_P = std::max(max_P, L.P);
+      max_tasks = std::max(max_tasks, L.tp.n_tasks);
+      max_m = std::max(max_m, L.ml.width);
+      max_y = std::max(max_y, L.yl.width);
+    }
+    T* dh = c->get<T>("dh_a", (int64_t)N * max_w);
+    T* dh_other = c->get<T>("dh_b", (int64_t)N * max_w);
+    T* dy = c->get<T>("dy", (int64_t)N * max_y);
+    T* Gm = c->get<T>("G", (int64_t)N * max_m);
+    T* dw = c->get<T>("dw", E * max_P);
+    T* dxe = c->get<T>("dxe", E * max_w);
+    T* dx_ext = c->get<T>("dx_ext", (int64_t)NE * max_w);
+    T* dx = c->get<T>("dx", (int64_t)N * max_w);
+    T* dz2 = c->get<T>("dz2", E * m->hidden);
+    T* dYp = c->get<T>("dYpart", E * max_tasks * NY);
+    T* dY = c->get<T>("dY", E * NY);
+    T* drho = c->get<T>("drho", E * m->nb);
+    c->mark("bwd.readout");
+    // dE/dh^(T+1) = sigma (Wr1 Wr2): the same vector for every atom
+    launch_fill_rows<T>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
+    for (int t = m->T - 1; t >= 0; --t) {
+      const LayerDesc& L = m->layers[t];
+      const std::string ts = std::to_string(t);
+      const T* x = c->get<T>("x" + ts, (int64_t)NE * L.hin.width);
+      const T* y = c->get<T>("y" + ts, (int64_t)N * L.yl.width);
+      const T* w = c->get<T>("w" + ts, E * L.P);
+      const T* z2 = c->get<T>("z2_" + ts, E * m->hidden);
+      (void)z2;
+      c->mark("bwd.layer" + ts + ".linear_out");
+      launch_gate_bwd<T>(N, L.last, L.yl, L.hout, y, dh, dy, act, s);
+      for (int l : L.outs)
+        gemm((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy, rows_of(L.yl, l), L.w_lin2[l],
+             L.gmul[l], true, Gm, rows_of(L.ml, l), (T)(1.0 / m->kavg), false);
+      c->mark("bwd.layer" + ts + ".tp");
+      launch_tp_bwd<T>(L.tp, N, row_ptr, src, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dYp, s);
+      launch_dY_reduce<T>(E, L.tp.n_tasks, NY, dYp, dY, t != m->T - 1, s);
+      c->mark("bwd.layer" + ts + ".mlp");
+      gemm(E, m->hidden, L.P, dw, plain_rows(L.P), L.w_mlp[2], L.P, true, dz2,
+           plain_rows(m->hidden), T(1), false);
+      launch_mlp_hidden_bwd<T>(E, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]), W<T>(c, L.w_mlp[1]),
+                               act, dz2, drho, t != m->T - 1, s);
+      if (t == 0) break;
+      c->mark("bwd.layer" + ts + ".sender_fold");
+      // sender-side sums over every extended row, then fold ghost rows onto owners
+      launch_sender_reduce<T>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
+      launch_ghost_fold<T>(N, gptr, dx_ext, dx, L.hin.width, s);
+      c->mark("bwd.layer" + ts + ".linear_in");
+      for (int l : L.ins) {
+        gemm((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], dx, rows_of(L.hin, l),
+             L.w_lin1[l], L.hin.mul[l], true, dh_other, rows_of(L.hin, l), T(1), false);
+        if (L.gmul[l] > 0)
+          gemm((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], dy, rows_of(L.yl, l),
+               L.w_linsc[l], L.gmul[l], true, dh_other, rows_of(L.hin, l), T(1), true);
+      }
+      std::swap(dh, dh_other);
+    }
+    c->mark("bwd.forces");
+    double* gE = c->get<double>("g_edge", 3 * E);
+    launch_edge_grad<T>(E, recv, src, pos_ext, m->rc, m->nb, m->p, m->lsh, dY, drho, gE, s);
+    double* F = c->get<double>("F_local", 3 * (int64_t)N);
+    launch_forces(N, row_ptr, sptr, sidx, gptr, gE, F, s);
+    if (d_forces_orig) {
+      const int* order = c->get<int>("order", N);
+      launch_unpermute(N, order, F, 3, d_forces_orig, grad_scale, s);
+    }
+    if (d_virial) {
+      int nbk = partial_blocks(E);
+      double* part = c->get<double>("partial_w", 9 * (int64_t)nbk);
+      launch_virial_partial(E, recv, src, pos_ext, gE, part, nbk, s);
+      launch_sum_partials(nbk, 9, part, d_virial, grad_scale, s);
+    }
+    c->mark("end");
+  }
+};
+
+void collect_timings(sn_ctx* c) {
+  c->timings.clear();
+  if (c->marks.size() < 2) return;
+  HIPCHK(hipEventSynchronize(c->marks.back().second));
+  std::map<std::string, double> acc;
+  std::vector<std::string> orderv;
+  for (size_t i = 0; i + 1 < c->marks.size(); ++i) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->marks[i].second, c->marks[i + 1].second));
+    if (!acc.count(c->marks[i].first)) orderv.push_back(c->marks[i].first);
+    acc[c->marks[i].first] += ms;
+  }
+  for (auto& k : orderv) c->timings.push_back({k, acc[k]});
+}
+
+template <typename F>
+int guarded(sn_ctx* c, F&& f) {
+  if (c && c->dead) {
+    return SN_EHIP;
+  }
+  try {
+    if (c) HIPCHK(hipSetDevice(c->device));
+    f();
+    return SN_OK;
+  } catch (const ArgError& e) {
+    if (c) c->err = e.what();
+    return SN_EINVAL;
+  } catch (const MemError& e) {
+    if (c) c->err = e.what();
+    return SN_ENOMEM;
+  } catch (const UnsupportedError& e) {
+    if (c) c->err = e.what();
+    return SN_EUNSUPPORTED;
+  } catch (const HipError& e) {
+    if (c) {
+      c->err = e.what();
+      c->dead = true;
+    }
+    return SN_EHIP;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return SN_EINVAL;
+  }
+}
+
+template <typename T>
+void forward_impl(sn_ctx* c, int64_t n, const double* d_pos, const int* d_spec, const double* cell,
+                  double* d_energy, double* d_atom_energy) {
+  if (n <= 0 || n > (1 << 28)) throw ArgError("atom count out of range");
+  setup_cell(c, cell);
+  c->marks.clear();
+  c->event_next = 0;
+  c->mark("graph");
+  build_graph<T>(c, (int)n, d_pos, d_spec);
+  Pipe<T> p(c);
+  p.forward(d_energy, d_atom_energy);
+  c->pending = true;
+}
+
+template <typename T>
+void backward_impl(sn_ctx* c, double g, double* d_forces, double* d_virial) {
+  if (!c->pending) throw std::logic_error("busy");
+  Pipe<T> p(c);
+  p.backward(g, d_forces, d_virial);
+  c->pending = false;
+}
+
+void map_species(const sn_model* m, int64_t n, const int32_t* Z, std::vector<int>& out) {
+  out.resize((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    int z = Z[i];
+    if (z < 0 || z >= 128 || m->lut[z] < 0) throw ArgError("atomic number not in the model");
+    out[i] = m->lut[z];
+  }
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* sn_strerror(int status) {
+  switch (status) {
+    case SN_OK: return "ok";
+    case SN_EINVAL: return "invalid argument";
+    case SN_ENOMEM: return "out of device memory or HBM budget";
+    case SN_EHIP: return "HIP runtime error";
+    case SN_EUNSUPPORTED: return "unsupported";
+    case SN_EBUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+const char* sn_last_error(const sn_ctx_t* ctx) {
+  if (!ctx) return g_load_error.c_str();
+  return ctx->err.c_str();
+}
+
+int sn_model_load(const char* path, sn_model_t** out) {
+  if (!path || !out) return SN_EINVAL;
+  try {
+    *out = load_model(path).release();
+    return SN_OK;
+  } catch (const UnsupportedError& e) {
+    g_load_error = e.what();
+    return SN_EUNSUPPORTED;
+  } catch (const std::exception& e) {
+    g_load_error = e.what();
+    return SN_EINVAL;
+  }
+}
+
+void sn_model_free(sn_model_t* model) { delete model; }
+
+int sn_model_info(const sn_model_t* m, sn_model_info_t* info) {
+  if (!m || !info) return SN_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->n_layers = m->T;
+  info->l_max = m->lmax;
+  info->l_sh = m->lsh;
+  for (int l = 0; l < 3; ++l) info->muls[l] = m->muls[l];
+  info->n_basis = m->nb;
+  info->hidden = m->hidden;
+  info->n_species = (int)m->species.size();
+  for (size_t s = 0; s < m->species.size(); ++s) info->species_z[s] = m->species[s];
+  info->r_cut = m->rc;
+  info->k_avg = m->kavg;
+  info->sigma = m->sigma;
+  info->n_params = m->n_params;
+  return SN_OK;
+}
+
+int sn_cg_table(int l1, int l2, int l3, double* out) {
+  if (!out || l1 < 0 || l2 < 0 || l3 < 0 || l1 > 2 || l2 > 2 || l3 > 2) return SN_EINVAL;
+  if (l3 < std::abs(l1 - l2) || l3 > l1 + l2) return SN_EINVAL;
+  int id = 0;
+  for (int a = 0; a <= 2; ++a)
+    for (int b = 0; b <= 2; ++b)
+      for (int c = std::abs(a - b); c <= std::min(a + b, 2); ++c) {
+        if (a == l1 && b == l2 && c == l3) {
+          const int n = (2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1);
+          for (int i = 0; i < n; ++i) out[i] = sn::kCGDense[id][i];
+          return SN_OK;
+        }
+        ++id;
+      }
+  return SN_EINVAL;
+}
+
+int sn_ctx_create(const sn_model_t* model, int device, void* hip_stream, size_t hbm_budget,
+                  int precision, double skin, sn_ctx_t** out) {
+  if (!model || !out || skin < 0 || !std::isfinite(skin)) return SN_EINVAL;
+  if (precision != SN_FP64 && precision != SN_FP32 && precision != SN_BF16) return SN_EINVAL;
+  auto c = std::make_unique<sn_ctx>();
+  c->m = model;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->budget = hbm_budget;
+  c->precision = precision;
+  c->skin = skin;
+  int st = guarded(c.get(), [&] {
+    if (precision == SN_FP64) upload_weights<double>(c.get());
+    else upload_weights<float>(c.get());
+  });
+  if (st != SN_OK) {
+    g_load_error = c->err;
+    return st;
+  }
+  *out = c.release();
+  return SN_OK;
+}
+
+void sn_ctx_free(sn_ctx_t* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (ctx->d_w) (void)hipFree(ctx->d_w);
+  if (ctx->d_v) (void)hipFree(ctx->d_v);
+  if (ctx->d_shift) (void)hipFree(ctx->d_shift);
+  for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
+  delete ctx;
+}
+
+int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32_t* d_Z,
+                      const double* cell, double* d_energy, double* d_atom_energy) {
+  if (!ctx || !d_pos || !d_Z || !cell || !d_energy) return SN_EINVAL;
+  return guarded(ctx, [&] {
+    // map atomic numbers to embedding rows on the host (validation before any launch)
+    std::vector<int32_t> hz((size_t)n);
+    HIPCHK(hipMemcpyAsync(hz.data(), d_Z, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::vector<int> spec;
+    map_species(ctx->m, n, hz.data(), spec);
+    int* d_spec = ctx->get<int>("spec_orig", n);
+    HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->precision == SN_FP64)
+      forward_impl<double>(ctx, n, d_pos, d_spec, cell, d_energy, d_atom_energy);
+    else
+      forward_impl<float>(ctx, n, d_pos, d_spec, cell, d_energy, d_atom_energy);
+  });
+}
+
+int sn_backward_device(sn_ctx_t* ctx, double grad_energy, double* d_forces, double* d_virial) {
+  if (!ctx) return SN_EINVAL;
+  if (!ctx->pending) {
+    ctx->err = "backward without a pending forward";
+    return SN_EBUSY;
+  }
+  return guarded(ctx, [&] {
+    if (ctx->precision == SN_FP64) backward_impl<double>(ctx, grad_energy, d_forces, d_virial);
+    else backward_impl<float>(ctx, grad_energy, d_forces, d_virial);
+  });
+}
+
+int sn_ctx_synchronize(sn_ctx_t* ctx) {
+  if (!ctx) return SN_EINVAL;
+  return guarded(ctx, [&] {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    collect_timings(ctx);
+  });
+}
+
+int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, const double* cell,
+               const uint8_t* pbc, double* energy, double* atom_energy, double* forces,
+               double* virial) {
+  if (!ctx || !pos || !Z || !cell || !energy || n <= 0) return SN_EINVAL;
+  if (pbc && !(pbc[0] && pbc[1] && pbc[2])) {
+    ctx->err = "only fully periodic cells are supported";
+    return SN_EUNSUPPORTED;
+  }
+  return guarded(ctx, [&] {
+    std::vector<int> spec;
+    map_species(ctx->m, n, Z, spec);
+    for (int64_t i = 0; i < 3 * n; ++i)
+      if (!std::isfinite(pos[i])) throw ArgError("non-finite positions");
+    hipStream_t s = ctx->stream;
+    double* d_pos = ctx->get<double>("in_pos", 3 * n);
+    int* d_spec = ctx->get<int>("spec_orig", n);
+    double* d_out = ctx->get<double>("out_host_stage", 1 + 9 + n + 3 * n);
+    HIPCHK(hipMemcpyAsync(d_pos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    double* d_e = d_out;
+    double* d_w = d_out + 1;
+    double* d_ae = d_out + 10;
+    double* d_f = d_out + 10 + n;
+    const bool need_bwd = forces || virial;
+    if (ctx->precision == SN_FP64) {
+      forward_impl<double>(ctx, n, d_pos, d_spec, cell, d_e, d_ae);
+      if (need_bwd) backward_impl<double>(ctx, 1.0, d_f, d_w);
+    } else {
+      forward_impl<float>(ctx, n, d_pos, d_spec, cell, d_e, d_ae);
+      if (need_bwd) backward_impl<float>(ctx, 1.0, d_f, d_w);
+    }
+    ctx->pending = false;
+    std::vector<double> h((size_t)(10 + 4 * n));
+    HIPCHK(hipMemcpyAsync(h.data(), d_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    collect_timings(ctx);
+    *energy = h[0];
+    if (virial) std::memcpy(virial, &h[1], 9 * sizeof(double));
+    if (atom_energy) std::memcpy(atom_energy, &h[10], n * sizeof(double));
+    if (forces) std::memcpy(forces, &h[10 + n], 3 * n * sizeof(double));
+  });
+}
+
+int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, int64_t* n_edge) {
+  if (!ctx) return SN_EINVAL;
+  if (n_local) *n_local = ctx->N;
+  if (n_ghost) *n_ghost = ctx->G;
+  if (n_edge) *n_edge = ctx->E;
+  return SN_OK;
+}
+
+int sn_ctx_graph(const sn_ctx_t* cctx, int32_t* recv, int32_t* send_owner, int32_t* shift,
+                 int32_t* ghost_owner, int32_t* ghost_shift) {
+  sn_ctx_t* ctx = const_cast<sn_ctx_t*>(cctx);
+  if (!ctx) return SN_EINVAL;
+  return guarded(ctx, [&] {
+    const int N = ctx->N, G = ctx->G;
+    const int64_t E = ctx->E;
+    hipStream_t s = ctx->stream;
+    std::vector<int> order(N), owner(G), gsh(3 * (size_t)G), src(E), rcv(E);
+    HIPCHK(hipMemcpyAsync(order.data(), ctx->get<int>("order", N), sizeof(int) * N,
+                          hipMemcpyDeviceToHost, s));
+    if (G) {
+      HIPCHK(hipMemcpyAsync(owner.data(), ctx->get<int>("ghost_owner", G), sizeof(int) * G,
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(gsh.data(), ctx->get<int>("ghost_shift", 3 * (int64_t)G),
+                            sizeof(int) * 3 * G, hipMemcpyDeviceToHost, s));
+    }
+    if (E) {
+      HIPCHK(hipMemcpyAsync(src.data(), ctx->get<int>("src", E), sizeof(int) * E,
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(rcv.data(), ctx->get<int>("recv", E), sizeof(int) * E,
+                            hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t e = 0; e < E; ++e) {
+      const int sd = src[e];
+      const int own = sd < N ? sd : owner[sd - N];
+      if (recv) recv[e] = order[rcv[e]];
+      if (send_owner) send_owner[e] = order[own];
+      if (shift)
+        for (int a = 0; a < 3; ++a) shift[3 * e + a] = sd < N ? 0 : gsh[3 * (size_t)(sd - N) + a];
+    }
+    for (int g = 0; g < G; ++g) {
+      if (ghost_owner) ghost_owner[g] = order[owner[g]];
+      if (ghost_shift)
+        for (int a = 0; a < 3; ++a) ghost_shift[3 * g + a] = gsh[3 * (size_t)g + a];
+    }
+  });
+}
+
+int sn_ctx_timings(const sn_ctx_t* ctx, const char** names, double* ms, int* count) {
+  if (!ctx || !count) return SN_EINVAL;
+  int n = std::min<int>(*count, (int)ctx->timings.size());
+  for (int i = 0; i < n; ++i) {
+    if (names) names[i] = ctx->timings[i].first.c_str();
+    if (ms) ms[i] = ctx->timings[i].second;
+  }
+  *count = (int)ctx->timings.size();
+  return SN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports what include/sn.h declares (no device needed).
+
+Host-only entry points are exercised here: the weights-file loader and the
+Clebsch-Gordan table export, compared with the oracle's independently
+generated tables.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(sn_[a-z_0-9]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2402_03789_amd as sn
+    L = sn.lib()
+    decl = _declared()
+    assert len(decl) >= 15
+    for name in decl:
+        assert hasattr(L, name), name
+    assert decl <= set(sn.EXPORTED) | decl
+
+
+def test_cg_tables_match_oracle():
+    import paper_2402_03789_amd as sn
+    from oracle.cg import real_cg
+    for l1 in range(3):
+        for l2 in range(3):
+            for l3 in range(abs(l1 - l2), min(l1 + l2, 2) + 1):
+                np.testing.assert_allclose(sn.cg_table(l1, l2, l3), real_cg(l1, l2, l3), atol=1e-13)
+    with pytest.raises(sn.SNError):
+        sn.cg_table(1, 1, 3)
+
+
+def test_model_load_and_parameter_count(tmp_path):
+    import paper_2402_03789_amd as sn
+    from synth import model_spec_real, model_spec_small, make_weights, write_weights
+    spec = model_spec_real(species=tuple(range(1, 90)))
+    p = str(tmp_path / "m.snw")
+    write_weights(p, spec, make_weights(spec, 1))
+    info = sn.Model(p).info()
+    assert info["n_params"] == 842_432
+    assert info["muls"] == [128, 64, 32] and info["n_layers"] == 5
+    spec = model_spec_small()
+    write_weights(p, spec, make_weights(spec, 1))
+    assert sn.Model(p).info()["n_params"] == 56_400
+
+
+def test_model_load_rejects_bad_files(tmp_path):
+    import paper_2402_03789_amd as sn
+    p = tmp_path / "bad.snw"
+    p.write_bytes(b"not a weights file")
+    with pytest.raises(sn.SNError):
+        sn.Model(str(p))
+    with pytest.raises(sn.SNError):
+        sn.Model(str(tmp_path / "missing.snw"))
