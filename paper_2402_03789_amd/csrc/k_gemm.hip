@@ -13,32 +13,30 @@ namespace sn {
 constexpr int GT = 64;   // tile rows / cols
 constexpr int GK = 16;   // k step
 
-template <typename T>
-__device__ inline T round_operand(T v, bool bf16) {
-  return v;
-}
-template <>
-__device__ inline float round_operand<float>(float v, bool bf16) {
-  if (!bf16) return v;
-  return __bfloat162float(__float2bfloat16(v));
+template <typename TACC, typename T>
+__device__ inline TACC load_operand(T v, bool bf16) {
+  if (bf16) return (TACC)__bfloat162float(__float2bfloat16((float)v));
+  return (TACC)v;
 }
 
-template <typename T, bool BT>
-__global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, const T* __restrict__ A,
-                                                    RowMap am, const T* __restrict__ B, int ldb,
-                                                    T* __restrict__ C, RowMap cm, T alpha, int accumulate,
-                                                    int bf16) {
-  __shared__ T As[GK][GT + 4];
-  __shared__ T Bs[GK][GT + 4];
+// C[M x N] (=|+=) alpha * A[M x K] op(B), with operand types TA/TB, result type TC
+// and accumulation in TACC.  64 x 64 tile per 256-thread block, 4 x 4 per thread.
+template <typename TA, typename TB, typename TC, typename TACC, bool BT>
+__global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, const TA* __restrict__ A,
+                                                    RowMap am, const TB* __restrict__ B, int ldb,
+                                                    TC* __restrict__ C, RowMap cm, TACC alpha,
+                                                    int accumulate, int bf16) {
+  __shared__ TACC As[GK][GT + 4];
+  __shared__ TACC Bs[GK][GT + 4];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   const int64_t m0 = (int64_t)blockIdx.x * GT;
   const int n0 = blockIdx.y * GT;
-  T acc[4][4];
+  TACC acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+    for (int j = 0; j < 4; ++j) acc[i][j] = TACC(0);
   const int ar = tid >> 2, ak = (tid & 3) * 4;
   const int64_t agm = m0 + ar;
   const int64_t arow = agm < M ? am(agm) : 0;
@@ -47,19 +45,20 @@ __global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, cons
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       int k = k0 + ak + j;
-      As[ak + j][ar] = (agm < M && k < K) ? round_operand(A[arow + k], bf16) : T(0);
+      As[ak + j][ar] = (agm < M && k < K) ? load_operand<TACC>(A[arow + k], bf16) : TACC(0);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       int n = n0 + bn + j, k = k0 + bk;
-      T v = T(0);
-      if (k < K && n < N) v = BT ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n];
-      Bs[bk][bn + j] = round_operand(v, bf16);
+      TACC v = TACC(0);
+      if (k < K && n < N)
+        v = load_operand<TACC>(BT ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n], bf16);
+      Bs[bk][bn + j] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < GK; ++kk) {
-      T a[4], b[4];
+      TACC a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
 #pragma unroll
@@ -75,34 +74,41 @@ __global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, cons
   for (int i = 0; i < 4; ++i) {
     int64_t row = m0 + ty * 4 + i;
     if (row >= M) continue;
-    T* c = C + cm(row);
+    TC* c = C + cm(row);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       int col = n0 + tx * 4 + j;
       if (col >= N) continue;
-      T v = alpha * acc[i][j];
-      c[col] = accumulate ? c[col] + v : v;
+      TACC v = alpha * acc[i][j];
+      c[col] = accumulate ? (TC)((TACC)c[col] + v) : (TC)v;
     }
   }
 }
 
-template <typename T>
-void launch_gemm(int64_t M, int N, int K, const T* A, RowMap am, const T* B, int ldb, bool bt, T* C,
-                 RowMap cm, T alpha, bool accumulate, bool bf16_operands, hipStream_t s) {
+template <typename TA, typename TB, typename TC, typename TACC>
+void launch_gemm(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, int ldb, bool bt,
+                 TC* C, RowMap cm, TACC alpha, bool accumulate, bool bf16_operands, hipStream_t s) {
   if (M <= 0 || N <= 0) return;
   dim3 grid((unsigned)((M + GT - 1) / GT), (unsigned)((N + GT - 1) / GT));
   if (bt)
-    k_gemm_valu<T, true><<<grid, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
-                                              bf16_operands);
+    k_gemm_valu<TA, TB, TC, TACC, true><<<grid, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, alpha,
+                                                             accumulate, bf16_operands);
   else
-    k_gemm_valu<T, false><<<grid, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
-                                               bf16_operands);
+    k_gemm_valu<TA, TB, TC, TACC, false><<<grid, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, alpha,
+                                                              accumulate, bf16_operands);
 }
 
-template void launch_gemm<float>(int64_t, int, int, const float*, RowMap, const float*, int, bool,
-                                 float*, RowMap, float, bool, bool, hipStream_t);
-template void launch_gemm<double>(int64_t, int, int, const double*, RowMap, const double*, int,
-                                  bool, double*, RowMap, double, bool, bool, hipStream_t);
+#define SN_GEMM_INST(TA, TB, TC, TACC)                                                          \
+  template void launch_gemm<TA, TB, TC, TACC>(int64_t, int, int, const TA*, RowMap, const TB*,   \
+                                              int, bool, TC*, RowMap, TACC, bool, bool,          \
+                                              hipStream_t);
+SN_GEMM_INST(double, double, double, double)
+SN_GEMM_INST(double, double, float, double)
+SN_GEMM_INST(float, float, double, float)
+SN_GEMM_INST(double, float, float, float)
+SN_GEMM_INST(double, float, double, float)
+SN_GEMM_INST(float, float, float, float)
+#undef SN_GEMM_INST
 
 // ------------------------------------------------------------------ radial MLP hidden layers
 // z2 = phi(phi(rho Wa) Wb); phi(z) = c z sigmoid(z); no biases.  One thread per edge,

@@ -114,12 +114,12 @@ __global__ void k_fill_rows(int n, const double* __restrict__ v, int C0, double 
 
 template <typename T>
 __global__ void k_sender_reduce(int n_rows, const int* __restrict__ sptr, const int* __restrict__ sidx,
-                                const T* __restrict__ dxe, int width, T* __restrict__ dx) {
+                                const T* __restrict__ dxe, int width, double* __restrict__ dx) {
   int s = blockIdx.x;
   int a = sptr[s], b = sptr[s + 1];
   for (int c = threadIdx.x; c < width; c += blockDim.x) {
-    T acc = T(0);
-    for (int q = a; q < b; ++q) acc += dxe[(int64_t)sidx[q] * width + c];
+    double acc = 0.0;
+    for (int q = a; q < b; ++q) acc += (double)dxe[(int64_t)sidx[q] * width + c];
     dx[(int64_t)s * width + c] = acc;
   }
 }
@@ -266,8 +266,8 @@ void launch_fill_rows(int n, const double* v, int C0, double scale, T* dh, int l
   if (n > 0) k_fill_rows<T><<<n, 128, 0, s>>>(n, v, C0, scale, dh, ldh);
 }
 template <typename T>
-void launch_sender_reduce(int n_rows, const int* sptr, const int* sidx, const T* dxe, int width, T* dx,
-                          hipStream_t s) {
+void launch_sender_reduce(int n_rows, const int* sptr, const int* sidx, const T* dxe, int width,
+                          double* dx, hipStream_t s) {
   if (n_rows > 0) k_sender_reduce<T><<<n_rows, 128, 0, s>>>(n_rows, sptr, sidx, dxe, width, dx);
 }
 template <typename T>
@@ -310,7 +310,7 @@ void launch_unpermute(int n, const int* order, const double* in_rows, int width,
   template void launch_readout<T>(int, const T*, int, const double*, int, double, const double*,  \
                                   const int*, double*, hipStream_t);                              \
   template void launch_fill_rows<T>(int, const double*, int, double, T*, int, hipStream_t);       \
-  template void launch_sender_reduce<T>(int, const int*, const int*, const T*, int, T*,           \
+  template void launch_sender_reduce<T>(int, const int*, const int*, const T*, int, double*,      \
                                         hipStream_t);                                             \
   template void launch_ghost_fold<T>(int, const int*, const T*, T*, int, hipStream_t);            \
   template void launch_dY_reduce<T>(int64_t, int, int, const T*, T*, bool, hipStream_t);

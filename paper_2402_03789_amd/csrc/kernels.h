@@ -48,10 +48,12 @@ void launch_edge_grad(int64_t E, const int* recv, const int* src, const double* 
                       double* g, hipStream_t s);
 
 // ---------------------------------------------------------------- dense algebra
-// C[M x N] (=|+=) alpha * A[M x K] * op(B); op(B) = B (K x N, ld ldb) or B^T (B is N x K)
-template <typename T>
-void launch_gemm(int64_t M, int N, int K, const T* A, RowMap am, const T* B, int ldb, bool bt,
-                 T* C, RowMap cm, T alpha, bool accumulate, bool bf16_operands, hipStream_t s);
+// C[M x N] (=|+=) alpha * A[M x K] * op(B); op(B) = B (K x N, ld ldb) or B^T (B is N x K).
+// Operands of types TA/TB are accumulated in TACC and stored as TC; with bf16_operands
+// both operands are first rounded to bfloat16 (round-to-nearest-even).
+template <typename TA, typename TB, typename TC, typename TACC>
+void launch_gemm(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, int ldb, bool bt,
+                 TC* C, RowMap cm, TACC alpha, bool accumulate, bool bf16_operands, hipStream_t s);
 
 template <typename T>
 void launch_mlp_hidden_fwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa,
@@ -111,7 +113,7 @@ void launch_fill_rows(int n, const double* v, int C0, double scale, T* dh, int l
                       hipStream_t s);
 template <typename T>
 void launch_sender_reduce(int n_rows, const int* sptr, const int* sidx, const T* dxe, int width,
-                          T* dx, hipStream_t s);
+                          double* dx, hipStream_t s);
 template <typename T>
 void launch_ghost_fold(int n_local, const int* gptr, const T* dx_ext, T* dx, int width,
                        hipStream_t s);

@@ -277,8 +277,9 @@ struct sn_ctx {
   std::map<std::string, Buf> bufs;
   size_t used = 0;
   bool dead = false;
-  // device weights
+  // device weights (float64 copy and float32 copy)
   void* d_w = nullptr;
+  void* d_w32 = nullptr;
   double* d_v = nullptr;
   double* d_shift = nullptr;
   // graph state
@@ -345,17 +346,24 @@ void zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 template <typename T>
-const T* W(const sn_ctx* c, int64_t off) {
-  return static_cast<const T*>(c->d_w) + off;
+const T* W(const sn_ctx* c, int64_t off);
+template <>
+const double* W<double>(const sn_ctx* c, int64_t off) {
+  return static_cast<const double*>(c->d_w) + off;
+}
+template <>
+const float* W<float>(const sn_ctx* c, int64_t off) {
+  return static_cast<const float*>(c->d_w32) + off;
 }
 
-template <typename T>
 void upload_weights(sn_ctx* c) {
   const sn_model* m = c->m;
-  std::vector<T> w(m->flat.size());
-  for (size_t i = 0; i < w.size(); ++i) w[i] = (T)m->flat[i];
-  HIPCHK(hipMalloc(&c->d_w, w.size() * sizeof(T)));
-  HIPCHK(hipMemcpy(c->d_w, w.data(), w.size() * sizeof(T), hipMemcpyHostToDevice));
+  std::vector<float> w32(m->flat.size());
+  for (size_t i = 0; i < w32.size(); ++i) w32[i] = (float)m->flat[i];
+  HIPCHK(hipMalloc(&c->d_w, m->flat.size() * sizeof(double)));
+  HIPCHK(hipMemcpy(c->d_w, m->flat.data(), m->flat.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&c->d_w32, w32.size() * sizeof(float)));
+  HIPCHK(hipMemcpy(c->d_w32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&c->d_v, m->readout_v.size() * sizeof(double)));
   HIPCHK(hipMemcpy(c->d_v, m->readout_v.data(), m->readout_v.size() * sizeof(double),
                    hipMemcpyHostToDevice));
@@ -506,6 +514,12 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
 }
 
 // ------------------------------------------------------------------ forward / backward
+// T is the per-edge arithmetic type (float64 in the FP64 form, float32 otherwise).  The
+// node-state chain -- features h, self-connection and gate input y, the gate, the
+// readout and the backward node gradients -- is float64 in every form: the
+// self-connection carries most of each atom's energy through all blocks and is the one
+// place where float32 rounding reaches the per-atom energy at the 1e-6 level.  x (the
+// sender features that feed the tensor product) and the messages M are type T.
 template <typename T>
 struct Pipe {
   sn_ctx* c;
@@ -515,9 +529,11 @@ struct Pipe {
   explicit Pipe(sn_ctx* ctx)
       : c(ctx), m(ctx->m), s(ctx->stream), bf16(ctx->precision == SN_BF16) {}
 
-  void gemm(int64_t rows, int N, int K, const T* A, RowMap am, int64_t woff, int ldb, bool bt,
-            T* C, RowMap cm, T alpha, bool acc) {
-    launch_gemm<T>(rows, N, K, A, am, W<T>(c, woff), ldb, bt, C, cm, alpha, acc, bf16, s);
+  template <typename TA, typename TB, typename TC, typename TACC>
+  void gemm(int64_t rows, int N, int K, const TA* A, RowMap am, int64_t woff, int ldb, bool bt,
+            TC* C, RowMap cm, TACC alpha, bool acc) {
+    launch_gemm<TA, TB, TC, TACC>(rows, N, K, A, am, W<TB>(c, woff), ldb, bt, C, cm, alpha, acc,
+                                  bf16, s);
   }
 
   void forward(double* d_energy, double* d_atom_energy_orig) {
@@ -537,19 +553,20 @@ struct Pipe {
     const T act = (T)m->act;
     const int C0 = m->muls[0];
     // h^(1): embedding rows for locals and ghosts (a ghost's first features come from its species)
-    T* h = c->get<T>("h_cur", (int64_t)NE * std::max(C0, m->layers[0].hout.width));
-    launch_embed<T>(NE, spec_ext, W<T>(c, m->off("embed", {(int)m->species.size(), C0})), C0, h,
-                    C0, s);
+    double* h = c->get<double>("h_cur", (int64_t)NE * C0);
+    launch_embed<double>(NE, spec_ext, W<double>(c, m->off("embed", {(int)m->species.size(), C0})),
+                         C0, h, C0, s);
     for (int t = 0; t < m->T; ++t) {
       const LayerDesc& L = m->layers[t];
       const std::string ts = std::to_string(t);
       c->mark("layer" + ts + ".linear_in");
       T* x = c->get<T>("x" + ts, (int64_t)NE * L.hin.width);
-      T* y = c->get<T>("y" + ts, (int64_t)N * L.yl.width);
+      double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
       const int xrows = (t == 0) ? NE : N;  // block 1: ghosts from their own species
       for (int l : L.ins)
-        gemm((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h, rows_of(L.hin, l),
-             L.w_lin1[l], L.hin.mul[l], false, x, rows_of(L.hin, l), T(1), false);
+        gemm<double, double, T, double>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
+                                        rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], false, x,
+                                        rows_of(L.hin, l), 1.0, false);
       if (t > 0) {
         c->mark("layer" + ts + ".ghost_refresh");
         launch_ghost_refresh<T>(N, G, owner, x, L.hin.width, s);
@@ -557,33 +574,34 @@ struct Pipe {
       c->mark("layer" + ts + ".linsc");
       for (int l : L.ins)
         if (L.gmul[l] > 0)
-          gemm((int64_t)N * (2 * l + 1), L.gmul[l], L.hin.mul[l], h, rows_of(L.hin, l), L.w_linsc[l],
-               L.gmul[l], false, y, rows_of(L.yl, l), T(1), false);
+          gemm<double, double, double, double>((int64_t)N * (2 * l + 1), L.gmul[l], L.hin.mul[l], h,
+                                               rows_of(L.hin, l), L.w_linsc[l], L.gmul[l], false, y,
+                                               rows_of(L.yl, l), 1.0, false);
       c->mark("layer" + ts + ".mlp");
       T* z2 = c->get<T>("z2_" + ts, E * m->hidden);
       launch_mlp_hidden_fwd<T>(E, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]), W<T>(c, L.w_mlp[1]),
                                act, z2, s);
       T* w = c->get<T>("w" + ts, E * L.P);
-      gemm(E, L.P, m->hidden, z2, plain_rows(m->hidden), L.w_mlp[2], L.P, false, w, plain_rows(L.P),
-           T(1), false);
+      gemm<T, T, T, T>(E, L.P, m->hidden, z2, plain_rows(m->hidden), L.w_mlp[2], L.P, false, w,
+                       plain_rows(L.P), T(1), false);
       c->mark("layer" + ts + ".tp");
       T* M = c->get<T>("M", (int64_t)N * L.ml.width);
       launch_tp_fwd<T>(L.tp, N, row_ptr, src, Y, x, w, M, (T)(1.0 / m->kavg), s);
       c->mark("layer" + ts + ".linear_out");
       for (int l : L.outs) {
         const bool has_sc = std::find(L.ins.begin(), L.ins.end(), l) != L.ins.end() && L.gmul[l] > 0;
-        gemm((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M, rows_of(L.ml, l), L.w_lin2[l],
-             L.gmul[l], false, y, rows_of(L.yl, l), T(1), has_sc);
+        gemm<T, T, double, T>((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M, rows_of(L.ml, l),
+                              L.w_lin2[l], L.gmul[l], false, y, rows_of(L.yl, l), T(1), has_sc);
       }
-      T* hn = c->get<T>(t % 2 ? "h_a" : "h_b", (int64_t)N * L.hout.width);
-      launch_gate_fwd<T>(N, L.last, L.yl, L.hout, y, hn, act, s);
+      double* hn = c->get<double>(t % 2 ? "h_a" : "h_b", (int64_t)N * L.hout.width);
+      launch_gate_fwd<double>(N, L.last, L.yl, L.hout, y, hn, m->act, s);
       h = hn;
     }
     c->mark("readout");
     double* ae = c->get<double>("atom_e", N);
     const int* spec_loc = c->get<int>("spec_local", N);
-    launch_readout<T>(N, h, m->layers.back().hout.width, c->d_v, C0, m->sigma, c->d_shift, spec_loc,
-                      ae, s);
+    launch_readout<double>(N, h, m->layers.back().hout.width, c->d_v, C0, m->sigma, c->d_shift,
+                           spec_loc, ae, s);
     int nbk = partial_blocks(N);
     double* part = c->get<double>("partial_e", nbk);
     launch_energy_partial(N, ae, part, nbk, s);
@@ -596,6 +614,7 @@ struct Pipe {
 
   void backward(double grad_scale, double* d_forces_orig, double* d_virial) {
     const int N = c->N, G = c->G, NE = N + G;
+    (void)G;
     const int64_t E = c->E;
     const int* row_ptr = c->get<int>("row_ptr", N + 1);
     const int* src = c->get<int>("src", E);
@@ -617,54 +636,55 @@ struct Pipe {
       max_m = std::max(max_m, L.ml.width);
       max_y = std::max(max_y, L.yl.width);
     }
-    T* dh = c->get<T>("dh_a", (int64_t)N * max_w);
-    T* dh_other = c->get<T>("dh_b", (int64_t)N * max_w);
-    T* dy = c->get<T>("dy", (int64_t)N * max_y);
+    double* dh = c->get<double>("dh_a", (int64_t)N * max_w);
+    double* dh_other = c->get<double>("dh_b", (int64_t)N * max_w);
+    double* dy = c->get<double>("dy", (int64_t)N * max_y);
     T* Gm = c->get<T>("G", (int64_t)N * max_m);
     T* dw = c->get<T>("dw", E * max_P);
     T* dxe = c->get<T>("dxe", E * max_w);
-    T* dx_ext = c->get<T>("dx_ext", (int64_t)NE * max_w);
-    T* dx = c->get<T>("dx", (int64_t)N * max_w);
+    double* dx_ext = c->get<double>("dx_ext", (int64_t)NE * max_w);
+    double* dx = c->get<double>("dx", (int64_t)N * max_w);
     T* dz2 = c->get<T>("dz2", E * m->hidden);
     T* dYp = c->get<T>("dYpart", E * max_tasks * NY);
     T* dY = c->get<T>("dY", E * NY);
     T* drho = c->get<T>("drho", E * m->nb);
     c->mark("bwd.readout");
     // dE/dh^(T+1) = sigma (Wr1 Wr2): the same vector for every atom
-    launch_fill_rows<T>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
+    launch_fill_rows<double>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
     for (int t = m->T - 1; t >= 0; --t) {
       const LayerDesc& L = m->layers[t];
       const std::string ts = std::to_string(t);
       const T* x = c->get<T>("x" + ts, (int64_t)NE * L.hin.width);
-      const T* y = c->get<T>("y" + ts, (int64_t)N * L.yl.width);
+      const double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
       const T* w = c->get<T>("w" + ts, E * L.P);
-      const T* z2 = c->get<T>("z2_" + ts, E * m->hidden);
-      (void)z2;
       c->mark("bwd.layer" + ts + ".linear_out");
-      launch_gate_bwd<T>(N, L.last, L.yl, L.hout, y, dh, dy, act, s);
+      launch_gate_bwd<double>(N, L.last, L.yl, L.hout, y, dh, dy, m->act, s);
       for (int l : L.outs)
-        gemm((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy, rows_of(L.yl, l), L.w_lin2[l],
-             L.gmul[l], true, Gm, rows_of(L.ml, l), (T)(1.0 / m->kavg), false);
+        gemm<double, T, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy, rows_of(L.yl, l),
+                              L.w_lin2[l], L.gmul[l], true, Gm, rows_of(L.ml, l),
+                              (T)(1.0 / m->kavg), false);
       c->mark("bwd.layer" + ts + ".tp");
       launch_tp_bwd<T>(L.tp, N, row_ptr, src, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dYp, s);
       launch_dY_reduce<T>(E, L.tp.n_tasks, NY, dYp, dY, t != m->T - 1, s);
       c->mark("bwd.layer" + ts + ".mlp");
-      gemm(E, m->hidden, L.P, dw, plain_rows(L.P), L.w_mlp[2], L.P, true, dz2,
-           plain_rows(m->hidden), T(1), false);
+      gemm<T, T, T, T>(E, m->hidden, L.P, dw, plain_rows(L.P), L.w_mlp[2], L.P, true, dz2,
+                       plain_rows(m->hidden), T(1), false);
       launch_mlp_hidden_bwd<T>(E, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]), W<T>(c, L.w_mlp[1]),
                                act, dz2, drho, t != m->T - 1, s);
       if (t == 0) break;
       c->mark("bwd.layer" + ts + ".sender_fold");
       // sender-side sums over every extended row, then fold ghost rows onto owners
       launch_sender_reduce<T>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
-      launch_ghost_fold<T>(N, gptr, dx_ext, dx, L.hin.width, s);
+      launch_ghost_fold<double>(N, gptr, dx_ext, dx, L.hin.width, s);
       c->mark("bwd.layer" + ts + ".linear_in");
       for (int l : L.ins) {
-        gemm((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], dx, rows_of(L.hin, l),
-             L.w_lin1[l], L.hin.mul[l], true, dh_other, rows_of(L.hin, l), T(1), false);
+        gemm<double, T, double, T>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], dx,
+                                   rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], true, dh_other,
+                                   rows_of(L.hin, l), T(1), false);
         if (L.gmul[l] > 0)
-          gemm((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], dy, rows_of(L.yl, l),
-               L.w_linsc[l], L.gmul[l], true, dh_other, rows_of(L.hin, l), T(1), true);
+          gemm<double, T, double, T>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], dy,
+                                     rows_of(L.yl, l), L.w_linsc[l], L.gmul[l], true, dh_other,
+                                     rows_of(L.hin, l), T(1), true);
       }
       std::swap(dh, dh_other);
     }
@@ -847,10 +867,7 @@ int sn_ctx_create(const sn_model_t* model, int device, void* hip_stream, size_t 
   c->budget = hbm_budget;
   c->precision = precision;
   c->skin = skin;
-  int st = guarded(c.get(), [&] {
-    if (precision == SN_FP64) upload_weights<double>(c.get());
-    else upload_weights<float>(c.get());
-  });
+  int st = guarded(c.get(), [&] { upload_weights(c.get()); });
   if (st != SN_OK) {
     g_load_error = c->err;
     return st;
@@ -866,6 +883,7 @@ void sn_ctx_free(sn_ctx_t* ctx) {
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (ctx->d_w) (void)hipFree(ctx->d_w);
+  if (ctx->d_w32) (void)hipFree(ctx->d_w32);
   if (ctx->d_v) (void)hipFree(ctx->d_v);
   if (ctx->d_shift) (void)hipFree(ctx->d_shift);
   for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
