@@ -114,7 +114,8 @@ SN_GEMM_INST(float, float, float, float)
 // z2 = phi(phi(rho Wa) Wb); phi(z) = c z sigmoid(z); no biases.  One thread per edge,
 // weights in LDS (read as broadcasts).
 template <typename T, int NB, int H>
-__global__ __launch_bounds__(256) void k_mlp_fwd(int64_t E, const T* __restrict__ rho,
+__global__ __launch_bounds__(256) void k_mlp_fwd(int64_t E, const int* __restrict__ rows,
+                                                  const T* __restrict__ rho,
                                                   const T* __restrict__ Wa, const T* __restrict__ Wb,
                                                   T c, T* __restrict__ z2) {
   __shared__ T sWa[NB * H];
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(int64_t E, const T* __restrict_
   if (e >= E) return;
   T r[NB];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) r[k] = rho[e * NB + k];
+  for (int k = 0; k < NB; ++k) r[k] = rho[(int64_t)rows[e] * NB + k];
   T z1[H];
 #pragma unroll
   for (int j = 0; j < H; ++j) {
@@ -144,7 +145,8 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(int64_t E, const T* __restrict_
 }
 
 template <typename T, int NB, int H>
-__global__ __launch_bounds__(256) void k_mlp_bwd(int64_t E, const T* __restrict__ rho,
+__global__ __launch_bounds__(256) void k_mlp_bwd(int64_t E, const int* __restrict__ rows,
+                                                  const T* __restrict__ rho,
                                                   const T* __restrict__ Wa, const T* __restrict__ Wb,
                                                   T c, const T* __restrict__ dz2,
                                                   T* __restrict__ drho, int accumulate) {
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int64_t E, const T* __restrict_
   if (e >= E) return;
   T r[NB];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) r[k] = rho[e * NB + k];
+  for (int k = 0; k < NB; ++k) r[k] = rho[(int64_t)rows[e] * NB + k];
   T z1[H], dz1[H];
 #pragma unroll
   for (int j = 0; j < H; ++j) {
@@ -188,33 +190,52 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int64_t E, const T* __restrict_
     for (int k = 0; k < NB; ++k) dr[k] += da * sWa[k * H + j];
   }
 #pragma unroll
-  for (int k = 0; k < NB; ++k) drho[e * NB + k] = accumulate ? drho[e * NB + k] + dr[k] : dr[k];
+  for (int k = 0; k < NB; ++k) {
+    const int64_t o = (int64_t)rows[e] * NB + k;
+    drho[o] = accumulate ? drho[o] + dr[k] : dr[k];
+  }
 }
 
 template <typename T>
-void launch_mlp_hidden_fwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa, const T* Wb,
-                           T c, T* z2, hipStream_t s) {
+void launch_mlp_hidden_fwd(int64_t E, const int* rows, const T* rho, int nb, int hidden,
+                           const T* Wa, const T* Wb, T c, T* z2, hipStream_t s) {
   if (E <= 0) return;
   // nb == 8, hidden == 64 (checked at model load)
-  k_mlp_fwd<T, 8, 64><<<(unsigned)((E + 255) / 256), 256, 0, s>>>(E, rho, Wa, Wb, c, z2);
+  k_mlp_fwd<T, 8, 64><<<(unsigned)((E + 255) / 256), 256, 0, s>>>(E, rows, rho, Wa, Wb, c, z2);
 }
 template <typename T>
-void launch_mlp_hidden_bwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa, const T* Wb,
-                           T c, const T* dz2, T* drho, bool accumulate, hipStream_t s) {
+void launch_mlp_hidden_bwd(int64_t E, const int* rows, const T* rho, int nb, int hidden,
+                           const T* Wa, const T* Wb, T c, const T* dz2, T* drho, bool accumulate,
+                           hipStream_t s) {
   if (E <= 0) return;
-  k_mlp_bwd<T, 8, 64><<<(unsigned)((E + 255) / 256), 256, 0, s>>>(E, rho, Wa, Wb, c, dz2, drho,
-                                                                  accumulate ? 1 : 0);
+  k_mlp_bwd<T, 8, 64><<<(unsigned)((E + 255) / 256), 256, 0, s>>>(E, rows, rho, Wa, Wb, c, dz2,
+                                                                  drho, accumulate ? 1 : 0);
 }
 
-template void launch_mlp_hidden_fwd<float>(int64_t, const float*, int, int, const float*,
-                                           const float*, float, float*, hipStream_t);
-template void launch_mlp_hidden_fwd<double>(int64_t, const double*, int, int, const double*,
-                                            const double*, double, double*, hipStream_t);
-template void launch_mlp_hidden_bwd<float>(int64_t, const float*, int, int, const float*,
-                                           const float*, float, const float*, float*, bool,
-                                           hipStream_t);
-template void launch_mlp_hidden_bwd<double>(int64_t, const double*, int, int, const double*,
-                                            const double*, double, const double*, double*, bool,
-                                            hipStream_t);
+template <typename T>
+__global__ void k_pair_sum(int64_t np, const int* __restrict__ pe1, const int* __restrict__ pe2,
+                           const T* __restrict__ dw, int P, T* __restrict__ out) {
+  const int64_t p = blockIdx.x;
+  const int64_t a = (int64_t)pe1[p] * P;
+  const int b = pe2[p];
+  for (int k = threadIdx.x; k < P; k += blockDim.x)
+    out[p * P + k] = dw[a + k] + (b >= 0 ? dw[(int64_t)b * P + k] : T(0));
+}
+
+template <typename T>
+void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const T* dw, int P, T* out,
+                     hipStream_t s) {
+  if (np > 0) k_pair_sum<T><<<(unsigned)np, 128, 0, s>>>(np, pe1, pe2, dw, P, out);
+}
+
+#define SN_MLPV_INST(T)                                                                          \
+  template void launch_mlp_hidden_fwd<T>(int64_t, const int*, const T*, int, int, const T*,      \
+                                         const T*, T, T*, hipStream_t);                          \
+  template void launch_mlp_hidden_bwd<T>(int64_t, const int*, const T*, int, int, const T*,      \
+                                         const T*, T, const T*, T*, bool, hipStream_t);          \
+  template void launch_pair_sum<T>(int64_t, const int*, const int*, const T*, int, T*, hipStream_t);
+SN_MLPV_INST(float)
+SN_MLPV_INST(double)
+#undef SN_MLPV_INST
 
 }  // namespace sn

@@ -306,3 +306,78 @@ void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, BinG
 }
 
 }  // namespace sn
+
+namespace sn {
+
+// ------------------------------------------------------------------ reverse edges and pairs
+// The reverse of e = (i <- s) is the edge of receiver o = owner(s) whose sender is an
+// image of i shifted by -shift(s) (the local atom i itself when s is local).  Found by a
+// scan of o's receiver segment; -1 when no such edge exists (possible only when the two
+// directions round to different sides of r_c).
+__global__ void k_reverse(int64_t E, int n_local, const int* __restrict__ recv,
+                          const int* __restrict__ src, const int* __restrict__ row_ptr,
+                          const int* __restrict__ owner, const int* __restrict__ shift,
+                          int* __restrict__ rev) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int i = recv[e], s = src[e];
+  int o = s, sx = 0, sy = 0, sz = 0;
+  if (s >= n_local) {
+    const int g = s - n_local;
+    o = owner[g];
+    sx = shift[3 * g];
+    sy = shift[3 * g + 1];
+    sz = shift[3 * g + 2];
+  }
+  int found = -1;
+  for (int q = row_ptr[o]; q < row_ptr[o + 1]; ++q) {
+    const int t = src[q];
+    if (t < n_local) {
+      if (t == i && sx == 0 && sy == 0 && sz == 0) { found = q; break; }
+    } else {
+      const int g = t - n_local;
+      if (owner[g] == i && shift[3 * g] == -sx && shift[3 * g + 1] == -sy &&
+          shift[3 * g + 2] == -sz) { found = q; break; }
+    }
+  }
+  rev[e] = found;
+}
+
+__global__ void k_canon_flags(int64_t E, const int* __restrict__ rev, int* __restrict__ flag) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int r = rev[e];
+  flag[e] = (r < 0 || e < r) ? 1 : 0;
+}
+
+__global__ void k_pairs(int64_t E, const int* __restrict__ rev, const int* __restrict__ flag,
+                        const int* __restrict__ fscan, int* __restrict__ pidx,
+                        int* __restrict__ pe1, int* __restrict__ pe2) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int r = rev[e];
+  if (flag[e]) {
+    const int p = fscan[e];
+    pidx[e] = p;
+    pe1[p] = (int)e;
+    pe2[p] = r;  // -1 when unpaired
+  } else {
+    pidx[e] = fscan[r];
+  }
+}
+
+void launch_pairs(int64_t E, int n_local, const int* recv, const int* src, const int* row_ptr,
+                  const int* owner, const int* shift, int* rev, int* flag, int* fscan, int* tmp,
+                  int* pidx, int* pe1, int* pe2, hipStream_t s) {
+  if (E <= 0) {
+    k_scan_total<<<1, 1, 0, s>>>(flag, fscan, 0);
+    return;
+  }
+  const unsigned g = (unsigned)((E + 255) / 256);
+  k_reverse<<<g, 256, 0, s>>>(E, n_local, recv, src, row_ptr, owner, shift, rev);
+  k_canon_flags<<<g, 256, 0, s>>>(E, rev, flag);
+  scan_exclusive(flag, fscan, E, tmp, s);
+  k_pairs<<<g, 256, 0, s>>>(E, rev, flag, fscan, pidx, pe1, pe2);
+}
+
+}  // namespace sn

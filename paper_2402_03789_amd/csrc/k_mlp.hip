@@ -1,0 +1,333 @@
+// Fused radial MLP on the matrix cores (float32 and bfloat16 forms).
+//
+// Per undirected edge pair (paper section 5.1, "learnable radial functions"
+// of the 8 Bessel features; the weights depend only on the distance, so an
+// edge and its reverse share them):
+//   a1 = rho Wa,  z1 = phi(a1),  a2 = z1 Wb,  z2 = phi(a2),  w = z2 Wc
+// with phi(z) = c z sigmoid(z) and no biases.  The adjoint maps
+// dE/dw = dw[e1] + dw[e2] (both directions of the pair) back to dE/drho:
+//   dz2 = dw Wc^T,  da2 = dz2 phi'(a2),  dz1 = da2 Wb^T,  da1 = dz1 phi'(a1),
+//   drho = da1 Wa^T   (hidden activations recomputed; drho lands on edge e1).
+//
+// One 256-thread block = 64 pairs; each of the 4 waves owns 16 pairs and
+// computes 16 x 64 output panels as four 16 x 16 MFMA tiles.  Hidden
+// activations stay on the CU (registers and a per-wave LDS panel that turns
+// the accumulator layout into the operand layout); weight panels are staged
+// in LDS once per block and shared by the four waves.  Output panels of w go
+// back through LDS so that every store is a full 256-byte row segment.
+//
+// MFMA layouts (lane l, 16 x 16 tiles):
+//   f32 16x16x4  : a = A[l%16][4s + l/16],     b = B[4s + l/16][l%16]
+//   bf16 16x16x32: a = A[l%16][32s + 8(l/16) + 0..7], b = B[32s + 8(l/16) + 0..7][l%16]
+//   result       : acc[r] = C[4(l/16) + r][l%16]
+// LDS strides: operand panels 68 floats, k-major weight panels 80 floats, chosen so
+// that the 64 lanes of a fragment read hit distinct banks.
+#include "kernels.h"
+
+namespace sn {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int EB = 64;   // pairs per block
+constexpr int HID = 64;  // hidden width
+constexpr int NBAS = 8;  // radial features
+constexpr int ZP = 68;   // operand panel stride (floats)
+constexpr int WP = 80;   // k-major weight panel stride (floats)
+constexpr int TP = 68;   // n-major weight panel stride (floats)
+constexpr int BP = 72;   // n-major bf16 panel stride (16-byte aligned rows)
+
+__device__ inline float phi(float z, float c) { return c * z / (1.f + __expf(-z)); }
+__device__ inline float dphi(float z, float c) {
+  float s = 1.f / (1.f + __expf(-z));
+  return c * (s + z * s * (1.f - s));
+}
+
+__device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline void zero4(floatx4 a[4]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) a[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+// acc += Z(16 x 64 operand panel) * W, W k-major [k][n] (stride WP)
+__device__ inline void panel_kn(const float* Z, const float* W, floatx4 acc[4], int lane) {
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < HID / 4; ++s) {
+    const float a = Z[r * ZP + 4 * s + q];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = mfma4(a, W[(4 * s + q) * WP + t * 16 + r], acc[t]);
+  }
+}
+
+// acc += Z * W^T with W k-major [n][k] as stored for the forward product (B[k][n] = W[n][k])
+__device__ inline void panel_kn_T(const float* Z, const float* W, floatx4 acc[4], int lane) {
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < HID / 4; ++s) {
+    const float a = Z[r * ZP + 4 * s + q];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = mfma4(a, W[(t * 16 + r) * WP + 4 * s + q], acc[t]);
+  }
+}
+
+// accumulator tiles (16 x 64) -> operand panel, applying f(v, tile, row)
+template <class F>
+__device__ inline void acc_to_panel(const floatx4 acc[4], float* Z, int lane, F&& f) {
+  const int c = lane & 15, rq = (lane >> 4) * 4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Z[(rq + rr) * ZP + t * 16 + c] = f(acc[t][rr], t, rr);
+}
+
+// a1 (accumulator layout) = rho(16 x 8) Wa(8 x 64); rho panel stride NBAS + 1
+__device__ inline void first_layer(const float* sRho, const float* sWa, floatx4 acc[4], int lane) {
+  const int r = lane & 15, q = lane >> 4;
+  zero4(acc);
+#pragma unroll
+  for (int s = 0; s < NBAS / 4; ++s) {
+    const float a = sRho[r * (NBAS + 1) + 4 * s + q];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = mfma4(a, sWa[(4 * s + q) * HID + t * 16 + r], acc[t]);
+  }
+}
+
+__device__ inline void stage_common(int64_t np, int64_t p0, const int* __restrict__ pe1,
+                                    const float* __restrict__ rho, const float* __restrict__ Wa,
+                                    const float* __restrict__ Wb, float* sWa, float* sWb,
+                                    float* sRho) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NBAS * HID; i += 256) sWa[i] = Wa[i];
+  for (int i = tid; i < HID * HID; i += 256) sWb[(i / HID) * WP + i % HID] = Wb[i];
+  for (int i = tid; i < EB * NBAS; i += 256) {
+    const int64_t p = p0 + i / NBAS;
+    sRho[(i / NBAS) * (NBAS + 1) + i % NBAS] = p < np ? rho[(int64_t)pe1[p] * NBAS + i % NBAS] : 0.f;
+  }
+}
+
+// ------------------------------------------------------------------ forward
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __restrict__ pe1,
+                                                        const float* __restrict__ rho,
+                                                        const float* __restrict__ Wa,
+                                                        const float* __restrict__ Wb,
+                                                        const float* __restrict__ Wc, int P, float c,
+                                                        float* __restrict__ w) {
+  __shared__ float sWa[NBAS * HID];
+  __shared__ float sWb[HID * WP];
+  __shared__ float sRho[EB * (NBAS + 1)];
+  __shared__ float sZ[4][16 * ZP];
+  __shared__ __attribute__((aligned(16))) float sBf[BF16 ? 4 : HID * WP];    // Wc panel [k][n]
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[BF16 ? HID * BP : 8];  // Wc panel [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * EB;
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
+  __syncthreads();
+  float* Z = sZ[wave];
+  floatx4 acc[4];
+  first_layer(sRho + wave * 16 * (NBAS + 1), sWa, acc, lane);
+  acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  __syncthreads();
+  zero4(acc);
+  panel_kn(Z, sWb, acc, lane);
+  __syncthreads();
+  acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  __syncthreads();
+  // z2 operand fragments, kept in registers for every output panel
+  const int r = lane & 15, q = lane >> 4;
+  float za[HID / 4];
+  bf16x8 zh[HID / 32];
+  if (BF16) {
+#pragma unroll
+    for (int s = 0; s < HID / 32; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) zh[s][e] = __float2bfloat16(Z[r * ZP + 32 * s + 8 * q + e]);
+  } else {
+#pragma unroll
+    for (int s = 0; s < HID / 4; ++s) za[s] = Z[r * ZP + 4 * s + q];
+  }
+  for (int n0 = 0; n0 < P; n0 += HID) {
+    // stage Wc[:, n0 .. n0 + 63]
+    for (int i = tid; i < HID * HID; i += 256) {
+      const int k = i / HID, n = i % HID;
+      const float v = (n0 + n < P) ? Wc[(int64_t)k * P + n0 + n] : 0.f;
+      if (BF16) sBh[n * BP + k] = __float2bfloat16(v);
+      else sBf[k * WP + n] = v;
+    }
+    __syncthreads();
+    zero4(acc);
+    if (BF16) {
+#pragma unroll
+      for (int s = 0; s < HID / 32; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sBh[(t * 16 + r) * BP + 32 * s + 8 * q]);
+          acc[t] = mfma32(zh[s], b, acc[t]);
+        }
+    } else {
+#pragma unroll
+      for (int s = 0; s < HID / 4; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = mfma4(za[s], sBf[(4 * s + q) * WP + t * 16 + r], acc[t]);
+    }
+    // through the wave's panel to full-row float4 stores
+    acc_to_panel(acc, Z, lane, [](float v, int, int) { return v; });
+    __syncthreads();
+    const int c4 = (lane & 15) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int row = (lane >> 4) + 4 * k;
+      const int64_t p = p0 + wave * 16 + row;
+      if (p < np && n0 + c4 < P) {
+        const float* zr = &Z[row * ZP + c4];
+        *reinterpret_cast<floatx4*>(&w[p * P + n0 + c4]) = floatx4{zr[0], zr[1], zr[2], zr[3]};
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ backward
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __restrict__ pe1,
+                                                        const int* __restrict__ pe2,
+                                                        const float* __restrict__ rho,
+                                                        const float* __restrict__ Wa,
+                                                        const float* __restrict__ Wb,
+                                                        const float* __restrict__ Wc, int P, float c,
+                                                        const float* __restrict__ dw,
+                                                        float* __restrict__ drho, int accumulate) {
+  __shared__ float sWa[NBAS * HID];
+  __shared__ float sWb[HID * WP];
+  __shared__ float sRho[EB * (NBAS + 1)];
+  __shared__ float sZ[4][16 * ZP];
+  __shared__ __attribute__((aligned(16))) float sBf[BF16 ? 4 : HID * TP];     // Wc[j][k-panel]
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[BF16 ? HID * BP : 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * EB;
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
+  __syncthreads();
+  float* Z = sZ[wave];
+  const int r = lane & 15, q = lane >> 4;
+  // recompute a1 and a2 (accumulator layout)
+  floatx4 a1[4], a2[4];
+  first_layer(sRho + wave * 16 * (NBAS + 1), sWa, a1, lane);
+  acc_to_panel(a1, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  __syncthreads();
+  zero4(a2);
+  panel_kn(Z, sWb, a2, lane);
+  // dz2 = (dw[e1] + dw[e2]) Wc^T, contraction over the P radial weights in 64-wide panels
+  floatx4 g[4];
+  zero4(g);
+  const int64_t pr = p0 + wave * 16 + r;
+  const bool row_ok = pr < np;
+  const int64_t r1 = row_ok ? (int64_t)pe1[pr] * P : 0;
+  const int e2 = row_ok ? pe2[pr] : -1;
+  const int64_t r2 = e2 >= 0 ? (int64_t)e2 * P : 0;
+  for (int k0 = 0; k0 < P; k0 += HID) {
+    __syncthreads();
+    for (int i = tid; i < HID * HID; i += 256) {
+      const int j = i / HID, k = i % HID;  // Wc row j (hidden), column k0 + k
+      const float v = (k0 + k < P) ? Wc[(int64_t)j * P + k0 + k] : 0.f;
+      if (BF16) sBh[j * BP + k] = __float2bfloat16(v);
+      else sBf[j * TP + k] = v;
+    }
+    __syncthreads();
+    if (BF16) {
+#pragma unroll
+      for (int s = 0; s < HID / 32; ++s) {
+        bf16x8 a;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = k0 + 32 * s + 8 * q + e;
+          float v = 0.f;
+          if (row_ok && k < P) v = dw[r1 + k] + (e2 >= 0 ? dw[r2 + k] : 0.f);
+          a[e] = __float2bfloat16(v);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sBh[(t * 16 + r) * BP + 32 * s + 8 * q]);
+          g[t] = mfma32(a, b, g[t]);
+        }
+      }
+    } else {
+      // k-permuted float4 operands: lane group q covers k = 16 u + 4 q + s
+#pragma unroll
+      for (int u = 0; u < HID / 16; ++u) {
+        const int kb = k0 + 16 * u + 4 * q;
+        floatx4 av = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (row_ok && kb < P) {  // P is a multiple of 4
+          av = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
+          if (e2 >= 0) av += *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const floatx4 bv =
+              *reinterpret_cast<const floatx4*>(&sBf[(t * 16 + r) * TP + 16 * u + 4 * q]);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) g[t] = mfma4(av[s], bv[s], g[t]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // da2 = dz2 * phi'(a2) -> operand panel;  dz1 = da2 Wb^T
+  acc_to_panel(g, Z, lane, [&](float v, int t, int rr) { return v * dphi(a2[t][rr], c); });
+  __syncthreads();
+  floatx4 d1[4];
+  zero4(d1);
+  panel_kn_T(Z, sWb, d1, lane);
+  __syncthreads();
+  // da1 = dz1 * phi'(a1) -> operand panel;  drho = da1 Wa^T (8 columns, padded to 16)
+  acc_to_panel(d1, Z, lane, [&](float v, int t, int rr) { return v * dphi(a1[t][rr], c); });
+  __syncthreads();
+  floatx4 dr = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < HID / 4; ++s) {
+    const float a = Z[r * ZP + 4 * s + q];
+    const float b = (r < NBAS) ? sWa[r * HID + 4 * s + q] : 0.f;
+    dr = mfma4(a, b, dr);
+  }
+  const int col = lane & 15, rq = (lane >> 4) * 4;
+  if (col < NBAS) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t p = p0 + wave * 16 + rq + rr;
+      if (p < np) {
+        const int64_t o = (int64_t)pe1[p] * NBAS + col;
+        const float v = dr[rr];
+        drho[o] = accumulate ? drho[o] + v : v;
+      }
+    }
+  }
+}
+
+void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
+                          const float* Wb, const float* Wc, int P, float c, float* w, bool bf16,
+                          hipStream_t s) {
+  if (np <= 0) return;
+  const unsigned grid = (unsigned)((np + EB - 1) / EB);
+  if (bf16) k_mlp_fused_fwd<true><<<grid, 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wc, P, c, w);
+  else k_mlp_fused_fwd<false><<<grid, 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wc, P, c, w);
+}
+
+void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
+                          const float* Wa, const float* Wb, const float* Wc, int P, float c,
+                          const float* dw, float* drho, bool accumulate, bool bf16, hipStream_t s) {
+  if (np <= 0) return;
+  const unsigned grid = (unsigned)((np + EB - 1) / EB);
+  const int acc = accumulate ? 1 : 0;
+  if (bf16)
+    k_mlp_fused_bwd<true><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wc, P, c, dw, drho, acc);
+  else
+    k_mlp_fused_bwd<false><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wc, P, c, dw, drho, acc);
+}
+
+}  // namespace sn

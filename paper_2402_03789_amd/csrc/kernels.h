@@ -38,6 +38,13 @@ void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, BinG
                       const int* cell_start, const int* cell_items, double rc2,
                       const int* row_ptr, int* src, int* recv, hipStream_t s);
 
+// Reverse-edge map and undirected pairs: rev[e] (-1 if none), pidx[e] (pair of each edge),
+// pe1[p] (canonical edge of pair p, the lower id) and pe2[p] (its reverse or -1).  The
+// number of pairs is fscan[E].  tmp is scan scratch.
+void launch_pairs(int64_t E, int n_local, const int* recv, const int* src, const int* row_ptr,
+                  const int* owner, const int* shift, int* rev, int* flag, int* fscan, int* tmp,
+                  int* pidx, int* pe1, int* pe2, hipStream_t s);
+
 // ---------------------------------------------------------------- edge basis
 template <typename T>
 void launch_edge_basis(int64_t E, const int* recv, const int* src, const double* pos_ext,
@@ -55,13 +62,36 @@ template <typename TA, typename TB, typename TC, typename TACC>
 void launch_gemm(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, int ldb, bool bt,
                  TC* C, RowMap cm, TACC alpha, bool accumulate, bool bf16_operands, hipStream_t s);
 
+// Same contraction on the matrix cores with float32 accumulation (bfloat16 operands
+// when bf16 is set).
+template <typename TA, typename TB, typename TC>
+void launch_gemm_mfma(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, int ldb, bool bt,
+                      TC* C, RowMap cm, float alpha, bool accumulate, bool bf16, hipStream_t s);
+
+// Vector-unit radial-MLP hidden layers over pairs (float64 form): rows of rho and drho
+// are taken at rows[p].
 template <typename T>
-void launch_mlp_hidden_fwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa,
-                           const T* Wb, T c, T* z2, hipStream_t s);
+void launch_mlp_hidden_fwd(int64_t np, const int* rows, const T* rho, int nb, int hidden,
+                           const T* Wa, const T* Wb, T c, T* z2, hipStream_t s);
 template <typename T>
-void launch_mlp_hidden_bwd(int64_t E, const T* rho, int nb, int hidden, const T* Wa,
-                           const T* Wb, T c, const T* dz2, T* drho, bool accumulate,
+void launch_mlp_hidden_bwd(int64_t np, const int* rows, const T* rho, int nb, int hidden,
+                           const T* Wa, const T* Wb, T c, const T* dz2, T* drho, bool accumulate,
                            hipStream_t s);
+// out[p] = dw[pe1[p]] + dw[pe2[p]] (second term absent when pe2[p] < 0), rows of width P
+template <typename T>
+void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const T* dw, int P, T* out,
+                     hipStream_t s);
+
+// Fused radial MLP (hidden layers + output layer) on the matrix cores, float32 storage;
+// bf16 selects bfloat16 operands for the two P-wide contractions.
+// Both run over undirected pairs: pair p takes rho of edge pe1[p]; the backward sums
+// dw[pe1[p]] + dw[pe2[p]] (pe2 = -1: unpaired) and adds drho into row pe1[p].
+void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
+                          const float* Wb, const float* Wc, int P, float c, float* w, bool bf16,
+                          hipStream_t s);
+void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
+                          const float* Wa, const float* Wb, const float* Wc, int P, float c,
+                          const float* dw, float* drho, bool accumulate, bool bf16, hipStream_t s);
 
 // ---------------------------------------------------------------- tensor product
 struct TPTask {  // one wave's work: one degree l1, 64 lanes over channels x edges
@@ -85,13 +115,17 @@ struct TPLayer {
   int NY;               // (l_sh + 1)^2
 };
 
+// Messages M [n_recv x Dm] of one block; w is indexed by the edge's pair pidx[e].
 template <typename T>
 void launch_tp_fwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const T* Y, const T* x, const T* w, T* M, T inv_k, hipStream_t s);
+                   const int* pidx, const T* Y, const T* x, const T* w, T* M, T inv_k,
+                   hipStream_t s);
+// Adjoint: writes dE/dw [E x P], per-edge dE/dx_sender rows dxe [E x Dx] (skipped when dxe is
+// null), and dE/dY [E x NY] (added to the existing values when accumulate is set).
 template <typename T>
 void launch_tp_bwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const T* Y, const T* x, const T* w, const T* G, T* dw, T* dxe,
-                   T* dYpart, hipStream_t s);
+                   const int* pidx, const T* Y, const T* x, const T* w, const T* G, T* dw,
+                   T* dxe, T* dY, bool accumulate, hipStream_t s);
 
 // ---------------------------------------------------------------- node-level and reductions
 template <typename T>

@@ -24,6 +24,7 @@
 #include <sstream>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -228,6 +229,8 @@ std::unique_ptr<sn_model> load_model(const char* path) {
   if (!((m->lmax == 1 && m->lsh == 1) || (m->lmax == 2 && m->lsh == 2)))
     throw UnsupportedError("supported (l_max, l_sh): (1, 1) and (2, 2)");
   if (m->muls[0] % 2 != 0) throw UnsupportedError("C0 must be even");
+  for (int l = 0; l < 3; ++l)
+    if (m->muls[l] < 0 || m->muls[l] > 128) throw UnsupportedError("at most 128 channels per degree");
   std::fill(m->lut, m->lut + 128, -1);
   for (size_t s = 0; s < m->species.size(); ++s) {
     int z = m->species[s];
@@ -284,7 +287,7 @@ struct sn_ctx {
   double* d_shift = nullptr;
   // graph state
   int N = 0, G = 0;
-  int64_t E = 0;
+  int64_t E = 0, NP = 0;  // directed edges, undirected pairs
   BinGrid grid{};
   double H[9], Hinv[9];
   bool pending = false;
@@ -511,6 +514,19 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   scan_exclusive(scount, sptr, NE, tmp, s);
   launch_scatter_keys((int)E, src, sptr, scur, sidx, s);
   launch_sort_segments(NE, sptr, sidx, s);
+  // reverse edges and undirected pairs (the radial MLP runs once per pair)
+  int* rev = c->get<int>("rev", E);
+  int* flag = c->get<int>("pair_flag", E);
+  int* fscan = c->get<int>("pair_scan", E + 1);
+  int* tmp_e = c->get<int>("scan_tmp_e", (int64_t)scan_tmp_ints(E + 1));
+  int* pidx = c->get<int>("pidx", E);
+  int* pe1 = c->get<int>("pair_e1", E);
+  int* pe2 = c->get<int>("pair_e2", E);
+  launch_pairs(E, N, recv, src, row_ptr, owner, shift, rev, flag, fscan, tmp_e, pidx, pe1, pe2, s);
+  int hP = 0;
+  HIPCHK(hipMemcpyAsync(&hP, fscan + E, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->NP = hP;
 }
 
 // ------------------------------------------------------------------ forward / backward
@@ -529,11 +545,51 @@ struct Pipe {
   explicit Pipe(sn_ctx* ctx)
       : c(ctx), m(ctx->m), s(ctx->stream), bf16(ctx->precision == SN_BF16) {}
 
+  // float32-accumulated contractions (and every contraction of the BF16 form) run on the
+  // matrix cores; float64-accumulated ones on the vector units.
   template <typename TA, typename TB, typename TC, typename TACC>
   void gemm(int64_t rows, int N, int K, const TA* A, RowMap am, int64_t woff, int ldb, bool bt,
             TC* C, RowMap cm, TACC alpha, bool acc) {
-    launch_gemm<TA, TB, TC, TACC>(rows, N, K, A, am, W<TB>(c, woff), ldb, bt, C, cm, alpha, acc,
-                                  bf16, s);
+    if (bf16 || std::is_same<TACC, float>::value)
+      launch_gemm_mfma<TA, TB, TC>(rows, N, K, A, am, W<TB>(c, woff), ldb, bt, C, cm, (float)alpha,
+                                   acc, bf16, s);
+    else
+      launch_gemm<TA, TB, TC, TACC>(rows, N, K, A, am, W<TB>(c, woff), ldb, bt, C, cm, alpha, acc,
+                                    false, s);
+  }
+
+  // radial MLP over undirected pairs: fused matrix-core kernels for float32 storage,
+  // vector-unit path for float64
+  void mlp_forward(const LayerDesc& L, const T* rho, T* w) {
+    const int64_t NPr = c->NP;
+    const int* pe1 = c->get<int>("pair_e1", c->E);
+    if constexpr (std::is_same<T, float>::value) {
+      launch_mlp_fused_fwd(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
+                           W<float>(c, L.w_mlp[2]), L.P, (float)m->act, w, bf16, s);
+    } else {
+      T* z2 = c->get<T>("z2", NPr * m->hidden);
+      launch_mlp_hidden_fwd<T>(NPr, pe1, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]),
+                               W<T>(c, L.w_mlp[1]), (T)m->act, z2, s);
+      gemm<T, T, T, T>(NPr, L.P, m->hidden, z2, plain_rows(m->hidden), L.w_mlp[2], L.P, false, w,
+                       plain_rows(L.P), T(1), false);
+    }
+  }
+  void mlp_backward(const LayerDesc& L, const T* rho, const T* dw, T* dz2, T* drho) {
+    const int64_t NPr = c->NP;
+    const int* pe1 = c->get<int>("pair_e1", c->E);
+    const int* pe2 = c->get<int>("pair_e2", c->E);
+    if constexpr (std::is_same<T, float>::value) {
+      (void)dz2;
+      launch_mlp_fused_bwd(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
+                           W<float>(c, L.w_mlp[2]), L.P, (float)m->act, dw, drho, true, bf16, s);
+    } else {
+      T* dws = c->get<T>("dw_pair", NPr * L.P);
+      launch_pair_sum<T>(NPr, pe1, pe2, dw, L.P, dws, s);
+      gemm<T, T, T, T>(NPr, m->hidden, L.P, dws, plain_rows(L.P), L.w_mlp[2], L.P, true, dz2,
+                       plain_rows(m->hidden), T(1), false);
+      launch_mlp_hidden_bwd<T>(NPr, pe1, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]),
+                               W<T>(c, L.w_mlp[1]), (T)m->act, dz2, drho, true, s);
+    }
   }
 
   void forward(double* d_energy, double* d_atom_energy_orig) {
@@ -545,6 +601,7 @@ struct Pipe {
     const double* pos_ext = c->get<double>("pos_ext", 3 * (int64_t)NE);
     const int* spec_ext = c->get<int>("spec_ext", NE);
     const int* owner = c->get<int>("ghost_owner", G);
+    const int* pidx = c->get<int>("pidx", E);
     const int NY = (m->lsh + 1) * (m->lsh + 1);
     T* Y = c->get<T>("Y", E * NY);
     T* rho = c->get<T>("rho", E * m->nb);
@@ -578,15 +635,11 @@ struct Pipe {
                                                rows_of(L.hin, l), L.w_linsc[l], L.gmul[l], false, y,
                                                rows_of(L.yl, l), 1.0, false);
       c->mark("layer" + ts + ".mlp");
-      T* z2 = c->get<T>("z2_" + ts, E * m->hidden);
-      launch_mlp_hidden_fwd<T>(E, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]), W<T>(c, L.w_mlp[1]),
-                               act, z2, s);
-      T* w = c->get<T>("w" + ts, E * L.P);
-      gemm<T, T, T, T>(E, L.P, m->hidden, z2, plain_rows(m->hidden), L.w_mlp[2], L.P, false, w,
-                       plain_rows(L.P), T(1), false);
+      T* w = c->get<T>("w" + ts, c->NP * L.P);
+      mlp_forward(L, rho, w);
       c->mark("layer" + ts + ".tp");
       T* M = c->get<T>("M", (int64_t)N * L.ml.width);
-      launch_tp_fwd<T>(L.tp, N, row_ptr, src, Y, x, w, M, (T)(1.0 / m->kavg), s);
+      launch_tp_fwd<T>(L.tp, N, row_ptr, src, pidx, Y, x, w, M, (T)(1.0 / m->kavg), s);
       c->mark("layer" + ts + ".linear_out");
       for (int l : L.outs) {
         const bool has_sc = std::find(L.ins.begin(), L.ins.end(), l) != L.ins.end() && L.gmul[l] > 0;
@@ -622,6 +675,7 @@ struct Pipe {
     const int* sptr = c->get<int>("send_ptr", NE + 1);
     const int* sidx = c->get<int>("send_idx", E);
     const int* gptr = c->get<int>("ghost_ptr", N + 1);
+    const int* pidx = c->get<int>("pidx", E);
     const double* pos_ext = c->get<double>("pos_ext", 3 * (int64_t)NE);
     const int NY = (m->lsh + 1) * (m->lsh + 1);
     const T* Y = c->get<T>("Y", E * NY);
@@ -644,10 +698,10 @@ struct Pipe {
     T* dxe = c->get<T>("dxe", E * max_w);
     double* dx_ext = c->get<double>("dx_ext", (int64_t)NE * max_w);
     double* dx = c->get<double>("dx", (int64_t)N * max_w);
-    T* dz2 = c->get<T>("dz2", E * m->hidden);
-    T* dYp = c->get<T>("dYpart", E * max_tasks * NY);
+    T* dz2 = c->get<T>("dz2", c->NP * m->hidden);
     T* dY = c->get<T>("dY", E * NY);
     T* drho = c->get<T>("drho", E * m->nb);
+    zero(drho, sizeof(T) * E * m->nb, s);  // only the first edge of each pair receives drho
     c->mark("bwd.readout");
     // dE/dh^(T+1) = sigma (Wr1 Wr2): the same vector for every atom
     launch_fill_rows<double>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
@@ -656,7 +710,7 @@ struct Pipe {
       const std::string ts = std::to_string(t);
       const T* x = c->get<T>("x" + ts, (int64_t)NE * L.hin.width);
       const double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
-      const T* w = c->get<T>("w" + ts, E * L.P);
+      const T* w = c->get<T>("w" + ts, c->NP * L.P);
       c->mark("bwd.layer" + ts + ".linear_out");
       launch_gate_bwd<double>(N, L.last, L.yl, L.hout, y, dh, dy, m->act, s);
       for (int l : L.outs)
@@ -664,13 +718,10 @@ struct Pipe {
                               L.w_lin2[l], L.gmul[l], true, Gm, rows_of(L.ml, l),
                               (T)(1.0 / m->kavg), false);
       c->mark("bwd.layer" + ts + ".tp");
-      launch_tp_bwd<T>(L.tp, N, row_ptr, src, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dYp, s);
-      launch_dY_reduce<T>(E, L.tp.n_tasks, NY, dYp, dY, t != m->T - 1, s);
+      launch_tp_bwd<T>(L.tp, N, row_ptr, src, pidx, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dY,
+                       t != m->T - 1, s);
       c->mark("bwd.layer" + ts + ".mlp");
-      gemm<T, T, T, T>(E, m->hidden, L.P, dw, plain_rows(L.P), L.w_mlp[2], L.P, true, dz2,
-                       plain_rows(m->hidden), T(1), false);
-      launch_mlp_hidden_bwd<T>(E, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]), W<T>(c, L.w_mlp[1]),
-                               act, dz2, drho, t != m->T - 1, s);
+      mlp_backward(L, rho, dw, dz2, drho);
       if (t == 0) break;
       c->mark("bwd.layer" + ts + ".sender_fold");
       // sender-side sums over every extended row, then fold ghost rows onto owners
