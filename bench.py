@@ -26,14 +26,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic work per directed edge of the dominant kernel family, used for the
-# roofline figure (derivation in the design doc).
-HIDDEN = 64
-
-
-def mlp_gemm_flops(E, P):
-    """w = z2 Wc: 2 * 64 * P flops per edge."""
-    return 2.0 * HIDDEN * P * E
+def _traffic(kernel, source, precision):
+    """Measured HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when absent or when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{precision}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(source, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != h:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
@@ -45,13 +51,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-si", type=int, default=512,
                     help="Si count of the SiO2 sample box timed with the CPU oracle")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build evaluates one subdomain on one GPU; "
                                    "--gpus must be 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2402_03789_amd as sn
@@ -76,6 +83,12 @@ def main():
         ctx.forward_device(pos, Z, s.cell, energy)
         ctx.backward_device(1.0, forces, virial)
 
+    if args.calib_copy:
+        buf = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        buf.fill_(1.0)
+        out_buf = buf.clone()
+        torch.cuda.synchronize()
+        del buf, out_buf
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -92,16 +105,30 @@ def main():
     n, g, e = ctx.graph_size()
     value = s.n * args.steps / dt
 
-    # dominant kernel family: radial-MLP output GEMMs (forward), timed by HIP events
-    P = [384, 960, 960, 960, 224]
-    mlp_ms = sum(v for k, v in phase_ms.items() if k.startswith("layer") and k.endswith(".mlp"))
-    mlp_ms /= args.steps
-    flops = sum(mlp_gemm_flops(e, p) + e * (2 * 8 * 64 + 2 * 64 * 64) for p in P)
-    peak = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[args.precision]
-    achieved = flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else None
-    roofline = {"bound": "mfma", "kernel": "radial MLP (forward, 5 blocks)",
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": (achieved / peak) if achieved else None, "traffic": None}
+    # Roofline of the dominant kernel: the fused radial-MLP adjoint, one launch per
+    # interaction block, each timed by HIP events on the context's stream (in the
+    # float32/bfloat16 forms each "bwd.layer<t>.mlp" phase holds exactly that launch).
+    # Algorithmic bytes of a launch with P radial weights per pair: read dE/dw of both
+    # edges of every pair (2 x 4P bytes), read rho and write drho (2 x 32 bytes).
+    npairs = ctx.n_pairs()
+    Ps = [960 if 0 < t < 4 else (384 if t == 0 else 224) for t in range(5)]
+    launches = [f"bwd.layer{t}.mlp" for t in range(5)]
+    launch_ms = sum(phase_ms.get(k, 0.0) for k in launches) / (len(launches) * args.steps)
+    P_mean = sum(Ps) / len(Ps)
+    bytes_per_launch = npairs * (2 * 4 * P_mean + 64)
+    flops_per_launch = npairs * (2 * 64 * P_mean + 2 * (8 * 64 + 64 * 64 + 64 * 64 + 64 * 8))
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else None
+    traffic = _traffic("k_mlp_fused_bwd", os.path.join(ROOT, "paper_2402_03789_amd", "csrc",
+                                                        "k_mlp.hip"), args.precision)
+    peak_tf = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[args.precision]
+    roofline = {"bound": "hbm", "kernel": "k_mlp_fused_bwd (radial-MLP adjoint over edge pairs)",
+                "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                "frac": (achieved / 8000.0) if achieved else None,
+                "traffic": traffic,
+                "launch_ms": launch_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "algorithmic_flops_per_launch": flops_per_launch,
+                "mfma_frac": (flops_per_launch / (launch_ms * 1e-3) / 1e12 / peak_tf)
+                if launch_ms > 0 else None}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -119,6 +119,11 @@ class Context:
         check(lib().sn_ctx_graph_size(self._h, C.byref(n), C.byref(g), C.byref(e)))
         return n.value, g.value, e.value
 
+    def n_pairs(self) -> int:
+        v = C.c_int64()
+        check(lib().sn_ctx_pair_count(self._h, C.byref(v)))
+        return v.value
+
     def graph(self) -> dict:
         n, g, e = self.graph_size()
         recv = np.zeros(e, np.int32)

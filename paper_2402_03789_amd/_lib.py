@@ -55,6 +55,7 @@ _SIGS = {
     "sn_ctx_synchronize": (C.c_int, [C.c_void_p]),
     "sn_ctx_graph_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64)]),
+    "sn_ctx_pair_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "sn_ctx_graph": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
     "sn_ctx_timings": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.c_void_p,

@@ -112,6 +112,33 @@ __device__ inline void stage_common(int64_t np, int64_t p0, const int* __restric
   }
 }
 
+// Weight-panel prefetch: each of the 256 threads holds 16 values (4 x 4) of a 64 x 64
+// panel in registers while the current panel is being multiplied.
+struct PanelRegs {
+  float v[16];
+};
+
+// Wc panel columns [n0, n0+64) of the forward product, element (k, n) at Wc[k * P + n0 + n]
+__device__ inline void fetch_fwd_panel(const float* __restrict__ Wc, int P, int n0, int tid,
+                                       PanelRegs& r) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = tid + 256 * j;
+    const int k = i / HID, n = i % HID;
+    r.v[j] = (n0 + n < P) ? Wc[(int64_t)k * P + n0 + n] : 0.f;
+  }
+}
+template <bool BF16>
+__device__ inline void store_fwd_panel(const PanelRegs& r, int tid, float* sf, __bf16* sh) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = tid + 256 * j;
+    const int k = i / HID, n = i % HID;
+    if (BF16) sh[n * BP + k] = __float2bfloat16(r.v[j]);
+    else sf[k * WP + n] = r.v[j];
+  }
+}
+
 // ------------------------------------------------------------------ forward
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __restrict__ pe1,
@@ -120,23 +147,25 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
                                                         const float* __restrict__ Wb,
                                                         const float* __restrict__ Wc, int P, float c,
                                                         float* __restrict__ w) {
+  constexpr int PANEL = BF16 ? (HID * BP) / 2 : HID * WP;  // floats per panel buffer
   __shared__ float sWa[NBAS * HID];
-  __shared__ float sWb[HID * WP];
   __shared__ float sRho[EB * (NBAS + 1)];
   __shared__ float sZ[4][16 * ZP];
-  __shared__ __attribute__((aligned(16))) float sBf[BF16 ? 4 : HID * WP];    // Wc panel [k][n]
-  __shared__ __attribute__((aligned(16))) __bf16 sBh[BF16 ? HID * BP : 8];  // Wc panel [n][k]
+  __shared__ __attribute__((aligned(16))) float sW[2][HID * WP];  // Wb, then Wc panels
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
-  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sW[1], sRho);
+  PanelRegs pr;
+  fetch_fwd_panel(Wc, P, 0, tid, pr);
   __syncthreads();
   float* Z = sZ[wave];
   floatx4 acc[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, acc, lane);
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  store_fwd_panel<BF16>(pr, tid, sW[0], reinterpret_cast<__bf16*>(sW[0]));
   __syncthreads();
   zero4(acc);
-  panel_kn(Z, sWb, acc, lane);
+  panel_kn(Z, sW[1], acc, lane);
   __syncthreads();
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
   __syncthreads();
@@ -153,32 +182,31 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
 #pragma unroll
     for (int s = 0; s < HID / 4; ++s) za[s] = Z[r * ZP + 4 * s + q];
   }
+  (void)PANEL;
+  int buf = 0;
   for (int n0 = 0; n0 < P; n0 += HID) {
-    // stage Wc[:, n0 .. n0 + 63]
-    for (int i = tid; i < HID * HID; i += 256) {
-      const int k = i / HID, n = i % HID;
-      const float v = (n0 + n < P) ? Wc[(int64_t)k * P + n0 + n] : 0.f;
-      if (BF16) sBh[n * BP + k] = __float2bfloat16(v);
-      else sBf[k * WP + n] = v;
-    }
-    __syncthreads();
+    const bool more = n0 + HID < P;
+    if (more) fetch_fwd_panel(Wc, P, n0 + HID, tid, pr);  // in flight during the MFMAs
+    const float* sf = sW[buf];
+    const __bf16* sh = reinterpret_cast<const __bf16*>(sW[buf]);
     zero4(acc);
     if (BF16) {
 #pragma unroll
       for (int s = 0; s < HID / 32; ++s)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sBh[(t * 16 + r) * BP + 32 * s + 8 * q]);
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
           acc[t] = mfma32(zh[s], b, acc[t]);
         }
     } else {
 #pragma unroll
       for (int s = 0; s < HID / 4; ++s)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = mfma4(za[s], sBf[(4 * s + q) * WP + t * 16 + r], acc[t]);
+        for (int t = 0; t < 4; ++t) acc[t] = mfma4(za[s], sf[(4 * s + q) * WP + t * 16 + r], acc[t]);
     }
-    // through the wave's panel to full-row float4 stores
+    // through the wave's own panel to full-row float4 stores
     acc_to_panel(acc, Z, lane, [](float v, int, int) { return v; });
+    if (more) store_fwd_panel<BF16>(pr, tid, sW[buf ^ 1], reinterpret_cast<__bf16*>(sW[buf ^ 1]));
     __syncthreads();
     const int c4 = (lane & 15) * 4;
 #pragma unroll
@@ -190,7 +218,47 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
         *reinterpret_cast<floatx4*>(&w[p * P + n0 + c4]) = floatx4{zr[0], zr[1], zr[2], zr[3]};
       }
     }
-    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// Wc panel for the adjoint: element (j, k) at Wc[j * P + k0 + k] (hidden row j)
+__device__ inline void fetch_bwd_panel(const float* __restrict__ Wc, int P, int k0, int tid,
+                                       PanelRegs& r) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = tid + 256 * j;
+    const int jj = i / HID, k = i % HID;
+    r.v[j] = (k0 + k < P) ? Wc[(int64_t)jj * P + k0 + k] : 0.f;
+  }
+}
+template <bool BF16>
+__device__ inline void store_bwd_panel(const PanelRegs& r, int tid, float* sf, __bf16* sh) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = tid + 256 * j;
+    const int jj = i / HID, k = i % HID;
+    if (BF16) sh[jj * BP + k] = __float2bfloat16(r.v[j]);
+    else sf[jj * TP + k] = r.v[j];
+  }
+}
+
+// dw operand of one lane for a 64-wide k panel: float32 k-permuted fragments
+// (lane group q covers k = 16 u + 4 q + s), summed over both edges of the pair.
+struct DwRegs {
+  floatx4 a[HID / 16];
+};
+__device__ inline void fetch_dw(const float* __restrict__ dw, bool row_ok, int64_t r1, int e2,
+                                int64_t r2, int P, int k0, int q, DwRegs& d) {
+#pragma unroll
+  for (int u = 0; u < HID / 16; ++u) {
+    const int kb = k0 + 16 * u + 4 * q;
+    floatx4 av = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (row_ok && kb < P) {  // P is a multiple of 4
+      av = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
+      if (e2 >= 0) av += *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
+    }
+    d.a[u] = av;
   }
 }
 
@@ -208,39 +276,42 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   __shared__ float sWb[HID * WP];
   __shared__ float sRho[EB * (NBAS + 1)];
   __shared__ float sZ[4][16 * ZP];
-  __shared__ __attribute__((aligned(16))) float sBf[BF16 ? 4 : HID * TP];     // Wc[j][k-panel]
-  __shared__ __attribute__((aligned(16))) __bf16 sBh[BF16 ? HID * BP : 8];
+  __shared__ __attribute__((aligned(16))) float sB[2][HID * TP];  // Wc[j][k-panel] (or bf16)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
   stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
+  const int r = lane & 15, q = lane >> 4;
+  const int64_t pr = p0 + wave * 16 + r;
+  const bool row_ok = pr < np;
+  const int64_t r1 = row_ok ? (int64_t)pe1[pr] * P : 0;
+  const int e2 = row_ok ? pe2[pr] : -1;
+  const int64_t r2 = e2 >= 0 ? (int64_t)e2 * P : 0;
+  PanelRegs wr;
+  DwRegs dr_cur, dr_nxt;
+  fetch_bwd_panel(Wc, P, 0, tid, wr);
+  if (!BF16) fetch_dw(dw, row_ok, r1, e2, r2, P, 0, q, dr_cur);
   __syncthreads();
   float* Z = sZ[wave];
-  const int r = lane & 15, q = lane >> 4;
   // recompute a1 and a2 (accumulator layout)
   floatx4 a1[4], a2[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, a1, lane);
   acc_to_panel(a1, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  store_bwd_panel<BF16>(wr, tid, sB[0], reinterpret_cast<__bf16*>(sB[0]));
   __syncthreads();
   zero4(a2);
   panel_kn(Z, sWb, a2, lane);
   // dz2 = (dw[e1] + dw[e2]) Wc^T, contraction over the P radial weights in 64-wide panels
   floatx4 g[4];
   zero4(g);
-  const int64_t pr = p0 + wave * 16 + r;
-  const bool row_ok = pr < np;
-  const int64_t r1 = row_ok ? (int64_t)pe1[pr] * P : 0;
-  const int e2 = row_ok ? pe2[pr] : -1;
-  const int64_t r2 = e2 >= 0 ? (int64_t)e2 * P : 0;
+  int buf = 0;
   for (int k0 = 0; k0 < P; k0 += HID) {
-    __syncthreads();
-    for (int i = tid; i < HID * HID; i += 256) {
-      const int j = i / HID, k = i % HID;  // Wc row j (hidden), column k0 + k
-      const float v = (k0 + k < P) ? Wc[(int64_t)j * P + k0 + k] : 0.f;
-      if (BF16) sBh[j * BP + k] = __float2bfloat16(v);
-      else sBf[j * TP + k] = v;
+    const bool more = k0 + HID < P;
+    if (more) {
+      fetch_bwd_panel(Wc, P, k0 + HID, tid, wr);
+      if (!BF16) fetch_dw(dw, row_ok, r1, e2, r2, P, k0 + HID, q, dr_nxt);
     }
-    __syncthreads();
     if (BF16) {
+      const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
 #pragma unroll
       for (int s = 0; s < HID / 32; ++s) {
         bf16x8 a;
@@ -253,31 +324,27 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sBh[(t * 16 + r) * BP + 32 * s + 8 * q]);
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
           g[t] = mfma32(a, b, g[t]);
         }
       }
     } else {
-      // k-permuted float4 operands: lane group q covers k = 16 u + 4 q + s
+      const float* sf = sB[buf];
 #pragma unroll
       for (int u = 0; u < HID / 16; ++u) {
-        const int kb = k0 + 16 * u + 4 * q;
-        floatx4 av = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (row_ok && kb < P) {  // P is a multiple of 4
-          av = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
-          if (e2 >= 0) av += *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
-        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const floatx4 bv =
-              *reinterpret_cast<const floatx4*>(&sBf[(t * 16 + r) * TP + 16 * u + 4 * q]);
+          const floatx4 bv = *reinterpret_cast<const floatx4*>(&sf[(t * 16 + r) * TP + 16 * u + 4 * q]);
 #pragma unroll
-          for (int s = 0; s < 4; ++s) g[t] = mfma4(av[s], bv[s], g[t]);
+          for (int s = 0; s < 4; ++s) g[t] = mfma4(dr_cur.a[u][s], bv[s], g[t]);
         }
       }
+      dr_cur = dr_nxt;
     }
+    if (more) store_bwd_panel<BF16>(wr, tid, sB[buf ^ 1], reinterpret_cast<__bf16*>(sB[buf ^ 1]));
+    __syncthreads();
+    buf ^= 1;
   }
-  __syncthreads();
   // da2 = dz2 * phi'(a2) -> operand panel;  dz1 = da2 Wb^T
   acc_to_panel(g, Z, lane, [&](float v, int t, int rr) { return v * dphi(a2[t][rr], c); });
   __syncthreads();

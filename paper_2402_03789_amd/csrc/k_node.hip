@@ -112,15 +112,37 @@ __global__ void k_fill_rows(int n, const double* __restrict__ v, int C0, double 
     dh[(int64_t)r * ldh + k] = k < C0 ? T(scale * v[k]) : T(0);
 }
 
+// One row per block; each thread owns 4 consecutive columns (one 16-byte load per edge
+// in float32) and accumulates in float64.  The edge loop is unrolled for memory-level
+// parallelism; the summation order stays the sender segment's order.
 template <typename T>
 __global__ void k_sender_reduce(int n_rows, const int* __restrict__ sptr, const int* __restrict__ sidx,
                                 const T* __restrict__ dxe, int width, double* __restrict__ dx) {
-  int s = blockIdx.x;
-  int a = sptr[s], b = sptr[s + 1];
-  for (int c = threadIdx.x; c < width; c += blockDim.x) {
-    double acc = 0.0;
-    for (int q = a; q < b; ++q) acc += (double)dxe[(int64_t)sidx[q] * width + c];
-    dx[(int64_t)s * width + c] = acc;
+  const int s = blockIdx.x;
+  const int a = sptr[s], b = sptr[s + 1];
+  for (int c = threadIdx.x * 4; c < width; c += blockDim.x * 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int q = a;
+    for (; q + 4 <= b; q += 4) {
+      T v[4][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const T* row = dxe + (int64_t)sidx[q + k] * width + c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[k][j] = row[j];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] += (double)v[k][j];
+    }
+    for (; q < b; ++q) {
+      const T* row = dxe + (int64_t)sidx[q] * width + c;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] += (double)row[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dx[(int64_t)s * width + c + j] = acc[j];
   }
 }
 

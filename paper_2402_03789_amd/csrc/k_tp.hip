@@ -106,6 +106,33 @@ __device__ inline void tp_paths(const T* xv, const T* Ye, T* t) {
   });
 }
 
+// Operands of one edge for one lane, loaded one edge ahead of their use.
+template <typename T, int D1, int NP, int NYc, int KC>
+struct EdgeOps {
+  T Y[NYc];
+  T x[KC][D1];
+  T w[KC][NP];
+};
+
+template <typename T, int D1, int NP, int NYc, int KC>
+__device__ inline void load_edge(const TPArgs& g, const TPDeg& a, int64_t e, int s, int pr, int uu,
+                                 const T* __restrict__ Y, const T* __restrict__ x,
+                                 const T* __restrict__ w, EdgeOps<T, D1, NP, NYc, KC>& o) {
+#pragma unroll
+  for (int q = 0; q < NYc; ++q) o.Y[q] = Y[e * g.NY + q];
+  const int64_t wrow = (int64_t)pr * g.P + a.woff;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const int u = uu + c * a.cpt;
+    const bool ok = c < a.cpl && u < a.mul;
+#pragma unroll
+    for (int m1 = 0; m1 < D1; ++m1)
+      o.x[c][m1] = ok ? x[(int64_t)s * g.Dx + a.xoff + m1 * a.mul + u] : T(0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) o.w[c][p] = ok ? w[wrow + p * a.mul + u] : T(0);
+  }
+}
+
 template <typename T, int L1, int LSH, int L3MAX, bool SO>
 __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ Y,
                                                  const T* __restrict__ x, const T* __restrict__ w,
@@ -127,32 +154,35 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
 #pragma unroll
     for (int q = 0; q < NO; ++q) acc[c][q] = T(0);
   const int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
-  for (int e0 = beg; e0 < end; e0 += EI) {
-    const int64_t e = e0 + ei;
-    if (e >= end) continue;
-    const int s = g.src[e];
-    const int64_t wrow = (int64_t)g.pidx[e] * g.P + a.woff;
-    T Ye[NYc];
+  const int n_it = (end - beg + EI - 1) / EI;
+  // software pipeline: indices two edges ahead, operands one edge ahead
+  int e1 = beg + ei, e2 = beg + EI + ei;
+  int s1 = e1 < end ? g.src[e1] : 0, p1 = e1 < end ? g.pidx[e1] : 0;
+  int s2 = e2 < end ? g.src[e2] : 0, p2 = e2 < end ? g.pidx[e2] : 0;
+  EdgeOps<T, D1, NP, NYc, KC> cur, nxt;
+  if (e1 < end) load_edge<T, D1, NP, NYc, KC>(g, a, e1, s1, p1, uu, Y, x, w, cur);
+  for (int it = 0; it < n_it; ++it) {
+    const int ec = beg + it * EI + ei;
+    const int en = ec + EI, e3 = ec + 2 * EI;
+    const int s3 = e3 < end ? g.src[e3] : 0, p3 = e3 < end ? g.pidx[e3] : 0;
+    if (en < end) load_edge<T, D1, NP, NYc, KC>(g, a, en, s2, p2, uu, Y, x, w, nxt);
+    if (ec < end) {
 #pragma unroll
-    for (int q = 0; q < NYc; ++q) Ye[q] = Y[e * g.NY + q];
+      for (int c = 0; c < KC; ++c) {
+        T t[NO];
+        tp_paths<T, L1, PL>(cur.x[c], cur.Y, t);
+        static_for<NP>([&](auto P) {
+          constexpr int p = decltype(P)::value;
+          constexpr int D3 = 2 * PL::l3(p) + 1;
+          constexpr int oo = PL::ooff(p);
 #pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      const int u = uu + c * cpt;
-      if (c >= a.cpl || u >= a.mul) break;
-      T xv[D1];
-#pragma unroll
-      for (int m1 = 0; m1 < D1; ++m1) xv[m1] = x[(int64_t)s * g.Dx + a.xoff + m1 * a.mul + u];
-      T t[NO];
-      tp_paths<T, L1, PL>(xv, Ye, t);
-      static_for<NP>([&](auto P) {
-        constexpr int p = decltype(P)::value;
-        constexpr int D3 = 2 * PL::l3(p) + 1;
-        constexpr int oo = PL::ooff(p);
-        const T wv = w[wrow + p * a.mul + u];
-#pragma unroll
-        for (int m3 = 0; m3 < D3; ++m3) acc[c][oo + m3] += wv * t[oo + m3];
-      });
+          for (int m3 = 0; m3 < D3; ++m3) acc[c][oo + m3] += cur.w[c][p] * t[oo + m3];
+        });
+      }
     }
+    cur = nxt;
+    s2 = s3;
+    p2 = p3;
   }
   for (int off = cpt; off < kWave; off <<= 1) {
 #pragma unroll
@@ -210,37 +240,40 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
     });
   }
   const int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
-  for (int e0 = beg; e0 < end; e0 += EI) {
-    const int64_t e = e0 + ei;
-    const bool active = e < end;
+  const int n_it = (end - beg + EI - 1) / EI;
+  int e1 = beg + ei, e2 = beg + EI + ei;
+  int s1 = e1 < end ? g.src[e1] : 0, p1 = e1 < end ? g.pidx[e1] : 0;
+  int s2 = e2 < end ? g.src[e2] : 0, p2 = e2 < end ? g.pidx[e2] : 0;
+  EdgeOps<T, D1, NP, NYc, KC> cur, nxt;
+  if (e1 < end) load_edge<T, D1, NP, NYc, KC>(g, a, e1, s1, p1, uu, Y, x, w, cur);
+  for (int it = 0; it < n_it; ++it) {
+    const int ec = beg + it * EI + ei;
+    const int en = ec + EI, e3 = ec + 2 * EI;
+    const int s3 = e3 < end ? g.src[e3] : 0, p3 = e3 < end ? g.pidx[e3] : 0;
+    if (en < end) load_edge<T, D1, NP, NYc, KC>(g, a, en, s2, p2, uu, Y, x, w, nxt);
+    const bool active = ec < end;
     T dYl[NYc];
 #pragma unroll
     for (int q = 0; q < NYc; ++q) dYl[q] = T(0);
     if (active) {
-      const int s = g.src[e];
-      const int64_t wrow = (int64_t)g.pidx[e] * g.P + a.woff;
+      const int64_t e = ec;
       const int64_t drow = e * g.P + a.woff;
-      T Ye[NYc];
-#pragma unroll
-      for (int q = 0; q < NYc; ++q) Ye[q] = Y[e * g.NY + q];
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
         const int u = uu + c * cpt;
         if (c >= a.cpl || u >= a.mul) break;
-        T xv[D1], dxv[D1];
+        const T* xv = cur.x[c];
+        T dxv[D1];
 #pragma unroll
-        for (int m1 = 0; m1 < D1; ++m1) {
-          xv[m1] = x[(int64_t)s * g.Dx + a.xoff + m1 * a.mul + u];
-          dxv[m1] = T(0);
-        }
+        for (int m1 = 0; m1 < D1; ++m1) dxv[m1] = T(0);
         T t[NO];
-        tp_paths<T, L1, PL>(xv, Ye, t);
+        tp_paths<T, L1, PL>(xv, cur.Y, t);
         static_for<NP>([&](auto P) {
           constexpr int p = decltype(P)::value;
           constexpr int l2 = PL::l2(p), l3 = PL::l3(p);
           constexpr int D3 = 2 * l3 + 1;
           constexpr int oo = PL::ooff(p);
-          const T wv = w[wrow + p * a.mul + u];
+          const T wv = cur.w[c][p];
           T dwv = T(0);
           T gg[D3];
 #pragma unroll
@@ -251,7 +284,7 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
           }
           dw[drow + p * a.mul + u] = dwv;
           CG<L1, l2, l3>::each([&](int m1, int m2, int m3, double cc) {
-            if (WRITE_DX) dxv[m1] += T(cc) * (Ye[l2 * l2 + m2] * gg[m3]);
+            if (WRITE_DX) dxv[m1] += T(cc) * (cur.Y[l2 * l2 + m2] * gg[m3]);
             dYl[l2 * l2 + m2] += T(cc) * (xv[m1] * gg[m3]);
           });
         });
@@ -266,10 +299,13 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
       for (int q = 0; q < NYc; ++q) dYl[q] += __shfl_xor(dYl[q], off);
     }
     if (uu == 0 && active) {
-      T* dst = dY + e * g.NY;
+      T* dst = dY + (int64_t)ec * g.NY;
 #pragma unroll
       for (int q = 0; q < NYc; ++q) dst[q] = accumulate ? dst[q] + dYl[q] : dYl[q];
     }
+    cur = nxt;
+    s2 = s3;
+    p2 = p3;
   }
 }
 

@@ -228,7 +228,8 @@ std::unique_ptr<sn_model> load_model(const char* path) {
   if (m->nb != 8 || m->hidden != 64) throw UnsupportedError("radial MLP must be 8 -> 64 -> 64");
   if (!((m->lmax == 1 && m->lsh == 1) || (m->lmax == 2 && m->lsh == 2)))
     throw UnsupportedError("supported (l_max, l_sh): (1, 1) and (2, 2)");
-  if (m->muls[0] % 2 != 0) throw UnsupportedError("C0 must be even");
+  if (m->muls[0] % 4 != 0 || m->muls[1] % 4 != 0 || m->muls[2] % 4 != 0)
+    throw UnsupportedError("channel counts must be multiples of 4");
   for (int l = 0; l < 3; ++l)
     if (m->muls[l] < 0 || m->muls[l] > 128) throw UnsupportedError("at most 128 channels per degree");
   std::fill(m->lut, m->lut + 128, -1);
@@ -1028,6 +1029,12 @@ int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, i
   if (n_local) *n_local = ctx->N;
   if (n_ghost) *n_ghost = ctx->G;
   if (n_edge) *n_edge = ctx->E;
+  return SN_OK;
+}
+
+int sn_ctx_pair_count(const sn_ctx_t* ctx, int64_t* n_pairs) {
+  if (!ctx || !n_pairs) return SN_EINVAL;
+  *n_pairs = ctx->NP;
   return SN_OK;
 }
 

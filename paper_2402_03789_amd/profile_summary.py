@@ -1,0 +1,69 @@
+"""Summaries of rocprofv3 outputs for profiles/ (kernel-trace stats and HBM counters).
+
+Usage:
+  python -m paper_2402_03789_amd.profile_summary stats <rocprof_dir> <steps> <out.md> <command...>
+  python -m paper_2402_03789_amd.profile_summary traffic <fetch_dir> <write_dir> <kernel> \
+        <source.hip> <precision> <out.json> <command...>
+
+The traffic summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by the
+readings of the same counters for the 256 MiB device copy that the benchmark
+runs first with --calib-copy (a copy reads and writes exactly 256 MiB).
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import sys
+
+
+def _rows(d, pattern):
+    files = glob.glob(f"{d}/**/{pattern}", recursive=True)
+    if not files:
+        raise FileNotFoundError(f"{pattern} under {d}")
+    return list(csv.DictReader(open(files[0])))
+
+
+def stats(d, steps, out, cmd):
+    rows = _rows(d, "*kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# Kernel-trace summary", "", f"Command: `{cmd}`", "",
+             f"Per step = totals / {steps} profiled steps (plus warm-up launches where noted by calls).",
+             "", "| kernel | calls | avg us | total ms/step | % |", "|---|---|---|---|---|"]
+    for r in rows[:30]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6 / steps:.3f} | {float(r['Percentage']):.2f} |")
+    lines += ["", f"Total GPU time per step: {total / 1e6 / steps:.3f} ms"]
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def traffic(fetch_dir, write_dir, kernel, source, precision, out, cmd):
+    f_rows = _rows(fetch_dir, "*counter_collection.csv")
+    w_rows = _rows(write_dir, "*counter_collection.csv")
+
+    def calib(rows, counter):
+        vals = [float(r["Counter_Value"]) for r in rows
+                if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
+        return max(vals)  # the 256 MiB copy is the largest
+    cf = calib(f_rows, "FETCH_SIZE") / (256 * 1024)
+    cw = calib(w_rows, "WRITE_SIZE") / (256 * 1024)
+    fk = [float(r["Counter_Value"]) for r in f_rows if kernel in r["Kernel_Name"]]
+    wk = [float(r["Counter_Value"]) for r in w_rows if kernel in r["Kernel_Name"]]
+    fetch = sum(fk) / len(fk) / cf * 1024
+    write = sum(wk) / len(wk) / cw * 1024
+    rec = {"kernel": kernel, "precision": precision, "command": cmd,
+           "calibration": {"fetch_KiB_per_copy_KiB": cf, "write_KiB_per_copy_KiB": cw},
+           "dispatches": len(fk), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "bytes_per_launch": fetch + write,
+           "source_sha256": hashlib.sha256(open(source, "rb").read()).hexdigest()}
+    json.dump(rec, open(out, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], float(sys.argv[3]), sys.argv[4], " ".join(sys.argv[5:]))
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:8], " ".join(sys.argv[8:]))
