@@ -115,6 +115,17 @@ int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, co
                const uint8_t* pbc, double* energy, double* atom_energy, double* forces,
                double* virial);
 
+/* ---- several structures in one packed graph, host buffers --------------------------
+ * B structures; offsets[B+1] (offsets[0] = 0) delimit each structure's atoms in pos[n*3]
+ * and Z[n] (n = offsets[B]); cells[B*9] holds each structure's cell (all periodic).  The
+ * structures are evaluated together as one graph (the kernels run once over all atoms
+ * and edges; edges never cross structures) and the results are exactly those of
+ * evaluating each structure alone, up to floating-point summation order.  Outputs:
+ * energies[B]; atom_energies[n], forces[n*3], virials[B*9] (each may be NULL). */
+int sn_compute_batch(sn_ctx_t* ctx, int B, const int64_t* offsets, const double* pos,
+                     const int32_t* Z, const double* cells, double* energies,
+                     double* atom_energies, double* forces, double* virials);
+
 /* ---- device buffers, stream-ordered (the autograd pair) -----------------------------
  * sn_forward_device builds the graph, runs every interaction block and the
  * readout, and keeps the activations the backward pass needs inside ctx.
@@ -128,6 +139,21 @@ int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, co
 int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32_t* d_Z,
                       const double* cell, double* d_energy, double* d_atom_energy);
 int sn_backward_device(sn_ctx_t* ctx, double grad_energy, double* d_forces, double* d_virial);
+
+/* Neighbour-list reuse for molecular dynamics.  With reuse enabled, a forward call whose
+ * atom count and cell equal those of the previous build keeps that graph (ghost shell and
+ * edges out to r_cut + skin) and only refreshes local and ghost positions from d_pos; the
+ * caller guarantees that no atom moved more than skin / 2 since the last build, and disables
+ * reuse for the call that should rebuild.  Results equal a fresh build because the envelope
+ * and its derivative vanish beyond r_cut. */
+int sn_ctx_set_graph_reuse(sn_ctx_t* ctx, int reuse);
+
+/* Velocity-Verlet half step on device arrays (harness of the MD workload), stream-ordered:
+ * stage 0: v += dt/2 a, x += dt v;  stage 1: v += dt/2 a;  a = F * inv_mass.
+ * d_pos, d_vel, d_forces are n x 3 float64; d_inv_mass[n] carries the unit conversion
+ * (for eV, angstrom, amu and fs: 0.0096485 / mass). */
+int sn_md_verlet(sn_ctx_t* ctx, int64_t n, double* d_pos, double* d_vel, const double* d_forces,
+                 const double* d_inv_mass, double dt, int stage);
 
 /* Wait for every queued operation of the context. */
 int sn_ctx_synchronize(sn_ctx_t* ctx);

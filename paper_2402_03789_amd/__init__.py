@@ -102,6 +102,33 @@ class Context:
             out["virial"] = w
         return out
 
+    def compute_batch(self, structures, forces=True, virial=True) -> list:
+        """Several structures (each (pos, Z, cell)) as one packed graph; per-structure results."""
+        B = len(structures)
+        offsets = np.zeros(B + 1, dtype=np.int64)
+        for b, (p, z, c) in enumerate(structures):
+            offsets[b + 1] = offsets[b] + len(z)
+        n = int(offsets[-1])
+        pos = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float64) for p, _, _ in structures]))
+        Z = np.ascontiguousarray(np.concatenate([np.asarray(z, np.int32) for _, z, _ in structures]))
+        cells = np.ascontiguousarray(np.stack([np.asarray(c, np.float64) for _, _, c in structures]))
+        e = np.zeros(B)
+        ae = np.zeros(n)
+        f = np.zeros((n, 3)) if forces else None
+        w = np.zeros((B, 3, 3)) if virial else None
+        check(lib().sn_compute_batch(self._h, B, ptr(offsets), ptr(pos), ptr(Z), ptr(cells), ptr(e),
+                                     ptr(ae), ptr(f), ptr(w)), self._h)
+        out = []
+        for b in range(B):
+            a, z = offsets[b], offsets[b + 1]
+            r = dict(energy=float(e[b]), atom_energy=ae[a:z])
+            if forces:
+                r["forces"] = f[a:z]
+            if virial:
+                r["virial"] = w[b]
+            out.append(r)
+        return out
+
     def forward_device(self, pos: torch.Tensor, Z: torch.Tensor, cell, energy: torch.Tensor,
                        atom_energy: torch.Tensor | None = None):
         cell = np.ascontiguousarray(cell, dtype=np.float64)
@@ -118,6 +145,13 @@ class Context:
         n, g, e = C.c_int64(), C.c_int64(), C.c_int64()
         check(lib().sn_ctx_graph_size(self._h, C.byref(n), C.byref(g), C.byref(e)))
         return n.value, g.value, e.value
+
+    def set_graph_reuse(self, reuse: bool):
+        check(lib().sn_ctx_set_graph_reuse(self._h, 1 if reuse else 0))
+
+    def verlet(self, pos, vel, forces, inv_mass, dt: float, stage: int):
+        check(lib().sn_md_verlet(self._h, pos.shape[0], ptr(pos), ptr(vel), ptr(forces),
+                                 ptr(inv_mass), float(dt), int(stage)), self._h)
 
     def n_pairs(self) -> int:
         v = C.c_int64()

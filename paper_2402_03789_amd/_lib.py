@@ -49,6 +49,8 @@ _SIGS = {
     "sn_ctx_free": (None, [C.c_void_p]),
     "sn_compute": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sn_compute_batch": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sn_forward_device": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
     "sn_backward_device": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
@@ -56,6 +58,9 @@ _SIGS = {
     "sn_ctx_graph_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64)]),
     "sn_ctx_pair_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "sn_ctx_set_graph_reuse": (C.c_int, [C.c_void_p, C.c_int]),
+    "sn_md_verlet": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_double, C.c_int]),
     "sn_ctx_graph": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
     "sn_ctx_timings": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.c_void_p,

@@ -77,6 +77,10 @@ __global__ void k_edge_grad(int64_t E, const int* __restrict__ recv, const int* 
   double xp = xp1 * xr;
   double u = 1.0 - c1 * xp + c2 * xp * xr - c3 * xp * xr * xr;
   double du = (-p * c1 * xp1 + (p + 1) * c2 * xp - (p + 2) * c3 * xp * xr) / r_cut;
+  if (xr >= 1.0) {  // skin edges beyond r_c: the envelope and its derivative vanish
+    u = 0.0;
+    du = 0.0;
+  }
   const double pi = 3.141592653589793;
   double dEdr = 0.0;
   for (int n = 1; n <= nb; ++n) {

@@ -71,6 +71,8 @@ void scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ binning helpers
+// Several structures can share one packed graph: every point carries its structure id,
+// and structure b bins into the global key range [bin_base, bin_base + nb0*nb1*nb2).
 __device__ inline int bin_axis(double f, const BinGrid& g, int a) {
   int b = (int)floor((f + g.delta[a]) / g.bw[a]);
   return min(max(b, 0), g.nb[a] - 1);
@@ -79,13 +81,12 @@ __device__ inline int bin_lin(const double* f, const BinGrid& g) {
   return (bin_axis(f[0], g, 0) * g.nb[1] + bin_axis(f[1], g, 1)) * g.nb[2] + bin_axis(f[2], g, 2);
 }
 
-struct Mat3 { double m[9]; };
-
-__global__ void k_wrap_bin(int n, const double* __restrict__ pos, Mat3 H, Mat3 Hinv, BinGrid g,
-                           double* __restrict__ posw, double* __restrict__ frac,
-                           int* __restrict__ key, int* __restrict__ err) {
+__global__ void k_wrap_bin(int n, const double* __restrict__ pos, const int* __restrict__ sid,
+                           const StructParams* __restrict__ sp, double* __restrict__ posw,
+                           double* __restrict__ frac, int* __restrict__ key, int* __restrict__ err) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const StructParams& P = sp[sid[i]];
   double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) {
     atomicOr(err, 1);
@@ -94,16 +95,16 @@ __global__ void k_wrap_bin(int n, const double* __restrict__ pos, Mat3 H, Mat3 H
   double f[3];
   for (int a = 0; a < 3; ++a) {
     // row vector p times Hinv
-    double v = p[0] * Hinv.m[0 * 3 + a] + p[1] * Hinv.m[1 * 3 + a] + p[2] * Hinv.m[2 * 3 + a];
+    double v = p[0] * P.Hinv[0 * 3 + a] + p[1] * P.Hinv[1 * 3 + a] + p[2] * P.Hinv[2 * 3 + a];
     v -= floor(v);
     if (v >= 1.0) v = 0.0;
     f[a] = v;
   }
   for (int a = 0; a < 3; ++a) {
     frac[3 * i + a] = f[a];
-    posw[3 * i + a] = f[0] * H.m[0 * 3 + a] + f[1] * H.m[1 * 3 + a] + f[2] * H.m[2 * 3 + a];
+    posw[3 * i + a] = f[0] * P.H[0 * 3 + a] + f[1] * P.H[1 * 3 + a] + f[2] * P.H[2 * 3 + a];
   }
-  key[i] = bin_lin(f, g);
+  key[i] = P.bin_base + bin_lin(f, P.g);
 }
 
 __global__ void k_count_keys(int n, const int* __restrict__ key, int* __restrict__ count) {
@@ -138,8 +139,9 @@ __global__ void k_sort_segments(int nseg, const int* __restrict__ start, int* __
 
 __global__ void k_gather_local(int n, const int* __restrict__ order, const double* __restrict__ posw,
                                const double* __restrict__ frac, const int* __restrict__ spec_orig,
-                               double* __restrict__ pos_ext, double* __restrict__ frac_ext,
-                               int* __restrict__ spec_ext) {
+                               const int* __restrict__ sid_orig, double* __restrict__ pos_ext,
+                               double* __restrict__ frac_ext, int* __restrict__ spec_ext,
+                               int* __restrict__ sid_ext) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int o = order[k];
@@ -148,6 +150,7 @@ __global__ void k_gather_local(int n, const int* __restrict__ order, const doubl
     frac_ext[3 * k + a] = frac[3 * o + a];
   }
   spec_ext[k] = spec_orig[o];
+  sid_ext[k] = sid_orig[o];
 }
 
 __device__ inline bool in_shell(const double* f, int sx, int sy, int sz, const BinGrid& g) {
@@ -157,10 +160,11 @@ __device__ inline bool in_shell(const double* f, int sx, int sy, int sz, const B
   return true;
 }
 
-__global__ void k_ghost_count(int n, const double* __restrict__ frac, BinGrid g,
-                              int* __restrict__ count) {
+__global__ void k_ghost_count(int n, const double* __restrict__ frac, const int* __restrict__ sid,
+                              const StructParams* __restrict__ sp, int* __restrict__ count) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
+  const BinGrid& g = sp[sid[k]].g;
   double f[3] = {frac[3 * k], frac[3 * k + 1], frac[3 * k + 2]};
   int c = 0;
   for (int sx = -g.nimg[0]; sx <= g.nimg[0]; ++sx)
@@ -173,12 +177,16 @@ __global__ void k_ghost_count(int n, const double* __restrict__ frac, BinGrid g,
 }
 
 __global__ void k_ghost_fill(int n, const double* __restrict__ frac, const double* __restrict__ pos,
-                             const int* __restrict__ spec, Mat3 H, BinGrid g,
-                             const int* __restrict__ gptr, int* __restrict__ owner,
-                             int* __restrict__ shift, double* __restrict__ pos_ext,
-                             double* __restrict__ frac_ext, int* __restrict__ spec_ext) {
+                             const int* __restrict__ spec, int* __restrict__ sid,
+                             const StructParams* __restrict__ sp, const int* __restrict__ gptr,
+                             int* __restrict__ owner, int* __restrict__ shift,
+                             double* __restrict__ pos_ext, double* __restrict__ frac_ext,
+                             int* __restrict__ spec_ext) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
+  const int b = sid[k];
+  const StructParams& P = sp[b];
+  const BinGrid& g = P.g;
   double f[3] = {frac[3 * k], frac[3 * k + 1], frac[3 * k + 2]};
   int w = gptr[k];
   for (int sx = -g.nimg[0]; sx <= g.nimg[0]; ++sx)
@@ -192,32 +200,38 @@ __global__ void k_ghost_fill(int n, const double* __restrict__ frac, const doubl
         shift[3 * w + 2] = sz;
         int r = n + w;
         for (int a = 0; a < 3; ++a) {
-          pos_ext[3 * r + a] = pos[3 * k + a] + sx * H.m[0 * 3 + a] + sy * H.m[1 * 3 + a] +
-                               sz * H.m[2 * 3 + a];
+          pos_ext[3 * r + a] = pos[3 * k + a] + sx * P.H[0 * 3 + a] + sy * P.H[1 * 3 + a] +
+                               sz * P.H[2 * 3 + a];
         }
         frac_ext[3 * r] = f[0] + sx;
         frac_ext[3 * r + 1] = f[1] + sy;
         frac_ext[3 * r + 2] = f[2] + sz;
         spec_ext[r] = spec[k];
+        sid[r] = b;
         ++w;
       }
 }
 
-__global__ void k_bin_keys(int n, const double* __restrict__ frac, BinGrid g, int* __restrict__ key) {
+__global__ void k_bin_keys(int n, const double* __restrict__ frac, const int* __restrict__ sid,
+                           const StructParams* __restrict__ sp, int* __restrict__ key) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const StructParams& P = sp[sid[i]];
   double f[3] = {frac[3 * i], frac[3 * i + 1], frac[3 * i + 2]};
-  key[i] = bin_lin(f, g);
+  key[i] = P.bin_base + bin_lin(f, P.g);
 }
 
 template <bool FILL>
 __global__ void k_edges(int n, const double* __restrict__ pos_ext, const double* __restrict__ frac_ext,
-                        BinGrid g, const int* __restrict__ cell_start,
-                        const int* __restrict__ cell_items, double rc2, int* __restrict__ count,
-                        int* __restrict__ err, const int* __restrict__ row_ptr,
-                        int* __restrict__ src, int* __restrict__ recv) {
+                        const int* __restrict__ sid, const StructParams* __restrict__ sp,
+                        const int* __restrict__ cell_start, const int* __restrict__ cell_items,
+                        double rc2, int* __restrict__ count, int* __restrict__ err,
+                        const int* __restrict__ row_ptr, int* __restrict__ src,
+                        int* __restrict__ recv) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
+  const StructParams& P = sp[sid[k]];
+  const BinGrid& g = P.g;
   double p[3] = {pos_ext[3 * k], pos_ext[3 * k + 1], pos_ext[3 * k + 2]};
   double f[3] = {frac_ext[3 * k], frac_ext[3 * k + 1], frac_ext[3 * k + 2]};
   int b[3];
@@ -227,7 +241,7 @@ __global__ void k_edges(int n, const double* __restrict__ pos_ext, const double*
   for (int bx = max(b[0] - 1, 0); bx <= min(b[0] + 1, g.nb[0] - 1); ++bx)
     for (int by = max(b[1] - 1, 0); by <= min(b[1] + 1, g.nb[1] - 1); ++by)
       for (int bz = max(b[2] - 1, 0); bz <= min(b[2] + 1, g.nb[2] - 1); ++bz) {
-        int cell = (bx * g.nb[1] + by) * g.nb[2] + bz;
+        int cell = P.bin_base + (bx * g.nb[1] + by) * g.nb[2] + bz;
         for (int q = cell_start[cell]; q < cell_start[cell + 1]; ++q) {
           int s = cell_items[q];
           if (s == k) continue;
@@ -252,11 +266,9 @@ __global__ void k_edges(int n, const double* __restrict__ pos_ext, const double*
 // ------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-void launch_wrap_bin(int n, const double* pos, const double* H, const double* Hinv, BinGrid g,
-                     double* posw, double* frac, int* key, int* err, hipStream_t s) {
-  Mat3 h, hi;
-  for (int i = 0; i < 9; ++i) { h.m[i] = H[i]; hi.m[i] = Hinv[i]; }
-  if (n > 0) k_wrap_bin<<<nblk(n, 256), 256, 0, s>>>(n, pos, h, hi, g, posw, frac, key, err);
+void launch_wrap_bin(int n, const double* pos, const int* sid, const StructParams* sp, double* posw,
+                     double* frac, int* key, int* err, hipStream_t s) {
+  if (n > 0) k_wrap_bin<<<nblk(n, 256), 256, 0, s>>>(n, pos, sid, sp, posw, frac, key, err);
 }
 void launch_count_keys(int n, const int* key, int* count, hipStream_t s) {
   if (n > 0) k_count_keys<<<nblk(n, 256), 256, 0, s>>>(n, key, count);
@@ -269,40 +281,42 @@ void launch_sort_segments(int nseg, const int* start, int* items, hipStream_t s)
   if (nseg > 0) k_sort_segments<<<nblk(nseg, 128), 128, 0, s>>>(nseg, start, items);
 }
 void launch_gather_local(int n, const int* order, const double* posw, const double* frac,
-                         const int* spec_orig, double* pos_ext, double* frac_ext, int* spec_ext,
-                         hipStream_t s) {
+                         const int* spec_orig, const int* sid_orig, double* pos_ext,
+                         double* frac_ext, int* spec_ext, int* sid_ext, hipStream_t s) {
   if (n > 0)
-    k_gather_local<<<nblk(n, 256), 256, 0, s>>>(n, order, posw, frac, spec_orig, pos_ext, frac_ext,
-                                                spec_ext);
+    k_gather_local<<<nblk(n, 256), 256, 0, s>>>(n, order, posw, frac, spec_orig, sid_orig, pos_ext,
+                                                frac_ext, spec_ext, sid_ext);
 }
-void launch_ghost_count(int n, const double* frac, BinGrid g, int* count, hipStream_t s) {
-  if (n > 0) k_ghost_count<<<nblk(n, 128), 128, 0, s>>>(n, frac, g, count);
+void launch_ghost_count(int n, const double* frac, const int* sid, const StructParams* sp,
+                        int* count, hipStream_t s) {
+  if (n > 0) k_ghost_count<<<nblk(n, 128), 128, 0, s>>>(n, frac, sid, sp, count);
 }
-void launch_ghost_fill(int n, const double* frac, const double* pos, const int* spec,
-                       const double* H, BinGrid g, const int* gptr, int* owner, int* shift,
+void launch_ghost_fill(int n, const double* frac, const double* pos, const int* spec, int* sid,
+                       const StructParams* sp, const int* gptr, int* owner, int* shift,
                        double* pos_ext, double* frac_ext, int* spec_ext, hipStream_t s) {
-  Mat3 h;
-  for (int i = 0; i < 9; ++i) h.m[i] = H[i];
   if (n > 0)
-    k_ghost_fill<<<nblk(n, 128), 128, 0, s>>>(n, frac, pos, spec, h, g, gptr, owner, shift, pos_ext,
-                                              frac_ext, spec_ext);
+    k_ghost_fill<<<nblk(n, 128), 128, 0, s>>>(n, frac, pos, spec, sid, sp, gptr, owner, shift,
+                                              pos_ext, frac_ext, spec_ext);
 }
-void launch_bin_keys(int n, const double* frac, BinGrid g, int* key, hipStream_t s) {
-  if (n > 0) k_bin_keys<<<nblk(n, 256), 256, 0, s>>>(n, frac, g, key);
+void launch_bin_keys(int n, const double* frac, const int* sid, const StructParams* sp, int* key,
+                     hipStream_t s) {
+  if (n > 0) k_bin_keys<<<nblk(n, 256), 256, 0, s>>>(n, frac, sid, sp, key);
 }
-void launch_edge_count(int n, const double* pos_ext, const double* frac_ext, BinGrid g,
-                       const int* cell_start, const int* cell_items, double rc2, int* count,
-                       int* err, hipStream_t s) {
+void launch_edge_count(int n, const double* pos_ext, const double* frac_ext, const int* sid,
+                       const StructParams* sp, const int* cell_start, const int* cell_items,
+                       double rc2, int* count, int* err, hipStream_t s) {
   if (n > 0)
-    k_edges<false><<<nblk(n, 128), 128, 0, s>>>(n, pos_ext, frac_ext, g, cell_start, cell_items, rc2,
-                                                 count, err, nullptr, nullptr, nullptr);
+    k_edges<false><<<nblk(n, 128), 128, 0, s>>>(n, pos_ext, frac_ext, sid, sp, cell_start,
+                                                 cell_items, rc2, count, err, nullptr, nullptr,
+                                                 nullptr);
 }
-void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, BinGrid g,
-                      const int* cell_start, const int* cell_items, double rc2,
-                      const int* row_ptr, int* src, int* recv, hipStream_t s) {
+void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, const int* sid,
+                      const StructParams* sp, const int* cell_start, const int* cell_items,
+                      double rc2, const int* row_ptr, int* src, int* recv, hipStream_t s) {
   if (n > 0)
-    k_edges<true><<<nblk(n, 128), 128, 0, s>>>(n, pos_ext, frac_ext, g, cell_start, cell_items, rc2,
-                                               nullptr, nullptr, row_ptr, src, recv);
+    k_edges<true><<<nblk(n, 128), 128, 0, s>>>(n, pos_ext, frac_ext, sid, sp, cell_start,
+                                                cell_items, rc2, nullptr, nullptr, row_ptr, src,
+                                                recv);
 }
 
 }  // namespace sn

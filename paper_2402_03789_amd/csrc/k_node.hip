@@ -18,6 +18,7 @@ namespace sn {
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+
 template <typename T>
 __global__ void k_embed(int rows, const int* __restrict__ spec, const T* __restrict__ Wemb, int C0,
                         T* __restrict__ h, int ldh) {
@@ -196,19 +197,37 @@ __global__ void k_forces(int n_local, const int* __restrict__ row_ptr, const int
 
 constexpr int kRedThreads = 256;
 
-// per-block sums of -d_e (x) g_e  (row-major 3x3)
-__global__ void k_virial_partial(int64_t E, const int* __restrict__ recv, const int* __restrict__ src,
-                                 const double* __restrict__ pos_ext, const double* __restrict__ g,
-                                 double* __restrict__ partial) {
+// Per-structure segmented sums in fixed order: one block per chunk (structure, begin,
+// end) reduces its items with a tree in shared memory; k_seg_finalize adds the chunks of
+// every structure in chunk order.
+__global__ void k_seg_energy(const int* __restrict__ chunks, const double* __restrict__ atom_e,
+                             double* __restrict__ partial) {
+  __shared__ double s[kRedThreads];
+  const int a = chunks[3 * blockIdx.x + 1], b = chunks[3 * blockIdx.x + 2];
+  double v = 0;
+  for (int i = a + threadIdx.x; i < b; i += blockDim.x) v += atom_e[i];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+// -d_e (x) g_e summed over the chunk's edges (row-major 3x3)
+__global__ void k_seg_virial(const int* __restrict__ chunks, const int* __restrict__ recv,
+                             const int* __restrict__ src, const double* __restrict__ pos_ext,
+                             const double* __restrict__ g, double* __restrict__ partial) {
   __shared__ double s[kRedThreads][9];
+  const int a = chunks[3 * blockIdx.x + 1], b = chunks[3 * blockIdx.x + 2];
   double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = a + threadIdx.x; e < b; e += blockDim.x) {
     int i = recv[e], j = src[e];
     double d[3];
-    for (int a = 0; a < 3; ++a) d[a] = pos_ext[3 * j + a] - pos_ext[3 * i + a];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) w[a * 3 + b] -= d[a] * g[3 * e + b];
+    for (int q = 0; q < 3; ++q) d[q] = pos_ext[3 * j + q] - pos_ext[3 * i + q];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) w[p * 3 + q] -= d[p] * g[3 * e + q];
   }
   for (int q = 0; q < 9; ++q) s[threadIdx.x][q] = w[q];
   __syncthreads();
@@ -221,27 +240,14 @@ __global__ void k_virial_partial(int64_t E, const int* __restrict__ recv, const 
     for (int q = 0; q < 9; ++q) partial[blockIdx.x * 9 + q] = s[0][q];
 }
 
-__global__ void k_energy_partial(int n, const double* __restrict__ atom_e, double* __restrict__ partial) {
-  __shared__ double s[kRedThreads];
+__global__ void k_seg_finalize(int B, const int* __restrict__ first, const double* __restrict__ partial,
+                               int width, double* __restrict__ out, double scale) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B * width) return;
+  int b = idx / width, q = idx % width;
   double v = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    v += atom_e[i];
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < (unsigned)off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
-}
-
-__global__ void k_sum_partials(int nblocks, int width, const double* __restrict__ partial,
-                               double* __restrict__ out, double scale) {
-  int q = threadIdx.x;
-  if (q >= width) return;
-  double s = 0;
-  for (int b = 0; b < nblocks; ++b) s += partial[b * width + q];
-  out[q] = scale * s;
+  for (int c = first[b]; c < first[b + 1]; ++c) v += partial[c * width + q];
+  out[idx] = scale * v;
 }
 
 __global__ void k_unpermute(int n, const int* __restrict__ order, const double* __restrict__ in_rows,
@@ -252,13 +258,70 @@ __global__ void k_unpermute(int n, const int* __restrict__ order, const double* 
   for (int a = 0; a < width; ++a) out_rows[(int64_t)o * width + a] = scale * in_rows[(int64_t)k * width + a];
 }
 
-// ------------------------------------------------------------------ launchers
-int partial_blocks(int64_t n) {
-  int64_t b = (n + kRedThreads - 1) / kRedThreads;
-  if (b > 1024) b = 1024;
-  if (b < 1) b = 1;
-  return (int)b;
+// Positions of a kept graph after the atoms moved: local rows in cell order from the
+// caller's positions plus the lattice translation applied when the graph was built
+// (wrap_off), ghost rows = owner row + shift . H.
+__global__ void k_refresh_positions(int n, const int* __restrict__ order,
+                                    const double* __restrict__ pos, const double* __restrict__ wrap_off,
+                                    double* __restrict__ pos_ext) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = order[k];
+  for (int a = 0; a < 3; ++a) pos_ext[3 * k + a] = pos[3 * o + a] + wrap_off[3 * k + a];
 }
+__global__ void k_refresh_ghosts(int n, int n_ghost, const int* __restrict__ owner,
+                                 const int* __restrict__ shift, const int* __restrict__ sid,
+                                 const StructParams* __restrict__ sp, double* __restrict__ pos_ext) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_ghost) return;
+  const int o = owner[g];
+  const double* H = sp[sid[n + g]].H;
+  const int sx = shift[3 * g], sy = shift[3 * g + 1], sz = shift[3 * g + 2];
+  for (int a = 0; a < 3; ++a)
+    pos_ext[3 * (int64_t)(n + g) + a] = pos_ext[3 * o + a] + sx * H[a] + sy * H[3 + a] + sz * H[6 + a];
+}
+
+// wrap_off[k] = wrapped - original position of local row k (a lattice translation)
+__global__ void k_wrap_offsets(int n, const int* __restrict__ order, const double* __restrict__ pos,
+                               const double* __restrict__ pos_ext, double* __restrict__ wrap_off) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = order[k];
+  for (int a = 0; a < 3; ++a) wrap_off[3 * k + a] = pos_ext[3 * k + a] - pos[3 * o + a];
+}
+
+// Velocity Verlet halves (harness of the molecular-dynamics workload):
+// stage 0: v += dt/2 a, x += dt v;  stage 1: v += dt/2 a, with a = F * inv_mass.
+__global__ void k_verlet(int n, double* __restrict__ pos, double* __restrict__ vel,
+                         const double* __restrict__ F, const double* __restrict__ inv_mass,
+                         double dt, int stage) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int a = 0; a < 3; ++a) {
+    double v = vel[3 * i + a] + 0.5 * dt * F[3 * i + a] * inv_mass[i];
+    vel[3 * i + a] = v;
+    if (stage == 0) pos[3 * i + a] += dt * v;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+void launch_refresh_positions(int n, int n_ghost, const int* order, const double* pos,
+                              const double* wrap_off, const int* owner, const int* shift,
+                              const int* sid_ext, const StructParams* sp, double* pos_ext,
+                              hipStream_t s) {
+  if (n > 0) k_refresh_positions<<<nblk(n, 256), 256, 0, s>>>(n, order, pos, wrap_off, pos_ext);
+  if (n_ghost > 0)
+    k_refresh_ghosts<<<nblk(n_ghost, 256), 256, 0, s>>>(n, n_ghost, owner, shift, sid_ext, sp, pos_ext);
+}
+void launch_wrap_offsets(int n, const int* order, const double* pos, const double* pos_ext,
+                         double* wrap_off, hipStream_t s) {
+  if (n > 0) k_wrap_offsets<<<nblk(n, 256), 256, 0, s>>>(n, order, pos, pos_ext, wrap_off);
+}
+void launch_verlet(int n, double* pos, double* vel, const double* F, const double* inv_mass,
+                   double dt, int stage, hipStream_t s) {
+  if (n > 0) k_verlet<<<nblk(n, 256), 256, 0, s>>>(n, pos, vel, F, inv_mass, dt, stage);
+}
+
 
 template <typename T>
 void launch_embed(int rows, const int* spec, const T* Wemb, int C0, T* h, int ldh, hipStream_t s) {
@@ -306,16 +369,17 @@ void launch_forces(int n_local, const int* row_ptr, const int* sptr, const int* 
                    const double* g, double* F, hipStream_t s) {
   if (n_local > 0) k_forces<<<nblk(n_local, 128), 128, 0, s>>>(n_local, row_ptr, sptr, sidx, gptr, g, F);
 }
-void launch_virial_partial(int64_t E, const int* recv, const int* src, const double* pos_ext,
-                           const double* g, double* partial, int nblocks, hipStream_t s) {
-  k_virial_partial<<<nblocks, kRedThreads, 0, s>>>(E, recv, src, pos_ext, g, partial);
+void launch_seg_energy(int nchunks, const int* chunks, const double* atom_e, double* partial,
+                       hipStream_t s) {
+  if (nchunks > 0) k_seg_energy<<<nchunks, kRedThreads, 0, s>>>(chunks, atom_e, partial);
 }
-void launch_energy_partial(int n, const double* atom_e, double* partial, int nblocks, hipStream_t s) {
-  k_energy_partial<<<nblocks, kRedThreads, 0, s>>>(n, atom_e, partial);
+void launch_seg_virial(int nchunks, const int* chunks, const int* recv, const int* src,
+                       const double* pos_ext, const double* g, double* partial, hipStream_t s) {
+  if (nchunks > 0) k_seg_virial<<<nchunks, kRedThreads, 0, s>>>(chunks, recv, src, pos_ext, g, partial);
 }
-void launch_sum_partials(int nblocks, int width, const double* partial, double* out, double scale,
-                         hipStream_t s) {
-  k_sum_partials<<<1, 64, 0, s>>>(nblocks, width, partial, out, scale);
+void launch_seg_finalize(int B, const int* first, const double* partial, int width, double* out,
+                         double scale, hipStream_t s) {
+  if (B > 0) k_seg_finalize<<<nblk((int64_t)B * width, 128), 128, 0, s>>>(B, first, partial, width, out, scale);
 }
 void launch_unpermute(int n, const int* order, const double* in_rows, int width, double* out_rows,
                       double scale, hipStream_t s) {

@@ -17,26 +17,37 @@ struct BinGrid {
 size_t scan_tmp_ints(int64_t n);
 void scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
 
-void launch_wrap_bin(int n, const double* pos, const double* H, const double* Hinv, BinGrid g,
-                     double* posw, double* frac, int* key, int* err, hipStream_t s);
+// Per-structure geometry of a packed graph.
+struct StructParams {
+  double H[9], Hinv[9];  // cell (rows a1 a2 a3) and its inverse
+  BinGrid g;
+  int bin_base;          // first global bin key of this structure
+  int pad;
+};
+
+void launch_wrap_bin(int n, const double* pos, const int* sid, const StructParams* sp, double* posw,
+                     double* frac, int* key, int* err, hipStream_t s);
 void launch_count_keys(int n, const int* key, int* count, hipStream_t s);
 void launch_scatter_keys(int n, const int* key, const int* start, int* cursor, int* items,
                          hipStream_t s);
 void launch_sort_segments(int nseg, const int* start, int* items, hipStream_t s);
 void launch_gather_local(int n, const int* order, const double* posw, const double* frac,
-                         const int* spec_orig, double* pos_ext, double* frac_ext, int* spec_ext,
-                         hipStream_t s);
-void launch_ghost_count(int n, const double* frac, BinGrid g, int* count, hipStream_t s);
-void launch_ghost_fill(int n, const double* frac, const double* pos, const int* spec,
-                       const double* H, BinGrid g, const int* gptr, int* owner, int* shift,
+                         const int* spec_orig, const int* sid_orig, double* pos_ext,
+                         double* frac_ext, int* spec_ext, int* sid_ext, hipStream_t s);
+void launch_ghost_count(int n, const double* frac, const int* sid, const StructParams* sp,
+                        int* count, hipStream_t s);
+// sid: structure id per extended row (locals on input; ghost rows filled here)
+void launch_ghost_fill(int n, const double* frac, const double* pos, const int* spec, int* sid,
+                       const StructParams* sp, const int* gptr, int* owner, int* shift,
                        double* pos_ext, double* frac_ext, int* spec_ext, hipStream_t s);
-void launch_bin_keys(int n, const double* frac, BinGrid g, int* key, hipStream_t s);
-void launch_edge_count(int n, const double* pos_ext, const double* frac_ext, BinGrid g,
-                       const int* cell_start, const int* cell_items, double rc2, int* count,
-                       int* err, hipStream_t s);
-void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, BinGrid g,
-                      const int* cell_start, const int* cell_items, double rc2,
-                      const int* row_ptr, int* src, int* recv, hipStream_t s);
+void launch_bin_keys(int n, const double* frac, const int* sid, const StructParams* sp, int* key,
+                     hipStream_t s);
+void launch_edge_count(int n, const double* pos_ext, const double* frac_ext, const int* sid,
+                       const StructParams* sp, const int* cell_start, const int* cell_items,
+                       double rc2, int* count, int* err, hipStream_t s);
+void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, const int* sid,
+                      const StructParams* sp, const int* cell_start, const int* cell_items,
+                      double rc2, const int* row_ptr, int* src, int* recv, hipStream_t s);
 
 // Reverse-edge map and undirected pairs: rev[e] (-1 if none), pidx[e] (pair of each edge),
 // pe1[p] (canonical edge of pair p, the lower id) and pe2[p] (its reverse or -1).  The
@@ -156,15 +167,29 @@ void launch_dY_reduce(int64_t E, int n_tasks, int NY, const T* part, T* dY, bool
                       hipStream_t s);
 void launch_forces(int n_local, const int* row_ptr, const int* sptr, const int* sidx,
                    const int* gptr, const double* g, double* F, hipStream_t s);
-void launch_virial_partial(int64_t E, const int* recv, const int* src, const double* pos_ext,
-                           const double* g, double* partial, int nblocks, hipStream_t s);
-void launch_sum_partials(int nblocks, int width, const double* partial, double* out,
+// Per-structure sums: chunks holds (structure, begin, end) triples; first[b]..first[b+1]
+// are structure b's chunks.  Energy sums atom energies; virial sums -d_e (x) g_e over edges.
+void launch_seg_energy(int nchunks, const int* chunks, const double* atom_e, double* partial,
+                       hipStream_t s);
+void launch_seg_virial(int nchunks, const int* chunks, const int* recv, const int* src,
+                       const double* pos_ext, const double* g, double* partial, hipStream_t s);
+void launch_seg_finalize(int B, const int* first, const double* partial, int width, double* out,
                          double scale, hipStream_t s);
-void launch_energy_partial(int n, const double* atom_e, double* partial, int nblocks,
-                           hipStream_t s);
 void launch_unpermute(int n, const int* order, const double* in_rows, int width,
                       double* out_rows, double scale, hipStream_t s);
 
-int partial_blocks(int64_t n);
+// Kept graph, moved atoms: local rows from pos[order[k]] + wrap_off[k], ghost rows from
+// owner row + shift . H.  wrap_off is recorded at build time by launch_wrap_offsets.
+void launch_refresh_positions(int n, int n_ghost, const int* order, const double* pos,
+                              const double* wrap_off, const int* owner, const int* shift,
+                              const int* sid_ext, const StructParams* sp, double* pos_ext,
+                              hipStream_t s);
+void launch_wrap_offsets(int n, const int* order, const double* pos, const double* pos_ext,
+                         double* wrap_off, hipStream_t s);
+// Velocity-Verlet half step (stage 0: kick + drift, stage 1: kick); a = F * inv_mass.
+void launch_verlet(int n, double* pos, double* vel, const double* F, const double* inv_mass,
+                   double dt, int stage, hipStream_t s);
+
+
 
 }  // namespace sn

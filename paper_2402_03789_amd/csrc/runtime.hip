@@ -289,9 +289,17 @@ struct sn_ctx {
   // graph state
   int N = 0, G = 0;
   int64_t E = 0, NP = 0;  // directed edges, undirected pairs
-  BinGrid grid{};
-  double H[9], Hinv[9];
+  // structures of the packed graph
+  int B = 0;
+  std::vector<int64_t> atom_off;   // B + 1 atom offsets (input order = packed local order)
+  std::vector<int64_t> edge_off;   // B + 1 edge offsets (edges are receiver-contiguous)
+  std::vector<StructParams> sp;    // per-structure geometry (host copy)
+  int nbins = 0;
+  int n_echunk = 0, n_vchunk = 0;
   bool pending = false;
+  bool reuse = false;       // keep the graph of the previous call when n and the cell match
+  bool have_graph = false;
+  std::vector<double> graph_cells;
   // timing
   std::vector<std::pair<std::string, hipEvent_t>> marks;
   std::vector<std::pair<std::string, double>> timings;
@@ -393,14 +401,39 @@ void inv3(const double* H, double* Hi, double* det_out) {
   Hi[8] = (H[0] * H[4] - H[1] * H[3]) * id;
 }
 
-void setup_cell(sn_ctx* c, const double* cell) {
+// Chunks of a per-structure segmented sum: (structure, begin, end), at most `len` items each,
+// plus the first chunk of every structure (B + 1 entries).
+struct SegChunks {
+  std::vector<int> chunk;  // 3 ints per chunk
+  std::vector<int> first;  // B + 1
+};
+SegChunks make_chunks(const std::vector<int64_t>& off, int64_t len) {
+  SegChunks sc;
+  const int B = (int)off.size() - 1;
+  for (int b = 0; b < B; ++b) {
+    sc.first.push_back((int)(sc.chunk.size() / 3));
+    int64_t a = off[b];
+    do {
+      const int64_t e = std::min(off[b + 1], a + len);
+      sc.chunk.push_back(b);
+      sc.chunk.push_back((int)a);
+      sc.chunk.push_back((int)e);
+      a = e;
+    } while (a < off[b + 1]);
+  }
+  sc.first.push_back((int)(sc.chunk.size() / 3));
+  return sc;
+}
+
+StructParams make_struct(const double* cell, double reach) {
+  StructParams P{};
   for (int i = 0; i < 9; ++i) {
     if (!std::isfinite(cell[i])) throw ArgError("cell has non-finite entries");
-    c->H[i] = cell[i];
+    P.H[i] = cell[i];
   }
   double det;
-  inv3(c->H, c->Hinv, &det);
-  const double* a = c->H;
+  inv3(P.H, P.Hinv, &det);
+  const double* a = P.H;
   double cr[3][3];
   for (int k = 0; k < 3; ++k) {
     const double* u = a + 3 * ((k + 1) % 3);
@@ -411,9 +444,7 @@ void setup_cell(sn_ctx* c, const double* cell) {
   }
   const double vol = std::fabs(det);
   if (!(vol > 1e-6)) throw ArgError("singular cell");
-  const double reach = c->m->rc + c->skin;
-  BinGrid& g = c->grid;
-  int64_t nbins = 1;
+  BinGrid& g = P.g;
   for (int k = 0; k < 3; ++k) {
     double w = vol / std::sqrt(cr[k][0] * cr[k][0] + cr[k][1] * cr[k][1] + cr[k][2] * cr[k][2]);
     g.delta[k] = reach / w;
@@ -421,24 +452,70 @@ void setup_cell(sn_ctx* c, const double* cell) {
     g.bw[k] = std::max(g.delta[k], span / 256.0);
     g.nb[k] = std::max(1, (int)std::ceil(span / g.bw[k] - 1e-12));
     g.nimg[k] = (int)std::ceil(g.delta[k]) + 1;
-    nbins *= g.nb[k];
   }
-  if (nbins > (1 << 24)) throw UnsupportedError("bin grid too large");
+  return P;
+}
+
+// Geometry of B structures: cells[b*9 .. b*9+8]; offsets[b] .. offsets[b+1] are the atoms
+// of structure b.  Uploads the per-structure table and the structure id of every atom.
+void setup_cells(sn_ctx* c, int B, const int64_t* offsets, const double* cells) {
+  if (B < 1) throw ArgError("no structures");
+  c->B = B;
+  c->atom_off.assign(offsets, offsets + B + 1);
+  c->sp.resize(B);
+  int64_t bins = 0;
+  const double reach = c->m->rc + c->skin;
+  for (int b = 0; b < B; ++b) {
+    if (offsets[b + 1] <= offsets[b]) throw ArgError("empty structure in batch");
+    c->sp[b] = make_struct(cells + 9 * b, reach);
+    c->sp[b].bin_base = (int)bins;
+    bins += (int64_t)c->sp[b].g.nb[0] * c->sp[b].g.nb[1] * c->sp[b].g.nb[2];
+    if (bins > (1 << 26)) throw UnsupportedError("bin grid too large");
+  }
+  c->nbins = (int)bins;
+  const int64_t N = offsets[B];
+  StructParams* dsp = c->get<StructParams>("struct_params", B);
+  HIPCHK(hipMemcpyAsync(dsp, c->sp.data(), sizeof(StructParams) * B, hipMemcpyHostToDevice,
+                        c->stream));
+  std::vector<int> sid((size_t)N);
+  for (int b = 0; b < B; ++b)
+    for (int64_t i = offsets[b]; i < offsets[b + 1]; ++i) sid[i] = b;
+  int* dsid = c->get<int>("sid_orig", N);
+  HIPCHK(hipMemcpyAsync(dsid, sid.data(), sizeof(int) * N, hipMemcpyHostToDevice, c->stream));
+  std::vector<int> offs(offsets, offsets + B + 1);
+  int* doff = c->get<int>("struct_atom_off", B + 1);
+  HIPCHK(hipMemcpyAsync(doff, offs.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, c->stream));
+  SegChunks ec = make_chunks(c->atom_off, 2048);
+  c->n_echunk = (int)(ec.chunk.size() / 3);
+  int* dch = c->get<int>("echunks", 3 * c->n_echunk);
+  int* dfi = c->get<int>("efirst", B + 1);
+  HIPCHK(hipMemcpyAsync(dch, ec.chunk.data(), sizeof(int) * ec.chunk.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(dfi, ec.first.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, c->stream));
+  // the pageable sources above must stay valid until the copies ran
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+__global__ void k_gather_offsets(int B, const int* __restrict__ row_ptr, const int* __restrict__ aoff,
+                                 int* __restrict__ eoff) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= B) eoff[b] = row_ptr[aoff[b]];
 }
 
 template <typename T>
 void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   hipStream_t s = c->stream;
-  const BinGrid g = c->grid;
-  const int nbins = g.nb[0] * g.nb[1] * g.nb[2];
+  const int nbins = c->nbins;
+  const StructParams* sp = c->get<StructParams>("struct_params", c->B);
+  const int* sid_orig = c->get<int>("sid_orig", N);
   c->N = N;
   int* err = c->get<int>("err", 4);
   zero(err, 16, s);
   double* posw = c->get<double>("posw", 3 * N);
   double* fracw = c->get<double>("fracw", 3 * N);
   int* key = c->get<int>("key", N);
-  launch_wrap_bin(N, d_pos, c->H, c->Hinv, g, posw, fracw, key, err, s);
-  // order local atoms by bin (cell order) for locality of neighbour gathers
+  launch_wrap_bin(N, d_pos, sid_orig, sp, posw, fracw, key, err, s);
+  // order local atoms by bin (cell order within each structure) for gather locality
   int* cnt = c->get<int>("bin_count", nbins + 1);
   int* start = c->get<int>("bin_start", nbins + 1);
   int* cursor = c->get<int>("bin_cursor", nbins + 1);
@@ -457,8 +534,9 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   double* fr_loc = c->get<double>("frac_local", 3 * N);
   double* pos_loc = c->get<double>("pos_local", 3 * N);
   int* spec_loc = c->get<int>("spec_local", N);
-  launch_gather_local(N, order, posw, fracw, d_spec, pos_loc, fr_loc, spec_loc, s);
-  launch_ghost_count(N, fr_loc, g, gcount, s);
+  int* sid_loc = c->get<int>("sid_local", N);
+  launch_gather_local(N, order, posw, fracw, d_spec, sid_orig, pos_loc, fr_loc, spec_loc, sid_loc, s);
+  launch_ghost_count(N, fr_loc, sid_loc, sp, gcount, s);
   scan_exclusive(gcount, gptr, N, tmp, s);
   int hG[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(&hG[0], gptr + N, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -471,17 +549,19 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   double* pos_ext = c->get<double>("pos_ext", 3 * (int64_t)NE);
   double* frac_ext = c->get<double>("frac_ext", 3 * (int64_t)NE);
   int* spec_ext = c->get<int>("spec_ext", NE);
+  int* sid_ext = c->get<int>("sid_ext", NE);
   int* owner = c->get<int>("ghost_owner", G);
   int* shift = c->get<int>("ghost_shift", 3 * (int64_t)G);
   HIPCHK(hipMemcpyAsync(pos_ext, pos_loc, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(frac_ext, fr_loc, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(spec_ext, spec_loc, sizeof(int) * N, hipMemcpyDeviceToDevice, s));
-  launch_ghost_fill(N, fr_loc, pos_loc, spec_loc, c->H, g, gptr, owner, shift, pos_ext, frac_ext,
-                    spec_ext, s);
+  HIPCHK(hipMemcpyAsync(sid_ext, sid_loc, sizeof(int) * N, hipMemcpyDeviceToDevice, s));
+  launch_ghost_fill(N, fr_loc, pos_loc, spec_loc, sid_ext, sp, gptr, owner, shift, pos_ext,
+                    frac_ext, spec_ext, s);
   // bin every extended point
   int* ekey = c->get<int>("ext_key", NE);
   int* cell_items = c->get<int>("cell_items", NE);
-  launch_bin_keys(NE, frac_ext, g, ekey, s);
+  launch_bin_keys(NE, frac_ext, sid_ext, sp, ekey, s);
   zero(cnt, sizeof(int) * nbins, s);
   zero(cursor, sizeof(int) * nbins, s);
   launch_count_keys(NE, ekey, cnt, s);
@@ -489,21 +569,28 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   launch_scatter_keys(NE, ekey, start, cursor, cell_items, s);
   launch_sort_segments(nbins, start, cell_items, s);
   // receiver CSR
-  const double rc2 = c->m->rc * c->m->rc;
+  // edges out to r_c + skin, so the list stays complete while atoms move < skin / 2
+  const double rc2 = (c->m->rc + c->skin) * (c->m->rc + c->skin);
   int* ecount = c->get<int>("edge_count", N + 1);
   int* row_ptr = c->get<int>("row_ptr", N + 1);
-  launch_edge_count(N, pos_ext, frac_ext, g, start, cell_items, rc2, ecount, err, s);
+  launch_edge_count(N, pos_ext, frac_ext, sid_ext, sp, start, cell_items, rc2, ecount, err, s);
   scan_exclusive(ecount, row_ptr, N, tmp, s);
-  int hE[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(&hE[0], row_ptr + N, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&hE[1], err, sizeof(int), hipMemcpyDeviceToHost, s));
+  // per-structure edge offsets (receivers of a structure are contiguous)
+  const int B = c->B;
+  int* eoff = c->get<int>("struct_edge_off", B + 1);
+  k_gather_offsets<<<(unsigned)((B + 1 + 255) / 256), 256, 0, s>>>(
+      B, row_ptr, c->get<int>("struct_atom_off", B + 1), eoff);
+  std::vector<int> hE((size_t)B + 2);
+  HIPCHK(hipMemcpyAsync(hE.data(), eoff, sizeof(int) * (B + 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hE[B + 1], err, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (hE[1] & 2) throw ArgError("two atoms at the same position (r = 0 pair)");
-  const int64_t E = hE[0];
+  if (hE[B + 1] & 2) throw ArgError("two atoms at the same position (r = 0 pair)");
+  c->edge_off.assign(hE.begin(), hE.begin() + B + 1);
+  const int64_t E = hE[B];
   c->E = E;
   int* src = c->get<int>("src", E);
   int* recv = c->get<int>("recv", E);
-  launch_edge_fill(N, pos_ext, frac_ext, g, start, cell_items, rc2, row_ptr, src, recv, s);
+  launch_edge_fill(N, pos_ext, frac_ext, sid_ext, sp, start, cell_items, rc2, row_ptr, src, recv, s);
   // sender CSR over extended rows (local and ghost senders)
   int* scount = c->get<int>("send_count", NE + 1);
   int* sptr = c->get<int>("send_ptr", NE + 1);
@@ -524,6 +611,12 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   int* pe1 = c->get<int>("pair_e1", E);
   int* pe2 = c->get<int>("pair_e2", E);
   launch_pairs(E, N, recv, src, row_ptr, owner, shift, rev, flag, fscan, tmp_e, pidx, pe1, pe2, s);
+  SegChunks vc = make_chunks(c->edge_off, 16384);
+  c->n_vchunk = (int)(vc.chunk.size() / 3);
+  int* dvc = c->get<int>("vchunks", 3 * c->n_vchunk);
+  int* dvf = c->get<int>("vfirst", B + 1);
+  HIPCHK(hipMemcpyAsync(dvc, vc.chunk.data(), sizeof(int) * vc.chunk.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dvf, vc.first.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, s));
   int hP = 0;
   HIPCHK(hipMemcpyAsync(&hP, fscan + E, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -656,10 +749,10 @@ struct Pipe {
     const int* spec_loc = c->get<int>("spec_local", N);
     launch_readout<double>(N, h, m->layers.back().hout.width, c->d_v, C0, m->sigma, c->d_shift,
                            spec_loc, ae, s);
-    int nbk = partial_blocks(N);
-    double* part = c->get<double>("partial_e", nbk);
-    launch_energy_partial(N, ae, part, nbk, s);
-    launch_sum_partials(nbk, 1, part, d_energy, 1.0, s);
+    // per-structure energies (eq 1): fixed-order segmented sums
+    double* part = c->get<double>("partial_e", c->n_echunk);
+    launch_seg_energy(c->n_echunk, c->get<int>("echunks", 3 * c->n_echunk), ae, part, s);
+    launch_seg_finalize(c->B, c->get<int>("efirst", c->B + 1), part, 1, d_energy, 1.0, s);
     if (d_atom_energy_orig) {
       const int* order = c->get<int>("order", N);
       launch_unpermute(N, order, ae, 1, d_atom_energy_orig, 1.0, s);
@@ -750,10 +843,10 @@ struct Pipe {
       launch_unpermute(N, order, F, 3, d_forces_orig, grad_scale, s);
     }
     if (d_virial) {
-      int nbk = partial_blocks(E);
-      double* part = c->get<double>("partial_w", 9 * (int64_t)nbk);
-      launch_virial_partial(E, recv, src, pos_ext, gE, part, nbk, s);
-      launch_sum_partials(nbk, 9, part, d_virial, grad_scale, s);
+      double* part = c->get<double>("partial_w", 9 * (int64_t)c->n_vchunk);
+      launch_seg_virial(c->n_vchunk, c->get<int>("vchunks", 3 * c->n_vchunk), recv, src, pos_ext,
+                        gE, part, s);
+      launch_seg_finalize(c->B, c->get<int>("vfirst", c->B + 1), part, 9, d_virial, grad_scale, s);
     }
     c->mark("end");
   }
@@ -805,14 +898,34 @@ int guarded(sn_ctx* c, F&& f) {
 }
 
 template <typename T>
-void forward_impl(sn_ctx* c, int64_t n, const double* d_pos, const int* d_spec, const double* cell,
-                  double* d_energy, double* d_atom_energy) {
+void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos, const int* d_spec,
+                  const double* cells, double* d_energy, double* d_atom_energy) {
+  const int64_t n = offsets[B];
   if (n <= 0 || n > (1 << 28)) throw ArgError("atom count out of range");
-  setup_cell(c, cell);
   c->marks.clear();
   c->event_next = 0;
   c->mark("graph");
-  build_graph<T>(c, (int)n, d_pos, d_spec);
+  const bool same = c->have_graph && c->B == B && c->N == n &&
+                    std::equal(offsets, offsets + B + 1, c->atom_off.begin()) &&
+                    std::memcmp(c->graph_cells.data(), cells, sizeof(double) * 9 * B) == 0;
+  if (c->reuse && same) {
+    // atoms moved less than skin/2 since the last build: refresh positions only
+    launch_refresh_positions(c->N, c->G, c->get<int>("order", c->N), d_pos,
+                             c->get<double>("wrap_off", 3 * (int64_t)c->N),
+                             c->get<int>("ghost_owner", c->G),
+                             c->get<int>("ghost_shift", 3 * (int64_t)c->G),
+                             c->get<int>("sid_ext", c->N + c->G),
+                             c->get<StructParams>("struct_params", c->B),
+                             c->get<double>("pos_ext", 3 * (int64_t)(c->N + c->G)), c->stream);
+  } else {
+    c->have_graph = false;
+    setup_cells(c, B, offsets, cells);
+    build_graph<T>(c, (int)n, d_pos, d_spec);
+    launch_wrap_offsets((int)n, c->get<int>("order", n), d_pos, c->get<double>("pos_ext", 3 * n),
+                        c->get<double>("wrap_off", 3 * n), c->stream);
+    c->graph_cells.assign(cells, cells + 9 * B);
+    c->have_graph = true;
+  }
   Pipe<T> p(c);
   p.forward(d_energy, d_atom_energy);
   c->pending = true;
@@ -944,7 +1057,7 @@ void sn_ctx_free(sn_ctx_t* ctx) {
 
 int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32_t* d_Z,
                       const double* cell, double* d_energy, double* d_atom_energy) {
-  if (!ctx || !d_pos || !d_Z || !cell || !d_energy) return SN_EINVAL;
+  if (!ctx || !d_pos || !d_Z || !cell || !d_energy || n <= 0) return SN_EINVAL;
   return guarded(ctx, [&] {
     // map atomic numbers to embedding rows on the host (validation before any launch)
     std::vector<int32_t> hz((size_t)n);
@@ -954,10 +1067,11 @@ int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32
     map_species(ctx->m, n, hz.data(), spec);
     int* d_spec = ctx->get<int>("spec_orig", n);
     HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
+    const int64_t off[2] = {0, n};
     if (ctx->precision == SN_FP64)
-      forward_impl<double>(ctx, n, d_pos, d_spec, cell, d_energy, d_atom_energy);
+      forward_impl<double>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
     else
-      forward_impl<float>(ctx, n, d_pos, d_spec, cell, d_energy, d_atom_energy);
+      forward_impl<float>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
   });
 }
 
@@ -981,14 +1095,14 @@ int sn_ctx_synchronize(sn_ctx_t* ctx) {
   });
 }
 
-int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, const double* cell,
-               const uint8_t* pbc, double* energy, double* atom_energy, double* forces,
-               double* virial) {
-  if (!ctx || !pos || !Z || !cell || !energy || n <= 0) return SN_EINVAL;
-  if (pbc && !(pbc[0] && pbc[1] && pbc[2])) {
-    ctx->err = "only fully periodic cells are supported";
-    return SN_EUNSUPPORTED;
-  }
+int sn_compute_batch(sn_ctx_t* ctx, int B, const int64_t* offsets, const double* pos,
+                     const int32_t* Z, const double* cells, double* energies,
+                     double* atom_energies, double* forces, double* virials) {
+  if (!ctx || B < 1 || !offsets || !pos || !Z || !cells || !energies) return SN_EINVAL;
+  if (offsets[0] != 0) return SN_EINVAL;
+  for (int b = 0; b < B; ++b)
+    if (offsets[b + 1] <= offsets[b]) return SN_EINVAL;
+  const int64_t n = offsets[B];
   return guarded(ctx, [&] {
     std::vector<int> spec;
     map_species(ctx->m, n, Z, spec);
@@ -997,31 +1111,44 @@ int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, co
     hipStream_t s = ctx->stream;
     double* d_pos = ctx->get<double>("in_pos", 3 * n);
     int* d_spec = ctx->get<int>("spec_orig", n);
-    double* d_out = ctx->get<double>("out_host_stage", 1 + 9 + n + 3 * n);
+    // staging for the results: B energies, B virials, n atom energies, n x 3 forces
+    double* d_out = ctx->get<double>("out_host_stage", 10 * (int64_t)B + 4 * n);
     HIPCHK(hipMemcpyAsync(d_pos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     double* d_e = d_out;
-    double* d_w = d_out + 1;
-    double* d_ae = d_out + 10;
-    double* d_f = d_out + 10 + n;
-    const bool need_bwd = forces || virial;
+    double* d_w = d_out + B;
+    double* d_ae = d_out + 10 * (int64_t)B;
+    double* d_f = d_ae + n;
+    const bool need_bwd = forces || virials;
     if (ctx->precision == SN_FP64) {
-      forward_impl<double>(ctx, n, d_pos, d_spec, cell, d_e, d_ae);
+      forward_impl<double>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
       if (need_bwd) backward_impl<double>(ctx, 1.0, d_f, d_w);
     } else {
-      forward_impl<float>(ctx, n, d_pos, d_spec, cell, d_e, d_ae);
+      forward_impl<float>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
       if (need_bwd) backward_impl<float>(ctx, 1.0, d_f, d_w);
     }
     ctx->pending = false;
-    std::vector<double> h((size_t)(10 + 4 * n));
+    std::vector<double> h((size_t)(10 * (int64_t)B + 4 * n));
     HIPCHK(hipMemcpyAsync(h.data(), d_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     collect_timings(ctx);
-    *energy = h[0];
-    if (virial) std::memcpy(virial, &h[1], 9 * sizeof(double));
-    if (atom_energy) std::memcpy(atom_energy, &h[10], n * sizeof(double));
-    if (forces) std::memcpy(forces, &h[10 + n], 3 * n * sizeof(double));
+    std::memcpy(energies, &h[0], B * sizeof(double));
+    if (virials) std::memcpy(virials, &h[B], 9 * (size_t)B * sizeof(double));
+    if (atom_energies) std::memcpy(atom_energies, &h[10 * (size_t)B], n * sizeof(double));
+    if (forces) std::memcpy(forces, &h[10 * (size_t)B + n], 3 * n * sizeof(double));
   });
+}
+
+int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, const double* cell,
+               const uint8_t* pbc, double* energy, double* atom_energy, double* forces,
+               double* virial) {
+  if (!ctx || !pos || !Z || !cell || !energy || n <= 0) return SN_EINVAL;
+  if (pbc && !(pbc[0] && pbc[1] && pbc[2])) {
+    ctx->err = "only fully periodic cells are supported";
+    return SN_EUNSUPPORTED;
+  }
+  const int64_t off[2] = {0, n};
+  return sn_compute_batch(ctx, 1, off, pos, Z, cell, energy, atom_energy, forces, virial);
 }
 
 int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, int64_t* n_edge) {
@@ -1030,6 +1157,21 @@ int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, i
   if (n_ghost) *n_ghost = ctx->G;
   if (n_edge) *n_edge = ctx->E;
   return SN_OK;
+}
+
+int sn_ctx_set_graph_reuse(sn_ctx_t* ctx, int reuse) {
+  if (!ctx) return SN_EINVAL;
+  ctx->reuse = reuse != 0;
+  return SN_OK;
+}
+
+int sn_md_verlet(sn_ctx_t* ctx, int64_t n, double* d_pos, double* d_vel, const double* d_forces,
+                 const double* d_inv_mass, double dt, int stage) {
+  if (!ctx || !d_pos || !d_vel || !d_forces || !d_inv_mass || n <= 0 || (stage != 0 && stage != 1))
+    return SN_EINVAL;
+  return guarded(ctx, [&] {
+    launch_verlet((int)n, d_pos, d_vel, d_forces, d_inv_mass, dt, stage, ctx->stream);
+  });
 }
 
 int sn_ctx_pair_count(const sn_ctx_t* ctx, int64_t* n_pairs) {

@@ -81,3 +81,13 @@ def test_wrap_into_cell():
     f = wrap(shifted, cell) @ np.linalg.inv(cell)
     assert f.min() >= 0 and f.max() < 1
     np.testing.assert_allclose(wrap(shifted, cell), wrap(pos, cell), atol=1e-12)
+
+
+def test_kdtree_path_matches_brute_force():
+    from oracle.graph import _kdtree_edges
+    s = sio2_box(400, seed=13)  # 1200 atoms: brute force is still quick
+    a = periodic_edges(s.pos, s.cell, 5.0)
+    b = _kdtree_edges(wrap(s.pos, s.cell), s.cell, 5.0)
+    c = periodic_edges(wrap(s.pos, s.cell), s.cell, 5.0)
+    assert _edge_set(*b) == _edge_set(*c)
+    assert len(a[0]) == len(b[0])
