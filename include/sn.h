@@ -46,11 +46,13 @@ extern "C" {
 
 /* ---- precision forms -------------------------------------------------------------- */
 #define SN_FP64 0  /* everything in float64 (reference-grade; for tests and finite differences) */
-#define SN_FP32 1  /* float32 storage and arithmetic; edge vectors from float64 positions;
+#define SN_FP32 1  /* per-edge work in float32 (basis, radial MLP, tensor product, edge
+                      gradients), edge vectors from float64 positions; the node-state chain
+                      (features, self-connection, gate, readout, node gradients) in float64;
                       energy and virial reductions in float64 */
-#define SN_BF16 2  /* radial MLP and channel-mixing linears with bfloat16 operands and float32
-                      accumulation on the matrix cores; tensor product in float32; float64
-                      energy and virial reductions */
+#define SN_BF16 2  /* as SN_FP32, but the radial MLP and the channel-mixing linears take
+                      bfloat16 operands with float32 accumulation on the matrix cores; tensor
+                      product in float32; float64 energy and virial reductions */
 
 typedef struct sn_model sn_model_t;
 typedef struct sn_ctx sn_ctx_t;
@@ -158,9 +160,65 @@ int sn_md_verlet(sn_ctx_t* ctx, int64_t n, double* d_pos, double* d_vel, const d
 /* Wait for every queued operation of the context. */
 int sn_ctx_synchronize(sn_ctx_t* ctx);
 
+/* ---- serving: continuous batching of structures of uneven size --------------------
+ * A server runs n_streams worker threads on one device, each with its own HIP stream and
+ * context (sharing the model).  Requests enter a FIFO queue; a free worker packs requests
+ * from the head of the queue into one graph while the batch stays within
+ * max_batch_atoms, max_batch_structures and its slice (hbm_budget / n_streams; 0 = no
+ * cap) of the HBM budget, judged from the device bytes per atom measured on earlier
+ * batches, and evaluates energy, forces and virial of every structure in the batch.
+ * Requests that arrive while batches run join the next batch of the first worker to free
+ * up, so the batches of different workers overlap on the device.  A batch that exceeds
+ * the budget anyway is split and retried; a structure that cannot fit alone completes with
+ * SN_ENOMEM.  Each structure's result is that of evaluating it alone (sn_compute_batch).
+ *
+ * Request buffers: pos, Z, cell are copied at submit.  atom_energy[n] and forces[n*3]
+ * (either may be NULL) are written by the library and must stay valid until the request's
+ * result has been returned by sn_server_poll.  Times are seconds since server creation. */
+typedef struct sn_server sn_server_t;
+
+typedef struct sn_request {
+  int64_t n;              /* atoms */
+  const double* pos;      /* n x 3, angstrom */
+  const int32_t* Z;       /* n atomic numbers */
+  const double* cell;     /* 3 x 3, rows a1 a2 a3 (periodic in all directions) */
+  double* atom_energy;    /* out: n, eV (may be NULL) */
+  double* forces;         /* out: n x 3, eV/angstrom (may be NULL) */
+} sn_request_t;
+
+typedef struct sn_result {
+  uint64_t ticket;        /* as returned by sn_server_submit */
+  int status;             /* SN_OK or the error of the batch the request ran in */
+  int batch_structures;   /* structures packed into the request's batch */
+  int64_t batch_atoms;    /* atoms of that batch */
+  double energy;          /* eV */
+  double virial[9];       /* eV */
+  double t_submit, t_start, t_done;  /* submit, batch launch and completion times */
+} sn_result_t;
+
+int sn_server_create(const sn_model_t* model, int device, int n_streams, int precision,
+                     size_t hbm_budget, int64_t max_batch_atoms, int max_batch_structures,
+                     sn_server_t** out);
+/* Queue one structure; *ticket identifies its result.  SN_EHIP when no worker is alive. */
+int sn_server_submit(sn_server_t* server, const sn_request_t* request, uint64_t* ticket);
+/* Move up to max finished results into out[]; *n_out receives the count.  Waits up to
+ * timeout_ms for the first one (0: do not wait, negative: wait without limit). */
+int sn_server_poll(sn_server_t* server, sn_result_t* out, int max, int timeout_ms, int* n_out);
+/* Requests waiting in the queue and requests inside running batches. */
+int sn_server_pending(sn_server_t* server, int64_t* queued, int64_t* running);
+/* Stop the workers after their current batches and release everything; requests still
+ * queued are dropped without a result. */
+void sn_server_free(sn_server_t* server);
+
 /* ---- inspection (tests and benchmarks) ---------------------------------------------
  * After a compute/forward, the graph sizes: local atoms, ghosts, directed edges. */
 int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, int64_t* n_edge);
+
+/* Undirected edge pairs of the last graph (the radial MLP runs once per pair). */
+int sn_ctx_pair_count(const sn_ctx_t* ctx, int64_t* n_pairs);
+
+/* Device bytes currently held by the context's workspace and weights. */
+int sn_ctx_memory(const sn_ctx_t* ctx, size_t* bytes);
 
 /* The last graph in the caller's atom order: recv[E], send_owner[E] (owner atom of
  * the sender), shift[E*3] (integer image shift of the sender), and ghost_owner[G],

@@ -153,6 +153,11 @@ class Context:
         check(lib().sn_md_verlet(self._h, pos.shape[0], ptr(pos), ptr(vel), ptr(forces),
                                  ptr(inv_mass), float(dt), int(stage)), self._h)
 
+    def memory(self) -> int:
+        v = C.c_size_t()
+        check(lib().sn_ctx_memory(self._h, C.byref(v)))
+        return v.value
+
     def n_pairs(self) -> int:
         v = C.c_int64()
         check(lib().sn_ctx_pair_count(self._h, C.byref(v)))

@@ -34,6 +34,21 @@ class ModelInfo(C.Structure):
     ]
 
 
+class Request(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("pos", C.c_void_p), ("Z", C.c_void_p), ("cell", C.c_void_p),
+        ("atom_energy", C.c_void_p), ("forces", C.c_void_p),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("ticket", C.c_uint64), ("status", C.c_int), ("batch_structures", C.c_int),
+        ("batch_atoms", C.c_int64), ("energy", C.c_double), ("virial", C.c_double * 9),
+        ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+    ]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -63,6 +78,14 @@ _SIGS = {
                                C.c_void_p, C.c_double, C.c_int]),
     "sn_ctx_graph": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
+    "sn_ctx_memory": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "sn_server_create": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_size_t, C.c_int64,
+                                   C.c_int, C.POINTER(C.c_void_p)]),
+    "sn_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "sn_server_poll": (C.c_int, [C.c_void_p, C.POINTER(Result), C.c_int, C.c_int,
+                                 C.POINTER(C.c_int)]),
+    "sn_server_pending": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "sn_server_free": (None, [C.c_void_p]),
     "sn_ctx_timings": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.c_void_p,
                                  C.POINTER(C.c_int)]),
 }
@@ -88,7 +111,7 @@ def lib():
 
 def check(status, ctx=None):
     if status != SN_OK:
-        msg = lib().sn_last_error(ctx).decode() if True else ""
+        msg = lib().sn_last_error(ctx).decode()
         raise SNError(status, f"{lib().sn_strerror(status).decode()}: {msg}")
 
 

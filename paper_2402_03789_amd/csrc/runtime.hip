@@ -284,6 +284,7 @@ struct sn_ctx {
   // device weights (float64 copy and float32 copy)
   void* d_w = nullptr;
   void* d_w32 = nullptr;
+  size_t weight_bytes = 0;
   double* d_v = nullptr;
   double* d_shift = nullptr;
   // graph state
@@ -382,6 +383,8 @@ void upload_weights(sn_ctx* c) {
   HIPCHK(hipMalloc(&c->d_shift, m->shift.size() * sizeof(double)));
   HIPCHK(hipMemcpy(c->d_shift, m->shift.data(), m->shift.size() * sizeof(double),
                    hipMemcpyHostToDevice));
+  c->weight_bytes = m->flat.size() * (sizeof(double) + sizeof(float)) +
+                    (m->readout_v.size() + m->shift.size()) * sizeof(double);
 }
 
 // ------------------------------------------------------------------ graph build
@@ -852,6 +855,21 @@ struct Pipe {
   }
 };
 
+// Free every workspace buffer (not the weights); the graph and any pending forward are
+// dropped.  False when the device reported an error meanwhile (the context is then dead).
+bool release_workspace(sn_ctx* c) {
+  bool ok = hipStreamSynchronize(c->stream) == hipSuccess;
+  for (auto& kv : c->bufs)
+    if (kv.second.p && hipFree(kv.second.p) != hipSuccess) ok = false;
+  c->bufs.clear();
+  c->used = 0;
+  c->have_graph = false;
+  c->pending = false;
+  c->marks.clear();
+  if (!ok) c->dead = true;
+  return ok;
+}
+
 void collect_timings(sn_ctx* c) {
   c->timings.clear();
   if (c->marks.size() < 2) return;
@@ -880,7 +898,11 @@ int guarded(sn_ctx* c, F&& f) {
     if (c) c->err = e.what();
     return SN_EINVAL;
   } catch (const MemError& e) {
-    if (c) c->err = e.what();
+    if (c) {
+      c->err = e.what();
+      // a partly grown workspace would make every later, smaller request fail as well
+      if (!release_workspace(c)) return SN_EHIP;
+    }
     return SN_ENOMEM;
   } catch (const UnsupportedError& e) {
     if (c) c->err = e.what();
@@ -1172,6 +1194,12 @@ int sn_md_verlet(sn_ctx_t* ctx, int64_t n, double* d_pos, double* d_vel, const d
   return guarded(ctx, [&] {
     launch_verlet((int)n, d_pos, d_vel, d_forces, d_inv_mass, dt, stage, ctx->stream);
   });
+}
+
+int sn_ctx_memory(const sn_ctx_t* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return SN_EINVAL;
+  *bytes = ctx->used + ctx->weight_bytes;
+  return SN_OK;
 }
 
 int sn_ctx_pair_count(const sn_ctx_t* ctx, int64_t* n_pairs) {
