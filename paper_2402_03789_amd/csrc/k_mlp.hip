@@ -262,6 +262,22 @@ __device__ inline void fetch_dw(const float* __restrict__ dw, bool row_ok, int64
   }
 }
 
+// bfloat16 form: lane group q covers k = 32 s + 8 q + 0..7 (s = 0, 1), i.e. two
+// contiguous float4 per s, in the order of the 16x16x32 operand.
+__device__ inline void fetch_dw_bf16(const float* __restrict__ dw, bool row_ok, int64_t r1, int e2,
+                                     int64_t r2, int P, int k0, int q, DwRegs& d) {
+#pragma unroll
+  for (int u = 0; u < HID / 16; ++u) {
+    const int kb = k0 + 32 * (u >> 1) + 8 * q + 4 * (u & 1);
+    floatx4 av = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (row_ok && kb < P) {  // P is a multiple of 4
+      av = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
+      if (e2 >= 0) av += *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
+    }
+    d.a[u] = av;
+  }
+}
+
 // ------------------------------------------------------------------ backward
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __restrict__ pe1,
@@ -289,7 +305,8 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   PanelRegs wr;
   DwRegs dr_cur, dr_nxt;
   fetch_bwd_panel(Wc, P, 0, tid, wr);
-  if (!BF16) fetch_dw(dw, row_ok, r1, e2, r2, P, 0, q, dr_cur);
+  if (BF16) fetch_dw_bf16(dw, row_ok, r1, e2, r2, P, 0, q, dr_cur);
+  else fetch_dw(dw, row_ok, r1, e2, r2, P, 0, q, dr_cur);
   __syncthreads();
   float* Z = sZ[wave];
   // recompute a1 and a2 (accumulator layout)
@@ -308,7 +325,8 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
     const bool more = k0 + HID < P;
     if (more) {
       fetch_bwd_panel(Wc, P, k0 + HID, tid, wr);
-      if (!BF16) fetch_dw(dw, row_ok, r1, e2, r2, P, k0 + HID, q, dr_nxt);
+      if (BF16) fetch_dw_bf16(dw, row_ok, r1, e2, r2, P, k0 + HID, q, dr_nxt);
+      else fetch_dw(dw, row_ok, r1, e2, r2, P, k0 + HID, q, dr_nxt);
     }
     if (BF16) {
       const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
@@ -316,11 +334,9 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
       for (int s = 0; s < HID / 32; ++s) {
         bf16x8 a;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = k0 + 32 * s + 8 * q + e;
-          float v = 0.f;
-          if (row_ok && k < P) v = dw[r1 + k] + (e2 >= 0 ? dw[r2 + k] : 0.f);
-          a[e] = __float2bfloat16(v);
+        for (int e = 0; e < 4; ++e) {
+          a[e] = __float2bfloat16(dr_cur.a[2 * s][e]);
+          a[e + 4] = __float2bfloat16(dr_cur.a[2 * s + 1][e]);
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -328,6 +344,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
           g[t] = mfma32(a, b, g[t]);
         }
       }
+      dr_cur = dr_nxt;
     } else {
       const float* sf = sB[buf];
 #pragma unroll

@@ -206,6 +206,52 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
   }
 }
 
+// Sum over the cpt lanes of an edge slot of NV values per lane (NV a power of two, the
+// first NYc of them meaningful), as a transposed butterfly: at each of the first
+// S = min(log2 NV, log2 cpt) stages a lane keeps one half of its values, receives its
+// partner's partial sums of that half and sends the other half, so the value count
+// halves per stage (NV/2 shuffles instead of NV); the remaining stages are plain.
+// Afterwards the lane holds the complete sums of values j0 .. j0 + (NV >> S) - 1, where
+// j0 = slot_first_value(lane, cpt), and lanes whose low bits (cpt >> S) - 1 are zero
+// hold distinct value groups.
+template <int NV>
+__device__ inline int slot_first_value(int lane, int cpt) {
+  int j0 = 0, o = cpt >> 1, h = NV >> 1;
+  while (o > 0 && h > 0) {
+    if (lane & o) j0 += h;
+    o >>= 1;
+    h >>= 1;
+  }
+  return j0;
+}
+template <int NV>
+__device__ inline int slot_store_mask(int cpt) {
+  int o = cpt, v = NV;
+  while (o > 1 && v > 1) {
+    o >>= 1;
+    v >>= 1;
+  }
+  return o - 1;  // lanes with (lane & mask) == 0 store
+}
+template <typename T, int NV>
+__device__ inline void slot_reduce(T (&v)[NV], int cpt, int lane) {
+  int o = cpt >> 1;
+  static_for<NV == 1 ? 0 : (NV == 2 ? 1 : (NV == 4 ? 2 : (NV == 8 ? 3 : 4)))>([&](auto K) {
+    constexpr int H = NV >> (decltype(K)::value + 1);
+    if (o > 0) {
+      const bool hi = (lane & o) != 0;
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        const T send = hi ? v[r] : v[r + H];
+        const T keep = hi ? v[r + H] : v[r];
+        v[r] = keep + __shfl_xor(send, o);
+      }
+      o >>= 1;
+    }
+  });
+  for (; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o);
+}
+
 // Adjoint of one degree's paths: writes dE/dw (per edge), the per-edge dE/dx rows, and
 // adds this degree's share of dE/dY (set instead when accumulate is 0).
 template <typename T, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX>
@@ -244,6 +290,14 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   int e1 = beg + ei, e2 = beg + EI + ei;
   int s1 = e1 < end ? g.src[e1] : 0, p1 = e1 < end ? g.pidx[e1] : 0;
   int s2 = e2 < end ? g.src[e2] : 0, p2 = e2 < end ? g.pidx[e2] : 0;
+  // dE/dY: NV = NYc rounded up to a power of two values per lane, reduced per edge slot.
+  // With at least NV lanes per slot (every degree of at least NV channels) the transposed
+  // butterfly leaves one complete value per storing lane; narrower slots take a plain
+  // butterfly and one storing lane.
+  constexpr int NV = NYc <= 1 ? 1 : (NYc <= 2 ? 2 : (NYc <= 4 ? 4 : (NYc <= 8 ? 8 : 16)));
+  const bool wide = cpt >= NV;
+  const int j0 = wide ? slot_first_value<NV>(uu, cpt) : 0;
+  const bool storer = wide ? (uu & slot_store_mask<NV>(cpt)) == 0 && j0 < NYc : uu == 0;
   EdgeOps<T, D1, NP, NYc, KC> cur, nxt;
   if (e1 < end) load_edge<T, D1, NP, NYc, KC>(g, a, e1, s1, p1, uu, Y, x, w, cur);
   for (int it = 0; it < n_it; ++it) {
@@ -252,9 +306,12 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
     const int s3 = e3 < end ? g.src[e3] : 0, p3 = e3 < end ? g.pidx[e3] : 0;
     if (en < end) load_edge<T, D1, NP, NYc, KC>(g, a, en, s2, p2, uu, Y, x, w, nxt);
     const bool active = ec < end;
-    T dYl[NYc];
+    // earlier degrees' (or blocks') share of this edge's dE/dY, fetched before the compute
+    T dYold = T(0);
+    if (wide && accumulate && active && storer) dYold = dY[(int64_t)ec * g.NY + j0];
+    T dYl[NV];
 #pragma unroll
-    for (int q = 0; q < NYc; ++q) dYl[q] = T(0);
+    for (int q = 0; q < NV; ++q) dYl[q] = T(0);
     if (active) {
       const int64_t e = ec;
       const int64_t drow = e * g.P + a.woff;
@@ -294,14 +351,19 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
         }
       }
     }
-    for (int off = 1; off < cpt; off <<= 1) {
+    if (wide) {
+      slot_reduce<T, NV>(dYl, cpt, lane);
+      if (active && storer) dY[(int64_t)ec * g.NY + j0] = dYold + dYl[0];
+    } else {
+      for (int off = 1; off < cpt; off <<= 1) {
 #pragma unroll
-      for (int q = 0; q < NYc; ++q) dYl[q] += __shfl_xor(dYl[q], off);
-    }
-    if (uu == 0 && active) {
-      T* dst = dY + (int64_t)ec * g.NY;
+        for (int q = 0; q < NYc; ++q) dYl[q] += __shfl_xor(dYl[q], off);
+      }
+      if (active && storer) {
+        T* dst = dY + (int64_t)ec * g.NY;
 #pragma unroll
-      for (int q = 0; q < NYc; ++q) dst[q] = accumulate ? dst[q] + dYl[q] : dYl[q];
+        for (int q = 0; q < NYc; ++q) dst[q] = accumulate ? dst[q] + dYl[q] : dYl[q];
+      }
     }
     cur = nxt;
     s2 = s3;
