@@ -53,11 +53,28 @@ def main():
                     help="Si count of the SiO2 sample box timed with the CPU oracle")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (HBM counter calibration)")
+    ap.add_argument("--workload", default="sio2_24k", choices=["sio2_24k", "md", "serving"],
+                    help="sio2_24k: the headline line (plus a short serving replay); md: the "
+                         "112k-atom Si3N4 Verlet run; serving: the full 2,000-request stream")
+    ap.add_argument("--serve-requests", type=int, default=None,
+                    help="requests of the serving stream to replay: default 400 beside the "
+                         "headline line (0 to skip), 2,000 for --workload serving")
+    ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--md-steps", type=int, default=100)
+    ap.add_argument("--md-warmup", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build evaluates one subdomain on one GPU; "
                                    "--gpus must be 1"}))
         sys.exit(2)
+
+    if args.workload == "md":
+        print(json.dumps(bench_md(args)))
+        return
+    if args.workload == "serving":
+        count = 2000 if args.serve_requests is None else args.serve_requests
+        print(json.dumps(bench_serving(args, count, args.precision, full=True)))
+        return
 
     import torch
 
@@ -144,6 +161,13 @@ def main():
                "sample": f"one FP64 E+F+virial evaluation of a {sample.n}-atom SiO2 box at the "
                          f"same density with the same model ({cdt:.1f} s)"}
 
+    serving = None
+    count = 400 if args.serve_requests is None else args.serve_requests
+    if count > 0:
+        del ctx
+        torch.cuda.empty_cache()
+        serving = bench_serving(args, count, args.precision, full=False)
+
     out = {
         "metric": "atom-steps/s (E+F), 5-layer l<=2 model, 24k-atom SiO2",
         "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -157,8 +181,96 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases_ms": {k: v / args.steps for k, v in phase_ms.items()},
+        "serving": serving,
     }
     print(json.dumps(out))
+
+
+def _model_file(species, seed):
+    from synth import model_spec_real, make_weights, write_weights
+    spec = model_spec_real(species)
+    path = os.path.join(tempfile.mkdtemp(), "model.snw")
+    write_weights(path, spec, make_weights(spec, seed))
+    return path
+
+
+def bench_serving(args, count, precision, full):
+    """Replay the serving stream (Poisson arrivals at 200 requests/s, 8-2,048 atoms,
+    1-4 of 89 species, triclinic cells) through the continuous-batching server and
+    through the plain single-structure path (one stream, one structure per launch)."""
+    import paper_2402_03789_amd as sn
+    from paper_2402_03789_amd.serve import Server, replay, latency_summary
+    from synth import serving_stream
+
+    t0 = time.perf_counter()
+    stream = serving_stream(count=count, seed=6)
+    gen_s = time.perf_counter() - t0
+    model = sn.Model(_model_file(tuple(range(1, 90)), 106))
+    warm = serving_stream(count=24, seed=60)
+    out = {"requests": count, "offered_rate_per_s": 200.0, "precision": precision,
+           "stream_seed": 6, "generation_s": gen_s}
+    for name, kw in (("batched", dict(n_streams=args.serve_streams, max_batch_atoms=16384,
+                                      max_batch_structures=256)),
+                     ("single", dict(n_streams=1, max_batch_atoms=1 << 40,
+                                     max_batch_structures=1))):
+        srv = Server(model, precision=precision, **kw)
+        replay(srv, [(0.0, s) for _, s in warm])  # allocate workspaces, load kernels
+        rep = replay(srv, stream)
+        srv.close()
+        summ = latency_summary(rep)
+        summ.update(kw)
+        out[name] = summ
+    if not full:
+        return out
+    atoms = out["batched"]["atoms"]
+    return {"metric": "serving stream: p50/p99 latency and atom-steps/s (E+F), 5-layer l<=2 "
+                      "model with 89 species",
+            "value": out["batched"]["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[precision],
+            "data": "synthetic",
+            "config": {"workload": f"{count} periodic structures, {atoms} atoms, Poisson "
+                                   "arrivals at 200/s", "precision": precision},
+            "p50_ms": out["batched"]["p50_ms"], "p99_ms": out["batched"]["p99_ms"],
+            "serving": out}
+
+
+def bench_md(args):
+    """112,000-atom amorphous-density Si3N4: velocity Verlet at dt = 1 fs from a 1500 K
+    Maxwell-Boltzmann start, neighbour list (skin 1 A) rebuilt every 10 steps."""
+    import torch
+
+    import paper_2402_03789_amd as sn
+    from paper_2402_03789_amd.md import VelocityVerlet
+    from synth import config_structure
+
+    t0 = time.perf_counter()
+    s = config_structure("si3n4_112k")
+    gen_s = time.perf_counter() - t0
+    ctx = sn.Context(sn.Model(_model_file((7, 14), 102)), precision=args.precision, skin=1.0)
+    md = VelocityVerlet(ctx, s.pos, s.Z, s.cell, s.masses(), dt=1.0, rebuild_every=10,
+                        temperature=1500.0, seed=5)
+    md.run(args.md_warmup)
+    e0 = md.kinetic_energy() + md.potential_energy()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    md.run(args.md_steps)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    e1 = md.kinetic_energy() + md.potential_energy()
+    n, g, e = ctx.graph_size()
+    return {"metric": "atom-steps/s (E+F), 5-layer l<=2 model, 112k-atom Si3N4 velocity-Verlet MD",
+            "value": s.n * args.md_steps / dt, "unit": "atom-steps/s", "n_gpus": 1,
+            "steps": args.md_steps, "warmup": args.md_warmup,
+            "ms_per_step": dt / args.md_steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
+            "data": "synthetic",
+            "config": {"workload": "Si3N4 112,000 atoms (48,000 Si + 64,000 N), 3.1 g/cm^3, periodic "
+                                   "cubic 106.33 A; dt 1 fs, 1500 K start, skin 1 A, rebuild every "
+                                   "10 steps", "n_atoms": n, "n_ghost": g, "n_edges": e,
+                       "precision": args.precision},
+            "energy_drift_eV_per_atom": (e1 - e0) / s.n, "generation_s": gen_s}
 
 
 if __name__ == "__main__":

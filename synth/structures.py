@@ -69,14 +69,18 @@ def rsa_box(cell: np.ndarray, n: int, dmin: float, rng: np.random.Generator,
     """Random sequential addition of n points in a periodic cell.
 
     Bins tile fractional space with a perpendicular width of at least dmin,
-    so every conflicting image lies in one of the 27 surrounding bins.
+    so every conflicting image lies in one of the 27 surrounding bins.  Each
+    try draws one uniform fractional point (three doubles from `rng`) and is
+    rejected when any stored point image in those bins lies closer than dmin.
     """
     cell = np.asarray(cell, dtype=np.float64)
     widths = _perp_widths(cell)
     if np.any(widths <= dmin):
         raise ValueError("cell thinner than the minimum distance")
     nb = np.maximum(1, np.floor(widths / dmin).astype(int))
-    bins: dict = {}
+    n0, n1, n2 = (int(x) for x in nb)
+    bins = [[] for _ in range(n0 * n1 * n2)]
+    neigh: dict = {}  # bin -> distinct (neighbour bin, image shift) pairs
     frac = np.empty((n, 3))
     d2min = dmin * dmin
     offs = [(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)]
@@ -88,29 +92,36 @@ def rsa_box(cell: np.ndarray, n: int, dmin: float, rng: np.random.Generator,
         if tries > limit:
             raise RuntimeError(f"RSA failed after {tries} tries ({placed}/{n})")
         f = rng.random(3)
-        b = np.minimum((f * nb).astype(int), nb - 1)
-        ok = True
-        seen = set()
-        for o in offs:
-            bb = b + o
-            shift = np.floor_divide(bb, nb)
-            key = tuple(bb - shift * nb)
-            tag = key + tuple(shift)
-            if tag in seen:
-                continue
-            seen.add(tag)
-            lst = bins.get(key)
-            if not lst:
-                continue
-            fo = frac[lst] + shift  # images of the stored points
-            d = (fo - f) @ cell
+        b0 = min(int(f[0] * n0), n0 - 1)
+        b1 = min(int(f[1] * n1), n1 - 1)
+        b2 = min(int(f[2] * n2), n2 - 1)
+        home = (b0 * n1 + b1) * n2 + b2
+        nl = neigh.get(home)
+        if nl is None:
+            nl = []
+            seen = set()
+            for o in offs:
+                c0, c1, c2 = b0 + o[0], b1 + o[1], b2 + o[2]
+                sh = (c0 // n0, c1 // n1, c2 // n2)
+                k = ((c0 - sh[0] * n0) * n1 + (c1 - sh[1] * n1)) * n2 + (c2 - sh[2] * n2)
+                if (k,) + sh in seen:
+                    continue
+                seen.add((k,) + sh)
+                nl.append((k, sh))
+            neigh[home] = nl
+        idx = []
+        shifts = []
+        for k, sh in nl:
+            lst = bins[k]
+            if lst:
+                idx.extend(lst)
+                shifts.extend([sh] * len(lst))
+        if idx:
+            d = (frac[idx] + np.array(shifts, dtype=np.float64) - f) @ cell
             if np.any(np.einsum("ij,ij->i", d, d) < d2min):
-                ok = False
-                break
-        if not ok:
-            continue
+                continue
         frac[placed] = f
-        bins.setdefault(tuple(b), []).append(placed)
+        bins[home].append(placed)
         placed += 1
     return frac @ cell
 
