@@ -105,6 +105,12 @@ int sn_cg_table(int l1, int l2, int l3, double* out);
  * skin / 2 (0 for a fresh list every call). */
 int sn_ctx_create(const sn_model_t* model, int device, void* hip_stream, size_t hbm_budget,
                   int precision, double skin, sn_ctx_t** out);
+/* A context also owns a second HIP stream on which the radial MLPs of every block run,
+ * overlapped with the node-feature chain (the MLP forward needs only the edge basis; the
+ * MLP adjoint of a block only that block's dE/dw).  Every call joins that stream back into
+ * the context's stream before it returns, so the entry points stay stream-ordered.  With
+ * SN_SERIAL=1 in the environment at creation, everything runs on the context's stream
+ * (per-kernel timings without overlap, for profiling). */
 void sn_ctx_free(sn_ctx_t* ctx);
 
 /* ---- single structure, host buffers -------------------------------------------------

@@ -215,11 +215,12 @@ void launch_mlp_hidden_bwd(int64_t E, const int* rows, const T* rho, int nb, int
 template <typename T>
 __global__ void k_pair_sum(int64_t np, const int* __restrict__ pe1, const int* __restrict__ pe2,
                            const T* __restrict__ dw, int P, T* __restrict__ out) {
+  // dE/dw is pair-major: rows 2p and 2p + 1 hold the pair's two directions
   const int64_t p = blockIdx.x;
-  const int64_t a = (int64_t)pe1[p] * P;
+  const int64_t a = 2 * p * P;
   const int b = pe2[p];
   for (int k = threadIdx.x; k < P; k += blockDim.x)
-    out[p * P + k] = dw[a + k] + (b >= 0 ? dw[(int64_t)b * P + k] : T(0));
+    out[p * P + k] = dw[a + k] + (b >= 0 ? dw[a + P + k] : T(0));
 }
 
 template <typename T>

@@ -369,14 +369,16 @@ __global__ void k_pairs(int64_t E, const int* __restrict__ rev, const int* __res
                         int* __restrict__ pe1, int* __restrict__ pe2) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
+  // pidx[e] = 2 p + side: p is the undirected pair (row of the shared radial weights), side
+  // 0 for the pair's first edge and 1 for its reverse (row 2p + side of the pair-major dE/dw)
   const int r = rev[e];
   if (flag[e]) {
     const int p = fscan[e];
-    pidx[e] = p;
+    pidx[e] = 2 * p;
     pe1[p] = (int)e;
     pe2[p] = r;  // -1 when unpaired
   } else {
-    pidx[e] = fscan[r];
+    pidx[e] = 2 * fscan[r] + 1;
   }
 }
 

@@ -141,15 +141,197 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int64_t M, int N, int K, cons
         if (row >= M) continue;
         TC* c = C + cm(row) + col;
         float v = alpha * acc[i][j][rr];
-        *c = accumulate ? (TC)((float)*c + v) : (TC)v;
+        *c = accumulate ? (TC)(*c + (TC)v) : (TC)v;
       }
     }
+}
+
+// ------------------------------------------------------------------ vector-load variant
+// Same contraction for aligned operands (rows, leading dimensions and offsets multiples of
+// 16 bytes, K and N multiples of 8): k-slabs of 32 loaded with 16-byte vector loads one
+// slab ahead into registers, staged in double-buffered LDS (one barrier per slab), and
+// block tiles of 64 x BN with BN = 32 for narrow outputs.
+template <typename T>
+__device__ inline void ld4(const T* p, float (&v)[4]);
+template <>
+__device__ inline void ld4<float>(const float* p, float (&v)[4]) {
+  const floatx4 a = *reinterpret_cast<const floatx4*>(p);
+  v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+}
+template <>
+__device__ inline void ld4<double>(const double* p, float (&v)[4]) {
+  typedef double doublex2 __attribute__((ext_vector_type(2)));
+  const doublex2 a = *reinterpret_cast<const doublex2*>(p);
+  const doublex2 b = *reinterpret_cast<const doublex2*>(p + 2);
+  v[0] = (float)a[0]; v[1] = (float)a[1]; v[2] = (float)b[0]; v[3] = (float)b[1];
+}
+
+template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN>
+__global__ __launch_bounds__(256) void k_gemm_mfma_v(int64_t M, int N, int K, const TA* __restrict__ A,
+                                                      RowMap am, const TB* __restrict__ B, int ldb,
+                                                      TC* __restrict__ C, RowMap cm, float alpha,
+                                                      int accumulate, int nbn, int64_t ntiles,
+                                                      int64_t chunk) {
+  constexpr int BM = 64, BK = 32;
+  constexpr int SP = BF16 ? BK + 8 : BK + 4;  // LDS row stride (16-byte aligned rows)
+  using ST = typename std::conditional<BF16, __bf16, float>::type;
+  __shared__ __attribute__((aligned(16))) ST As[2][BM][SP];
+  __shared__ __attribute__((aligned(16))) ST Bs[2][BN][SP];  // stored [n][k]
+  const int64_t p = blockIdx.x;
+  const int64_t tile = (p % 8) * chunk + p / 8;
+  if (tile >= ntiles) return;
+  const int64_t m0 = (tile / nbn) * BM;
+  const int n0 = (int)(tile % nbn) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int TM = BN == 64 ? 2 : 1;  // 16-row tiles per wave
+  const int wr = BN == 64 ? (wave >> 1) * 32 : wave * 16;
+  const int wc = BN == 64 ? (wave & 1) * 32 : 0;
+  floatx4 acc[TM][2];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // A: thread covers row tid/4, k = 8 (tid%4) .. +7
+  const int ar = tid >> 2, ak = (tid & 3) * 8;
+  const bool a_ok = m0 + ar < M;
+  const TA* a_src = A + (a_ok ? am(m0 + ar) : 0) + ak;
+  // B: BN*BK/256 elements per thread
+  constexpr int BE = BN * BK / 256;  // 8 or 4
+  int bn, bk;
+  if (BT) {  // B[n][k]: thread covers n, BE consecutive k
+    bn = tid / (BK / BE);
+    bk = (tid % (BK / BE)) * BE;
+  } else {   // B[k][n]: thread covers k, BE consecutive n
+    bk = tid / (BN / BE);
+    bn = (tid % (BN / BE)) * BE;
+  }
+  const bool b_ok = BT ? (n0 + bn < N) : (n0 + bn < N);
+  const TB* b_src = BT ? B + (int64_t)(n0 + bn) * ldb + bk : B + (int64_t)bk * ldb + n0 + bn;
+  float ra[8], rb[BE];
+  auto fetch = [&](int k0) {
+    float t[4];
+    if (a_ok && k0 + ak < K) {  // K is a multiple of 8: a thread's 8 values are all in or out
+      ld4<TA>(a_src + k0, t);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ra[e] = t[e];
+      ld4<TA>(a_src + k0 + 4, t);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ra[4 + e] = t[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[e] = 0.f;
+    }
+    const bool kin = k0 + bk < K;
+    if (b_ok && kin) {
+      const TB* q = BT ? b_src + k0 : b_src + (int64_t)k0 * ldb;
+#pragma unroll
+      for (int e = 0; e < BE; e += 4) {
+        ld4<TB>(q + e, t);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) rb[e + f] = t[f];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < BE; ++e) rb[e] = 0.f;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) As[buf][ar][ak + e] = (ST)ra[e];
+    if (BT) {
+#pragma unroll
+      for (int e = 0; e < BE; ++e) Bs[buf][bn][bk + e] = (ST)rb[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < BE; ++e) Bs[buf][bn + e][bk] = (ST)rb[e];
+    }
+  };
+  fetch(0);
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    stage(buf);
+    __syncthreads();
+    if (k0 + BK < K) fetch(k0 + BK);
+    if constexpr (BF16) {
+      const int r = lane & 15, kq = (lane >> 4) * 8;
+      bf16x8 a[TM], b[2];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wr + i * 16 + r][kq]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wc + j * 16 + r][kq]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    } else {
+      const int r = lane & 15, kq = lane >> 4;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        float a[TM], b[2];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = As[buf][wr + i * 16 + r][kk + kq];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[buf][wc + j * 16 + r][kk + kq];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    buf ^= 1;
+  }
+  const int col_l = lane & 15, row_q = (lane >> 4) * 4;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wc + j * 16 + col_l;
+      if (col >= N) continue;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int64_t row = m0 + wr + i * 16 + row_q + rr;
+        if (row >= M) continue;
+        TC* c = C + cm(row) + col;
+        float v = alpha * acc[i][j][rr];
+        *c = accumulate ? (TC)(*c + (TC)v) : (TC)v;
+      }
+    }
+}
+
+template <typename T>
+static bool aligned16(const T* p, int64_t a, int64_t b, int64_t c) {
+  constexpr int64_t q = 16 / sizeof(T);
+  return ((uintptr_t)p % 16 == 0) && a % q == 0 && b % q == 0 && c % q == 0;
 }
 
 template <typename TA, typename TB, typename TC>
 void launch_gemm_mfma(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, int ldb, bool bt,
                       TC* C, RowMap cm, float alpha, bool accumulate, bool bf16, hipStream_t s) {
   if (M <= 0 || N <= 0) return;
+  const bool vec = K % 8 == 0 && N % 8 == 0 && aligned16(A, am.stride, am.off, am.nm > 1 ? am.ld : 0) &&
+                   aligned16(B, ldb, 0, 0);
+  if (vec) {
+    const int bn = N <= 32 ? 32 : 64;
+    const int nbn = (N + bn - 1) / bn;
+    const int64_t ntiles = ((M + 63) / 64) * nbn;
+    const int64_t chunk = (ntiles + 7) / 8;
+    const unsigned grid = (unsigned)(chunk * 8);
+    const int accv = accumulate ? 1 : 0;
+#define SN_V(BTV, BFV, BNV)                                                                      \
+  k_gemm_mfma_v<TA, TB, TC, BTV, BFV, BNV><<<grid, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm,    \
+                                                               alpha, accv, nbn, ntiles, chunk)
+    if (bn == 32) {
+      if (bt) { if (bf16) SN_V(true, true, 32); else SN_V(true, false, 32); }
+      else { if (bf16) SN_V(false, true, 32); else SN_V(false, false, 32); }
+    } else {
+      if (bt) { if (bf16) SN_V(true, true, 64); else SN_V(true, false, 64); }
+      else { if (bf16) SN_V(false, true, 64); else SN_V(false, false, 64); }
+    }
+#undef SN_V
+    return;
+  }
   const int nbn = (N + MT - 1) / MT;
   const int64_t nbm = (M + MT - 1) / MT;
   const int64_t ntiles = nbm * nbn;

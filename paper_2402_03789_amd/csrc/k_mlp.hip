@@ -5,7 +5,8 @@
 // edge and its reverse share them):
 //   a1 = rho Wa,  z1 = phi(a1),  a2 = z1 Wb,  z2 = phi(a2),  w = z2 Wc
 // with phi(z) = c z sigmoid(z) and no biases.  The adjoint maps
-// dE/dw = dw[e1] + dw[e2] (both directions of the pair) back to dE/drho:
+// dE/dw = dw[2p] + dw[2p+1] (both directions of pair p, stored in adjacent rows) back to
+// dE/drho:
 //   dz2 = dw Wc^T,  da2 = dz2 phi'(a2),  dz1 = da2 Wb^T,  da1 = dz1 phi'(a1),
 //   drho = da1 Wa^T   (hidden activations recomputed; drho lands on edge e1).
 //
@@ -113,7 +114,10 @@ __device__ inline void stage_common(int64_t np, int64_t p0, const int* __restric
 }
 
 // Weight-panel prefetch: each of the 256 threads holds 16 values (4 x 4) of a 64 x 64
-// panel in registers while the current panel is being multiplied.
+// panel in registers while the current panel is being multiplied.  Loads are issued
+// unconditionally from clamped addresses (a load under a branch makes the compiler wait
+// for it, and for every other load in flight, inside that branch); columns past P are
+// zeroed when the panel is staged.
 struct PanelRegs {
   float v[16];
 };
@@ -125,17 +129,19 @@ __device__ inline void fetch_fwd_panel(const float* __restrict__ Wc, int P, int 
   for (int j = 0; j < 16; ++j) {
     const int i = tid + 256 * j;
     const int k = i / HID, n = i % HID;
-    r.v[j] = (n0 + n < P) ? Wc[(int64_t)k * P + n0 + n] : 0.f;
+    r.v[j] = Wc[(int64_t)k * P + min(n0 + n, P - 1)];
   }
 }
 template <bool BF16>
-__device__ inline void store_fwd_panel(const PanelRegs& r, int tid, float* sf, __bf16* sh) {
+__device__ inline void store_fwd_panel(const PanelRegs& r, int tid, int P, int n0, float* sf,
+                                       __bf16* sh) {
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int i = tid + 256 * j;
     const int k = i / HID, n = i % HID;
-    if (BF16) sh[n * BP + k] = __float2bfloat16(r.v[j]);
-    else sf[k * WP + n] = r.v[j];
+    const float v = n0 + n < P ? r.v[j] : 0.f;
+    if (BF16) sh[n * BP + k] = __float2bfloat16(v);
+    else sf[k * WP + n] = v;
   }
 }
 
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   floatx4 acc[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, acc, lane);
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
-  store_fwd_panel<BF16>(pr, tid, sW[0], reinterpret_cast<__bf16*>(sW[0]));
+  store_fwd_panel<BF16>(pr, tid, P, 0, sW[0], reinterpret_cast<__bf16*>(sW[0]));
   __syncthreads();
   zero4(acc);
   panel_kn(Z, sW[1], acc, lane);
@@ -185,8 +191,8 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   (void)PANEL;
   int buf = 0;
   for (int n0 = 0; n0 < P; n0 += HID) {
-    const bool more = n0 + HID < P;
-    if (more) fetch_fwd_panel(Wc, P, n0 + HID, tid, pr);  // in flight during the MFMAs
+    fetch_fwd_panel(Wc, P, n0 + HID, tid, pr);  // in flight during the MFMAs (clamped past P)
+    __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
     const float* sf = sW[buf];
     const __bf16* sh = reinterpret_cast<const __bf16*>(sW[buf]);
     zero4(acc);
@@ -206,7 +212,9 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
     }
     // through the wave's own panel to full-row float4 stores
     acc_to_panel(acc, Z, lane, [](float v, int, int) { return v; });
-    if (more) store_fwd_panel<BF16>(pr, tid, sW[buf ^ 1], reinterpret_cast<__bf16*>(sW[buf ^ 1]));
+    // staged unconditionally (the panel past the last is never read): a conditional store
+    // would let the compiler sink the panel loads into the branch, after the MFMAs
+    store_fwd_panel<BF16>(pr, tid, P, n0 + HID, sW[buf ^ 1], reinterpret_cast<__bf16*>(sW[buf ^ 1]));
     __syncthreads();
     const int c4 = (lane & 15) * 4;
 #pragma unroll
@@ -229,53 +237,50 @@ __device__ inline void fetch_bwd_panel(const float* __restrict__ Wc, int P, int 
   for (int j = 0; j < 16; ++j) {
     const int i = tid + 256 * j;
     const int jj = i / HID, k = i % HID;
-    r.v[j] = (k0 + k < P) ? Wc[(int64_t)jj * P + k0 + k] : 0.f;
+    r.v[j] = Wc[(int64_t)jj * P + min(k0 + k, P - 1)];
   }
 }
 template <bool BF16>
-__device__ inline void store_bwd_panel(const PanelRegs& r, int tid, float* sf, __bf16* sh) {
+__device__ inline void store_bwd_panel(const PanelRegs& r, int tid, int P, int k0, float* sf,
+                                       __bf16* sh) {
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int i = tid + 256 * j;
     const int jj = i / HID, k = i % HID;
-    if (BF16) sh[jj * BP + k] = __float2bfloat16(r.v[j]);
-    else sf[jj * TP + k] = r.v[j];
+    const float v = k0 + k < P ? r.v[j] : 0.f;
+    if (BF16) sh[jj * BP + k] = __float2bfloat16(v);
+    else sf[jj * TP + k] = v;
   }
 }
 
-// dw operand of one lane for a 64-wide k panel: float32 k-permuted fragments
-// (lane group q covers k = 16 u + 4 q + s), summed over both edges of the pair.
+// dw operand of one lane for a 64-wide k panel, both edges of the pair loaded separately
+// and unconditionally (clamped addresses; a missing reverse edge reads the first row
+// again) and combined when the panel is used.  float32 form: lane group q covers
+// k = 16 u + 4 q + 0..3; bfloat16 form: k = 32 (u / 2) + 8 q + 4 (u % 2) + 0..3, the order
+// of the 16x16x32 operand.
 struct DwRegs {
-  floatx4 a[HID / 16];
+  floatx4 a[HID / 16], b[HID / 16];
 };
-__device__ inline void fetch_dw(const float* __restrict__ dw, bool row_ok, int64_t r1, int e2,
-                                int64_t r2, int P, int k0, int q, DwRegs& d) {
+template <bool BF16>
+__device__ inline int dw_col(int k0, int u, int q) {
+  return BF16 ? k0 + 32 * (u >> 1) + 8 * q + 4 * (u & 1) : k0 + 16 * u + 4 * q;
+}
+template <bool BF16>
+__device__ inline void fetch_dw(const float* __restrict__ dw, int64_t r1, int64_t r2, int P, int k0,
+                                int q, DwRegs& d) {
 #pragma unroll
   for (int u = 0; u < HID / 16; ++u) {
-    const int kb = k0 + 16 * u + 4 * q;
-    floatx4 av = floatx4{0.f, 0.f, 0.f, 0.f};
-    if (row_ok && kb < P) {  // P is a multiple of 4
-      av = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
-      if (e2 >= 0) av += *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
-    }
-    d.a[u] = av;
+    const int kb = min(dw_col<BF16>(k0, u, q), P - 4);  // P is a multiple of 4
+    d.a[u] = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
+    d.b[u] = *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
   }
 }
-
-// bfloat16 form: lane group q covers k = 32 s + 8 q + 0..7 (s = 0, 1), i.e. two
-// contiguous float4 per s, in the order of the 16x16x32 operand.
-__device__ inline void fetch_dw_bf16(const float* __restrict__ dw, bool row_ok, int64_t r1, int e2,
-                                     int64_t r2, int P, int k0, int q, DwRegs& d) {
-#pragma unroll
-  for (int u = 0; u < HID / 16; ++u) {
-    const int kb = k0 + 32 * (u >> 1) + 8 * q + 4 * (u & 1);
-    floatx4 av = floatx4{0.f, 0.f, 0.f, 0.f};
-    if (row_ok && kb < P) {  // P is a multiple of 4
-      av = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
-      if (e2 >= 0) av += *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
-    }
-    d.a[u] = av;
-  }
+template <bool BF16>
+__device__ inline floatx4 dw_value(const DwRegs& d, int u, bool row_ok, bool has2, int P, int k0,
+                                   int q) {
+  const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+  if (!row_ok || dw_col<BF16>(k0, u, q) >= P) return z;
+  return has2 ? d.a[u] + d.b[u] : d.a[u];
 }
 
 // ------------------------------------------------------------------ backward
@@ -299,68 +304,77 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   const int r = lane & 15, q = lane >> 4;
   const int64_t pr = p0 + wave * 16 + r;
   const bool row_ok = pr < np;
-  const int64_t r1 = row_ok ? (int64_t)pe1[pr] * P : 0;
-  const int e2 = row_ok ? pe2[pr] : -1;
-  const int64_t r2 = e2 >= 0 ? (int64_t)e2 * P : 0;
+  // dE/dw is pair-major: rows 2p (first edge) and 2p + 1 (its reverse, when present)
+  const int64_t r1 = row_ok ? 2 * pr * P : 0;
+  const bool has2 = row_ok && pe2[pr] >= 0;
+  const int64_t r2 = has2 ? r1 + P : r1;
   PanelRegs wr;
   DwRegs dr_cur, dr_nxt;
   fetch_bwd_panel(Wc, P, 0, tid, wr);
-  if (BF16) fetch_dw_bf16(dw, row_ok, r1, e2, r2, P, 0, q, dr_cur);
-  else fetch_dw(dw, row_ok, r1, e2, r2, P, 0, q, dr_cur);
+  fetch_dw<BF16>(dw, r1, r2, P, 0, q, dr_cur);
   __syncthreads();
   float* Z = sZ[wave];
   // recompute a1 and a2 (accumulator layout)
   floatx4 a1[4], a2[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, a1, lane);
   acc_to_panel(a1, Z, lane, [&](float v, int, int) { return phi(v, c); });
-  store_bwd_panel<BF16>(wr, tid, sB[0], reinterpret_cast<__bf16*>(sB[0]));
+  store_bwd_panel<BF16>(wr, tid, P, 0, sB[0], reinterpret_cast<__bf16*>(sB[0]));
   __syncthreads();
   zero4(a2);
   panel_kn(Z, sWb, a2, lane);
   // dz2 = (dw[e1] + dw[e2]) Wc^T, contraction over the P radial weights in 64-wide panels
   floatx4 g[4];
   zero4(g);
+  // One panel step: the loads of the next panel (dw of both edges, the Wc panel) are issued
+  // first and unconditionally, so they stay in flight across this panel's MFMAs; the
+  // panel loop is unrolled by two so the two operand sets alternate registers (no copies).
+  const int npan = (P + HID - 1) / HID;
   int buf = 0;
-  for (int k0 = 0; k0 < P; k0 += HID) {
-    const bool more = k0 + HID < P;
-    if (more) {
-      fetch_bwd_panel(Wc, P, k0 + HID, tid, wr);
-      if (BF16) fetch_dw_bf16(dw, row_ok, r1, e2, r2, P, k0 + HID, q, dr_nxt);
-      else fetch_dw(dw, row_ok, r1, e2, r2, P, k0 + HID, q, dr_nxt);
-    }
-    if (BF16) {
-      const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
+  auto step = [&](int jj, const DwRegs& cur, DwRegs& nxt) {
+    const int k0 = jj * HID;
+    fetch_bwd_panel(Wc, P, k0 + HID, tid, wr);
+    fetch_dw<BF16>(dw, r1, r2, P, k0 + HID, q, nxt);
+    if (jj < npan) {
+      if (BF16) {
+        const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
 #pragma unroll
-      for (int s = 0; s < HID / 32; ++s) {
-        bf16x8 a;
+        for (int s = 0; s < HID / 32; ++s) {
+          bf16x8 a;
+          const floatx4 lo = dw_value<true>(cur, 2 * s, row_ok, has2, P, k0, q);
+          const floatx4 hi = dw_value<true>(cur, 2 * s + 1, row_ok, has2, P, k0, q);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          a[e] = __float2bfloat16(dr_cur.a[2 * s][e]);
-          a[e + 4] = __float2bfloat16(dr_cur.a[2 * s + 1][e]);
+          for (int e = 0; e < 4; ++e) {
+            a[e] = __float2bfloat16(lo[e]);
+            a[e + 4] = __float2bfloat16(hi[e]);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
+            g[t] = mfma32(a, b, g[t]);
+          }
         }
+      } else {
+        const float* sf = sB[buf];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
-          g[t] = mfma32(a, b, g[t]);
+        for (int u = 0; u < HID / 16; ++u) {
+          const floatx4 av = dw_value<false>(cur, u, row_ok, has2, P, k0, q);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const floatx4 bv =
+                *reinterpret_cast<const floatx4*>(&sf[(t * 16 + r) * TP + 16 * u + 4 * q]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) g[t] = mfma4(av[s], bv[s], g[t]);
+          }
         }
       }
-      dr_cur = dr_nxt;
-    } else {
-      const float* sf = sB[buf];
-#pragma unroll
-      for (int u = 0; u < HID / 16; ++u) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const floatx4 bv = *reinterpret_cast<const floatx4*>(&sf[(t * 16 + r) * TP + 16 * u + 4 * q]);
-#pragma unroll
-          for (int s = 0; s < 4; ++s) g[t] = mfma4(dr_cur.a[u][s], bv[s], g[t]);
-        }
-      }
-      dr_cur = dr_nxt;
     }
-    if (more) store_bwd_panel<BF16>(wr, tid, sB[buf ^ 1], reinterpret_cast<__bf16*>(sB[buf ^ 1]));
+    store_bwd_panel<BF16>(wr, tid, P, k0 + HID, sB[buf ^ 1], reinterpret_cast<__bf16*>(sB[buf ^ 1]));
     __syncthreads();
     buf ^= 1;
+  };
+  for (int j = 0; j < npan; j += 2) {
+    step(j, dr_cur, dr_nxt);
+    step(j + 1, dr_nxt, dr_cur);
   }
   // da2 = dz2 * phi'(a2) -> operand panel;  dz1 = da2 Wb^T
   acc_to_panel(g, Z, lane, [&](float v, int t, int rr) { return v * dphi(a2[t][rr], c); });

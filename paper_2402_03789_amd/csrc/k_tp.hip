@@ -20,6 +20,8 @@
 // The adjoint uses dE/dq = G / k_avg with G = dE/dM of the receiver (register
 // resident per lane) and produces, per edge:
 //   dE/dw[p,u] = sum_m3 G[p,u,m3] t[p,u,m3],  t[m3] = sum C x[m1] Y[m2]
+//     (stored pair-major: the two edges of a pair write adjacent rows, so the MLP
+//     adjoint streams them in pair order)
 //   dE/dx_s[u, m1] (a per-edge row, reduced over senders by a separate pass)
 //   dE/dY[m2] = sum_{p,u} sum C[m1,m2,m3] x[u,m1] w[p,u] G[p,u,m3]
 // The channel sum of dE/dY runs as shuffles inside each wave; the per-degree
@@ -79,7 +81,7 @@ struct TPDeg {
 struct TPArgs {
   const int* row_ptr;
   const int* src;
-  const int* pidx;  // pair of each edge: row of the shared radial weights
+  const int* pidx;  // 2 p + side: pair p holds the shared radial weights, 2 p + side the dE/dw row
   int n_recv;
   int Dx, P, Dm, NY;
   TPDeg d;
@@ -106,34 +108,76 @@ __device__ inline void tp_paths(const T* xv, const T* Ye, T* t) {
   });
 }
 
-// Operands of one edge for one lane, loaded one edge ahead of their use.
+// Operands of one edge for one lane.  The edge loop is software-pipelined through a
+// ring of R operand sets (static slots, the loop unrolled by R): indices are loaded 2R-1
+// iterations ahead of their edge's compute and operands R-1 ahead.  Every load is
+// unconditional from a valid address (edge index clamped to the receiver's last edge,
+// channel clamped to 0 on idle lanes) and the values are masked where they are used: a
+// load under a branch makes the compiler wait for it, and for every other load in
+// flight, inside that branch, which would undo the prefetch.
 template <typename T, int D1, int NP, int NYc, int KC>
 struct EdgeOps {
   T Y[NYc];
   T x[KC][D1];
   T w[KC][NP];
+  T dyo;  // adjoint: this edge's earlier share of dE/dY (the lane's value)
+  int p;  // pair slot 2 p + side
+};
+struct EdgeIdx {
+  int s, p;
 };
 
 template <typename T, int D1, int NP, int NYc, int KC>
-__device__ inline void load_edge(const TPArgs& g, const TPDeg& a, int64_t e, int s, int pr, int uu,
-                                 const T* __restrict__ Y, const T* __restrict__ x,
+__device__ inline void load_edge(const TPArgs& g, const TPDeg& a, const int (&uc)[KC], int64_t e,
+                                 const EdgeIdx& ix, const T* __restrict__ Y, const T* __restrict__ x,
                                  const T* __restrict__ w, EdgeOps<T, D1, NP, NYc, KC>& o) {
 #pragma unroll
   for (int q = 0; q < NYc; ++q) o.Y[q] = Y[e * g.NY + q];
-  const int64_t wrow = (int64_t)pr * g.P + a.woff;
+  const int64_t wrow = (int64_t)(ix.p >> 1) * g.P + a.woff;
+  const int64_t xrow = (int64_t)ix.s * g.Dx + a.xoff;
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
-    const int u = uu + c * a.cpt;
-    const bool ok = c < a.cpl && u < a.mul;
 #pragma unroll
-    for (int m1 = 0; m1 < D1; ++m1)
-      o.x[c][m1] = ok ? x[(int64_t)s * g.Dx + a.xoff + m1 * a.mul + u] : T(0);
+    for (int m1 = 0; m1 < D1; ++m1) o.x[c][m1] = x[xrow + m1 * a.mul + uc[c]];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) o.w[c][p] = ok ? w[wrow + p * a.mul + u] : T(0);
+    for (int p = 0; p < NP; ++p) o.w[c][p] = w[wrow + p * a.mul + uc[c]];
+  }
+  o.p = ix.p;
+}
+
+// Runs compute(k, ops) for every edge iteration k < n_it of a receiver through the ring
+// pipeline; extra(k, ops) adds per-edge loads of the caller (issued with the operands).
+template <int R, typename OPS, class Load, class Compute>
+__device__ inline void edge_pipeline(const TPArgs& g, int beg, int end, int EI, int ei, int n_it,
+                                     Load&& load, Compute&& compute) {
+  const int deg = end - beg;
+  auto edge_of = [&](int kl) { return beg + min(kl * EI + ei, deg - 1); };
+  auto load_idx = [&](int kl, EdgeIdx& d) {
+    const int e = edge_of(kl);
+    d.s = g.src[e];
+    d.p = g.pidx[e];
+  };
+  EdgeIdx ix[R];
+  OPS ops[R];
+  static_for<R>([&](auto J) { load_idx(decltype(J)::value, ix[decltype(J)::value]); });
+  static_for<R - 1>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    load(edge_of(j), ix[j], ops[j]);
+    load_idx(j + R, ix[j]);
+  });
+  for (int k = 0; k < n_it; k += R) {
+    static_for<R>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      constexpr int jf = (j + R - 1) % R;
+      const int kk = k + j;
+      load(edge_of(kk + R - 1), ix[jf], ops[jf]);
+      load_idx(kk + 2 * R - 1, ix[jf]);
+      if (kk < n_it) compute(kk, ops[j]);
+    });
   }
 }
 
-template <typename T, int L1, int LSH, int L3MAX, bool SO>
+template <typename T, int L1, int LSH, int L3MAX, bool SO, int CPT>
 __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ Y,
                                                  const T* __restrict__ x, const T* __restrict__ w,
                                                  T* __restrict__ M, T inv_k) {
@@ -143,11 +187,14 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
   constexpr int NYc = (LSH + 1) * (LSH + 1);
   constexpr int NO = PL::NOUT;
   constexpr int KC = CPL<L1>::value;
-  const int i = blockIdx.x * kRecvPerBlock + (threadIdx.x >> 6);
+  // receiver of this wave (wave-uniform; kept in a scalar register)
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kRecvPerBlock + (threadIdx.x >> 6));
   if (i >= g.n_recv) return;
   const TPDeg& a = g.d;
   const int lane = threadIdx.x & 63;
-  const int cpt = a.cpt, EI = kWave / cpt, ei = lane / cpt, uu = lane % cpt;
+  // lanes per edge slot: a compile-time 64 or 32 for the common widths (a 64-lane slot makes
+  // every edge index wave-uniform), else the runtime value
+  const int cpt = CPT ? CPT : a.cpt, EI = kWave / cpt, ei = lane / cpt, uu = lane % cpt;
   T acc[KC][NO];
 #pragma unroll
   for (int c = 0; c < KC; ++c)
@@ -155,35 +202,37 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
     for (int q = 0; q < NO; ++q) acc[c][q] = T(0);
   const int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
   const int n_it = (end - beg + EI - 1) / EI;
-  // software pipeline: indices two edges ahead, operands one edge ahead
-  int e1 = beg + ei, e2 = beg + EI + ei;
-  int s1 = e1 < end ? g.src[e1] : 0, p1 = e1 < end ? g.pidx[e1] : 0;
-  int s2 = e2 < end ? g.src[e2] : 0, p2 = e2 < end ? g.pidx[e2] : 0;
-  EdgeOps<T, D1, NP, NYc, KC> cur, nxt;
-  if (e1 < end) load_edge<T, D1, NP, NYc, KC>(g, a, e1, s1, p1, uu, Y, x, w, cur);
-  for (int it = 0; it < n_it; ++it) {
-    const int ec = beg + it * EI + ei;
-    const int en = ec + EI, e3 = ec + 2 * EI;
-    const int s3 = e3 < end ? g.src[e3] : 0, p3 = e3 < end ? g.pidx[e3] : 0;
-    if (en < end) load_edge<T, D1, NP, NYc, KC>(g, a, en, s2, p2, uu, Y, x, w, nxt);
-    if (ec < end) {
+  int uc[KC];
+  bool ok[KC];
 #pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        T t[NO];
-        tp_paths<T, L1, PL>(cur.x[c], cur.Y, t);
-        static_for<NP>([&](auto P) {
-          constexpr int p = decltype(P)::value;
-          constexpr int D3 = 2 * PL::l3(p) + 1;
-          constexpr int oo = PL::ooff(p);
-#pragma unroll
-          for (int m3 = 0; m3 < D3; ++m3) acc[c][oo + m3] += cur.w[c][p] * t[oo + m3];
-        });
-      }
-    }
-    cur = nxt;
-    s2 = s3;
-    p2 = p3;
+  for (int c = 0; c < KC; ++c) {
+    const int u = uu + c * cpt;
+    ok[c] = c < a.cpl && u < a.mul;
+    uc[c] = ok[c] ? u : 0;
   }
+  using Ops = EdgeOps<T, D1, NP, NYc, KC>;
+  if (n_it > 0)
+    edge_pipeline<4, Ops>(
+        g, beg, end, EI, ei, n_it,
+        [&](int e, const EdgeIdx& ix, Ops& o) {
+          load_edge<T, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
+        },
+        [&](int k, const Ops& cur) {
+          const bool active = beg + k * EI + ei < end;
+#pragma unroll
+          for (int c = 0; c < KC; ++c) {
+            T t[NO];
+            tp_paths<T, L1, PL>(cur.x[c], cur.Y, t);
+            static_for<NP>([&](auto P) {
+              constexpr int p = decltype(P)::value;
+              constexpr int D3 = 2 * PL::l3(p) + 1;
+              constexpr int oo = PL::ooff(p);
+              const T wv = (active && ok[c]) ? cur.w[c][p] : T(0);
+#pragma unroll
+              for (int m3 = 0; m3 < D3; ++m3) acc[c][oo + m3] += wv * t[oo + m3];
+            });
+          }
+        });
   for (int off = cpt; off < kWave; off <<= 1) {
 #pragma unroll
     for (int c = 0; c < KC; ++c)
@@ -254,7 +303,7 @@ __device__ inline void slot_reduce(T (&v)[NV], int cpt, int lane) {
 
 // Adjoint of one degree's paths: writes dE/dw (per edge), the per-edge dE/dx rows, and
 // adds this degree's share of dE/dY (set instead when accumulate is 0).
-template <typename T, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX>
+template <typename T, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX, int CPT>
 __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ Y,
                                                  const T* __restrict__ x, const T* __restrict__ w,
                                                  const T* __restrict__ G, T* __restrict__ dw,
@@ -266,11 +315,14 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   constexpr int NYc = (LSH + 1) * (LSH + 1);
   constexpr int NO = PL::NOUT;
   constexpr int KC = CPL<L1>::value;
-  const int i = blockIdx.x * kRecvPerBlock + (threadIdx.x >> 6);
+  // receiver of this wave (wave-uniform; kept in a scalar register)
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kRecvPerBlock + (threadIdx.x >> 6));
   if (i >= g.n_recv) return;
   const TPDeg& a = g.d;
   const int lane = threadIdx.x & 63;
-  const int cpt = a.cpt, EI = kWave / cpt, ei = lane / cpt, uu = lane % cpt;
+  // lanes per edge slot: a compile-time 64 or 32 for the common widths (a 64-lane slot makes
+  // every edge index wave-uniform), else the runtime value
+  const int cpt = CPT ? CPT : a.cpt, EI = kWave / cpt, ei = lane / cpt, uu = lane % cpt;
   T gin[KC][NO];
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
@@ -287,9 +339,13 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   }
   const int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
   const int n_it = (end - beg + EI - 1) / EI;
-  int e1 = beg + ei, e2 = beg + EI + ei;
-  int s1 = e1 < end ? g.src[e1] : 0, p1 = e1 < end ? g.pidx[e1] : 0;
-  int s2 = e2 < end ? g.src[e2] : 0, p2 = e2 < end ? g.pidx[e2] : 0;
+  if (n_it == 0) return;
+  int uc[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const int u = uu + c * cpt;
+    uc[c] = (c < a.cpl && u < a.mul) ? u : 0;
+  }
   // dE/dY: NV = NYc rounded up to a power of two values per lane, reduced per edge slot.
   // With at least NV lanes per slot (every degree of at least NV channels) the transposed
   // butterfly leaves one complete value per storing lane; narrower slots take a plain
@@ -298,77 +354,74 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   const bool wide = cpt >= NV;
   const int j0 = wide ? slot_first_value<NV>(uu, cpt) : 0;
   const bool storer = wide ? (uu & slot_store_mask<NV>(cpt)) == 0 && j0 < NYc : uu == 0;
-  EdgeOps<T, D1, NP, NYc, KC> cur, nxt;
-  if (e1 < end) load_edge<T, D1, NP, NYc, KC>(g, a, e1, s1, p1, uu, Y, x, w, cur);
-  for (int it = 0; it < n_it; ++it) {
-    const int ec = beg + it * EI + ei;
-    const int en = ec + EI, e3 = ec + 2 * EI;
-    const int s3 = e3 < end ? g.src[e3] : 0, p3 = e3 < end ? g.pidx[e3] : 0;
-    if (en < end) load_edge<T, D1, NP, NYc, KC>(g, a, en, s2, p2, uu, Y, x, w, nxt);
-    const bool active = ec < end;
-    // earlier degrees' (or blocks') share of this edge's dE/dY, fetched before the compute
-    T dYold = T(0);
-    if (wide && accumulate && active && storer) dYold = dY[(int64_t)ec * g.NY + j0];
-    T dYl[NV];
+  const int jl = min(j0, NYc - 1);
+  using Ops = EdgeOps<T, D1, NP, NYc, KC>;
+  edge_pipeline<3, Ops>(
+      g, beg, end, EI, ei, n_it,
+      [&](int e, const EdgeIdx& ix, Ops& o) {
+        load_edge<T, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
+        o.dyo = dY[(int64_t)e * g.NY + jl];  // earlier share of this edge's dE/dY
+      },
+      [&](int k, const Ops& cur) {
+        const int ec = beg + k * EI + ei;
+        const bool active = ec < end;
+        T dYl[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) dYl[q] = T(0);
-    if (active) {
-      const int64_t e = ec;
-      const int64_t drow = e * g.P + a.woff;
+        for (int q = 0; q < NV; ++q) dYl[q] = T(0);
+        if (active) {
+          const int64_t e = ec;
+          const int64_t drow = (int64_t)cur.p * g.P + a.woff;  // pair-major dE/dw row
 #pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        const int u = uu + c * cpt;
-        if (c >= a.cpl || u >= a.mul) break;
-        const T* xv = cur.x[c];
-        T dxv[D1];
+          for (int c = 0; c < KC; ++c) {
+            const int u = uu + c * cpt;
+            if (c >= a.cpl || u >= a.mul) break;
+            const T* xv = cur.x[c];
+            T dxv[D1];
 #pragma unroll
-        for (int m1 = 0; m1 < D1; ++m1) dxv[m1] = T(0);
-        T t[NO];
-        tp_paths<T, L1, PL>(xv, cur.Y, t);
-        static_for<NP>([&](auto P) {
-          constexpr int p = decltype(P)::value;
-          constexpr int l2 = PL::l2(p), l3 = PL::l3(p);
-          constexpr int D3 = 2 * l3 + 1;
-          constexpr int oo = PL::ooff(p);
-          const T wv = cur.w[c][p];
-          T dwv = T(0);
-          T gg[D3];
+            for (int m1 = 0; m1 < D1; ++m1) dxv[m1] = T(0);
+            T t[NO];
+            tp_paths<T, L1, PL>(xv, cur.Y, t);
+            static_for<NP>([&](auto P) {
+              constexpr int p = decltype(P)::value;
+              constexpr int l2 = PL::l2(p), l3 = PL::l3(p);
+              constexpr int D3 = 2 * l3 + 1;
+              constexpr int oo = PL::ooff(p);
+              const T wv = cur.w[c][p];
+              T dwv = T(0);
+              T gg[D3];
 #pragma unroll
-          for (int m3 = 0; m3 < D3; ++m3) {
-            const T gi = gin[c][oo + m3];
-            dwv += gi * t[oo + m3];
-            gg[m3] = wv * gi;
+              for (int m3 = 0; m3 < D3; ++m3) {
+                const T gi = gin[c][oo + m3];
+                dwv += gi * t[oo + m3];
+                gg[m3] = wv * gi;
+              }
+              dw[drow + p * a.mul + u] = dwv;
+              CG<L1, l2, l3>::each([&](int m1, int m2, int m3, double cc) {
+                if (WRITE_DX) dxv[m1] += T(cc) * (cur.Y[l2 * l2 + m2] * gg[m3]);
+                dYl[l2 * l2 + m2] += T(cc) * (xv[m1] * gg[m3]);
+              });
+            });
+            if (WRITE_DX) {
+#pragma unroll
+              for (int m1 = 0; m1 < D1; ++m1) dxe[e * g.Dx + a.xoff + m1 * a.mul + u] = dxv[m1];
+            }
           }
-          dw[drow + p * a.mul + u] = dwv;
-          CG<L1, l2, l3>::each([&](int m1, int m2, int m3, double cc) {
-            if (WRITE_DX) dxv[m1] += T(cc) * (cur.Y[l2 * l2 + m2] * gg[m3]);
-            dYl[l2 * l2 + m2] += T(cc) * (xv[m1] * gg[m3]);
-          });
-        });
-        if (WRITE_DX) {
-#pragma unroll
-          for (int m1 = 0; m1 < D1; ++m1) dxe[e * g.Dx + a.xoff + m1 * a.mul + u] = dxv[m1];
         }
-      }
-    }
-    if (wide) {
-      slot_reduce<T, NV>(dYl, cpt, lane);
-      if (active && storer) dY[(int64_t)ec * g.NY + j0] = dYold + dYl[0];
-    } else {
-      for (int off = 1; off < cpt; off <<= 1) {
+        if (wide) {
+          slot_reduce<T, NV>(dYl, cpt, lane);
+          if (active && storer) dY[(int64_t)ec * g.NY + j0] = (accumulate ? cur.dyo : T(0)) + dYl[0];
+        } else {
+          for (int off = 1; off < cpt; off <<= 1) {
 #pragma unroll
-        for (int q = 0; q < NYc; ++q) dYl[q] += __shfl_xor(dYl[q], off);
-      }
-      if (active && storer) {
-        T* dst = dY + (int64_t)ec * g.NY;
+            for (int q = 0; q < NYc; ++q) dYl[q] += __shfl_xor(dYl[q], off);
+          }
+          if (active && storer) {
+            T* dst = dY + (int64_t)ec * g.NY;
 #pragma unroll
-        for (int q = 0; q < NYc; ++q) dst[q] = accumulate ? dst[q] + dYl[q] : dYl[q];
-      }
-    }
-    cur = nxt;
-    s2 = s3;
-    p2 = p3;
-  }
+            for (int q = 0; q < NYc; ++q) dst[q] = accumulate ? dst[q] + dYl[q] : dYl[q];
+          }
+        }
+      });
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -399,17 +452,29 @@ static TPArgs make_args(const TPLayer& L, int l1, int n_recv, const int* row_ptr
   return a;
 }
 
-template <typename T, int L1, int LSH, int LMX, bool SO>
-static void launch_one(bool fwd, const TPArgs& a, const T* Y, const T* x, const T* w, T* M, T inv_k,
+template <typename T, int L1, int LSH, int LMX, bool SO, int CPT>
+static void launch_cpt(bool fwd, const TPArgs& a, const T* Y, const T* x, const T* w, T* M, T inv_k,
                        const T* G, T* dw, T* dxe, T* dY, int acc, hipStream_t s) {
   const unsigned grid = (unsigned)((a.n_recv + kRecvPerBlock - 1) / kRecvPerBlock);
   const unsigned block = kWave * kRecvPerBlock;
   if (fwd)
-    k_tp_fwd<T, L1, LSH, LMX, SO><<<grid, block, 0, s>>>(a, Y, x, w, M, inv_k);
+    k_tp_fwd<T, L1, LSH, LMX, SO, CPT><<<grid, block, 0, s>>>(a, Y, x, w, M, inv_k);
   else if (dxe)
-    k_tp_bwd<T, L1, LSH, LMX, SO, true><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
+    k_tp_bwd<T, L1, LSH, LMX, SO, true, CPT><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
   else
-    k_tp_bwd<T, L1, LSH, LMX, SO, false><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
+    k_tp_bwd<T, L1, LSH, LMX, SO, false, CPT><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
+}
+template <typename T, int L1, int LSH, int LMX, bool SO>
+static void launch_one(bool fwd, const TPArgs& a, const T* Y, const T* x, const T* w, T* M, T inv_k,
+                       const T* G, T* dw, T* dxe, T* dY, int acc, hipStream_t s) {
+  // the forward gains from compile-time slot widths; the adjoint, whose per-edge shuffles
+  // share the scalar-load counter, runs faster with the runtime width
+  if (fwd && a.d.cpt == 64)
+    launch_cpt<T, L1, LSH, LMX, SO, 64>(fwd, a, Y, x, w, M, inv_k, G, dw, dxe, dY, acc, s);
+  else if (fwd && a.d.cpt == 32)
+    launch_cpt<T, L1, LSH, LMX, SO, 32>(fwd, a, Y, x, w, M, inv_k, G, dw, dxe, dY, acc, s);
+  else
+    launch_cpt<T, L1, LSH, LMX, SO, 0>(fwd, a, Y, x, w, M, inv_k, G, dw, dxe, dY, acc, s);
 }
 
 template <typename T>

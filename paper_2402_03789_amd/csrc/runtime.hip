@@ -17,6 +17,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -301,8 +302,14 @@ struct sn_ctx {
   bool reuse = false;       // keep the graph of the previous call when n and the cell match
   bool have_graph = false;
   std::vector<double> graph_cells;
+  // second stream for the radial MLPs, which depend only on the edge basis (forward) or
+  // on their own block's dE/dw (adjoint), so they overlap with the node-feature chain
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t> sync_pool;  // dependency events between the two streams
+  size_t sync_next = 0;
   // timing
   std::vector<std::pair<std::string, hipEvent_t>> marks;
+  std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> aux_marks;
   std::vector<std::pair<std::string, double>> timings;
   std::vector<hipEvent_t> event_pool;
   size_t event_next = 0;
@@ -315,6 +322,7 @@ struct sn_ctx {
       throw MemError("HBM budget exceeded allocating " + name);
     if (b.p) {
       HIPCHK(hipStreamSynchronize(stream));
+      if (aux) HIPCHK(hipStreamSynchronize(aux));
       HIPCHK(hipFree(b.p));
       used -= b.cap;
       b.p = nullptr;
@@ -333,6 +341,40 @@ struct sn_ctx {
   template <typename T>
   T* get(const std::string& name, int64_t count) {
     return static_cast<T*>(raw(name, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+  }
+  hipEvent_t sync_event() {
+    if (sync_next >= sync_pool.size()) {
+      hipEvent_t ev;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      sync_pool.push_back(ev);
+    }
+    return sync_pool[sync_next++];
+  }
+  // record on `producer`, make `waiter` wait for it; returns the event
+  hipEvent_t join(hipStream_t waiter, hipStream_t producer) {
+    hipEvent_t ev = sync_event();
+    HIPCHK(hipEventRecord(ev, producer));
+    HIPCHK(hipStreamWaitEvent(waiter, ev, 0));
+    return ev;
+  }
+  hipEvent_t timing_event() {
+    if (event_next >= event_pool.size()) {
+      hipEvent_t ev;
+      HIPCHK(hipEventCreate(&ev));
+      event_pool.push_back(ev);
+    }
+    return event_pool[event_next++];
+  }
+  // time one launch sequence on the aux stream
+  void aux_begin(const std::string& name) {
+    hipEvent_t a = timing_event();
+    HIPCHK(hipEventRecord(a, aux));
+    aux_marks.push_back({name, {a, nullptr}});
+  }
+  void aux_end() {
+    hipEvent_t b = timing_event();
+    HIPCHK(hipEventRecord(b, aux));
+    aux_marks.back().second.second = b;
   }
   void mark(const std::string& name) {
     if (event_next >= event_pool.size()) {
@@ -371,6 +413,11 @@ const float* W<float>(const sn_ctx* c, int64_t off) {
 
 void upload_weights(sn_ctx* c) {
   const sn_model* m = c->m;
+  // SN_SERIAL in the environment keeps every launch on the context's stream (clean
+  // per-kernel timings for profiling); otherwise the radial MLPs get a second stream
+  const char* serial = std::getenv("SN_SERIAL");
+  if (serial && serial[0] && serial[0] != '0') c->aux = c->stream;
+  else HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
   std::vector<float> w32(m->flat.size());
   for (size_t i = 0; i < w32.size(); ++i) w32[i] = (float)m->flat[i];
   HIPCHK(hipMalloc(&c->d_w, m->flat.size() * sizeof(double)));
@@ -641,6 +688,13 @@ struct Pipe {
   bool bf16;
   explicit Pipe(sn_ctx* ctx)
       : c(ctx), m(ctx->m), s(ctx->stream), bf16(ctx->precision == SN_BF16) {}
+  // launches inside the scope go to another stream
+  struct OnStream {
+    Pipe* p;
+    hipStream_t old;
+    OnStream(Pipe* pp, hipStream_t ns) : p(pp), old(pp->s) { p->s = ns; }
+    ~OnStream() { p->s = old; }
+  };
 
   // float32-accumulated contractions (and every contraction of the BF16 form) run on the
   // matrix cores; float64-accumulated ones on the vector units.
@@ -704,6 +758,22 @@ struct Pipe {
     T* rho = c->get<T>("rho", E * m->nb);
     c->mark("edge_basis");
     launch_edge_basis<T>(E, recv, src, pos_ext, m->rc, m->nb, m->p, m->lsh, Y, rho, s);
+    // radial weights of every block on the aux stream: they need only rho
+    std::vector<hipEvent_t> w_ready(m->T);
+    c->join(c->aux, s);
+    for (int t = 0; t < m->T; ++t) {
+      const LayerDesc& L = m->layers[t];
+      const std::string ts = std::to_string(t);
+      T* w = c->get<T>("w" + ts, c->NP * L.P);
+      c->aux_begin("layer" + ts + ".mlp");
+      {
+        OnStream os(this, c->aux);
+        mlp_forward(L, rho, w);
+      }
+      c->aux_end();
+      w_ready[t] = c->sync_event();
+      HIPCHK(hipEventRecord(w_ready[t], c->aux));
+    }
     const T act = (T)m->act;
     const int C0 = m->muls[0];
     // h^(1): embedding rows for locals and ghosts (a ghost's first features come from its species)
@@ -717,10 +787,11 @@ struct Pipe {
       T* x = c->get<T>("x" + ts, (int64_t)NE * L.hin.width);
       double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
       const int xrows = (t == 0) ? NE : N;  // block 1: ghosts from their own species
+      // Lin1 accumulates in the edge type: x only feeds the tensor product, which runs in it
       for (int l : L.ins)
-        gemm<double, double, T, double>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
-                                        rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], false, x,
-                                        rows_of(L.hin, l), 1.0, false);
+        gemm<double, T, T, T>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
+                              rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], false, x,
+                              rows_of(L.hin, l), T(1), false);
       if (t > 0) {
         c->mark("layer" + ts + ".ghost_refresh");
         launch_ghost_refresh<T>(N, G, owner, x, L.hin.width, s);
@@ -731,10 +802,9 @@ struct Pipe {
           gemm<double, double, double, double>((int64_t)N * (2 * l + 1), L.gmul[l], L.hin.mul[l], h,
                                                rows_of(L.hin, l), L.w_linsc[l], L.gmul[l], false, y,
                                                rows_of(L.yl, l), 1.0, false);
-      c->mark("layer" + ts + ".mlp");
       T* w = c->get<T>("w" + ts, c->NP * L.P);
-      mlp_forward(L, rho, w);
       c->mark("layer" + ts + ".tp");
+      HIPCHK(hipStreamWaitEvent(s, w_ready[t], 0));
       T* M = c->get<T>("M", (int64_t)N * L.ml.width);
       launch_tp_fwd<T>(L.tp, N, row_ptr, src, pidx, Y, x, w, M, (T)(1.0 / m->kavg), s);
       c->mark("layer" + ts + ".linear_out");
@@ -791,7 +861,10 @@ struct Pipe {
     double* dh_other = c->get<double>("dh_b", (int64_t)N * max_w);
     double* dy = c->get<double>("dy", (int64_t)N * max_y);
     T* Gm = c->get<T>("G", (int64_t)N * max_m);
-    T* dw = c->get<T>("dw", E * max_P);
+    // dE/dw alternates between two buffers: the MLP adjoint of block t (aux stream) reads
+    // one while the tensor-product adjoint of block t-1 writes the other
+    T* dw_buf[2] = {c->get<T>("dw_a", 2 * c->NP * max_P), c->get<T>("dw_b", 2 * c->NP * max_P)};
+    std::vector<hipEvent_t> mlp_done(m->T, nullptr);
     T* dxe = c->get<T>("dxe", E * max_w);
     double* dx_ext = c->get<double>("dx_ext", (int64_t)NE * max_w);
     double* dx = c->get<double>("dx", (int64_t)N * max_w);
@@ -815,10 +888,19 @@ struct Pipe {
                               L.w_lin2[l], L.gmul[l], true, Gm, rows_of(L.ml, l),
                               (T)(1.0 / m->kavg), false);
       c->mark("bwd.layer" + ts + ".tp");
+      T* dw = dw_buf[t % 2];
+      if (t + 2 < m->T) HIPCHK(hipStreamWaitEvent(s, mlp_done[t + 2], 0));
       launch_tp_bwd<T>(L.tp, N, row_ptr, src, pidx, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dY,
                        t != m->T - 1, s);
-      c->mark("bwd.layer" + ts + ".mlp");
-      mlp_backward(L, rho, dw, dz2, drho);
+      c->join(c->aux, s);
+      c->aux_begin("bwd.layer" + ts + ".mlp");
+      {
+        OnStream os(this, c->aux);
+        mlp_backward(L, rho, dw, dz2, drho);
+      }
+      c->aux_end();
+      mlp_done[t] = c->sync_event();
+      HIPCHK(hipEventRecord(mlp_done[t], c->aux));
       if (t == 0) break;
       c->mark("bwd.layer" + ts + ".sender_fold");
       // sender-side sums over every extended row, then fold ghost rows onto owners
@@ -838,6 +920,7 @@ struct Pipe {
     }
     c->mark("bwd.forces");
     double* gE = c->get<double>("g_edge", 3 * E);
+    HIPCHK(hipStreamWaitEvent(s, mlp_done[0], 0));  // every block's dE/drho is in
     launch_edge_grad<T>(E, recv, src, pos_ext, m->rc, m->nb, m->p, m->lsh, dY, drho, gE, s);
     double* F = c->get<double>("F_local", 3 * (int64_t)N);
     launch_forces(N, row_ptr, sptr, sidx, gptr, gE, F, s);
@@ -859,6 +942,7 @@ struct Pipe {
 // dropped.  False when the device reported an error meanwhile (the context is then dead).
 bool release_workspace(sn_ctx* c) {
   bool ok = hipStreamSynchronize(c->stream) == hipSuccess;
+  if (c->aux && hipStreamSynchronize(c->aux) != hipSuccess) ok = false;
   for (auto& kv : c->bufs)
     if (kv.second.p && hipFree(kv.second.p) != hipSuccess) ok = false;
   c->bufs.clear();
@@ -866,6 +950,7 @@ bool release_workspace(sn_ctx* c) {
   c->have_graph = false;
   c->pending = false;
   c->marks.clear();
+  c->aux_marks.clear();
   if (!ok) c->dead = true;
   return ok;
 }
@@ -881,6 +966,14 @@ void collect_timings(sn_ctx* c) {
     HIPCHK(hipEventElapsedTime(&ms, c->marks[i].second, c->marks[i + 1].second));
     if (!acc.count(c->marks[i].first)) orderv.push_back(c->marks[i].first);
     acc[c->marks[i].first] += ms;
+  }
+  for (auto& am : c->aux_marks) {
+    if (!am.second.second) continue;
+    HIPCHK(hipEventSynchronize(am.second.second));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, am.second.first, am.second.second));
+    if (!acc.count(am.first)) orderv.push_back(am.first);
+    acc[am.first] += ms;
   }
   for (auto& k : orderv) c->timings.push_back({k, acc[k]});
 }
@@ -925,7 +1018,9 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
   const int64_t n = offsets[B];
   if (n <= 0 || n > (1 << 28)) throw ArgError("atom count out of range");
   c->marks.clear();
+  c->aux_marks.clear();
   c->event_next = 0;
+  c->sync_next = 0;
   c->mark("graph");
   const bool same = c->have_graph && c->B == B && c->N == n &&
                     std::equal(offsets, offsets + B + 1, c->atom_off.begin()) &&
@@ -1067,6 +1162,7 @@ void sn_ctx_free(sn_ctx_t* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (ctx->d_w) (void)hipFree(ctx->d_w);
@@ -1074,6 +1170,11 @@ void sn_ctx_free(sn_ctx_t* ctx) {
   if (ctx->d_v) (void)hipFree(ctx->d_v);
   if (ctx->d_shift) (void)hipFree(ctx->d_shift);
   for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
+  for (auto ev : ctx->sync_pool) (void)hipEventDestroy(ev);
+  if (ctx->aux && ctx->aux != ctx->stream) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
   delete ctx;
 }
 
@@ -1113,6 +1214,7 @@ int sn_ctx_synchronize(sn_ctx_t* ctx) {
   if (!ctx) return SN_EINVAL;
   return guarded(ctx, [&] {
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->aux));
     collect_timings(ctx);
   });
 }
