@@ -126,13 +126,15 @@ def main():
     # interaction block, each timed by HIP events on the context's stream (in the
     # float32/bfloat16 forms each "bwd.layer<t>.mlp" phase holds exactly that launch).
     # Algorithmic bytes of a launch with P radial weights per pair: read dE/dw of both
-    # edges of every pair (2 x 4P bytes), read rho and write drho (2 x 32 bytes).
+    # edges of every pair (2 x P values of 4 bytes, 2 in the BF16 form, 8 in the FP64 form),
+    # read rho and write drho (2 x 32 bytes).
     npairs = ctx.n_pairs()
     Ps = [960 if 0 < t < 4 else (384 if t == 0 else 224) for t in range(5)]
     launches = [f"bwd.layer{t}.mlp" for t in range(5)]
     launch_ms = sum(phase_ms.get(k, 0.0) for k in launches) / (len(launches) * args.steps)
     P_mean = sum(Ps) / len(Ps)
-    bytes_per_launch = npairs * (2 * 4 * P_mean + 64)
+    wbytes = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
+    bytes_per_launch = npairs * (2 * wbytes * P_mean + 64)
     flops_per_launch = npairs * (2 * 64 * P_mean + 2 * (8 * 64 + 64 * 64 + 64 * 64 + 64 * 8))
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else None
     traffic = _traffic("k_mlp_fused_bwd", os.path.join(ROOT, "paper_2402_03789_amd", "csrc",

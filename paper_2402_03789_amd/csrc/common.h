@@ -36,6 +36,29 @@ __host__ __device__ inline RowMap plain_rows(int ld) { return RowMap{1, 0, (int6
 
 template <typename T> struct Acc { using type = T; };
 
+// bfloat16 storage of per-edge and per-node intermediates in the bfloat16 form (arithmetic
+// stays in float32): round to nearest even when stored, exact widening when loaded.
+struct bf16_t {
+  uint16_t u;
+};
+__device__ inline float sload(float v) { return v; }
+__device__ inline double sload(double v) { return v; }
+__device__ inline float sload(bf16_t v) { return __uint_as_float((uint32_t)v.u << 16); }
+template <typename S, typename T>
+__device__ inline S sstore(T v) {
+  return S(v);
+}
+template <>
+__device__ inline bf16_t sstore<bf16_t, float>(float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16_t{(uint16_t)(u >> 16)};
+}
+template <>
+__device__ inline bf16_t sstore<bf16_t, double>(double v) {
+  return sstore<bf16_t, float>((float)v);
+}
+
 __device__ inline float to_f(float v) { return v; }
 __device__ inline double to_f(double v) { return v; }
 

@@ -26,6 +26,16 @@ constexpr int MT = 64;  // block tile rows / cols
 template <typename T>
 __device__ inline float to_float(T v) { return (float)v; }
 
+// C element update (= v or += v) in the output type
+template <typename TC>
+__device__ inline void put(TC* c, float v, int accumulate) {
+  *c = accumulate ? (TC)(*c + (TC)v) : (TC)v;
+}
+template <>
+__device__ inline void put<bf16_t>(bf16_t* c, float v, int accumulate) {
+  *c = sstore<bf16_t>(accumulate ? sload(*c) + v : v);
+}
+
 __device__ inline __bf16 to_bf16(float v) {
   return __float2bfloat16(v);
 }
@@ -139,9 +149,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int64_t M, int N, int K, cons
       for (int rr = 0; rr < 4; ++rr) {
         const int64_t row = m0 + wr + i * 16 + row_q + rr;
         if (row >= M) continue;
-        TC* c = C + cm(row) + col;
-        float v = alpha * acc[i][j][rr];
-        *c = accumulate ? (TC)(*c + (TC)v) : (TC)v;
+        put(C + cm(row) + col, alpha * acc[i][j][rr], accumulate);
       }
     }
 }
@@ -293,9 +301,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_v(int64_t M, int N, int K, co
       for (int rr = 0; rr < 4; ++rr) {
         const int64_t row = m0 + wr + i * 16 + row_q + rr;
         if (row >= M) continue;
-        TC* c = C + cm(row) + col;
-        float v = alpha * acc[i][j][rr];
-        *c = accumulate ? (TC)(*c + (TC)v) : (TC)v;
+        put(C + cm(row) + col, alpha * acc[i][j][rr], accumulate);
       }
     }
 }
@@ -358,6 +364,7 @@ SN_MFMA_INST(double, float, float)
 SN_MFMA_INST(double, float, double)
 SN_MFMA_INST(double, double, float)
 SN_MFMA_INST(double, double, double)
+SN_MFMA_INST(double, float, bf16_t)
 #undef SN_MFMA_INST
 
 }  // namespace sn

@@ -25,6 +25,8 @@
 // that the 64 lanes of a fragment read hit distinct banks.
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace sn {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -147,12 +149,15 @@ __device__ inline void store_fwd_panel(const PanelRegs& r, int tid, int P, int n
 
 // ------------------------------------------------------------------ forward
 template <bool BF16>
+using WStore = typename std::conditional<BF16, bf16_t, float>::type;
+
+template <bool BF16>
 __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __restrict__ pe1,
                                                         const float* __restrict__ rho,
                                                         const float* __restrict__ Wa,
                                                         const float* __restrict__ Wb,
                                                         const float* __restrict__ Wc, int P, float c,
-                                                        float* __restrict__ w) {
+                                                        WStore<BF16>* __restrict__ w) {
   constexpr int PANEL = BF16 ? (HID * BP) / 2 : HID * WP;  // floats per panel buffer
   __shared__ float sWa[NBAS * HID];
   __shared__ float sRho[EB * (NBAS + 1)];
@@ -223,7 +228,14 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
       const int64_t p = p0 + wave * 16 + row;
       if (p < np && n0 + c4 < P) {
         const float* zr = &Z[row * ZP + c4];
-        *reinterpret_cast<floatx4*>(&w[p * P + n0 + c4]) = floatx4{zr[0], zr[1], zr[2], zr[3]};
+        if constexpr (BF16) {  // four bfloat16 values per lane: 128 contiguous bytes per row
+          uint2 v;
+          v.x = (uint32_t)sstore<bf16_t>(zr[0]).u | ((uint32_t)sstore<bf16_t>(zr[1]).u << 16);
+          v.y = (uint32_t)sstore<bf16_t>(zr[2]).u | ((uint32_t)sstore<bf16_t>(zr[3]).u << 16);
+          *reinterpret_cast<uint2*>(&w[p * P + n0 + c4]) = v;
+        } else {
+          *reinterpret_cast<floatx4*>(&w[p * P + n0 + c4]) = floatx4{zr[0], zr[1], zr[2], zr[3]};
+        }
       }
     }
     buf ^= 1;
@@ -258,29 +270,61 @@ __device__ inline void store_bwd_panel(const PanelRegs& r, int tid, int P, int k
 // again) and combined when the panel is used.  float32 form: lane group q covers
 // k = 16 u + 4 q + 0..3; bfloat16 form: k = 32 (u / 2) + 8 q + 4 (u % 2) + 0..3, the order
 // of the 16x16x32 operand.
-struct DwRegs {
+template <bool BF16>
+struct DwRegs;
+template <>
+struct DwRegs<false> {  // float32 dE/dw: 16 values per edge row per panel
   floatx4 a[HID / 16], b[HID / 16];
 };
-template <bool BF16>
-__device__ inline int dw_col(int k0, int u, int q) {
-  return BF16 ? k0 + 32 * (u >> 1) + 8 * q + 4 * (u & 1) : k0 + 16 * u + 4 * q;
-}
-template <bool BF16>
+template <>
+struct DwRegs<true> {  // bfloat16 dE/dw: 2 x 8 values per edge row per panel
+  uint4 a[HID / 32], b[HID / 32];
+};
+__device__ inline int dw_col(int k0, int u, int q) { return k0 + 16 * u + 4 * q; }
+__device__ inline int dw_col16(int k0, int s, int q) { return k0 + 32 * s + 8 * q; }
+
 __device__ inline void fetch_dw(const float* __restrict__ dw, int64_t r1, int64_t r2, int P, int k0,
-                                int q, DwRegs& d) {
+                                int q, DwRegs<false>& d) {
 #pragma unroll
   for (int u = 0; u < HID / 16; ++u) {
-    const int kb = min(dw_col<BF16>(k0, u, q), P - 4);  // P is a multiple of 4
+    const int kb = min(dw_col(k0, u, q), P - 4);  // P is a multiple of 4
     d.a[u] = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
     d.b[u] = *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
   }
 }
-template <bool BF16>
-__device__ inline floatx4 dw_value(const DwRegs& d, int u, bool row_ok, bool has2, int P, int k0,
-                                   int q) {
+__device__ inline void fetch_dw(const bf16_t* __restrict__ dw, int64_t r1, int64_t r2, int P,
+                                int k0, int q, DwRegs<true>& d) {
+#pragma unroll
+  for (int s = 0; s < HID / 32; ++s) {
+    const int kb = min(dw_col16(k0, s, q), P - 8);  // P is a multiple of 8
+    d.a[s] = *reinterpret_cast<const uint4*>(&dw[r1 + kb]);
+    d.b[s] = *reinterpret_cast<const uint4*>(&dw[r2 + kb]);
+  }
+}
+__device__ inline floatx4 dw_value(const DwRegs<false>& d, int u, bool row_ok, bool has2, int P,
+                                   int k0, int q) {
   const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
-  if (!row_ok || dw_col<BF16>(k0, u, q) >= P) return z;
+  if (!row_ok || dw_col(k0, u, q) >= P) return z;
   return has2 ? d.a[u] + d.b[u] : d.a[u];
+}
+// operand of the 16x16x32 product: the pair's summed dE/dw at k = 32 s + 8 q + 0..7
+__device__ inline bf16x8 dw_value16(const DwRegs<true>& d, int s, bool row_ok, bool has2, int P,
+                                    int k0, int q) {
+  const bool valid = row_ok && dw_col16(k0, s, q) < P;
+  const uint32_t av[4] = {d.a[s].x, d.a[s].y, d.a[s].z, d.a[s].w};
+  const uint32_t bv[4] = {d.b[s].x, d.b[s].y, d.b[s].z, d.b[s].w};
+  bf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float fa = __uint_as_float(h ? (av[i] & 0xffff0000u) : (av[i] << 16));
+      const float fb = __uint_as_float(h ? (bv[i] & 0xffff0000u) : (bv[i] << 16));
+      const float f = valid ? (has2 ? fa + fb : fa) : 0.f;
+      r[2 * i + h] = __float2bfloat16(f);
+    }
+  }
+  return r;
 }
 
 // ------------------------------------------------------------------ backward
@@ -291,7 +335,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
                                                         const float* __restrict__ Wa,
                                                         const float* __restrict__ Wb,
                                                         const float* __restrict__ Wc, int P, float c,
-                                                        const float* __restrict__ dw,
+                                                        const WStore<BF16>* __restrict__ dw,
                                                         float* __restrict__ drho, int accumulate) {
   __shared__ float sWa[NBAS * HID];
   __shared__ float sWb[HID * WP];
@@ -309,9 +353,9 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   const bool has2 = row_ok && pe2[pr] >= 0;
   const int64_t r2 = has2 ? r1 + P : r1;
   PanelRegs wr;
-  DwRegs dr_cur, dr_nxt;
+  DwRegs<BF16> dr_cur, dr_nxt;
   fetch_bwd_panel(Wc, P, 0, tid, wr);
-  fetch_dw<BF16>(dw, r1, r2, P, 0, q, dr_cur);
+  fetch_dw(dw, r1, r2, P, 0, q, dr_cur);
   __syncthreads();
   float* Z = sZ[wave];
   // recompute a1 and a2 (accumulator layout)
@@ -330,23 +374,16 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   // panel loop is unrolled by two so the two operand sets alternate registers (no copies).
   const int npan = (P + HID - 1) / HID;
   int buf = 0;
-  auto step = [&](int jj, const DwRegs& cur, DwRegs& nxt) {
+  auto step = [&](int jj, const DwRegs<BF16>& cur, DwRegs<BF16>& nxt) {
     const int k0 = jj * HID;
     fetch_bwd_panel(Wc, P, k0 + HID, tid, wr);
-    fetch_dw<BF16>(dw, r1, r2, P, k0 + HID, q, nxt);
+    fetch_dw(dw, r1, r2, P, k0 + HID, q, nxt);
     if (jj < npan) {
-      if (BF16) {
+      if constexpr (BF16) {
         const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
 #pragma unroll
         for (int s = 0; s < HID / 32; ++s) {
-          bf16x8 a;
-          const floatx4 lo = dw_value<true>(cur, 2 * s, row_ok, has2, P, k0, q);
-          const floatx4 hi = dw_value<true>(cur, 2 * s + 1, row_ok, has2, P, k0, q);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            a[e] = __float2bfloat16(lo[e]);
-            a[e + 4] = __float2bfloat16(hi[e]);
-          }
+          const bf16x8 a = dw_value16(cur, s, row_ok, has2, P, k0, q);
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
@@ -357,7 +394,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
         const float* sf = sB[buf];
 #pragma unroll
         for (int u = 0; u < HID / 16; ++u) {
-          const floatx4 av = dw_value<false>(cur, u, row_ok, has2, P, k0, q);
+          const floatx4 av = dw_value(cur, u, row_ok, has2, P, k0, q);
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const floatx4 bv =
@@ -407,25 +444,37 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   }
 }
 
+template <typename WS>
 void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
-                          const float* Wb, const float* Wc, int P, float c, float* w, bool bf16,
-                          hipStream_t s) {
+                          const float* Wb, const float* Wc, int P, float c, WS* w, hipStream_t s) {
   if (np <= 0) return;
   const unsigned grid = (unsigned)((np + EB - 1) / EB);
-  if (bf16) k_mlp_fused_fwd<true><<<grid, 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wc, P, c, w);
-  else k_mlp_fused_fwd<false><<<grid, 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wc, P, c, w);
+  constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
+  k_mlp_fused_fwd<BF16><<<grid, 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wc, P, c, w);
 }
 
+template <typename WS>
 void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
                           const float* Wa, const float* Wb, const float* Wc, int P, float c,
-                          const float* dw, float* drho, bool accumulate, bool bf16, hipStream_t s) {
+                          const WS* dw, float* drho, bool accumulate, hipStream_t s) {
   if (np <= 0) return;
   const unsigned grid = (unsigned)((np + EB - 1) / EB);
-  const int acc = accumulate ? 1 : 0;
-  if (bf16)
-    k_mlp_fused_bwd<true><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wc, P, c, dw, drho, acc);
-  else
-    k_mlp_fused_bwd<false><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wc, P, c, dw, drho, acc);
+  constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
+  k_mlp_fused_bwd<BF16><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wc, P, c, dw, drho,
+                                             accumulate ? 1 : 0);
 }
+
+template void launch_mlp_fused_fwd<float>(int64_t, const int*, const float*, const float*,
+                                          const float*, const float*, int, float, float*,
+                                          hipStream_t);
+template void launch_mlp_fused_fwd<bf16_t>(int64_t, const int*, const float*, const float*,
+                                           const float*, const float*, int, float, bf16_t*,
+                                           hipStream_t);
+template void launch_mlp_fused_bwd<float>(int64_t, const int*, const int*, const float*,
+                                          const float*, const float*, const float*, int, float,
+                                          const float*, float*, bool, hipStream_t);
+template void launch_mlp_fused_bwd<bf16_t>(int64_t, const int*, const int*, const float*,
+                                           const float*, const float*, const float*, int, float,
+                                           const bf16_t*, float*, bool, hipStream_t);
 
 }  // namespace sn

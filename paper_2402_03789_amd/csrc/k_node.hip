@@ -135,12 +135,12 @@ __global__ void k_sender_reduce(int n_rows, const int* __restrict__ sptr, const 
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] += (double)v[k][j];
+        for (int j = 0; j < 4; ++j) acc[j] += (double)sload(v[k][j]);
     }
     for (; q < b; ++q) {
       const T* row = dxe + (int64_t)sidx[q] * width + c;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] += (double)row[j];
+      for (int j = 0; j < 4; ++j) acc[j] += (double)sload(row[j]);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) dx[(int64_t)s * width + c + j] = acc[j];
@@ -403,5 +403,9 @@ void launch_unpermute(int n, const int* order, const double* in_rows, int width,
 SN_INST(float)
 SN_INST(double)
 #undef SN_INST
+// bfloat16 storage of sender features and per-edge sender gradient rows
+template void launch_ghost_refresh<bf16_t>(int, int, const int*, bf16_t*, int, hipStream_t);
+template void launch_sender_reduce<bf16_t>(int, const int*, const int*, const bf16_t*, int, double*,
+                                           hipStream_t);
 
 }  // namespace sn

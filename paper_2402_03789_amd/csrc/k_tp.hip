@@ -127,10 +127,10 @@ struct EdgeIdx {
   int s, p;
 };
 
-template <typename T, int D1, int NP, int NYc, int KC>
+template <typename T, typename S, int D1, int NP, int NYc, int KC>
 __device__ inline void load_edge(const TPArgs& g, const TPDeg& a, const int (&uc)[KC], int64_t e,
-                                 const EdgeIdx& ix, const T* __restrict__ Y, const T* __restrict__ x,
-                                 const T* __restrict__ w, EdgeOps<T, D1, NP, NYc, KC>& o) {
+                                 const EdgeIdx& ix, const T* __restrict__ Y, const S* __restrict__ x,
+                                 const S* __restrict__ w, EdgeOps<T, D1, NP, NYc, KC>& o) {
 #pragma unroll
   for (int q = 0; q < NYc; ++q) o.Y[q] = Y[e * g.NY + q];
   const int64_t wrow = (int64_t)(ix.p >> 1) * g.P + a.woff;
@@ -138,9 +138,9 @@ __device__ inline void load_edge(const TPArgs& g, const TPDeg& a, const int (&uc
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
 #pragma unroll
-    for (int m1 = 0; m1 < D1; ++m1) o.x[c][m1] = x[xrow + m1 * a.mul + uc[c]];
+    for (int m1 = 0; m1 < D1; ++m1) o.x[c][m1] = (T)sload(x[xrow + m1 * a.mul + uc[c]]);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) o.w[c][p] = w[wrow + p * a.mul + uc[c]];
+    for (int p = 0; p < NP; ++p) o.w[c][p] = (T)sload(w[wrow + p * a.mul + uc[c]]);
   }
   o.p = ix.p;
 }
@@ -177,9 +177,9 @@ __device__ inline void edge_pipeline(const TPArgs& g, int beg, int end, int EI, 
   }
 }
 
-template <typename T, int L1, int LSH, int L3MAX, bool SO, int CPT>
+template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, int CPT>
 __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ Y,
-                                                 const T* __restrict__ x, const T* __restrict__ w,
+                                                 const S* __restrict__ x, const S* __restrict__ w,
                                                  T* __restrict__ M, T inv_k) {
   using PL = PathList<L1, LSH, L3MAX, SO>;
   constexpr int NP = PL::count();
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
     edge_pipeline<4, Ops>(
         g, beg, end, EI, ei, n_it,
         [&](int e, const EdgeIdx& ix, Ops& o) {
-          load_edge<T, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
+          load_edge<T, S, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
         },
         [&](int k, const Ops& cur) {
           const bool active = beg + k * EI + ei < end;
@@ -303,11 +303,11 @@ __device__ inline void slot_reduce(T (&v)[NV], int cpt, int lane) {
 
 // Adjoint of one degree's paths: writes dE/dw (per edge), the per-edge dE/dx rows, and
 // adds this degree's share of dE/dY (set instead when accumulate is 0).
-template <typename T, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX, int CPT>
+template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX, int CPT>
 __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ Y,
-                                                 const T* __restrict__ x, const T* __restrict__ w,
-                                                 const T* __restrict__ G, T* __restrict__ dw,
-                                                 T* __restrict__ dxe, T* __restrict__ dY,
+                                                 const S* __restrict__ x, const S* __restrict__ w,
+                                                 const T* __restrict__ G, S* __restrict__ dw,
+                                                 S* __restrict__ dxe, T* __restrict__ dY,
                                                  int accumulate) {
   using PL = PathList<L1, LSH, L3MAX, SO>;
   constexpr int NP = PL::count();
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   edge_pipeline<3, Ops>(
       g, beg, end, EI, ei, n_it,
       [&](int e, const EdgeIdx& ix, Ops& o) {
-        load_edge<T, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
+        load_edge<T, S, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
         o.dyo = dY[(int64_t)e * g.NY + jl];  // earlier share of this edge's dE/dY
       },
       [&](int k, const Ops& cur) {
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
                 dwv += gi * t[oo + m3];
                 gg[m3] = wv * gi;
               }
-              dw[drow + p * a.mul + u] = dwv;
+              dw[drow + p * a.mul + u] = sstore<S>(dwv);
               CG<L1, l2, l3>::each([&](int m1, int m2, int m3, double cc) {
                 if (WRITE_DX) dxv[m1] += T(cc) * (cur.Y[l2 * l2 + m2] * gg[m3]);
                 dYl[l2 * l2 + m2] += T(cc) * (xv[m1] * gg[m3]);
@@ -403,7 +403,8 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
             });
             if (WRITE_DX) {
 #pragma unroll
-              for (int m1 = 0; m1 < D1; ++m1) dxe[e * g.Dx + a.xoff + m1 * a.mul + u] = dxv[m1];
+              for (int m1 = 0; m1 < D1; ++m1)
+                dxe[e * g.Dx + a.xoff + m1 * a.mul + u] = sstore<S>(dxv[m1]);
             }
           }
         }
@@ -452,35 +453,35 @@ static TPArgs make_args(const TPLayer& L, int l1, int n_recv, const int* row_ptr
   return a;
 }
 
-template <typename T, int L1, int LSH, int LMX, bool SO, int CPT>
-static void launch_cpt(bool fwd, const TPArgs& a, const T* Y, const T* x, const T* w, T* M, T inv_k,
-                       const T* G, T* dw, T* dxe, T* dY, int acc, hipStream_t s) {
+template <typename T, typename S, int L1, int LSH, int LMX, bool SO, int CPT>
+static void launch_fwd(const TPArgs& a, const T* Y, const S* x, const S* w, T* M, T inv_k,
+                       hipStream_t s) {
   const unsigned grid = (unsigned)((a.n_recv + kRecvPerBlock - 1) / kRecvPerBlock);
-  const unsigned block = kWave * kRecvPerBlock;
-  if (fwd)
-    k_tp_fwd<T, L1, LSH, LMX, SO, CPT><<<grid, block, 0, s>>>(a, Y, x, w, M, inv_k);
-  else if (dxe)
-    k_tp_bwd<T, L1, LSH, LMX, SO, true, CPT><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
-  else
-    k_tp_bwd<T, L1, LSH, LMX, SO, false, CPT><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
+  k_tp_fwd<T, S, L1, LSH, LMX, SO, CPT><<<grid, kWave * kRecvPerBlock, 0, s>>>(a, Y, x, w, M, inv_k);
 }
-template <typename T, int L1, int LSH, int LMX, bool SO>
-static void launch_one(bool fwd, const TPArgs& a, const T* Y, const T* x, const T* w, T* M, T inv_k,
-                       const T* G, T* dw, T* dxe, T* dY, int acc, hipStream_t s) {
+template <typename T, typename S, int L1, int LSH, int LMX, bool SO>
+static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const S* w, T* M, T inv_k,
+                       const T* G, S* dw, S* dxe, T* dY, int acc, hipStream_t s) {
   // the forward gains from compile-time slot widths; the adjoint, whose per-edge shuffles
   // share the scalar-load counter, runs faster with the runtime width
-  if (fwd && a.d.cpt == 64)
-    launch_cpt<T, L1, LSH, LMX, SO, 64>(fwd, a, Y, x, w, M, inv_k, G, dw, dxe, dY, acc, s);
-  else if (fwd && a.d.cpt == 32)
-    launch_cpt<T, L1, LSH, LMX, SO, 32>(fwd, a, Y, x, w, M, inv_k, G, dw, dxe, dY, acc, s);
+  if (fwd) {
+    if (a.d.cpt == 64) launch_fwd<T, S, L1, LSH, LMX, SO, 64>(a, Y, x, w, M, inv_k, s);
+    else if (a.d.cpt == 32) launch_fwd<T, S, L1, LSH, LMX, SO, 32>(a, Y, x, w, M, inv_k, s);
+    else launch_fwd<T, S, L1, LSH, LMX, SO, 0>(a, Y, x, w, M, inv_k, s);
+    return;
+  }
+  const unsigned grid = (unsigned)((a.n_recv + kRecvPerBlock - 1) / kRecvPerBlock);
+  const unsigned block = kWave * kRecvPerBlock;
+  if (dxe)
+    k_tp_bwd<T, S, L1, LSH, LMX, SO, true, 0><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
   else
-    launch_cpt<T, L1, LSH, LMX, SO, 0>(fwd, a, Y, x, w, M, inv_k, G, dw, dxe, dY, acc, s);
+    k_tp_bwd<T, S, L1, LSH, LMX, SO, false, 0><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
 }
 
-template <typename T>
+template <typename T, typename S>
 static void run(const TPLayer& L, bool fwd, int n_recv, const int* row_ptr, const int* src,
-                const int* pidx, const T* Y, const T* x, const T* w, T* M, T inv_k, const T* G,
-                T* dw, T* dxe, T* dY, bool accumulate, hipStream_t s) {
+                const int* pidx, const T* Y, const S* x, const S* w, T* M, T inv_k, const T* G,
+                S* dw, S* dxe, T* dY, bool accumulate, hipStream_t s) {
   if (n_recv <= 0) return;
   bool first = true;
   for (int l1 = 0; l1 <= L.lmax; ++l1) {
@@ -490,7 +491,7 @@ static void run(const TPLayer& L, bool fwd, int n_recv, const int* row_ptr, cons
     first = false;
 #define SN_TP_CASE(LL1, LSH, LMX, SO)                                                        \
   if (l1 == LL1 && L.lsh == LSH && L.lmax == LMX && L.scalar_only == SO) {                   \
-    launch_one<T, LL1, LSH, LMX, SO>(fwd, a, Y, x, w, M, inv_k, G, dw, dxe, dY, acc, s);     \
+    launch_one<T, S, LL1, LSH, LMX, SO>(fwd, a, Y, x, w, M, inv_k, G, dw, dxe, dY, acc, s);     \
     continue;                                                                                \
   }
     SN_TP_CASE(0, 1, 1, false) SN_TP_CASE(1, 1, 1, false)
@@ -501,32 +502,30 @@ static void run(const TPLayer& L, bool fwd, int n_recv, const int* row_ptr, cons
   }
 }
 
-template <typename T>
+template <typename T, typename S>
 void launch_tp_fwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const int* pidx, const T* Y, const T* x, const T* w, T* M, T inv_k,
+                   const int* pidx, const T* Y, const S* x, const S* w, T* M, T inv_k,
                    hipStream_t s) {
-  run<T>(L, true, n_recv, row_ptr, src, pidx, Y, x, w, M, inv_k, nullptr, nullptr, nullptr, nullptr,
-         false, s);
+  run<T, S>(L, true, n_recv, row_ptr, src, pidx, Y, x, w, M, inv_k, nullptr, nullptr, nullptr,
+            nullptr, false, s);
 }
-template <typename T>
+template <typename T, typename S>
 void launch_tp_bwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const int* pidx, const T* Y, const T* x, const T* w, const T* G, T* dw, T* dxe,
+                   const int* pidx, const T* Y, const S* x, const S* w, const T* G, S* dw, S* dxe,
                    T* dY, bool accumulate, hipStream_t s) {
-  run<T>(L, false, n_recv, row_ptr, src, pidx, Y, x, w, nullptr, T(0), G, dw, dxe, dY, accumulate,
-         s);
+  run<T, S>(L, false, n_recv, row_ptr, src, pidx, Y, x, w, nullptr, T(0), G, dw, dxe, dY,
+            accumulate, s);
 }
 
-template void launch_tp_fwd<float>(const TPLayer&, int, const int*, const int*, const int*,
-                                   const float*, const float*, const float*, float*, float,
-                                   hipStream_t);
-template void launch_tp_fwd<double>(const TPLayer&, int, const int*, const int*, const int*,
-                                    const double*, const double*, const double*, double*, double,
+#define SN_TP_INST(T, S)                                                                       \
+  template void launch_tp_fwd<T, S>(const TPLayer&, int, const int*, const int*, const int*,     \
+                                    const T*, const S*, const S*, T*, T, hipStream_t);          \
+  template void launch_tp_bwd<T, S>(const TPLayer&, int, const int*, const int*, const int*,     \
+                                    const T*, const S*, const S*, const T*, S*, S*, T*, bool,    \
                                     hipStream_t);
-template void launch_tp_bwd<float>(const TPLayer&, int, const int*, const int*, const int*,
-                                   const float*, const float*, const float*, const float*, float*,
-                                   float*, float*, bool, hipStream_t);
-template void launch_tp_bwd<double>(const TPLayer&, int, const int*, const int*, const int*,
-                                    const double*, const double*, const double*, const double*,
-                                    double*, double*, double*, bool, hipStream_t);
+SN_TP_INST(float, float)
+SN_TP_INST(float, bf16_t)
+SN_TP_INST(double, double)
+#undef SN_TP_INST
 
 }  // namespace sn

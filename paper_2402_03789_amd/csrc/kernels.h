@@ -93,16 +93,18 @@ template <typename T>
 void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const T* dw, int P, T* out,
                      hipStream_t s);
 
-// Fused radial MLP (hidden layers + output layer) on the matrix cores, float32 storage;
-// bf16 selects bfloat16 operands for the two P-wide contractions.
-// Both run over undirected pairs: pair p takes rho of edge pe1[p]; the backward sums
-// dw[pe1[p]] + dw[pe2[p]] (pe2 = -1: unpaired) and adds drho into row pe1[p].
+// Fused radial MLP (hidden layers + output layer) on the matrix cores.  WS = float: float32
+// operands and storage; WS = bf16_t: bfloat16 operands for the two P-wide contractions and
+// bfloat16 storage of w and dE/dw.  Both run over undirected pairs: pair p takes rho of
+// edge pe1[p]; the backward sums the pair-major dE/dw rows 2p and 2p+1 (the latter absent
+// when pe2[p] < 0) and adds drho into row pe1[p].  P must be a multiple of 8.
+template <typename WS>
 void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
-                          const float* Wb, const float* Wc, int P, float c, float* w, bool bf16,
-                          hipStream_t s);
+                          const float* Wb, const float* Wc, int P, float c, WS* w, hipStream_t s);
+template <typename WS>
 void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
                           const float* Wa, const float* Wb, const float* Wc, int P, float c,
-                          const float* dw, float* drho, bool accumulate, bool bf16, hipStream_t s);
+                          const WS* dw, float* drho, bool accumulate, hipStream_t s);
 
 // ---------------------------------------------------------------- tensor product
 struct TPTask {  // one wave's work: one degree l1, 64 lanes over channels x edges
@@ -126,17 +128,19 @@ struct TPLayer {
   int NY;               // (l_sh + 1)^2
 };
 
-// Messages M [n_recv x Dm] of one block; w is indexed by the edge's pair pidx[e].
-template <typename T>
+// Messages M [n_recv x Dm] of one block; w is indexed by the edge's pair pidx[e] / 2.
+// S is the storage type of x, w, dE/dw and the per-edge dE/dx rows (T, or bf16_t in the
+// bfloat16 form); arithmetic is in T.
+template <typename T, typename S>
 void launch_tp_fwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const int* pidx, const T* Y, const T* x, const T* w, T* M, T inv_k,
+                   const int* pidx, const T* Y, const S* x, const S* w, T* M, T inv_k,
                    hipStream_t s);
 // Adjoint: writes dE/dw [E x P], per-edge dE/dx_sender rows dxe [E x Dx] (skipped when dxe is
 // null), and dE/dY [E x NY] (added to the existing values when accumulate is set).
-template <typename T>
+template <typename T, typename S>
 void launch_tp_bwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const int* pidx, const T* Y, const T* x, const T* w, const T* G, T* dw,
-                   T* dxe, T* dY, bool accumulate, hipStream_t s);
+                   const int* pidx, const T* Y, const S* x, const S* w, const T* G, S* dw,
+                   S* dxe, T* dY, bool accumulate, hipStream_t s);
 
 // ---------------------------------------------------------------- node-level and reductions
 template <typename T>

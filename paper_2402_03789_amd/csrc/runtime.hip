@@ -680,7 +680,9 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
 // self-connection carries most of each atom's energy through all blocks and is the one
 // place where float32 rounding reaches the per-atom energy at the 1e-6 level.  x (the
 // sender features that feed the tensor product) and the messages M are type T.
-template <typename T>
+// S is the storage type of the sender features x, the radial weights w, dE/dw and the
+// per-edge sender gradient rows: T, or bfloat16 in the BF16 form (arithmetic stays in T).
+template <typename T, typename S>
 struct Pipe {
   sn_ctx* c;
   const sn_model* m;
@@ -701,22 +703,28 @@ struct Pipe {
   template <typename TA, typename TB, typename TC, typename TACC>
   void gemm(int64_t rows, int N, int K, const TA* A, RowMap am, int64_t woff, int ldb, bool bt,
             TC* C, RowMap cm, TACC alpha, bool acc) {
-    if (bf16 || std::is_same<TACC, float>::value)
+    if constexpr (std::is_same<TC, bf16_t>::value) {
       launch_gemm_mfma<TA, TB, TC>(rows, N, K, A, am, W<TB>(c, woff), ldb, bt, C, cm, (float)alpha,
                                    acc, bf16, s);
-    else
-      launch_gemm<TA, TB, TC, TACC>(rows, N, K, A, am, W<TB>(c, woff), ldb, bt, C, cm, alpha, acc,
-                                    false, s);
+    } else {
+      if (bf16 || std::is_same<TACC, float>::value)
+        launch_gemm_mfma<TA, TB, TC>(rows, N, K, A, am, W<TB>(c, woff), ldb, bt, C, cm,
+                                     (float)alpha, acc, bf16, s);
+      else
+        launch_gemm<TA, TB, TC, TACC>(rows, N, K, A, am, W<TB>(c, woff), ldb, bt, C, cm, alpha, acc,
+                                      false, s);
+    }
   }
 
   // radial MLP over undirected pairs: fused matrix-core kernels for float32 storage,
   // vector-unit path for float64
-  void mlp_forward(const LayerDesc& L, const T* rho, T* w) {
+  void mlp_forward(const LayerDesc& L, const T* rho, S* w) {
     const int64_t NPr = c->NP;
     const int* pe1 = c->get<int>("pair_e1", c->E);
     if constexpr (std::is_same<T, float>::value) {
-      launch_mlp_fused_fwd(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
-                           W<float>(c, L.w_mlp[2]), L.P, (float)m->act, w, bf16, s);
+      if (L.P % 8) throw UnsupportedError("radial weight count not a multiple of 8");
+      launch_mlp_fused_fwd<S>(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
+                              W<float>(c, L.w_mlp[2]), L.P, (float)m->act, w, s);
     } else {
       T* z2 = c->get<T>("z2", NPr * m->hidden);
       launch_mlp_hidden_fwd<T>(NPr, pe1, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]),
@@ -725,14 +733,14 @@ struct Pipe {
                        plain_rows(L.P), T(1), false);
     }
   }
-  void mlp_backward(const LayerDesc& L, const T* rho, const T* dw, T* dz2, T* drho) {
+  void mlp_backward(const LayerDesc& L, const T* rho, const S* dw, T* dz2, T* drho) {
     const int64_t NPr = c->NP;
     const int* pe1 = c->get<int>("pair_e1", c->E);
     const int* pe2 = c->get<int>("pair_e2", c->E);
     if constexpr (std::is_same<T, float>::value) {
       (void)dz2;
-      launch_mlp_fused_bwd(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
-                           W<float>(c, L.w_mlp[2]), L.P, (float)m->act, dw, drho, true, bf16, s);
+      launch_mlp_fused_bwd<S>(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
+                              W<float>(c, L.w_mlp[2]), L.P, (float)m->act, dw, drho, true, s);
     } else {
       T* dws = c->get<T>("dw_pair", NPr * L.P);
       launch_pair_sum<T>(NPr, pe1, pe2, dw, L.P, dws, s);
@@ -764,7 +772,7 @@ struct Pipe {
     for (int t = 0; t < m->T; ++t) {
       const LayerDesc& L = m->layers[t];
       const std::string ts = std::to_string(t);
-      T* w = c->get<T>("w" + ts, c->NP * L.P);
+      S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->aux_begin("layer" + ts + ".mlp");
       {
         OnStream os(this, c->aux);
@@ -784,17 +792,17 @@ struct Pipe {
       const LayerDesc& L = m->layers[t];
       const std::string ts = std::to_string(t);
       c->mark("layer" + ts + ".linear_in");
-      T* x = c->get<T>("x" + ts, (int64_t)NE * L.hin.width);
+      S* x = c->get<S>("x" + ts, (int64_t)NE * L.hin.width);
       double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
       const int xrows = (t == 0) ? NE : N;  // block 1: ghosts from their own species
       // Lin1 accumulates in the edge type: x only feeds the tensor product, which runs in it
       for (int l : L.ins)
-        gemm<double, T, T, T>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
+        gemm<double, T, S, T>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
                               rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], false, x,
                               rows_of(L.hin, l), T(1), false);
       if (t > 0) {
         c->mark("layer" + ts + ".ghost_refresh");
-        launch_ghost_refresh<T>(N, G, owner, x, L.hin.width, s);
+        launch_ghost_refresh<S>(N, G, owner, x, L.hin.width, s);
       }
       c->mark("layer" + ts + ".linsc");
       for (int l : L.ins)
@@ -802,11 +810,11 @@ struct Pipe {
           gemm<double, double, double, double>((int64_t)N * (2 * l + 1), L.gmul[l], L.hin.mul[l], h,
                                                rows_of(L.hin, l), L.w_linsc[l], L.gmul[l], false, y,
                                                rows_of(L.yl, l), 1.0, false);
-      T* w = c->get<T>("w" + ts, c->NP * L.P);
+      S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("layer" + ts + ".tp");
       HIPCHK(hipStreamWaitEvent(s, w_ready[t], 0));
       T* M = c->get<T>("M", (int64_t)N * L.ml.width);
-      launch_tp_fwd<T>(L.tp, N, row_ptr, src, pidx, Y, x, w, M, (T)(1.0 / m->kavg), s);
+      launch_tp_fwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, M, (T)(1.0 / m->kavg), s);
       c->mark("layer" + ts + ".linear_out");
       for (int l : L.outs) {
         const bool has_sc = std::find(L.ins.begin(), L.ins.end(), l) != L.ins.end() && L.gmul[l] > 0;
@@ -863,9 +871,9 @@ struct Pipe {
     T* Gm = c->get<T>("G", (int64_t)N * max_m);
     // dE/dw alternates between two buffers: the MLP adjoint of block t (aux stream) reads
     // one while the tensor-product adjoint of block t-1 writes the other
-    T* dw_buf[2] = {c->get<T>("dw_a", 2 * c->NP * max_P), c->get<T>("dw_b", 2 * c->NP * max_P)};
+    S* dw_buf[2] = {c->get<S>("dw_a", 2 * c->NP * max_P), c->get<S>("dw_b", 2 * c->NP * max_P)};
     std::vector<hipEvent_t> mlp_done(m->T, nullptr);
-    T* dxe = c->get<T>("dxe", E * max_w);
+    S* dxe = c->get<S>("dxe", E * max_w);
     double* dx_ext = c->get<double>("dx_ext", (int64_t)NE * max_w);
     double* dx = c->get<double>("dx", (int64_t)N * max_w);
     T* dz2 = c->get<T>("dz2", c->NP * m->hidden);
@@ -878,9 +886,9 @@ struct Pipe {
     for (int t = m->T - 1; t >= 0; --t) {
       const LayerDesc& L = m->layers[t];
       const std::string ts = std::to_string(t);
-      const T* x = c->get<T>("x" + ts, (int64_t)NE * L.hin.width);
+      const S* x = c->get<S>("x" + ts, (int64_t)NE * L.hin.width);
       const double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
-      const T* w = c->get<T>("w" + ts, c->NP * L.P);
+      const S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("bwd.layer" + ts + ".linear_out");
       launch_gate_bwd<double>(N, L.last, L.yl, L.hout, y, dh, dy, m->act, s);
       for (int l : L.outs)
@@ -888,10 +896,10 @@ struct Pipe {
                               L.w_lin2[l], L.gmul[l], true, Gm, rows_of(L.ml, l),
                               (T)(1.0 / m->kavg), false);
       c->mark("bwd.layer" + ts + ".tp");
-      T* dw = dw_buf[t % 2];
+      S* dw = dw_buf[t % 2];
       if (t + 2 < m->T) HIPCHK(hipStreamWaitEvent(s, mlp_done[t + 2], 0));
-      launch_tp_bwd<T>(L.tp, N, row_ptr, src, pidx, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dY,
-                       t != m->T - 1, s);
+      launch_tp_bwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dY,
+                          t != m->T - 1, s);
       c->join(c->aux, s);
       c->aux_begin("bwd.layer" + ts + ".mlp");
       {
@@ -904,7 +912,7 @@ struct Pipe {
       if (t == 0) break;
       c->mark("bwd.layer" + ts + ".sender_fold");
       // sender-side sums over every extended row, then fold ghost rows onto owners
-      launch_sender_reduce<T>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
+      launch_sender_reduce<S>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
       launch_ghost_fold<double>(N, gptr, dx_ext, dx, L.hin.width, s);
       c->mark("bwd.layer" + ts + ".linear_in");
       for (int l : L.ins) {
@@ -1012,7 +1020,7 @@ int guarded(sn_ctx* c, F&& f) {
   }
 }
 
-template <typename T>
+template <typename T, typename S>
 void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos, const int* d_spec,
                   const double* cells, double* d_energy, double* d_atom_energy) {
   const int64_t n = offsets[B];
@@ -1043,15 +1051,15 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
     c->graph_cells.assign(cells, cells + 9 * B);
     c->have_graph = true;
   }
-  Pipe<T> p(c);
+  Pipe<T, S> p(c);
   p.forward(d_energy, d_atom_energy);
   c->pending = true;
 }
 
-template <typename T>
+template <typename T, typename S>
 void backward_impl(sn_ctx* c, double g, double* d_forces, double* d_virial) {
   if (!c->pending) throw std::logic_error("busy");
-  Pipe<T> p(c);
+  Pipe<T, S> p(c);
   p.backward(g, d_forces, d_virial);
   c->pending = false;
 }
@@ -1192,9 +1200,11 @@ int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32
     HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
     const int64_t off[2] = {0, n};
     if (ctx->precision == SN_FP64)
-      forward_impl<double>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+      forward_impl<double, double>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+    else if (ctx->precision == SN_BF16)
+      forward_impl<float, bf16_t>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
     else
-      forward_impl<float>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+      forward_impl<float, float>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
   });
 }
 
@@ -1205,8 +1215,9 @@ int sn_backward_device(sn_ctx_t* ctx, double grad_energy, double* d_forces, doub
     return SN_EBUSY;
   }
   return guarded(ctx, [&] {
-    if (ctx->precision == SN_FP64) backward_impl<double>(ctx, grad_energy, d_forces, d_virial);
-    else backward_impl<float>(ctx, grad_energy, d_forces, d_virial);
+    if (ctx->precision == SN_FP64) backward_impl<double, double>(ctx, grad_energy, d_forces, d_virial);
+    else if (ctx->precision == SN_BF16) backward_impl<float, bf16_t>(ctx, grad_energy, d_forces, d_virial);
+    else backward_impl<float, float>(ctx, grad_energy, d_forces, d_virial);
   });
 }
 
@@ -1245,11 +1256,14 @@ int sn_compute_batch(sn_ctx_t* ctx, int B, const int64_t* offsets, const double*
     double* d_f = d_ae + n;
     const bool need_bwd = forces || virials;
     if (ctx->precision == SN_FP64) {
-      forward_impl<double>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
-      if (need_bwd) backward_impl<double>(ctx, 1.0, d_f, d_w);
+      forward_impl<double, double>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
+      if (need_bwd) backward_impl<double, double>(ctx, 1.0, d_f, d_w);
+    } else if (ctx->precision == SN_BF16) {
+      forward_impl<float, bf16_t>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
+      if (need_bwd) backward_impl<float, bf16_t>(ctx, 1.0, d_f, d_w);
     } else {
-      forward_impl<float>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
-      if (need_bwd) backward_impl<float>(ctx, 1.0, d_f, d_w);
+      forward_impl<float, float>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
+      if (need_bwd) backward_impl<float, float>(ctx, 1.0, d_f, d_w);
     }
     ctx->pending = false;
     std::vector<double> h((size_t)(10 * (int64_t)B + 4 * n));
