@@ -26,10 +26,20 @@
 #include "kernels.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace sn {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <class F, int... I>
+__device__ inline void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int EB = 64;   // pairs per block
@@ -80,6 +90,33 @@ __device__ inline void panel_kn_T(const float* Z, const float* W, floatx4 acc[4]
   }
 }
 
+// bfloat16 form of the hidden 64 x 64 products: acc += Z * B with Z the float operand
+// panel (rounded to bfloat16 as it is read) and B^T stored as bfloat16 rows [n][k]
+// (stride BP), two 16x16x32 steps per tile
+__device__ inline void panel_bf16(const float* Z, const __bf16* Bt, floatx4 acc[4], int lane) {
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < HID / 32; ++s) {
+    bf16x8 a;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a[e] = __float2bfloat16(Z[r * ZP + 32 * s + 8 * q + e]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      acc[t] = mfma32(a, *reinterpret_cast<const bf16x8*>(&Bt[(t * 16 + r) * BP + 32 * s + 8 * q]),
+                      acc[t]);
+  }
+}
+// Wb staged as bfloat16 B^T panels: for z1 Wb (bt[n][k] = Wb[k][n]) and, when wanted, for
+// da2 Wb^T (bn[n][k] = Wb[n][k])
+__device__ inline void stage_wb_bf16(const float* __restrict__ Wb, __bf16* bt, __bf16* bn) {
+  for (int i = threadIdx.x; i < HID * HID; i += 256) {
+    const int k = i / HID, n = i % HID;  // Wb[k][n]
+    const __bf16 v = __float2bfloat16(Wb[i]);
+    bt[n * BP + k] = v;
+    if (bn) bn[k * BP + n] = v;
+  }
+}
+
 // accumulator tiles (16 x 64) -> operand panel, applying f(v, tile, row)
 template <class F>
 __device__ inline void acc_to_panel(const floatx4 acc[4], float* Z, int lane, F&& f) {
@@ -108,7 +145,8 @@ __device__ inline void stage_common(int64_t np, int64_t p0, const int* __restric
                                     float* sRho) {
   const int tid = threadIdx.x;
   for (int i = tid; i < NBAS * HID; i += 256) sWa[i] = Wa[i];
-  for (int i = tid; i < HID * HID; i += 256) sWb[(i / HID) * WP + i % HID] = Wb[i];
+  if (sWb)
+    for (int i = tid; i < HID * HID; i += 256) sWb[(i / HID) * WP + i % HID] = Wb[i];
   for (int i = tid; i < EB * NBAS; i += 256) {
     const int64_t p = p0 + i / NBAS;
     sRho[(i / NBAS) * (NBAS + 1) + i % NBAS] = p < np ? rho[(int64_t)pe1[p] * NBAS + i % NBAS] : 0.f;
@@ -166,6 +204,8 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
   stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sW[1], sRho);
+  __shared__ __attribute__((aligned(16))) __bf16 sWbT[BF16 ? HID * BP : 8];
+  if (BF16) stage_wb_bf16(Wb, sWbT, nullptr);
   PanelRegs pr;
   fetch_fwd_panel(Wc, P, 0, tid, pr);
   __syncthreads();
@@ -176,7 +216,8 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   store_fwd_panel<BF16>(pr, tid, P, 0, sW[0], reinterpret_cast<__bf16*>(sW[0]));
   __syncthreads();
   zero4(acc);
-  panel_kn(Z, sW[1], acc, lane);
+  if (BF16) panel_bf16(Z, sWbT, acc, lane);
+  else panel_kn(Z, sW[1], acc, lane);
   __syncthreads();
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
   __syncthreads();
@@ -338,13 +379,17 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
                                                         const WStore<BF16>* __restrict__ dw,
                                                         float* __restrict__ drho, int accumulate) {
   __shared__ float sWa[NBAS * HID];
-  __shared__ float sWb[HID * WP];
+  __shared__ float sWb[BF16 ? 4 : HID * WP];  // float32 form only (bfloat16 copies below)
   __shared__ float sRho[EB * (NBAS + 1)];
   __shared__ float sZ[4][16 * ZP];
-  __shared__ __attribute__((aligned(16))) float sB[2][HID * TP];  // Wc[j][k-panel] (or bf16)
+  // Wc[j][k-panel]: float32 rows of stride TP, or bfloat16 rows of stride BP
+  __shared__ __attribute__((aligned(16))) float sB[2][BF16 ? HID * BP / 2 : HID * TP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
-  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, BF16 ? nullptr : sWb, sRho);
+  __shared__ __attribute__((aligned(16))) __bf16 sWbT[BF16 ? HID * BP : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sWbN[BF16 ? HID * BP : 8];
+  if (BF16) stage_wb_bf16(Wb, sWbT, sWbN);
   const int r = lane & 15, q = lane >> 4;
   const int64_t pr = p0 + wave * 16 + r;
   const bool row_ok = pr < np;
@@ -353,9 +398,14 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   const bool has2 = row_ok && pe2[pr] >= 0;
   const int64_t r2 = has2 ? r1 + P : r1;
   PanelRegs wr;
-  DwRegs<BF16> dr_cur, dr_nxt;
+  // dE/dw panels in flight: a ring of RING register sets (RING - 1 panels ahead); the
+  // bfloat16 operands are small and the matrix cores fast, so that form looks further ahead
+  constexpr int RING = BF16 ? 4 : 2;
+  DwRegs<BF16> ring[RING];
   fetch_bwd_panel(Wc, P, 0, tid, wr);
-  fetch_dw(dw, r1, r2, P, 0, q, dr_cur);
+  static_for<RING - 1>([&](auto J) {
+    fetch_dw(dw, r1, r2, P, decltype(J)::value * HID, q, ring[decltype(J)::value]);
+  });
   __syncthreads();
   float* Z = sZ[wave];
   // recompute a1 and a2 (accumulator layout)
@@ -365,19 +415,23 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   store_bwd_panel<BF16>(wr, tid, P, 0, sB[0], reinterpret_cast<__bf16*>(sB[0]));
   __syncthreads();
   zero4(a2);
-  panel_kn(Z, sWb, a2, lane);
+  if (BF16) panel_bf16(Z, sWbT, a2, lane);
+  else panel_kn(Z, sWb, a2, lane);
   // dz2 = (dw[e1] + dw[e2]) Wc^T, contraction over the P radial weights in 64-wide panels
   floatx4 g[4];
   zero4(g);
-  // One panel step: the loads of the next panel (dw of both edges, the Wc panel) are issued
-  // first and unconditionally, so they stay in flight across this panel's MFMAs; the
-  // panel loop is unrolled by two so the two operand sets alternate registers (no copies).
+  // One panel step: the loads ahead (dw of both edges RING - 1 panels ahead, the next Wc
+  // panel) are issued first and unconditionally, so they stay in flight across this
+  // panel's MFMAs; the panel loop is unrolled by RING so the operand sets rotate through
+  // fixed registers (no copies).
   const int npan = (P + HID - 1) / HID;
   int buf = 0;
-  auto step = [&](int jj, const DwRegs<BF16>& cur, DwRegs<BF16>& nxt) {
+  auto step = [&](int jj, auto SLOT) {
+    constexpr int rc = decltype(SLOT)::value, rn = (rc + RING - 1) % RING;
+    const DwRegs<BF16>& cur = ring[rc];
     const int k0 = jj * HID;
     fetch_bwd_panel(Wc, P, k0 + HID, tid, wr);
-    fetch_dw(dw, r1, r2, P, k0 + HID, q, nxt);
+    fetch_dw(dw, r1, r2, P, k0 + (RING - 1) * HID, q, ring[rn]);
     if (jj < npan) {
       if constexpr (BF16) {
         const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
@@ -409,16 +463,16 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
     __syncthreads();
     buf ^= 1;
   };
-  for (int j = 0; j < npan; j += 2) {
-    step(j, dr_cur, dr_nxt);
-    step(j + 1, dr_nxt, dr_cur);
+  for (int j = 0; j < npan; j += RING) {
+    static_for<RING>([&](auto J) { step(j + decltype(J)::value, J); });
   }
   // da2 = dz2 * phi'(a2) -> operand panel;  dz1 = da2 Wb^T
   acc_to_panel(g, Z, lane, [&](float v, int t, int rr) { return v * dphi(a2[t][rr], c); });
   __syncthreads();
   floatx4 d1[4];
   zero4(d1);
-  panel_kn_T(Z, sWb, d1, lane);
+  if (BF16) panel_bf16(Z, sWbN, d1, lane);
+  else panel_kn_T(Z, sWb, d1, lane);
   __syncthreads();
   // da1 = dz1 * phi'(a1) -> operand panel;  drho = da1 Wa^T (8 columns, padded to 16)
   acc_to_panel(d1, Z, lane, [&](float v, int t, int rr) { return v * dphi(a1[t][rr], c); });
