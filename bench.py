@@ -149,6 +149,28 @@ def main():
                 "mfma_frac": (flops_per_launch / (launch_ms * 1e-3) / 1e12 / peak_tf)
                 if launch_ms > 0 else None}
 
+    # The same kernel timed in isolation: a second context created with SN_SERIAL=1 runs
+    # every launch on one stream (the timed steps above overlap the radial MLPs with the
+    # node-feature chain, which stretches each launch while two kernels share the GPU).
+    os.environ["SN_SERIAL"] = "1"
+    sctx = sn.Context(sn.Model(wpath), device=0, precision=args.precision)
+    del os.environ["SN_SERIAL"]
+    iso = {}
+    for k in range(3):
+        sctx.forward_device(pos, Z, s.cell, energy)
+        sctx.backward_device(1.0, forces, virial)
+        sctx.synchronize()
+        if k > 0:
+            for kk, v in sctx.timings().items():
+                iso[kk] = iso.get(kk, 0.0) + v / 2
+    iso_ms = sum(iso.get(kk, 0.0) for kk in launches) / len(launches)
+    if iso_ms > 0:
+        roofline["isolated"] = {"launch_ms": iso_ms,
+                                "achieved": bytes_per_launch / (iso_ms * 1e-3) / 1e9,
+                                "frac": bytes_per_launch / (iso_ms * 1e-3) / 1e9 / 8000.0,
+                                "mfma_frac": flops_per_launch / (iso_ms * 1e-3) / 1e12 / peak_tf}
+    del sctx
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle.model import OracleModel, evaluate
