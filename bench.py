@@ -60,6 +60,9 @@ def main():
                     help="requests of the serving stream to replay: default 400 beside the "
                          "headline line (0 to skip), 2,000 for --workload serving")
     ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--domains", default="1,1,1",
+                    help="nx,ny,nz spatial subdomains of the 24k-atom box, each with its own "
+                         "ghost shell (halo refresh and fold in device memory)")
     ap.add_argument("--md-steps", type=int, default=100)
     ap.add_argument("--md-warmup", type=int, default=10)
     args = ap.parse_args()
@@ -90,6 +93,9 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = sn.Context(sn.Model(wpath), device=0, precision=args.precision)
+    domains = tuple(int(v) for v in args.domains.split(","))
+    if domains != (1, 1, 1):
+        ctx.set_domains(*domains)
     pos = torch.tensor(s.pos, dtype=torch.float64, device=dev)
     Z = torch.tensor(s.Z, dtype=torch.int32, device=dev)
     energy = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -155,6 +161,8 @@ def main():
     os.environ["SN_SERIAL"] = "1"
     sctx = sn.Context(sn.Model(wpath), device=0, precision=args.precision)
     del os.environ["SN_SERIAL"]
+    if domains != (1, 1, 1):
+        sctx.set_domains(*domains)
     iso = {}
     for k in range(3):
         sctx.forward_device(pos, Z, s.cell, energy)
@@ -201,7 +209,8 @@ def main():
         "config": {"workload": "SiO2 24,000 atoms (8,000 Si + 16,000 O), 2.2 g/cm^3, periodic cubic "
                                "71.32 A; 5 blocks 128x0e+64x1e+32x2e, l<=2, r_c 5 A; E+F+virial "
                                "as one subdomain + r_c ghost shell",
-                   "n_atoms": n, "n_ghost": g, "n_edges": e, "precision": args.precision},
+                   "n_atoms": n, "n_ghost": g, "n_edges": e, "precision": args.precision,
+                   "subdomains": list(domains)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases_ms": {k: v / args.steps for k, v in phase_ms.items()},

@@ -156,6 +156,17 @@ int sn_backward_device(sn_ctx_t* ctx, double grad_energy, double* d_forces, doub
  * and its derivative vanish beyond r_cut. */
 int sn_ctx_set_graph_reuse(sn_ctx_t* ctx, int reuse);
 
+/* Spatial decomposition on one device (paper section 3.1, Fig 3): split every structure of
+ * later calls into nx x ny x nz subdomains, the fractional boxes [i/nx, (i+1)/nx) x ... of its
+ * cell.  Each subdomain owns the atoms inside its box and gets its own ghost shell of width
+ * r_cut + skin; a ghost's owner is a local atom of any subdomain (a shift-0 image when the
+ * owner lies in a neighbouring subdomain), so the per-block ghost refresh and the backward
+ * ghost fold are the halo exchanges of the multi-device method, carried out in device
+ * memory.  Edges never cross subdomains.  Results equal the undivided evaluation up to the
+ * order of floating-point sums.  1 x 1 x 1 (the default) is one subdomain per structure.
+ * SN_EINVAL for a count below 1 or more than 4096 subdomains. */
+int sn_ctx_set_domains(sn_ctx_t* ctx, int nx, int ny, int nz);
+
 /* Velocity-Verlet half step on device arrays (harness of the MD workload), stream-ordered:
  * stage 0: v += dt/2 a, x += dt v;  stage 1: v += dt/2 a;  a = F * inv_mass.
  * d_pos, d_vel, d_forces are n x 3 float64; d_inv_mass[n] carries the unit conversion

@@ -146,6 +146,10 @@ class Context:
         check(lib().sn_ctx_graph_size(self._h, C.byref(n), C.byref(g), C.byref(e)))
         return n.value, g.value, e.value
 
+    def set_domains(self, nx: int, ny: int = 1, nz: int = 1):
+        """Evaluate later calls as nx x ny x nz subdomains, each with its own ghost shell."""
+        check(lib().sn_ctx_set_domains(self._h, int(nx), int(ny), int(nz)), self._h)
+
     def set_graph_reuse(self, reuse: bool):
         check(lib().sn_ctx_set_graph_reuse(self._h, 1 if reuse else 0))
 

@@ -1,9 +1,10 @@
 // Graph build: wrap, cell binning, ghost shell, receiver and sender CSR.
 //
-// One subdomain with a ghost shell (paper section 3.1): every periodic image
-// of an atom whose fractional coordinates fall within (r_c + skin) / w_a of
-// the cell on each axis (w_a: perpendicular width) is a ghost with an owner
-// and an integer image shift.  Edges join a local receiver to any local or
+// Subdomains with ghost shells (paper section 3.1): a structure is one subdomain (its
+// whole cell) or a grid of fractional boxes.  Every image of an atom whose fractional
+// coordinates fall within (r_c + skin) / w_a of a subdomain's box on each axis (w_a:
+// perpendicular width), other than the atom itself in its own subdomain, is a ghost of that
+// subdomain with an owner and an integer image shift.  Edges join a local receiver to any local or
 // ghost sender closer than r_c (section 2), found by scanning the 27 bins
 // around the receiver on a grid over the extended fractional region whose
 // bin width is at least the shell half-width.  Every list is made
@@ -74,8 +75,15 @@ void scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t s)
 // Several structures can share one packed graph: every point carries its structure id,
 // and structure b bins into the global key range [bin_base, bin_base + nb0*nb1*nb2).
 __device__ inline int bin_axis(double f, const BinGrid& g, int a) {
-  int b = (int)floor((f + g.delta[a]) / g.bw[a]);
+  int b = (int)floor((f - g.lo[a] + g.delta[a]) / g.bw[a]);
   return min(max(b, 0), g.nb[a] - 1);
+}
+// subdomain index of fractional coordinate f on an axis split into n boxes [j/n, (j+1)/n)
+__device__ inline int dom_axis(double f, int n) {
+  int j = min(max((int)floor(f * n), 0), n - 1);
+  if (j > 0 && f < (double)j / n) --j;
+  if (j < n - 1 && f >= (double)(j + 1) / n) ++j;
+  return j;
 }
 __device__ inline int bin_lin(const double* f, const BinGrid& g) {
   return (bin_axis(f[0], g, 0) * g.nb[1] + bin_axis(f[1], g, 1)) * g.nb[2] + bin_axis(f[2], g, 2);
@@ -83,10 +91,11 @@ __device__ inline int bin_lin(const double* f, const BinGrid& g) {
 
 __global__ void k_wrap_bin(int n, const double* __restrict__ pos, const int* __restrict__ sid,
                            const StructParams* __restrict__ sp, double* __restrict__ posw,
-                           double* __restrict__ frac, int* __restrict__ key, int* __restrict__ err) {
+                           double* __restrict__ frac, int* __restrict__ key, int* __restrict__ rid,
+                           int* __restrict__ err) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const StructParams& P = sp[sid[i]];
+  const StructParams& P0 = sp[sid[i]];
   double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) {
     atomicOr(err, 1);
@@ -95,16 +104,21 @@ __global__ void k_wrap_bin(int n, const double* __restrict__ pos, const int* __r
   double f[3];
   for (int a = 0; a < 3; ++a) {
     // row vector p times Hinv
-    double v = p[0] * P.Hinv[0 * 3 + a] + p[1] * P.Hinv[1 * 3 + a] + p[2] * P.Hinv[2 * 3 + a];
+    double v = p[0] * P0.Hinv[0 * 3 + a] + p[1] * P0.Hinv[1 * 3 + a] + p[2] * P0.Hinv[2 * 3 + a];
     v -= floor(v);
     if (v >= 1.0) v = 0.0;
     f[a] = v;
   }
   for (int a = 0; a < 3; ++a) {
     frac[3 * i + a] = f[a];
-    posw[3 * i + a] = f[0] * P.H[0 * 3 + a] + f[1] * P.H[1 * 3 + a] + f[2] * P.H[2 * 3 + a];
+    posw[3 * i + a] = f[0] * P0.H[0 * 3 + a] + f[1] * P0.H[1 * 3 + a] + f[2] * P0.H[2 * 3 + a];
   }
-  key[i] = P.bin_base + bin_lin(f, P.g);
+  // the atom's subdomain (region) within its structure
+  const int r = sid[i] + (dom_axis(f[0], P0.ndom[0]) * P0.ndom[1] + dom_axis(f[1], P0.ndom[1])) *
+                             P0.ndom[2] +
+                dom_axis(f[2], P0.ndom[2]);
+  rid[i] = r;
+  key[i] = sp[r].bin_base + bin_lin(f, sp[r].g);
 }
 
 __global__ void k_count_keys(int n, const int* __restrict__ key, int* __restrict__ count) {
@@ -156,23 +170,39 @@ __global__ void k_gather_local(int n, const int* __restrict__ order, const doubl
 __device__ inline bool in_shell(const double* f, int sx, int sy, int sz, const BinGrid& g) {
   double v[3] = {f[0] + sx, f[1] + sy, f[2] + sz};
   for (int a = 0; a < 3; ++a)
-    if (!(v[a] >= -g.delta[a] && v[a] < 1.0 + g.delta[a])) return false;
+    if (!(v[a] >= g.lo[a] - g.delta[a] && v[a] < g.hi[a] + g.delta[a])) return false;
   return true;
+}
+
+// Ghosts of local atom k: every image (shift n) inside the extended box of a region of
+// its structure, except the atom itself in its own region (n = 0).  With one region per
+// structure these are the periodic images around the cell; with several, an atom is also
+// a shift-0 ghost of every neighbouring subdomain whose shell reaches it.  Order: region,
+// then shift (owner-major overall, so each owner's ghosts are contiguous).
+template <class F>
+__device__ inline void for_each_ghost(const double* f, int own_region,
+                                      const StructParams* __restrict__ sp, F&& emit) {
+  const StructParams& P = sp[own_region];
+  const int nreg = P.ndom[0] * P.ndom[1] * P.ndom[2];
+  const BinGrid& g0 = P.g;
+  for (int d = P.first_region; d < P.first_region + nreg; ++d) {
+    const BinGrid& g = sp[d].g;
+    for (int sx = -g0.nimg[0]; sx <= g0.nimg[0]; ++sx)
+      for (int sy = -g0.nimg[1]; sy <= g0.nimg[1]; ++sy)
+        for (int sz = -g0.nimg[2]; sz <= g0.nimg[2]; ++sz) {
+          if (sx == 0 && sy == 0 && sz == 0 && d == own_region) continue;
+          if (in_shell(f, sx, sy, sz, g)) emit(d, sx, sy, sz);
+        }
+  }
 }
 
 __global__ void k_ghost_count(int n, const double* __restrict__ frac, const int* __restrict__ sid,
                               const StructParams* __restrict__ sp, int* __restrict__ count) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const BinGrid& g = sp[sid[k]].g;
   double f[3] = {frac[3 * k], frac[3 * k + 1], frac[3 * k + 2]};
   int c = 0;
-  for (int sx = -g.nimg[0]; sx <= g.nimg[0]; ++sx)
-    for (int sy = -g.nimg[1]; sy <= g.nimg[1]; ++sy)
-      for (int sz = -g.nimg[2]; sz <= g.nimg[2]; ++sz) {
-        if (sx == 0 && sy == 0 && sz == 0) continue;
-        c += in_shell(f, sx, sy, sz, g) ? 1 : 0;
-      }
+  for_each_ghost(f, sid[k], sp, [&](int, int, int, int) { ++c; });
   count[k] = c;
 }
 
@@ -184,32 +214,25 @@ __global__ void k_ghost_fill(int n, const double* __restrict__ frac, const doubl
                              int* __restrict__ spec_ext) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const int b = sid[k];
-  const StructParams& P = sp[b];
-  const BinGrid& g = P.g;
+  const StructParams& P = sp[sid[k]];
   double f[3] = {frac[3 * k], frac[3 * k + 1], frac[3 * k + 2]};
   int w = gptr[k];
-  for (int sx = -g.nimg[0]; sx <= g.nimg[0]; ++sx)
-    for (int sy = -g.nimg[1]; sy <= g.nimg[1]; ++sy)
-      for (int sz = -g.nimg[2]; sz <= g.nimg[2]; ++sz) {
-        if (sx == 0 && sy == 0 && sz == 0) continue;
-        if (!in_shell(f, sx, sy, sz, g)) continue;
-        owner[w] = k;
-        shift[3 * w] = sx;
-        shift[3 * w + 1] = sy;
-        shift[3 * w + 2] = sz;
-        int r = n + w;
-        for (int a = 0; a < 3; ++a) {
-          pos_ext[3 * r + a] = pos[3 * k + a] + sx * P.H[0 * 3 + a] + sy * P.H[1 * 3 + a] +
-                               sz * P.H[2 * 3 + a];
-        }
-        frac_ext[3 * r] = f[0] + sx;
-        frac_ext[3 * r + 1] = f[1] + sy;
-        frac_ext[3 * r + 2] = f[2] + sz;
-        spec_ext[r] = spec[k];
-        sid[r] = b;
-        ++w;
-      }
+  for_each_ghost(f, sid[k], sp, [&](int d, int sx, int sy, int sz) {
+    owner[w] = k;
+    shift[3 * w] = sx;
+    shift[3 * w + 1] = sy;
+    shift[3 * w + 2] = sz;
+    const int r = n + w;
+    for (int a = 0; a < 3; ++a)
+      pos_ext[3 * r + a] =
+          pos[3 * k + a] + sx * P.H[0 * 3 + a] + sy * P.H[1 * 3 + a] + sz * P.H[2 * 3 + a];
+    frac_ext[3 * r] = f[0] + sx;
+    frac_ext[3 * r + 1] = f[1] + sy;
+    frac_ext[3 * r + 2] = f[2] + sz;
+    spec_ext[r] = spec[k];
+    sid[r] = d;
+    ++w;
+  });
 }
 
 __global__ void k_bin_keys(int n, const double* __restrict__ frac, const int* __restrict__ sid,
@@ -267,8 +290,8 @@ __global__ void k_edges(int n, const double* __restrict__ pos_ext, const double*
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_wrap_bin(int n, const double* pos, const int* sid, const StructParams* sp, double* posw,
-                     double* frac, int* key, int* err, hipStream_t s) {
-  if (n > 0) k_wrap_bin<<<nblk(n, 256), 256, 0, s>>>(n, pos, sid, sp, posw, frac, key, err);
+                     double* frac, int* key, int* rid, int* err, hipStream_t s) {
+  if (n > 0) k_wrap_bin<<<nblk(n, 256), 256, 0, s>>>(n, pos, sid, sp, posw, frac, key, rid, err);
 }
 void launch_count_keys(int n, const int* key, int* count, hipStream_t s) {
   if (n > 0) k_count_keys<<<nblk(n, 256), 256, 0, s>>>(n, key, count);

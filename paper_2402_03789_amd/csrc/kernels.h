@@ -11,22 +11,28 @@ struct BinGrid {
   double bw[3];     // bin width (fractional units), >= delta
   double delta[3];  // shell half-width (fractional units) = (r_c + skin) / perpendicular width
   int nimg[3];      // image-shift search range per axis
+  double lo[3], hi[3];  // the region's own fractional box [lo, hi); bins cover [lo-delta, hi+delta)
 };
 
 // exclusive scan of n ints into out[0..n] (out[n] = total); tmp needs scan_tmp_ints(n) ints
 size_t scan_tmp_ints(int64_t n);
 void scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
 
-// Per-structure geometry of a packed graph.
+// Geometry of one region of a packed graph.  A region is one spatial subdomain of a
+// structure (the whole cell unless the structure is split into ndom[0] x ndom[1] x ndom[2]
+// fractional boxes).  Each region has its own ghost shell; edges never cross regions.
 struct StructParams {
   double H[9], Hinv[9];  // cell (rows a1 a2 a3) and its inverse
   BinGrid g;
-  int bin_base;          // first global bin key of this structure
+  int bin_base;          // first global bin key of this region
+  int first_region;      // index of the structure's first region (its regions are consecutive)
+  int ndom[3];           // the structure's subdomain grid
   int pad;
 };
 
+// sid: first region of each atom's structure; rid receives the atom's own region.
 void launch_wrap_bin(int n, const double* pos, const int* sid, const StructParams* sp, double* posw,
-                     double* frac, int* key, int* err, hipStream_t s);
+                     double* frac, int* key, int* rid, int* err, hipStream_t s);
 void launch_count_keys(int n, const int* key, int* count, hipStream_t s);
 void launch_scatter_keys(int n, const int* key, const int* start, int* cursor, int* items,
                          hipStream_t s);

@@ -291,8 +291,11 @@ struct sn_ctx {
   // graph state
   int N = 0, G = 0;
   int64_t E = 0, NP = 0;  // directed edges, undirected pairs
-  // structures of the packed graph
+  // structures of the packed graph, each split into domains[0] x domains[1] x domains[2]
+  // spatial subdomains (regions, R = B x subdomains), each with its own ghost shell
   int B = 0;
+  int R = 0;
+  int domains[3] = {1, 1, 1};
   std::vector<int64_t> atom_off;   // B + 1 atom offsets (input order = packed local order)
   std::vector<int64_t> edge_off;   // B + 1 edge offsets (edges are receiver-contiguous)
   std::vector<StructParams> sp;    // per-structure geometry (host copy)
@@ -475,7 +478,8 @@ SegChunks make_chunks(const std::vector<int64_t>& off, int64_t len) {
   return sc;
 }
 
-StructParams make_struct(const double* cell, double reach) {
+// One region: the fractional box [lo, hi) of a cell, its shell half-width and bin grid.
+StructParams make_struct(const double* cell, double reach, const double* lo, const double* hi) {
   StructParams P{};
   for (int i = 0; i < 9; ++i) {
     if (!std::isfinite(cell[i])) throw ArgError("cell has non-finite entries");
@@ -498,7 +502,9 @@ StructParams make_struct(const double* cell, double reach) {
   for (int k = 0; k < 3; ++k) {
     double w = vol / std::sqrt(cr[k][0] * cr[k][0] + cr[k][1] * cr[k][1] + cr[k][2] * cr[k][2]);
     g.delta[k] = reach / w;
-    double span = 1.0 + 2.0 * g.delta[k];
+    g.lo[k] = lo[k];
+    g.hi[k] = hi[k];
+    double span = (hi[k] - lo[k]) + 2.0 * g.delta[k];
     g.bw[k] = std::max(g.delta[k], span / 256.0);
     g.nb[k] = std::max(1, (int)std::ceil(span / g.bw[k] - 1e-12));
     g.nimg[k] = (int)std::ceil(g.delta[k]) + 1;
@@ -512,24 +518,39 @@ void setup_cells(sn_ctx* c, int B, const int64_t* offsets, const double* cells) 
   if (B < 1) throw ArgError("no structures");
   c->B = B;
   c->atom_off.assign(offsets, offsets + B + 1);
-  c->sp.resize(B);
+  const int* nd = c->domains;
+  const int D = nd[0] * nd[1] * nd[2];
+  c->R = B * D;
+  c->sp.resize(c->R);
   int64_t bins = 0;
   const double reach = c->m->rc + c->skin;
   for (int b = 0; b < B; ++b) {
     if (offsets[b + 1] <= offsets[b]) throw ArgError("empty structure in batch");
-    c->sp[b] = make_struct(cells + 9 * b, reach);
-    c->sp[b].bin_base = (int)bins;
-    bins += (int64_t)c->sp[b].g.nb[0] * c->sp[b].g.nb[1] * c->sp[b].g.nb[2];
-    if (bins > (1 << 26)) throw UnsupportedError("bin grid too large");
+    for (int dx = 0; dx < nd[0]; ++dx)
+      for (int dy = 0; dy < nd[1]; ++dy)
+        for (int dz = 0; dz < nd[2]; ++dz) {
+          const int r = b * D + (dx * nd[1] + dy) * nd[2] + dz;
+          const double lo[3] = {(double)dx / nd[0], (double)dy / nd[1], (double)dz / nd[2]};
+          const double hi[3] = {(double)(dx + 1) / nd[0], (double)(dy + 1) / nd[1],
+                                (double)(dz + 1) / nd[2]};
+          StructParams& P = c->sp[r];
+          P = make_struct(cells + 9 * b, reach, lo, hi);
+          P.bin_base = (int)bins;
+          P.first_region = b * D;
+          for (int a = 0; a < 3; ++a) P.ndom[a] = nd[a];
+          bins += (int64_t)P.g.nb[0] * P.g.nb[1] * P.g.nb[2];
+          if (bins > (1 << 26)) throw UnsupportedError("bin grid too large");
+        }
   }
   c->nbins = (int)bins;
   const int64_t N = offsets[B];
-  StructParams* dsp = c->get<StructParams>("struct_params", B);
-  HIPCHK(hipMemcpyAsync(dsp, c->sp.data(), sizeof(StructParams) * B, hipMemcpyHostToDevice,
+  StructParams* dsp = c->get<StructParams>("struct_params", c->R);
+  HIPCHK(hipMemcpyAsync(dsp, c->sp.data(), sizeof(StructParams) * c->R, hipMemcpyHostToDevice,
                         c->stream));
+  // every atom starts with its structure's first region; the wrap kernel picks its own
   std::vector<int> sid((size_t)N);
   for (int b = 0; b < B; ++b)
-    for (int64_t i = offsets[b]; i < offsets[b + 1]; ++i) sid[i] = b;
+    for (int64_t i = offsets[b]; i < offsets[b + 1]; ++i) sid[i] = b * D;
   int* dsid = c->get<int>("sid_orig", N);
   HIPCHK(hipMemcpyAsync(dsid, sid.data(), sizeof(int) * N, hipMemcpyHostToDevice, c->stream));
   std::vector<int> offs(offsets, offsets + B + 1);
@@ -556,15 +577,16 @@ template <typename T>
 void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   hipStream_t s = c->stream;
   const int nbins = c->nbins;
-  const StructParams* sp = c->get<StructParams>("struct_params", c->B);
+  const StructParams* sp = c->get<StructParams>("struct_params", c->R);
   const int* sid_orig = c->get<int>("sid_orig", N);
+  int* rid = c->get<int>("region_orig", N);
   c->N = N;
   int* err = c->get<int>("err", 4);
   zero(err, 16, s);
   double* posw = c->get<double>("posw", 3 * N);
   double* fracw = c->get<double>("fracw", 3 * N);
   int* key = c->get<int>("key", N);
-  launch_wrap_bin(N, d_pos, sid_orig, sp, posw, fracw, key, err, s);
+  launch_wrap_bin(N, d_pos, sid_orig, sp, posw, fracw, key, rid, err, s);
   // order local atoms by bin (cell order within each structure) for gather locality
   int* cnt = c->get<int>("bin_count", nbins + 1);
   int* start = c->get<int>("bin_start", nbins + 1);
@@ -585,7 +607,7 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   double* pos_loc = c->get<double>("pos_local", 3 * N);
   int* spec_loc = c->get<int>("spec_local", N);
   int* sid_loc = c->get<int>("sid_local", N);
-  launch_gather_local(N, order, posw, fracw, d_spec, sid_orig, pos_loc, fr_loc, spec_loc, sid_loc, s);
+  launch_gather_local(N, order, posw, fracw, d_spec, rid, pos_loc, fr_loc, spec_loc, sid_loc, s);
   launch_ghost_count(N, fr_loc, sid_loc, sp, gcount, s);
   scan_exclusive(gcount, gptr, N, tmp, s);
   int hG[2] = {0, 0};
@@ -1040,7 +1062,7 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
                              c->get<int>("ghost_owner", c->G),
                              c->get<int>("ghost_shift", 3 * (int64_t)c->G),
                              c->get<int>("sid_ext", c->N + c->G),
-                             c->get<StructParams>("struct_params", c->B),
+                             c->get<StructParams>("struct_params", c->R),
                              c->get<double>("pos_ext", 3 * (int64_t)(c->N + c->G)), c->stream);
   } else {
     c->have_graph = false;
@@ -1294,6 +1316,15 @@ int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, i
   if (n_local) *n_local = ctx->N;
   if (n_ghost) *n_ghost = ctx->G;
   if (n_edge) *n_edge = ctx->E;
+  return SN_OK;
+}
+
+int sn_ctx_set_domains(sn_ctx_t* ctx, int nx, int ny, int nz) {
+  if (!ctx || nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz > 4096) return SN_EINVAL;
+  ctx->domains[0] = nx;
+  ctx->domains[1] = ny;
+  ctx->domains[2] = nz;
+  ctx->have_graph = false;  // the next call rebuilds
   return SN_OK;
 }
 

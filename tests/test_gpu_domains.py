@@ -1,0 +1,86 @@
+"""Spatial decomposition on one device: k subdomains, each with its own ghost shell whose
+owners are local atoms of other subdomains (halo refresh and fold in device memory).
+Energies, forces and virials equal the undivided evaluation; ghost and edge counts equal
+the oracle's subdomain construction."""
+import numpy as np
+import pytest
+
+from gpu_common import log, write_model
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2402_03789_amd as sn  # noqa: E402
+from oracle.graph import subdomains, wrap  # noqa: E402
+from synth import model_spec_real, sio2_box, rsa_box  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def model(tmp_path_factory):
+    path, _ = write_model(tmp_path_factory.mktemp("m"), model_spec_real(), 107)
+    return sn.Model(path)
+
+
+def _triclinic():
+    cell = np.array([[13.0, 0, 0], [3.0, 12.0, 0], [-2.0, 2.5, 12.5]])
+    rng = np.random.Generator(np.random.PCG64(31))
+    pos = rsa_box(cell, 160, 1.3, rng)
+    Z = np.where(np.arange(160) % 3 == 0, 14, 8).astype(np.int32)
+    return pos, Z, cell
+
+
+CASES = {
+    "sio2_slabs": (lambda: (lambda s: (s.pos, s.Z, s.cell))(sio2_box(40, seed=5)), (2, 1, 1)),
+    "sio2_2x2x2": (lambda: (lambda s: (s.pos, s.Z, s.cell))(sio2_box(60, seed=6)), (2, 2, 2)),
+    "triclinic_3x1x2": (_triclinic, (3, 1, 2)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_domains_equal_whole_box_fp64(model, name):
+    make, splits = CASES[name]
+    pos, Z, cell = make()
+    log(f"domains {name} splits={splits} n={len(Z)}")
+    one = sn.Context(model, precision="fp64")
+    ref = one.compute(pos, Z, cell)
+    n1, g1, e1 = one.graph_size()
+    ctx = sn.Context(model, precision="fp64")
+    ctx.set_domains(*splits)
+    got = ctx.compute(pos, Z, cell)
+    n, g, e = ctx.graph_size()
+    doms = subdomains(wrap(pos, cell), cell, 5.0, splits)
+    assert n == n1 == len(Z)
+    assert g == sum(len(D["ghost_owner"]) for D in doms)
+    assert e == e1 == sum(len(D["recv"]) for D in doms)
+    log(f"  ghosts {g1} -> {g}, edges {e}")
+    assert abs(got["energy"] - ref["energy"]) <= 1e-10 * abs(ref["energy"])
+    np.testing.assert_allclose(got["atom_energy"], ref["atom_energy"], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(got["forces"], ref["forces"], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(got["virial"], ref["virial"], rtol=0, atol=1e-9)
+
+
+def test_domains_fp32_and_batch(model):
+    s = sio2_box(300, seed=8)  # 900 atoms
+    t = sio2_box(20, seed=9)
+    one = sn.Context(model, precision="fp32")
+    ref = [one.compute(s.pos, s.Z, s.cell), one.compute(t.pos, t.Z, t.cell)]
+    ctx = sn.Context(model, precision="fp32")
+    ctx.set_domains(2, 2, 2)
+    got = ctx.compute_batch([(s.pos, s.Z, s.cell), (t.pos, t.Z, t.cell)])
+    for g, r in zip(got, ref):
+        rms = np.sqrt(np.mean(r["atom_energy"] ** 2))
+        assert np.abs(g["atom_energy"] - r["atom_energy"]).max() / rms < 1e-6
+        assert np.abs(g["forces"] - r["forces"]).max() < 1e-4
+    # back to one subdomain per structure: identical to the undivided context
+    ctx.set_domains(1, 1, 1)
+    again = ctx.compute(s.pos, s.Z, s.cell)
+    assert again["energy"] == ref[0]["energy"]
+
+
+def test_domains_rejects_bad_counts(model):
+    ctx = sn.Context(model, precision="fp32")
+    with pytest.raises(sn.SNError):
+        ctx.set_domains(0, 1, 1)
