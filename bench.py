@@ -63,6 +63,11 @@ def main():
     ap.add_argument("--domains", default="1,1,1",
                     help="nx,ny,nz spatial subdomains of the 24k-atom box, each with its own "
                          "ghost shell (halo refresh and fold in device memory)")
+    ap.add_argument("--md-system", default="si3n4_112k", choices=["si3n4_112k", "sio2_192"],
+                    help="MD box: the 112k-atom Si3N4 workload, or a 192-atom SiO2 box where "
+                         "launch overhead matters")
+    ap.add_argument("--capture", action="store_true",
+                    help="MD: replay the steps between rebuilds from a recorded HIP graph")
     ap.add_argument("--md-steps", type=int, default=100)
     ap.add_argument("--md-warmup", type=int, default=10)
     args = ap.parse_args()
@@ -277,12 +282,15 @@ def bench_md(args):
     from paper_2402_03789_amd.md import VelocityVerlet
     from synth import config_structure
 
+    from synth import sio2_box
     t0 = time.perf_counter()
-    s = config_structure("si3n4_112k")
+    small = args.md_system == "sio2_192"
+    s = sio2_box(64, seed=1) if small else config_structure("si3n4_112k")
     gen_s = time.perf_counter() - t0
-    ctx = sn.Context(sn.Model(_model_file((7, 14), 102)), precision=args.precision, skin=1.0)
+    species = (8, 14) if small else (7, 14)
+    ctx = sn.Context(sn.Model(_model_file(species, 102)), precision=args.precision, skin=1.0)
     md = VelocityVerlet(ctx, s.pos, s.Z, s.cell, s.masses(), dt=1.0, rebuild_every=10,
-                        temperature=1500.0, seed=5)
+                        temperature=1500.0, seed=5, capture=args.capture)
     md.run(args.md_warmup)
     e0 = md.kinetic_energy() + md.potential_energy()
     torch.cuda.synchronize()
@@ -293,16 +301,17 @@ def bench_md(args):
     dt = time.perf_counter() - t1
     e1 = md.kinetic_energy() + md.potential_energy()
     n, g, e = ctx.graph_size()
-    return {"metric": "atom-steps/s (E+F), 5-layer l<=2 model, 112k-atom Si3N4 velocity-Verlet MD",
+    workload = ("SiO2 192 atoms, 2.2 g/cm^3, periodic cubic 14.26 A" if small else
+                "Si3N4 112,000 atoms (48,000 Si + 64,000 N), 3.1 g/cm^3, periodic cubic 106.33 A")
+    return {"metric": f"atom-steps/s (E+F), 5-layer l<=2 model, {s.n}-atom velocity-Verlet MD",
             "value": s.n * args.md_steps / dt, "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.md_steps, "warmup": args.md_warmup,
             "ms_per_step": dt / args.md_steps * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
             "data": "synthetic",
-            "config": {"workload": "Si3N4 112,000 atoms (48,000 Si + 64,000 N), 3.1 g/cm^3, periodic "
-                                   "cubic 106.33 A; dt 1 fs, 1500 K start, skin 1 A, rebuild every "
+            "config": {"workload": workload + "; dt 1 fs, 1500 K start, skin 1 A, rebuild every "
                                    "10 steps", "n_atoms": n, "n_ghost": g, "n_edges": e,
-                       "precision": args.precision},
+                       "precision": args.precision, "graph_replay": bool(args.capture)},
             "energy_drift_eV_per_atom": (e1 - e0) / s.n, "generation_s": gen_s}
 
 

@@ -167,6 +167,14 @@ int sn_ctx_set_graph_reuse(sn_ctx_t* ctx, int reuse);
  * SN_EINVAL for a count below 1 or more than 4096 subdomains. */
 int sn_ctx_set_domains(sn_ctx_t* ctx, int nx, int ny, int nz);
 
+/* hipGraph replay for molecular dynamics.  With capture on and graph reuse enabled, a
+ * forward/backward pair that reuses the kept neighbour list is recorded once into a HIP
+ * graph (all launches on one stream, no timing events) and replayed on later reuse calls
+ * with the same device pointers and upstream gradient; a rebuild, other pointers or another
+ * gradient record a new graph.  The first reuse call after a build runs eagerly (it sizes
+ * the workspace).  Results are bitwise those of the eager launches. */
+int sn_ctx_set_capture(sn_ctx_t* ctx, int on);
+
 /* Velocity-Verlet half step on device arrays (harness of the MD workload), stream-ordered:
  * stage 0: v += dt/2 a, x += dt v;  stage 1: v += dt/2 a;  a = F * inv_mass.
  * d_pos, d_vel, d_forces are n x 3 float64; d_inv_mass[n] carries the unit conversion

@@ -150,6 +150,10 @@ class Context:
         """Evaluate later calls as nx x ny x nz subdomains, each with its own ghost shell."""
         check(lib().sn_ctx_set_domains(self._h, int(nx), int(ny), int(nz)), self._h)
 
+    def set_capture(self, on: bool):
+        """Replay reused-neighbour-list evaluations from a recorded HIP graph."""
+        check(lib().sn_ctx_set_capture(self._h, 1 if on else 0), self._h)
+
     def set_graph_reuse(self, reuse: bool):
         check(lib().sn_ctx_set_graph_reuse(self._h, 1 if reuse else 0))
 

@@ -75,6 +75,7 @@ _SIGS = {
     "sn_ctx_pair_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "sn_ctx_set_graph_reuse": (C.c_int, [C.c_void_p, C.c_int]),
     "sn_ctx_set_domains": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "sn_ctx_set_capture": (C.c_int, [C.c_void_p, C.c_int]),
     "sn_md_verlet": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_double, C.c_int]),
     "sn_ctx_graph": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -304,6 +304,19 @@ struct sn_ctx {
   bool pending = false;
   bool reuse = false;       // keep the graph of the previous call when n and the cell match
   bool have_graph = false;
+  // hipGraph replay of the reused-graph evaluation (see sn_ctx_set_capture)
+  bool capture = false;
+  bool capturing = false;        // launches are being recorded: no timing events
+  uint64_t graph_version = 0;    // bumped at every neighbour-list build
+  int reuse_runs = 0;            // eager forward calls on the current graph
+  bool last_fwd_reused = false;
+  hipStream_t cap_stream = nullptr;  // private stream for capture when the context's is null
+  struct Replay {
+    hipGraphExec_t exec = nullptr;
+    uint64_t version = ~0ull;
+    const void* key[3] = {nullptr, nullptr, nullptr};
+    double g = 0;
+  } rp_fwd, rp_bwd;
   std::vector<double> graph_cells;
   // second stream for the radial MLPs, which depend only on the edge basis (forward) or
   // on their own block's dE/dw (adjoint), so they overlap with the node-feature chain
@@ -370,16 +383,19 @@ struct sn_ctx {
   }
   // time one launch sequence on the aux stream
   void aux_begin(const std::string& name) {
+    if (capturing) return;
     hipEvent_t a = timing_event();
     HIPCHK(hipEventRecord(a, aux));
     aux_marks.push_back({name, {a, nullptr}});
   }
   void aux_end() {
+    if (capturing) return;
     hipEvent_t b = timing_event();
     HIPCHK(hipEventRecord(b, aux));
     aux_marks.back().second.second = b;
   }
   void mark(const std::string& name) {
+    if (capturing) return;
     if (event_next >= event_pool.size()) {
       hipEvent_t ev;
       HIPCHK(hipEventCreate(&ev));
@@ -968,10 +984,13 @@ struct Pipe {
   }
 };
 
+void destroy_replays(sn_ctx* c);
+
 // Free every workspace buffer (not the weights); the graph and any pending forward are
 // dropped.  False when the device reported an error meanwhile (the context is then dead).
 bool release_workspace(sn_ctx* c) {
   bool ok = hipStreamSynchronize(c->stream) == hipSuccess;
+  destroy_replays(c);
   if (c->aux && hipStreamSynchronize(c->aux) != hipSuccess) ok = false;
   for (auto& kv : c->bufs)
     if (kv.second.p && hipFree(kv.second.p) != hipSuccess) ok = false;
@@ -1042,6 +1061,66 @@ int guarded(sn_ctx* c, F&& f) {
   }
 }
 
+// ------------------------------------------------------------------ hipGraph replay
+// Records the launches of f() into a graph and instantiates it.  Everything is recorded on
+// one stream (the aux stream is folded into it while recording) and without timing events;
+// when the context's stream is the null stream, a private stream records and replays,
+// ordered against the null stream by events.
+hipStream_t replay_stream(sn_ctx* c) {
+  if (c->stream) return c->stream;
+  if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  return c->cap_stream;
+}
+void destroy_replays(sn_ctx* c) {
+  for (sn_ctx::Replay* r : {&c->rp_fwd, &c->rp_bwd}) {
+    if (r->exec) (void)hipGraphExecDestroy(r->exec);
+    r->exec = nullptr;
+    r->version = ~0ull;
+  }
+}
+template <class F>
+hipGraphExec_t record_graph(sn_ctx* c, F&& f) {
+  hipStream_t cs = replay_stream(c);
+  hipStream_t user = c->stream, aux = c->aux;
+  c->stream = cs;
+  c->aux = cs;
+  c->capturing = true;
+  auto restore = [&] {
+    c->stream = user;
+    c->aux = aux;
+    c->capturing = false;
+  };
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  try {
+    f();
+  } catch (...) {
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    restore();
+    throw;
+  }
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  restore();
+  HIPCHK(e);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(ei);
+  return exec;
+}
+void launch_replay(sn_ctx* c, hipGraphExec_t exec) {
+  hipStream_t cs = replay_stream(c);
+  if (cs != c->stream) c->join(cs, c->stream);
+  HIPCHK(hipGraphLaunch(exec, cs));
+  if (cs != c->stream) c->join(c->stream, cs);
+}
+bool replay_hit(const sn_ctx::Replay& r, uint64_t version, const void* k0, const void* k1,
+                const void* k2, double g) {
+  return r.exec && r.version == version && r.key[0] == k0 && r.key[1] == k1 && r.key[2] == k2 &&
+         r.g == g;
+}
+
 template <typename T, typename S>
 void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos, const int* d_spec,
                   const double* cells, double* d_energy, double* d_atom_energy) {
@@ -1057,22 +1136,49 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
                     std::memcmp(c->graph_cells.data(), cells, sizeof(double) * 9 * B) == 0;
   if (c->reuse && same) {
     // atoms moved less than skin/2 since the last build: refresh positions only
-    launch_refresh_positions(c->N, c->G, c->get<int>("order", c->N), d_pos,
-                             c->get<double>("wrap_off", 3 * (int64_t)c->N),
-                             c->get<int>("ghost_owner", c->G),
-                             c->get<int>("ghost_shift", 3 * (int64_t)c->G),
-                             c->get<int>("sid_ext", c->N + c->G),
-                             c->get<StructParams>("struct_params", c->R),
-                             c->get<double>("pos_ext", 3 * (int64_t)(c->N + c->G)), c->stream);
-  } else {
-    c->have_graph = false;
-    setup_cells(c, B, offsets, cells);
-    build_graph<T>(c, (int)n, d_pos, d_spec);
-    launch_wrap_offsets((int)n, c->get<int>("order", n), d_pos, c->get<double>("pos_ext", 3 * n),
-                        c->get<double>("wrap_off", 3 * n), c->stream);
-    c->graph_cells.assign(cells, cells + 9 * B);
-    c->have_graph = true;
+    auto body = [&] {
+      launch_refresh_positions(c->N, c->G, c->get<int>("order", c->N), d_pos,
+                               c->get<double>("wrap_off", 3 * (int64_t)c->N),
+                               c->get<int>("ghost_owner", c->G),
+                               c->get<int>("ghost_shift", 3 * (int64_t)c->G),
+                               c->get<int>("sid_ext", c->N + c->G),
+                               c->get<StructParams>("struct_params", c->R),
+                               c->get<double>("pos_ext", 3 * (int64_t)(c->N + c->G)), c->stream);
+      Pipe<T, S> p(c);
+      p.forward(d_energy, d_atom_energy);
+    };
+    c->last_fwd_reused = true;
+    c->pending = true;
+    sn_ctx::Replay& r = c->rp_fwd;
+    // replay once an eager run on this graph has sized every buffer
+    if (c->capture && c->reuse_runs >= 1) {
+      if (!replay_hit(r, c->graph_version, d_pos, d_energy, d_atom_energy, 0.0)) {
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        r.exec = nullptr;
+        r.exec = record_graph(c, body);
+        r.version = c->graph_version;
+        r.key[0] = d_pos;
+        r.key[1] = d_energy;
+        r.key[2] = d_atom_energy;
+        r.g = 0.0;
+      }
+      launch_replay(c, r.exec);
+      return;
+    }
+    body();
+    ++c->reuse_runs;
+    return;
   }
+  c->have_graph = false;
+  c->last_fwd_reused = false;
+  c->reuse_runs = 0;
+  ++c->graph_version;
+  setup_cells(c, B, offsets, cells);
+  build_graph<T>(c, (int)n, d_pos, d_spec);
+  launch_wrap_offsets((int)n, c->get<int>("order", n), d_pos, c->get<double>("pos_ext", 3 * n),
+                      c->get<double>("wrap_off", 3 * n), c->stream);
+  c->graph_cells.assign(cells, cells + 9 * B);
+  c->have_graph = true;
   Pipe<T, S> p(c);
   p.forward(d_energy, d_atom_energy);
   c->pending = true;
@@ -1081,9 +1187,27 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
 template <typename T, typename S>
 void backward_impl(sn_ctx* c, double g, double* d_forces, double* d_virial) {
   if (!c->pending) throw std::logic_error("busy");
-  Pipe<T, S> p(c);
-  p.backward(g, d_forces, d_virial);
+  auto body = [&] {
+    Pipe<T, S> p(c);
+    p.backward(g, d_forces, d_virial);
+  };
   c->pending = false;
+  sn_ctx::Replay& r = c->rp_bwd;
+  if (c->capture && c->last_fwd_reused && c->reuse_runs >= 1) {
+    if (!replay_hit(r, c->graph_version, d_forces, d_virial, nullptr, g)) {
+      if (r.exec) (void)hipGraphExecDestroy(r.exec);
+      r.exec = nullptr;
+      r.exec = record_graph(c, body);
+      r.version = c->graph_version;
+      r.key[0] = d_forces;
+      r.key[1] = d_virial;
+      r.key[2] = nullptr;
+      r.g = g;
+    }
+    launch_replay(c, r.exec);
+    return;
+  }
+  body();
 }
 
 void map_species(const sn_model* m, int64_t n, const int32_t* Z, std::vector<int>& out) {
@@ -1199,6 +1323,11 @@ void sn_ctx_free(sn_ctx_t* ctx) {
   if (ctx->d_w32) (void)hipFree(ctx->d_w32);
   if (ctx->d_v) (void)hipFree(ctx->d_v);
   if (ctx->d_shift) (void)hipFree(ctx->d_shift);
+  destroy_replays(ctx);
+  if (ctx->cap_stream) {
+    (void)hipStreamSynchronize(ctx->cap_stream);
+    (void)hipStreamDestroy(ctx->cap_stream);
+  }
   for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
   for (auto ev : ctx->sync_pool) (void)hipEventDestroy(ev);
   if (ctx->aux && ctx->aux != ctx->stream) {
@@ -1212,6 +1341,19 @@ int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32
                       const double* cell, double* d_energy, double* d_atom_energy) {
   if (!ctx || !d_pos || !d_Z || !cell || !d_energy || n <= 0) return SN_EINVAL;
   return guarded(ctx, [&] {
+    const int64_t off[2] = {0, n};
+    const bool reusable = ctx->reuse && ctx->have_graph && ctx->B == 1 && ctx->N == n &&
+                          std::memcmp(ctx->graph_cells.data(), cell, sizeof(double) * 9) == 0;
+    if (reusable) {  // the species of the kept graph stay (reuse contract): no host round trip
+      const int* d_spec = ctx->get<int>("spec_orig", n);
+      if (ctx->precision == SN_FP64)
+        forward_impl<double, double>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+      else if (ctx->precision == SN_BF16)
+        forward_impl<float, bf16_t>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+      else
+        forward_impl<float, float>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+      return;
+    }
     // map atomic numbers to embedding rows on the host (validation before any launch)
     std::vector<int32_t> hz((size_t)n);
     HIPCHK(hipMemcpyAsync(hz.data(), d_Z, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
@@ -1220,7 +1362,6 @@ int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32
     map_species(ctx->m, n, hz.data(), spec);
     int* d_spec = ctx->get<int>("spec_orig", n);
     HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
-    const int64_t off[2] = {0, n};
     if (ctx->precision == SN_FP64)
       forward_impl<double, double>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
     else if (ctx->precision == SN_BF16)
@@ -1316,6 +1457,12 @@ int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, i
   if (n_local) *n_local = ctx->N;
   if (n_ghost) *n_ghost = ctx->G;
   if (n_edge) *n_edge = ctx->E;
+  return SN_OK;
+}
+
+int sn_ctx_set_capture(sn_ctx_t* ctx, int on) {
+  if (!ctx) return SN_EINVAL;
+  ctx->capture = on != 0;
   return SN_OK;
 }
 

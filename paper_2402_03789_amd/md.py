@@ -32,9 +32,10 @@ def maxwell_boltzmann(masses: np.ndarray, temperature: float, seed: int) -> np.n
 class VelocityVerlet:
     def __init__(self, ctx: Context, pos, Z, cell, masses, dt: float = 1.0,
                  rebuild_every: int = 10, temperature: float = 1500.0, seed: int = 5,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", capture: bool = False):
         dev = torch.device(device)
         self.ctx = ctx
+        ctx.set_capture(capture)  # replay the steps between rebuilds from a HIP graph
         self.cell = np.ascontiguousarray(cell, dtype=np.float64)
         self.n = len(Z)
         self.masses = np.asarray(masses, dtype=np.float64)
