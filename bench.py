@@ -53,7 +53,7 @@ def main():
                     help="Si count of the SiO2 sample box timed with the CPU oracle")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (HBM counter calibration)")
-    ap.add_argument("--workload", default="sio2_24k", choices=["sio2_24k", "md", "serving"],
+    ap.add_argument("--workload", default="sio2_24k", choices=["sio2_24k", "md", "serving", "fd"],
                     help="sio2_24k: the headline line (plus a short serving replay); md: the "
                          "112k-atom Si3N4 Verlet run; serving: the full 2,000-request stream")
     ap.add_argument("--serve-requests", type=int, default=None,
@@ -78,6 +78,9 @@ def main():
 
     if args.workload == "md":
         print(json.dumps(bench_md(args)))
+        return
+    if args.workload == "fd":
+        print(json.dumps(bench_fd(args)))
         return
     if args.workload == "serving":
         count = 2000 if args.serve_requests is None else args.serve_requests
@@ -271,6 +274,68 @@ def bench_serving(args, count, precision, full):
                                    "arrivals at 200/s", "precision": precision},
             "p50_ms": out["batched"]["p50_ms"], "p99_ms": out["batched"]["p99_ms"],
             "serving": out}
+
+
+def bench_fd(args):
+    """Differentiation and precision report on the 24k-atom SiO2 box: forces from the
+    hand-written adjoint behind torch.autograd.Function against central differences of the
+    FP64 energy (h = 1e-4 A on 32 seeded atoms), and the FP32 and BF16 forms against the
+    stored FP64 oracle values of 256 sampled atoms."""
+    import numpy as np
+    import torch
+
+    import paper_2402_03789_amd as sn
+    from synth import config_structure
+
+    s = config_structure("sio2_24k")
+    model = sn.Model(_model_file((8, 14), 102))
+    dev = torch.device("cuda:0")
+    Z = torch.tensor(s.Z, dtype=torch.int32, device=dev)
+    ctx = sn.Context(model, precision="fp64")
+    pos = torch.tensor(s.pos, dtype=torch.float64, device=dev, requires_grad=True)
+    t0 = time.perf_counter()
+    E = sn.energy(pos, Z, s.cell, ctx)
+    E.backward()
+    F = -pos.grad.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(3))
+    atoms = rng.choice(s.n, size=32, replace=False)
+    h = 1e-4
+    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    err = 0.0
+    base = torch.tensor(s.pos, dtype=torch.float64, device=dev)
+    for i in atoms:
+        for a in range(3):
+            vals = []
+            for sgn in (1.0, -1.0):
+                p = base.clone()
+                p[i, a] += sgn * h
+                ctx.forward_device(p, Z, s.cell, e)
+                vals.append(float(e.cpu()[0]))
+            fd = -(vals[0] - vals[1]) / (2 * h)
+            err = max(err, abs(fd - F[i, a]))
+    fd_s = time.perf_counter() - t0
+    out = {"metric": "force error of the hand-written adjoint (eV/A)", "workload":
+           "SiO2 24,000 atoms; 5 blocks 128x0e+64x1e+32x2e, l<=2, r_c 5 A",
+           "fd": {"atoms": 32, "h_A": h, "max_abs_fp64_vs_central_difference": err,
+                  "seconds": fd_s}}
+    gpath = os.path.join(ROOT, "tests", "golden", "sio2_24k.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            gold = json.load(f)
+        idx = np.array(gold["sample_index"])
+        ref = np.array(gold["sample_forces"])
+        for prec in ("fp64", "fp32", "bf16"):
+            c = sn.Context(model, precision=prec)
+            r = c.compute(s.pos, s.Z, s.cell)
+            d = r["forces"][idx] - ref
+            de = np.abs(r["atom_energy"][idx] - np.array(gold["sample_atom_energy"]))
+            out[prec] = {"force_max_abs": float(np.abs(d).max()),
+                         "force_rms_rel": float(np.sqrt(np.mean(d ** 2)) / gold["force_rms"]),
+                         "atom_energy_max_rel": float(de.max() / gold["atom_energy_rms"]),
+                         "virial_rel": float(np.linalg.norm(r["virial"].ravel() - np.array(gold["virial"]))
+                                             / np.linalg.norm(gold["virial"]))}
+            del c
+    return out
 
 
 def bench_md(args):

@@ -176,6 +176,25 @@ def test_finite_differences_fp64(real_model):
             assert abs(fd - F[i, a]) < 1e-7 * max(1.0, abs(fd))
 
 
+def test_virial_finite_strain_fp64(real_model):
+    # W = -sum_e d_e (x) dE/dd_e equals -dE/d(strain) for positions and cell strained together
+    spec, path, w, om = real_model
+    pos, Z, cell = _tri(n=16, seed=12)
+    log("virial by finite strain fp64")
+    ctx = sn.Context(sn.Model(path), precision="fp64")
+    W = ctx.compute(pos, Z, cell)["virial"]
+    h = 1e-5
+    for a in range(3):
+        for b in range(3):
+            E = []
+            for sgn in (1, -1):
+                eps = np.eye(3)
+                eps[a, b] += sgn * h
+                E.append(ctx.compute(pos @ eps, Z, cell @ eps, forces=False, virial=False)["energy"])
+            fd = -(E[0] - E[1]) / (2 * h)
+            assert abs(fd - W[a, b]) < 1e-6 * max(1.0, abs(fd)), (a, b, fd, W[a, b])
+
+
 def test_errors_are_reported(small_model):
     spec, path, w, om = small_model
     ctx = sn.Context(sn.Model(path), precision="fp32")
