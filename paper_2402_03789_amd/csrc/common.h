@@ -45,17 +45,17 @@ __device__ inline float sload(float v) { return v; }
 __device__ inline double sload(double v) { return v; }
 __device__ inline float sload(bf16_t v) { return __uint_as_float((uint32_t)v.u << 16); }
 template <typename S, typename T>
-__device__ inline S sstore(T v) {
+__host__ __device__ inline S sstore(T v) {
   return S(v);
 }
 template <>
-__device__ inline bf16_t sstore<bf16_t, float>(float v) {
-  uint32_t u = __float_as_uint(v);
+__host__ __device__ inline bf16_t sstore<bf16_t, float>(float v) {
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
   u += 0x7fffu + ((u >> 16) & 1u);
   return bf16_t{(uint16_t)(u >> 16)};
 }
 template <>
-__device__ inline bf16_t sstore<bf16_t, double>(double v) {
+__host__ __device__ inline bf16_t sstore<bf16_t, double>(double v) {
   return sstore<bf16_t, float>((float)v);
 }
 

@@ -14,8 +14,11 @@
 // computes 16 x 64 output panels as four 16 x 16 MFMA tiles.  Hidden
 // activations stay on the CU (registers and a per-wave LDS panel that turns
 // the accumulator layout into the operand layout); weight panels are staged
-// in LDS once per block and shared by the four waves.  Output panels of w go
-// back through LDS so that every store is a full 256-byte row segment.
+// in LDS once per block and shared by the four waves.  The output layer is
+// computed transposed (w^T = Wc^T z2^T), so a lane's accumulators hold
+// consecutive weights of one pair and go to memory as 16-byte stores.  The
+// adjoint reads dE/dw row-coalesced and turns it into the operand layout
+// through the wave's LDS panel.
 //
 // MFMA layouts (lane l, 16 x 16 tiles):
 //   f32 16x16x4  : a = A[l%16][4s + l/16],     b = B[4s + l/16][l%16]
@@ -153,35 +156,39 @@ __device__ inline void stage_common(int64_t np, int64_t p0, const int* __restric
   }
 }
 
-// Weight-panel prefetch: each of the 256 threads holds 16 values (4 x 4) of a 64 x 64
-// panel in registers while the current panel is being multiplied.  Loads are issued
-// unconditionally from clamped addresses (a load under a branch makes the compiler wait
-// for it, and for every other load in flight, inside that branch); columns past P are
-// zeroed when the panel is staged.
-struct PanelRegs {
-  float v[16];
-};
-
-// Wc panel columns [n0, n0+64) of the forward product, element (k, n) at Wc[k * P + n0 + n]
-__device__ inline void fetch_fwd_panel(const float* __restrict__ Wc, int P, int n0, int tid,
-                                       PanelRegs& r) {
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int i = tid + 256 * j;
-    const int k = i / HID, n = i % HID;
-    r.v[j] = Wc[(int64_t)k * P + min(n0 + n, P - 1)];
-  }
-}
+// Output-layer weights Wc [64 x P] arrive rearranged into 64-column panels, each a
+// contiguous 64 x 64 block (zero past column P): [panel][j][c] (hidden row j, column c) in
+// float32 or bfloat16, or transposed per panel, [panel][c][j], in bfloat16.  A panel is
+// staged into LDS through registers: each of the 256 threads loads 16 bytes per step
+// (four steps in float32, two in bfloat16) while the current panel is being multiplied,
+// and stores them as 16-byte segments of the LDS panel's rows.  Loads past the last panel
+// read the last one again (valid memory; the copy is never used).
 template <bool BF16>
-__device__ inline void store_fwd_panel(const PanelRegs& r, int tid, int P, int n0, float* sf,
-                                       __bf16* sh) {
+using WPan = typename std::conditional<BF16, bf16_t, float>::type;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <bool BF16>
+struct PanelRegs {
+  u32x4 v[BF16 ? 2 : 4];
+};
+constexpr int kPanel = HID * HID;  // elements per panel
+
+template <bool BF16>
+__device__ inline void fetch_panel(const WPan<BF16>* __restrict__ pan, int panel, int npan, int tid,
+                                   PanelRegs<BF16>& r) {
+  const WPan<BF16>* src = pan + (int64_t)min(panel, npan - 1) * kPanel;
+  constexpr int PER = BF16 ? 8 : 4;  // elements per 16 bytes
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int i = tid + 256 * j;
-    const int k = i / HID, n = i % HID;
-    const float v = n0 + n < P ? r.v[j] : 0.f;
-    if (BF16) sh[n * BP + k] = __float2bfloat16(v);
-    else sf[k * WP + n] = v;
+  for (int j = 0; j < (BF16 ? 2 : 4); ++j)
+    r.v[j] = *reinterpret_cast<const u32x4*>(src + (tid + 256 * j) * PER);
+}
+// store into an LDS panel of row stride ld elements (a multiple of 16 bytes)
+template <bool BF16>
+__device__ inline void store_panel(const PanelRegs<BF16>& r, int tid, WPan<BF16>* lds, int ld) {
+  constexpr int PER = BF16 ? 8 : 4;
+#pragma unroll
+  for (int j = 0; j < (BF16 ? 2 : 4); ++j) {
+    const int i = (tid + 256 * j) * PER;
+    *reinterpret_cast<u32x4*>(lds + (i / HID) * ld + i % HID) = r.v[j];
   }
 }
 
@@ -194,9 +201,8 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
                                                         const float* __restrict__ rho,
                                                         const float* __restrict__ Wa,
                                                         const float* __restrict__ Wb,
-                                                        const float* __restrict__ Wc, int P, float c,
-                                                        WStore<BF16>* __restrict__ w) {
-  constexpr int PANEL = BF16 ? (HID * BP) / 2 : HID * WP;  // floats per panel buffer
+                                                        const WPan<BF16>* __restrict__ Wcp, int P,
+                                                        float c, WStore<BF16>* __restrict__ w) {
   __shared__ float sWa[NBAS * HID];
   __shared__ float sRho[EB * (NBAS + 1)];
   __shared__ float sZ[4][16 * ZP];
@@ -206,14 +212,15 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sW[1], sRho);
   __shared__ __attribute__((aligned(16))) __bf16 sWbT[BF16 ? HID * BP : 8];
   if (BF16) stage_wb_bf16(Wb, sWbT, nullptr);
-  PanelRegs pr;
-  fetch_fwd_panel(Wc, P, 0, tid, pr);
+  const int npan = (P + HID - 1) / HID;
+  PanelRegs<BF16> pr;
+  fetch_panel<BF16>(Wcp, 0, npan, tid, pr);
   __syncthreads();
   float* Z = sZ[wave];
   floatx4 acc[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, acc, lane);
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
-  store_fwd_panel<BF16>(pr, tid, P, 0, sW[0], reinterpret_cast<__bf16*>(sW[0]));
+  store_panel<BF16>(pr, tid, reinterpret_cast<WPan<BF16>*>(sW[0]), BF16 ? BP : WP);
   __syncthreads();
   zero4(acc);
   if (BF16) panel_bf16(Z, sWbT, acc, lane);
@@ -234,138 +241,144 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
 #pragma unroll
     for (int s = 0; s < HID / 4; ++s) za[s] = Z[r * ZP + 4 * s + q];
   }
-  (void)PANEL;
   int buf = 0;
   for (int n0 = 0; n0 < P; n0 += HID) {
-    fetch_fwd_panel(Wc, P, n0 + HID, tid, pr);  // in flight during the MFMAs (clamped past P)
+    fetch_panel<BF16>(Wcp, n0 / HID + 1, npan, tid, pr);  // in flight during the MFMAs
     __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
     const float* sf = sW[buf];
     const __bf16* sh = reinterpret_cast<const __bf16*>(sW[buf]);
+    // the transposed product w^T = Wc^T z2^T: lane (r, q) receives weights of pair r only.
+    // float32: row i of tile t is panel column 16 t + i, so acc[t] = w[pair r][n0 + 16 t +
+    // 4 q + 0..3] (the A rows read from LDS stay bank-conflict free); bfloat16: row i of
+    // tile t is column 16 (i / 4) + 4 t + i % 4, so acc[0..3][0..3] = w[pair r][n0 + 16 q +
+    // 0..15], sixteen consecutive values for two 16-byte stores
     zero4(acc);
     if (BF16) {
+      const int ca = 16 * (r >> 2) + (r & 3);
 #pragma unroll
       for (int s = 0; s < HID / 32; ++s)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
-          acc[t] = mfma32(zh[s], b, acc[t]);
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sh[(ca + 4 * t) * BP + 32 * s + 8 * q]);
+          acc[t] = mfma32(a, zh[s], acc[t]);
         }
     } else {
 #pragma unroll
       for (int s = 0; s < HID / 4; ++s)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = mfma4(za[s], sf[(4 * s + q) * WP + t * 16 + r], acc[t]);
+        for (int t = 0; t < 4; ++t) acc[t] = mfma4(sf[(4 * s + q) * WP + 16 * t + r], za[s], acc[t]);
     }
-    // through the wave's own panel to full-row float4 stores
-    acc_to_panel(acc, Z, lane, [](float v, int, int) { return v; });
     // staged unconditionally (the panel past the last is never read): a conditional store
     // would let the compiler sink the panel loads into the branch, after the MFMAs
-    store_fwd_panel<BF16>(pr, tid, P, n0 + HID, sW[buf ^ 1], reinterpret_cast<__bf16*>(sW[buf ^ 1]));
-    __syncthreads();
-    const int c4 = (lane & 15) * 4;
+    store_panel<BF16>(pr, tid, reinterpret_cast<WPan<BF16>*>(sW[buf ^ 1]), BF16 ? BP : WP);
+    const int64_t p = p0 + wave * 16 + r;
+    if (p < np) {
+      if constexpr (BF16) {  // two 16-byte stores of eight bfloat16 values
+        const int c0 = n0 + 16 * q;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int row = (lane >> 4) + 4 * k;
-      const int64_t p = p0 + wave * 16 + row;
-      if (p < np && n0 + c4 < P) {
-        const float* zr = &Z[row * ZP + c4];
-        if constexpr (BF16) {  // four bfloat16 values per lane: 128 contiguous bytes per row
-          uint2 v;
-          v.x = (uint32_t)sstore<bf16_t>(zr[0]).u | ((uint32_t)sstore<bf16_t>(zr[1]).u << 16);
-          v.y = (uint32_t)sstore<bf16_t>(zr[2]).u | ((uint32_t)sstore<bf16_t>(zr[3]).u << 16);
-          *reinterpret_cast<uint2*>(&w[p * P + n0 + c4]) = v;
-        } else {
-          *reinterpret_cast<floatx4*>(&w[p * P + n0 + c4]) = floatx4{zr[0], zr[1], zr[2], zr[3]};
+        for (int h = 0; h < 2; ++h) {
+          if (c0 + 8 * h < P) {  // P is a multiple of 8
+            u32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int t = 2 * h + (e >> 1), rr = 2 * (e & 1);
+              v[e] = (uint32_t)sstore<bf16_t>(acc[t][rr]).u |
+                     ((uint32_t)sstore<bf16_t>(acc[t][rr + 1]).u << 16);
+            }
+            *reinterpret_cast<u32x4*>(&w[p * P + c0 + 8 * h]) = v;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int col = n0 + 16 * t + 4 * q;
+          if (col < P) *reinterpret_cast<floatx4*>(&w[p * P + col]) = acc[t];  // P % 4 == 0
         }
       }
     }
+    __syncthreads();
     buf ^= 1;
   }
 }
 
-// Wc panel for the adjoint: element (j, k) at Wc[j * P + k0 + k] (hidden row j)
-__device__ inline void fetch_bwd_panel(const float* __restrict__ Wc, int P, int k0, int tid,
-                                       PanelRegs& r) {
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int i = tid + 256 * j;
-    const int jj = i / HID, k = i % HID;
-    r.v[j] = Wc[(int64_t)jj * P + min(k0 + k, P - 1)];
-  }
-}
+// dE/dw of the 16 pairs of a wave for one 64-wide k panel, loaded row-coalesced: the
+// float32 form covers rows 4 i + l / 16 (i = 0..3) and columns 4 (l % 16) .. + 3 of the
+// panel (each load is four full 256-byte row segments); the bfloat16 form covers rows
+// 8 i + l / 8 (i = 0..1) and columns 8 (l % 8) .. + 7 (eight full 128-byte row
+// segments).  Both edges of a pair are loaded unconditionally (the reverse edge's row
+// 2p + 1 exists in the buffer even when the pair has none; rows past the last pair are
+// clamped to it) and combined, masked, when the panel is staged.
 template <bool BF16>
-__device__ inline void store_bwd_panel(const PanelRegs& r, int tid, int P, int k0, float* sf,
-                                       __bf16* sh) {
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int i = tid + 256 * j;
-    const int jj = i / HID, k = i % HID;
-    const float v = k0 + k < P ? r.v[j] : 0.f;
-    if (BF16) sh[jj * BP + k] = __float2bfloat16(v);
-    else sf[jj * TP + k] = v;
-  }
-}
-
-// dw operand of one lane for a 64-wide k panel, both edges of the pair loaded separately
-// and unconditionally (clamped addresses; a missing reverse edge reads the first row
-// again) and combined when the panel is used.  float32 form: lane group q covers
-// k = 16 u + 4 q + 0..3; bfloat16 form: k = 32 (u / 2) + 8 q + 4 (u % 2) + 0..3, the order
-// of the 16x16x32 operand.
+struct DwRegs {
+  static constexpr int N = BF16 ? 2 : 4;  // loads per edge side
+  u32x4 a[N], b[N];
+};
+// row of load i of this lane and its base offset (row 2p of the pair-major buffer)
 template <bool BF16>
-struct DwRegs;
-template <>
-struct DwRegs<false> {  // float32 dE/dw: 16 values per edge row per panel
-  floatx4 a[HID / 16], b[HID / 16];
-};
-template <>
-struct DwRegs<true> {  // bfloat16 dE/dw: 2 x 8 values per edge row per panel
-  uint4 a[HID / 32], b[HID / 32];
-};
-__device__ inline int dw_col(int k0, int u, int q) { return k0 + 16 * u + 4 * q; }
-__device__ inline int dw_col16(int k0, int s, int q) { return k0 + 32 * s + 8 * q; }
-
-__device__ inline void fetch_dw(const float* __restrict__ dw, int64_t r1, int64_t r2, int P, int k0,
-                                int q, DwRegs<false>& d) {
+struct DwRows {
+  static constexpr int N = DwRegs<BF16>::N;
+  int64_t base[N];
+  unsigned ok = 0, two = 0;  // per load: row is a pair; the pair has a reverse edge
+  __device__ DwRows(int64_t np, int64_t p_first, const int* __restrict__ pe2, int P, int lane) {
 #pragma unroll
-  for (int u = 0; u < HID / 16; ++u) {
-    const int kb = min(dw_col(k0, u, q), P - 4);  // P is a multiple of 4
-    d.a[u] = *reinterpret_cast<const floatx4*>(&dw[r1 + kb]);
-    d.b[u] = *reinterpret_cast<const floatx4*>(&dw[r2 + kb]);
-  }
-}
-__device__ inline void fetch_dw(const bf16_t* __restrict__ dw, int64_t r1, int64_t r2, int P,
-                                int k0, int q, DwRegs<true>& d) {
-#pragma unroll
-  for (int s = 0; s < HID / 32; ++s) {
-    const int kb = min(dw_col16(k0, s, q), P - 8);  // P is a multiple of 8
-    d.a[s] = *reinterpret_cast<const uint4*>(&dw[r1 + kb]);
-    d.b[s] = *reinterpret_cast<const uint4*>(&dw[r2 + kb]);
-  }
-}
-__device__ inline floatx4 dw_value(const DwRegs<false>& d, int u, bool row_ok, bool has2, int P,
-                                   int k0, int q) {
-  const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
-  if (!row_ok || dw_col(k0, u, q) >= P) return z;
-  return has2 ? d.a[u] + d.b[u] : d.a[u];
-}
-// operand of the 16x16x32 product: the pair's summed dE/dw at k = 32 s + 8 q + 0..7
-__device__ inline bf16x8 dw_value16(const DwRegs<true>& d, int s, bool row_ok, bool has2, int P,
-                                    int k0, int q) {
-  const bool valid = row_ok && dw_col16(k0, s, q) < P;
-  const uint32_t av[4] = {d.a[s].x, d.a[s].y, d.a[s].z, d.a[s].w};
-  const uint32_t bv[4] = {d.b[s].x, d.b[s].y, d.b[s].z, d.b[s].w};
-  bf16x8 r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const float fa = __uint_as_float(h ? (av[i] & 0xffff0000u) : (av[i] << 16));
-      const float fb = __uint_as_float(h ? (bv[i] & 0xffff0000u) : (bv[i] << 16));
-      const float f = valid ? (has2 ? fa + fb : fa) : 0.f;
-      r[2 * i + h] = __float2bfloat16(f);
+    for (int i = 0; i < N; ++i) {
+      const int64_t p = p_first + (BF16 ? 8 * i + (lane >> 3) : 4 * i + (lane >> 4));
+      const int64_t pc = p < np ? p : np - 1;
+      base[i] = 2 * pc * P;
+      if (p < np) {
+        ok |= 1u << i;
+        if (pe2[p] >= 0) two |= 1u << i;
+      }
     }
   }
-  return r;
+};
+template <bool BF16>
+__device__ inline int dw_lane_col(int lane) {
+  return BF16 ? 8 * (lane & 7) : 4 * (lane & 15);
+}
+template <bool BF16>
+__device__ inline void fetch_dw(const WStore<BF16>* __restrict__ dw, const DwRows<BF16>& rows, int P,
+                                int k0, int lane, DwRegs<BF16>& d) {
+  constexpr int PER = BF16 ? 8 : 4;
+  const int kb = min(k0 + dw_lane_col<BF16>(lane), P - PER);  // P is a multiple of 8
+#pragma unroll
+  for (int i = 0; i < DwRegs<BF16>::N; ++i) {
+    d.a[i] = *reinterpret_cast<const u32x4*>(&dw[rows.base[i] + kb]);
+    d.b[i] = *reinterpret_cast<const u32x4*>(&dw[rows.base[i] + P + kb]);
+  }
+}
+// the pair sums of one panel into the wave's LDS tile: float32 rows of stride ZP, or
+// bfloat16 rows of stride BP (rounded to nearest even)
+template <bool BF16>
+__device__ inline void stage_dw(const DwRegs<BF16>& d, const DwRows<BF16>& rows, int P, int k0,
+                                int lane, float* Z) {
+  const int col = dw_lane_col<BF16>(lane);
+  const bool col_ok = k0 + col < P;
+#pragma unroll
+  for (int i = 0; i < DwRegs<BF16>::N; ++i) {
+    const bool valid = col_ok && ((rows.ok >> i) & 1u);
+    const bool two = (rows.two >> i) & 1u;
+    if constexpr (BF16) {
+      const int row = 8 * i + (lane >> 3);
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float fa = __uint_as_float(h ? (d.a[i][e] & 0xffff0000u) : (d.a[i][e] << 16));
+          const float fb = __uint_as_float(h ? (d.b[i][e] & 0xffff0000u) : (d.b[i][e] << 16));
+          v[2 * e + h] = __float2bfloat16(valid ? (two ? fa + fb : fa) : 0.f);
+        }
+      }
+      *reinterpret_cast<bf16x8*>(reinterpret_cast<__bf16*>(Z) + row * BP + col) = v;
+    } else {
+      const int row = 4 * i + (lane >> 4);
+      const floatx4 fa = __builtin_bit_cast(floatx4, d.a[i]);
+      const floatx4 fb = __builtin_bit_cast(floatx4, d.b[i]);
+      const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+      *reinterpret_cast<floatx4*>(Z + row * ZP + col) = valid ? (two ? fa + fb : fa) : z;
+    }
+  }
 }
 
 // ------------------------------------------------------------------ backward
@@ -375,8 +388,8 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
                                                         const float* __restrict__ rho,
                                                         const float* __restrict__ Wa,
                                                         const float* __restrict__ Wb,
-                                                        const float* __restrict__ Wc, int P, float c,
-                                                        const WStore<BF16>* __restrict__ dw,
+                                                        const WPan<BF16>* __restrict__ Wcp, int P,
+                                                        float c, const WStore<BF16>* __restrict__ dw,
                                                         float* __restrict__ drho, int accumulate) {
   __shared__ float sWa[NBAS * HID];
   __shared__ float sWb[BF16 ? 4 : HID * WP];  // float32 form only (bfloat16 copies below)
@@ -391,20 +404,17 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   __shared__ __attribute__((aligned(16))) __bf16 sWbN[BF16 ? HID * BP : 8];
   if (BF16) stage_wb_bf16(Wb, sWbT, sWbN);
   const int r = lane & 15, q = lane >> 4;
-  const int64_t pr = p0 + wave * 16 + r;
-  const bool row_ok = pr < np;
   // dE/dw is pair-major: rows 2p (first edge) and 2p + 1 (its reverse, when present)
-  const int64_t r1 = row_ok ? 2 * pr * P : 0;
-  const bool has2 = row_ok && pe2[pr] >= 0;
-  const int64_t r2 = has2 ? r1 + P : r1;
-  PanelRegs wr;
+  const DwRows<BF16> rows(np, p0 + wave * 16, pe2, P, lane);
+  const int npan = (P + HID - 1) / HID;
+  PanelRegs<BF16> wr;
   // dE/dw panels in flight: a ring of RING register sets (RING - 1 panels ahead); the
   // bfloat16 operands are small and the matrix cores fast, so that form looks further ahead
-  constexpr int RING = BF16 ? 4 : 2;
+  constexpr int RING = BF16 ? 6 : 3;
   DwRegs<BF16> ring[RING];
-  fetch_bwd_panel(Wc, P, 0, tid, wr);
+  fetch_panel<BF16>(Wcp, 0, npan, tid, wr);
   static_for<RING - 1>([&](auto J) {
-    fetch_dw(dw, r1, r2, P, decltype(J)::value * HID, q, ring[decltype(J)::value]);
+    fetch_dw<BF16>(dw, rows, P, decltype(J)::value * HID, lane, ring[decltype(J)::value]);
   });
   __syncthreads();
   float* Z = sZ[wave];
@@ -412,7 +422,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   floatx4 a1[4], a2[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, a1, lane);
   acc_to_panel(a1, Z, lane, [&](float v, int, int) { return phi(v, c); });
-  store_bwd_panel<BF16>(wr, tid, P, 0, sB[0], reinterpret_cast<__bf16*>(sB[0]));
+  store_panel<BF16>(wr, tid, reinterpret_cast<WPan<BF16>*>(sB[0]), BF16 ? BP : TP);
   __syncthreads();
   zero4(a2);
   if (BF16) panel_bf16(Z, sWbT, a2, lane);
@@ -424,20 +434,22 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   // panel) are issued first and unconditionally, so they stay in flight across this
   // panel's MFMAs; the panel loop is unrolled by RING so the operand sets rotate through
   // fixed registers (no copies).
-  const int npan = (P + HID - 1) / HID;
   int buf = 0;
   auto step = [&](int jj, auto SLOT) {
     constexpr int rc = decltype(SLOT)::value, rn = (rc + RING - 1) % RING;
     const DwRegs<BF16>& cur = ring[rc];
     const int k0 = jj * HID;
-    fetch_bwd_panel(Wc, P, k0 + HID, tid, wr);
-    fetch_dw(dw, r1, r2, P, k0 + (RING - 1) * HID, q, ring[rn]);
+    fetch_panel<BF16>(Wcp, jj + 1, npan, tid, wr);
+    fetch_dw<BF16>(dw, rows, P, k0 + (RING - 1) * HID, lane, ring[rn]);
     if (jj < npan) {
+      // the pairs' summed dE/dw through the wave's LDS tile into the operand layout
+      stage_dw<BF16>(cur, rows, P, k0, lane, Z);
       if constexpr (BF16) {
         const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
+        const __bf16* zh = reinterpret_cast<const __bf16*>(Z);
 #pragma unroll
         for (int s = 0; s < HID / 32; ++s) {
-          const bf16x8 a = dw_value16(cur, s, row_ok, has2, P, k0, q);
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&zh[r * BP + 32 * s + 8 * q]);
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
@@ -448,7 +460,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
         const float* sf = sB[buf];
 #pragma unroll
         for (int u = 0; u < HID / 16; ++u) {
-          const floatx4 av = dw_value(cur, u, row_ok, has2, P, k0, q);
+          const floatx4 av = *reinterpret_cast<const floatx4*>(&Z[r * ZP + 16 * u + 4 * q]);
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const floatx4 bv =
@@ -459,7 +471,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
         }
       }
     }
-    store_bwd_panel<BF16>(wr, tid, P, k0 + HID, sB[buf ^ 1], reinterpret_cast<__bf16*>(sB[buf ^ 1]));
+    store_panel<BF16>(wr, tid, reinterpret_cast<WPan<BF16>*>(sB[buf ^ 1]), BF16 ? BP : TP);
     __syncthreads();
     buf ^= 1;
   };
@@ -500,21 +512,21 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
 
 template <typename WS>
 void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
-                          const float* Wb, const float* Wc, int P, float c, WS* w, hipStream_t s) {
+                          const float* Wb, const WS* Wcp, int P, float c, WS* w, hipStream_t s) {
   if (np <= 0) return;
   const unsigned grid = (unsigned)((np + EB - 1) / EB);
   constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
-  k_mlp_fused_fwd<BF16><<<grid, 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wc, P, c, w);
+  k_mlp_fused_fwd<BF16><<<grid, 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wcp, P, c, w);
 }
 
 template <typename WS>
 void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
-                          const float* Wa, const float* Wb, const float* Wc, int P, float c,
+                          const float* Wa, const float* Wb, const WS* Wcp, int P, float c,
                           const WS* dw, float* drho, bool accumulate, hipStream_t s) {
   if (np <= 0) return;
   const unsigned grid = (unsigned)((np + EB - 1) / EB);
   constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
-  k_mlp_fused_bwd<BF16><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wc, P, c, dw, drho,
+  k_mlp_fused_bwd<BF16><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wcp, P, c, dw, drho,
                                              accumulate ? 1 : 0);
 }
 
@@ -522,13 +534,13 @@ template void launch_mlp_fused_fwd<float>(int64_t, const int*, const float*, con
                                           const float*, const float*, int, float, float*,
                                           hipStream_t);
 template void launch_mlp_fused_fwd<bf16_t>(int64_t, const int*, const float*, const float*,
-                                           const float*, const float*, int, float, bf16_t*,
+                                           const float*, const bf16_t*, int, float, bf16_t*,
                                            hipStream_t);
 template void launch_mlp_fused_bwd<float>(int64_t, const int*, const int*, const float*,
                                           const float*, const float*, const float*, int, float,
                                           const float*, float*, bool, hipStream_t);
 template void launch_mlp_fused_bwd<bf16_t>(int64_t, const int*, const int*, const float*,
-                                           const float*, const float*, const float*, int, float,
+                                           const float*, const float*, const bf16_t*, int, float,
                                            const bf16_t*, float*, bool, hipStream_t);
 
 }  // namespace sn

@@ -104,12 +104,15 @@ void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const T* dw, in
 // bfloat16 storage of w and dE/dw.  Both run over undirected pairs: pair p takes rho of
 // edge pe1[p]; the backward sums the pair-major dE/dw rows 2p and 2p+1 (the latter absent
 // when pe2[p] < 0) and adds drho into row pe1[p].  P must be a multiple of 8.
+// The output weights Wc [64 x P] come as 64-column panels, each 64 x 64 contiguous and
+// zero past column P (see wc_panels): [panel][j][c] for the backward and for the float32
+// forward, [panel][c][j] for the bfloat16 forward.
 template <typename WS>
 void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
-                          const float* Wb, const float* Wc, int P, float c, WS* w, hipStream_t s);
+                          const float* Wb, const WS* Wcp, int P, float c, WS* w, hipStream_t s);
 template <typename WS>
 void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
-                          const float* Wa, const float* Wb, const float* Wc, int P, float c,
+                          const float* Wa, const float* Wb, const WS* Wcp, int P, float c,
                           const WS* dw, float* drho, bool accumulate, hipStream_t s);
 
 // ---------------------------------------------------------------- tensor product

@@ -285,6 +285,10 @@ struct sn_ctx {
   // device weights (float64 copy and float32 copy)
   void* d_w = nullptr;
   void* d_w32 = nullptr;
+  // per block: the radial MLP's output weights as 64-column panels (wc_panels)
+  void* d_wpan = nullptr;
+  std::vector<const float*> wc_pan;
+  std::vector<const bf16_t*> wc_pan16, wc_panT16;
   size_t weight_bytes = 0;
   double* d_v = nullptr;
   double* d_shift = nullptr;
@@ -430,6 +434,51 @@ const float* W<float>(const sn_ctx* c, int64_t off) {
   return static_cast<const float*>(c->d_w32) + off;
 }
 
+// The radial MLP's output weights Wc [hidden x P] of every block, rearranged for the fused
+// matrix-core kernels into 64-column panels of 64 x 64 contiguous values, zero past column
+// P: float32 [panel][j][c], bfloat16 [panel][j][c], and bfloat16 [panel][c][j].
+void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
+  const sn_model* m = c->m;
+  constexpr int H = 64, K = H * H;  // the model's hidden width (checked at load)
+  std::vector<size_t> off;
+  size_t total = 0;
+  for (const LayerDesc& L : m->layers) {
+    off.push_back(total);
+    total += (size_t)((L.P + H - 1) / H) * K;
+  }
+  std::vector<float> f(total, 0.f);
+  std::vector<bf16_t> h(total), ht(total);
+  for (size_t t = 0; t < m->layers.size(); ++t) {
+    const LayerDesc& L = m->layers[t];
+    const float* wc = w32.data() + L.w_mlp[2];
+    for (int pan = 0; pan * H < L.P; ++pan)
+      for (int j = 0; j < H; ++j)
+        for (int q = 0; q < H; ++q) {
+          const int col = pan * H + q;
+          const float v = col < L.P ? wc[(size_t)j * L.P + col] : 0.f;
+          const size_t b = off[t] + (size_t)pan * K;
+          f[b + j * H + q] = v;
+          h[b + j * H + q] = sstore<bf16_t>(v);
+          ht[b + q * H + j] = sstore<bf16_t>(v);
+        }
+  }
+  const size_t bytes = total * (sizeof(float) + 2 * sizeof(bf16_t));
+  HIPCHK(hipMalloc(&c->d_wpan, bytes));
+  char* d = static_cast<char*>(c->d_wpan);
+  float* df = reinterpret_cast<float*>(d);
+  bf16_t* dh = reinterpret_cast<bf16_t*>(d + total * sizeof(float));
+  bf16_t* dht = dh + total;
+  HIPCHK(hipMemcpy(df, f.data(), total * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dh, h.data(), total * sizeof(bf16_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dht, ht.data(), total * sizeof(bf16_t), hipMemcpyHostToDevice));
+  for (size_t t = 0; t < m->layers.size(); ++t) {
+    c->wc_pan.push_back(df + off[t]);
+    c->wc_pan16.push_back(dh + off[t]);
+    c->wc_panT16.push_back(dht + off[t]);
+  }
+  c->weight_bytes += bytes;
+}
+
 void upload_weights(sn_ctx* c) {
   const sn_model* m = c->m;
   // SN_SERIAL in the environment keeps every launch on the context's stream (clean
@@ -451,6 +500,7 @@ void upload_weights(sn_ctx* c) {
                    hipMemcpyHostToDevice));
   c->weight_bytes = m->flat.size() * (sizeof(double) + sizeof(float)) +
                     (m->readout_v.size() + m->shift.size()) * sizeof(double);
+  wc_panels(c, w32);
 }
 
 // ------------------------------------------------------------------ graph build
@@ -754,6 +804,15 @@ struct Pipe {
     }
   }
 
+  // panels of block L's output weights for the fused kernels (the transposed bfloat16
+  // copy for the bfloat16 forward)
+  template <typename WS>
+  const WS* wc_panel(const LayerDesc& L, bool fwd) const {
+    const size_t t = (size_t)(&L - m->layers.data());
+    if constexpr (std::is_same<WS, bf16_t>::value) return fwd ? c->wc_panT16[t] : c->wc_pan16[t];
+    else return c->wc_pan[t];
+  }
+
   // radial MLP over undirected pairs: fused matrix-core kernels for float32 storage,
   // vector-unit path for float64
   void mlp_forward(const LayerDesc& L, const T* rho, S* w) {
@@ -762,7 +821,7 @@ struct Pipe {
     if constexpr (std::is_same<T, float>::value) {
       if (L.P % 8) throw UnsupportedError("radial weight count not a multiple of 8");
       launch_mlp_fused_fwd<S>(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
-                              W<float>(c, L.w_mlp[2]), L.P, (float)m->act, w, s);
+                              wc_panel<S>(L, true), L.P, (float)m->act, w, s);
     } else {
       T* z2 = c->get<T>("z2", NPr * m->hidden);
       launch_mlp_hidden_fwd<T>(NPr, pe1, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]),
@@ -778,7 +837,7 @@ struct Pipe {
     if constexpr (std::is_same<T, float>::value) {
       (void)dz2;
       launch_mlp_fused_bwd<S>(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
-                              W<float>(c, L.w_mlp[2]), L.P, (float)m->act, dw, drho, true, s);
+                              wc_panel<S>(L, false), L.P, (float)m->act, dw, drho, true, s);
     } else {
       T* dws = c->get<T>("dw_pair", NPr * L.P);
       launch_pair_sum<T>(NPr, pe1, pe2, dw, L.P, dws, s);
@@ -1321,6 +1380,7 @@ void sn_ctx_free(sn_ctx_t* ctx) {
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (ctx->d_w) (void)hipFree(ctx->d_w);
   if (ctx->d_w32) (void)hipFree(ctx->d_w32);
+  if (ctx->d_wpan) (void)hipFree(ctx->d_wpan);
   if (ctx->d_v) (void)hipFree(ctx->d_v);
   if (ctx->d_shift) (void)hipFree(ctx->d_shift);
   destroy_replays(ctx);
