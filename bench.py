@@ -42,6 +42,31 @@ def _traffic(kernel, source, precision):
     return rec.get("bytes_per_launch")
 
 
+def _tp_blocks(spec):
+    """(P, Dx, Dm, writes dE/dx) of every interaction block's tensor product: radial weights
+    per edge, sender feature width, message width, and whether the adjoint writes per-edge
+    sender gradients (not for the first block, whose inputs are the species embedding)."""
+    out = []
+    for t in range(spec.n_layers):
+        paths = spec._paths(t)
+        P = sum(spec.muls[l1] for (l1, _, _) in paths)
+        Dm = sum(spec.muls[l1] * (2 * l3 + 1) for (l1, _, l3) in paths)
+        Dx = sum(spec.muls[l] * (2 * l + 1) for l in spec._in_ls(t))
+        out.append((P, Dx, Dm, t > 0))
+    return out
+
+
+def _roofline_entry(kernel, nbytes, nflops, ms, traffic, peak_tf):
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
+    e = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+         "frac": (achieved / 8000.0) if achieved else None, "traffic": traffic,
+         "launch_ms": ms, "algorithmic_bytes_per_launch": nbytes}
+    if nflops:
+        e["algorithmic_flops_per_launch"] = nflops
+        e["mfma_frac"] = nflops / (ms * 1e-3) / 1e12 / peak_tf if ms > 0 else None
+    return e
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +74,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-isolated", action="store_true",
+                    help="skip the single-stream context that times the roofline kernels in "
+                         "isolation (for kernel traces of the overlapped steps alone)")
     ap.add_argument("--cpu-sample-si", type=int, default=512,
                     help="Si count of the SiO2 sample box timed with the CPU oracle")
     ap.add_argument("--calib-copy", action="store_true",
@@ -136,56 +164,74 @@ def main():
     n, g, e = ctx.graph_size()
     value = s.n * args.steps / dt
 
-    # Roofline of the dominant kernel: the fused radial-MLP adjoint, one launch per
-    # interaction block, each timed by HIP events on the context's stream (in the
-    # float32/bfloat16 forms each "bwd.layer<t>.mlp" phase holds exactly that launch).
-    # Algorithmic bytes of a launch with P radial weights per pair: read dE/dw of both
-    # edges of every pair (2 x P values of 4 bytes, 2 in the BF16 form, 8 in the FP64 form),
-    # read rho and write drho (2 x 32 bytes).
-    npairs = ctx.n_pairs()
-    Ps = [960 if 0 < t < 4 else (384 if t == 0 else 224) for t in range(5)]
-    launches = [f"bwd.layer{t}.mlp" for t in range(5)]
-    launch_ms = sum(phase_ms.get(k, 0.0) for k in launches) / (len(launches) * args.steps)
-    P_mean = sum(Ps) / len(Ps)
+    # Roofline of the dominant kernel, the tensor-product adjoint (k_tp_bwd, about a third
+    # of the GPU time of a step).  Unit: the adjoint of one interaction block, i.e. its
+    # per-degree launches, which are exactly the "bwd.layer<t>.tp" phase timed by HIP events
+    # on the context's stream; averaged over the five blocks.  Algorithmic bytes of block t
+    # (b = storage bytes of w, dE/dw and the dE/dx rows: 4 in FP32, 2 in BF16, 8 in FP64):
+    # per edge, read the pair's w slice and write dE/dw (2 b P_t), write the dE/dx row
+    # (b Dx_t, not in the first block) and, per degree launch, read Y and read and write
+    # dE/dY (3 x 9 x 4 bytes each); per receiver, read G (Dm_t x 4 bytes); every sender row
+    # once (NE x Dx_t x b: the per-edge gathers of x hit the caches).
     wbytes = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
-    bytes_per_launch = npairs * (2 * wbytes * P_mean + 64)
-    flops_per_launch = npairs * (2 * 64 * P_mean + 2 * (8 * 64 + 64 * 64 + 64 * 64 + 64 * 8))
-    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else None
-    traffic = _traffic("k_mlp_fused_bwd", os.path.join(ROOT, "paper_2402_03789_amd", "csrc",
-                                                        "k_mlp.hip"), args.precision)
-    peak_tf = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[args.precision]
-    roofline = {"bound": "hbm", "kernel": "k_mlp_fused_bwd (radial-MLP adjoint over edge pairs)",
-                "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": (achieved / 8000.0) if achieved else None,
-                "traffic": traffic,
-                "launch_ms": launch_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "algorithmic_flops_per_launch": flops_per_launch,
-                "mfma_frac": (flops_per_launch / (launch_ms * 1e-3) / 1e12 / peak_tf)
-                if launch_ms > 0 else None}
+    tbytes = 8 if args.precision == "fp64" else 4
+    blocks = _tp_blocks(spec)
+    tp_bytes = [e * (2 * wbytes * P + (wbytes * Dx if wdx else 0) + 3 * 3 * 9 * tbytes)
+                + n * Dm * tbytes + (n + g) * Dx * wbytes for (P, Dx, Dm, wdx) in blocks]
+    bytes_tp = sum(tp_bytes) / len(tp_bytes)
+    tp_phases = [f"bwd.layer{t}.tp" for t in range(len(blocks))]
+    tp_ms = sum(phase_ms.get(k, 0.0) for k in tp_phases) / (len(tp_phases) * args.steps)
+    roofline = _roofline_entry(
+        "k_tp_bwd (tensor-product adjoint; one interaction block = its degree launches)",
+        bytes_tp, None, tp_ms,
+        _traffic("k_tp_bwd", os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_tp.hip"),
+                 args.precision), None)
 
-    # The same kernel timed in isolation: a second context created with SN_SERIAL=1 runs
+    # The radial-MLP adjoint (one launch per block, "bwd.layer<t>.mlp" on the MLP stream):
+    # read dE/dw of both edges of every pair (2 b P), read rho and write drho (2 x 32 bytes).
+    npairs = ctx.n_pairs()
+    Ps = [b[0] for b in blocks]
+    mlp_phases = [f"bwd.layer{t}.mlp" for t in range(len(blocks))]
+    mlp_ms = sum(phase_ms.get(k, 0.0) for k in mlp_phases) / (len(mlp_phases) * args.steps)
+    P_mean = sum(Ps) / len(Ps)
+    bytes_mlp = npairs * (2 * wbytes * P_mean + 64)
+    flops_mlp = npairs * (2 * 64 * P_mean + 2 * (8 * 64 + 64 * 64 + 64 * 64 + 64 * 8))
+    peak_tf = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[args.precision]
+    roofline_mlp = _roofline_entry(
+        "k_mlp_fused_bwd (radial-MLP adjoint over edge pairs)", bytes_mlp, flops_mlp, mlp_ms,
+        _traffic("k_mlp_fused_bwd", os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_mlp.hip"),
+                 args.precision), peak_tf)
+
+    # The same kernels timed in isolation: a second context created with SN_SERIAL=1 runs
     # every launch on one stream (the timed steps above overlap the radial MLPs with the
-    # node-feature chain, which stretches each launch while two kernels share the GPU).
-    os.environ["SN_SERIAL"] = "1"
-    sctx = sn.Context(sn.Model(wpath), device=0, precision=args.precision)
-    del os.environ["SN_SERIAL"]
-    if domains != (1, 1, 1):
-        sctx.set_domains(*domains)
+    # node-feature chain, which stretches the launches of both while they share the GPU).
     iso = {}
-    for k in range(3):
-        sctx.forward_device(pos, Z, s.cell, energy)
-        sctx.backward_device(1.0, forces, virial)
-        sctx.synchronize()
-        if k > 0:
-            for kk, v in sctx.timings().items():
-                iso[kk] = iso.get(kk, 0.0) + v / 2
-    iso_ms = sum(iso.get(kk, 0.0) for kk in launches) / len(launches)
-    if iso_ms > 0:
-        roofline["isolated"] = {"launch_ms": iso_ms,
-                                "achieved": bytes_per_launch / (iso_ms * 1e-3) / 1e9,
-                                "frac": bytes_per_launch / (iso_ms * 1e-3) / 1e9 / 8000.0,
-                                "mfma_frac": flops_per_launch / (iso_ms * 1e-3) / 1e12 / peak_tf}
-    del sctx
+    if not args.no_isolated:
+        prev = os.environ.get("SN_SERIAL")
+        os.environ["SN_SERIAL"] = "1"
+        sctx = sn.Context(sn.Model(wpath), device=0, precision=args.precision)
+        if prev is None:
+            del os.environ["SN_SERIAL"]
+        else:
+            os.environ["SN_SERIAL"] = prev
+        if domains != (1, 1, 1):
+            sctx.set_domains(*domains)
+        for k in range(3):
+            sctx.forward_device(pos, Z, s.cell, energy)
+            sctx.backward_device(1.0, forces, virial)
+            sctx.synchronize()
+            if k > 0:
+                for kk, v in sctx.timings().items():
+                    iso[kk] = iso.get(kk, 0.0) + v / 2
+        del sctx
+    for entry, phases, nbytes, nflops in ((roofline, tp_phases, bytes_tp, None),
+                                          (roofline_mlp, mlp_phases, bytes_mlp, flops_mlp)):
+        iso_ms = sum(iso.get(kk, 0.0) for kk in phases) / len(phases)
+        if iso_ms > 0:
+            entry["isolated"] = {"launch_ms": iso_ms, "achieved": nbytes / (iso_ms * 1e-3) / 1e9,
+                                 "frac": nbytes / (iso_ms * 1e-3) / 1e9 / 8000.0}
+            if nflops:
+                entry["isolated"]["mfma_frac"] = nflops / (iso_ms * 1e-3) / 1e12 / peak_tf
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -220,6 +266,7 @@ def main():
                    "n_atoms": n, "n_ghost": g, "n_edges": e, "precision": args.precision,
                    "subdomains": list(domains)},
         "roofline": roofline,
+        "roofline_mlp_adjoint": roofline_mlp,
         "cpu_baseline": cpu,
         "phases_ms": {k: v / args.steps for k, v in phase_ms.items()},
         "serving": serving,

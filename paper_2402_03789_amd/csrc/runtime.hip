@@ -385,15 +385,20 @@ struct sn_ctx {
     }
     return event_pool[event_next++];
   }
-  // time one launch sequence on the aux stream
+  // time one launch sequence on the aux stream (with a single stream, a phase of the
+  // stream's own sequence that the next mark ends)
   void aux_begin(const std::string& name) {
     if (capturing) return;
+    if (aux == stream) {
+      mark(name);
+      return;
+    }
     hipEvent_t a = timing_event();
     HIPCHK(hipEventRecord(a, aux));
     aux_marks.push_back({name, {a, nullptr}});
   }
   void aux_end() {
-    if (capturing) return;
+    if (capturing || aux == stream) return;
     hipEvent_t b = timing_event();
     HIPCHK(hipEventRecord(b, aux));
     aux_marks.back().second.second = b;
@@ -882,6 +887,7 @@ struct Pipe {
     const T act = (T)m->act;
     const int C0 = m->muls[0];
     // h^(1): embedding rows for locals and ghosts (a ghost's first features come from its species)
+    c->mark("embed");
     double* h = c->get<double>("h_cur", (int64_t)NE * C0);
     launch_embed<double>(NE, spec_ext, W<double>(c, m->off("embed", {(int)m->species.size(), C0})),
                          C0, h, C0, s);
@@ -992,9 +998,12 @@ struct Pipe {
         gemm<double, T, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy, rows_of(L.yl, l),
                               L.w_lin2[l], L.gmul[l], true, Gm, rows_of(L.ml, l),
                               (T)(1.0 / m->kavg), false);
-      c->mark("bwd.layer" + ts + ".tp");
       S* dw = dw_buf[t % 2];
-      if (t + 2 < m->T) HIPCHK(hipStreamWaitEvent(s, mlp_done[t + 2], 0));
+      if (t + 2 < m->T) {  // dw_buf[t % 2] is free once the MLP adjoint of block t + 2 is done
+        c->mark("bwd.layer" + ts + ".mlp_wait");
+        HIPCHK(hipStreamWaitEvent(s, mlp_done[t + 2], 0));
+      }
+      c->mark("bwd.layer" + ts + ".tp");
       launch_tp_bwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dY,
                           t != m->T - 1, s);
       c->join(c->aux, s);

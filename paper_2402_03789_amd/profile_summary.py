@@ -7,7 +7,13 @@ Usage:
 
 The traffic summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by the
 readings of the same counters for the 256 MiB device copy that the benchmark
-runs first with --calib-copy (a copy reads and writes exactly 256 MiB).
+runs first with --calib-copy (a copy reads and writes exactly 256 MiB).  A kernel
+given as NAME@UNIT is reported per dispatch of UNIT: the bytes of all NAME
+dispatches divided by the number of UNIT dispatches (k_tp_bwd@k_mlp_fused_bwd: per
+interaction block, since the radial-MLP adjoint runs once per block).
+
+The stats summary also gives, for the tensor-product and radial-MLP kernels, the
+GPU time per interaction block (all their dispatches of a step / 5 blocks).
 """
 from __future__ import annotations
 
@@ -36,7 +42,11 @@ def stats(d, steps, out, cmd):
         name = r["Name"].split("(")[0].replace("void ", "")
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / 1e6 / steps:.3f} | {float(r['Percentage']):.2f} |")
-    lines += ["", f"Total GPU time per step: {total / 1e6 / steps:.3f} ms"]
+    lines += ["", f"Total GPU time per step: {total / 1e6 / steps:.3f} ms", "",
+              "Per interaction block (sum over the kernel's instantiations per step / 5 blocks):", ""]
+    for k in ("k_tp_bwd", "k_tp_fwd", "k_mlp_fused_bwd", "k_mlp_fused_fwd"):
+        t = sum(float(r["TotalDurationNs"]) for r in rows if f"::{k}<" in r["Name"])
+        lines.append(f"- `{k}`: {t / 1e3 / steps / 5:.1f} us")
     open(out, "w").write("\n".join(lines) + "\n")
 
 
@@ -50,11 +60,17 @@ def traffic(fetch_dir, write_dir, kernel, source, precision, out, cmd):
         return max(vals)  # the 256 MiB copy is the largest
     cf = calib(f_rows, "FETCH_SIZE") / (256 * 1024)
     cw = calib(w_rows, "WRITE_SIZE") / (256 * 1024)
-    fk = [float(r["Counter_Value"]) for r in f_rows if kernel in r["Kernel_Name"]]
-    wk = [float(r["Counter_Value"]) for r in w_rows if kernel in r["Kernel_Name"]]
-    fetch = sum(fk) / len(fk) / cf * 1024
-    write = sum(wk) / len(wk) / cw * 1024
-    rec = {"kernel": kernel, "precision": precision, "command": cmd,
+    kernel, _, unit = kernel.partition("@")
+    fk = [float(r["Counter_Value"]) for r in f_rows if f"::{kernel}<" in r["Kernel_Name"]]
+    wk = [float(r["Counter_Value"]) for r in w_rows if f"::{kernel}<" in r["Kernel_Name"]]
+    nf = nw = len(fk)
+    if unit:
+        nf = sum(1 for r in f_rows if f"::{unit}<" in r["Kernel_Name"])
+        nw = sum(1 for r in w_rows if f"::{unit}<" in r["Kernel_Name"])
+    fetch = sum(fk) / nf / cf * 1024
+    write = sum(wk) / nw / cw * 1024
+    rec = {"kernel": kernel, "per": f"dispatch of {unit}" if unit else "dispatch",
+           "precision": precision, "command": cmd,
            "calibration": {"fetch_KiB_per_copy_KiB": cf, "write_KiB_per_copy_KiB": cw},
            "dispatches": len(fk), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "bytes_per_launch": fetch + write,
