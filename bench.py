@@ -81,9 +81,12 @@ def main():
                     help="Si count of the SiO2 sample box timed with the CPU oracle")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (HBM counter calibration)")
-    ap.add_argument("--workload", default="sio2_24k", choices=["sio2_24k", "md", "serving", "fd"],
-                    help="sio2_24k: the headline line (plus a short serving replay); md: the "
-                         "112k-atom Si3N4 Verlet run; serving: the full 2,000-request stream")
+    ap.add_argument("--workload", default="sio2_24k",
+                    choices=["sio2_24k", "md", "serving", "fd", "size_sweep"],
+                    help="sio2_24k: the headline line (plus a short serving replay); md: molecular "
+                         "dynamics (default the 112k-atom Si3N4 Verlet run); serving: the full "
+                         "2,000-request stream; fd: the differentiation and precision report; "
+                         "size_sweep: throughput against atom count")
     ap.add_argument("--serve-requests", type=int, default=None,
                     help="requests of the serving stream to replay: default 400 beside the "
                          "headline line (0 to skip), 2,000 for --workload serving")
@@ -91,13 +94,28 @@ def main():
     ap.add_argument("--domains", default="1,1,1",
                     help="nx,ny,nz spatial subdomains of the 24k-atom box, each with its own "
                          "ghost shell (halo refresh and fold in device memory)")
-    ap.add_argument("--md-system", default="si3n4_112k", choices=["si3n4_112k", "sio2_192"],
+    ap.add_argument("--md-system", default="si3n4_112k", choices=["si3n4_112k", "sio2_24k", "sio2_192"],
                     help="MD box: the 112k-atom Si3N4 workload, or a 192-atom SiO2 box where "
                          "launch overhead matters")
     ap.add_argument("--capture", action="store_true",
                     help="MD: replay the steps between rebuilds from a recorded HIP graph")
     ap.add_argument("--md-steps", type=int, default=100)
     ap.add_argument("--md-warmup", type=int, default=10)
+    ap.add_argument("--thermostat", choices=["none", "nh"], default="none",
+                    help="MD: none (velocity Verlet) or one Nose-Hoover thermostat (NVT)")
+    ap.add_argument("--md-temperature", type=float, default=None,
+                    help="MD start (and thermostat) temperature, K; default 1500, or 300 for the "
+                         "24k-atom SiO2 box")
+    ap.add_argument("--md-tau", type=float, default=100.0, help="Nose-Hoover time constant, fs")
+    ap.add_argument("--md-skin", type=float, default=1.0,
+                    help="neighbour-list skin, A (0 with --md-rebuild 1: a fresh list every step)")
+    ap.add_argument("--md-rebuild", default=None,
+                    help="MD: steps between neighbour-list rebuilds (default 10), or 'skin' to "
+                         "rebuild when an atom has moved more than half the skin (the default "
+                         "with --paper-protocol)")
+    ap.add_argument("--paper-protocol", action="store_true",
+                    help="MD as in the paper's benchmarks (section 4): NVT Nose-Hoover, 210 steps "
+                         "of which the last 100 are timed; the list is rebuilt on the skin trigger")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build evaluates one subdomain on one GPU; "
@@ -109,6 +127,9 @@ def main():
         return
     if args.workload == "fd":
         print(json.dumps(bench_fd(args)))
+        return
+    if args.workload == "size_sweep":
+        print(json.dumps(bench_size_sweep(args)))
         return
     if args.workload == "serving":
         count = 2000 if args.serve_requests is None else args.serve_requests
@@ -385,46 +406,115 @@ def bench_fd(args):
     return out
 
 
-def bench_md(args):
-    """112,000-atom amorphous-density Si3N4: velocity Verlet at dt = 1 fs from a 1500 K
-    Maxwell-Boltzmann start, neighbour list (skin 1 A) rebuilt every 10 steps."""
+def bench_size_sweep(args):
+    """One-GPU throughput against system size (the paper's single-GPU utilisation curve,
+    section 4.2): E+F+virial evaluations, graph build included, of SiO2 boxes at
+    2.2 g/cm^3 from 192 to 48,000 atoms with the 5-block l <= 2 model."""
     import torch
 
     import paper_2402_03789_amd as sn
-    from paper_2402_03789_amd.md import VelocityVerlet
-    from synth import config_structure
+    from synth import model_spec_real, make_weights, write_weights, sio2_box
 
-    from synth import sio2_box
+    spec = model_spec_real()
+    wpath = os.path.join(tempfile.mkdtemp(), "model.snw")
+    write_weights(wpath, spec, make_weights(spec, 102))
+    model = sn.Model(wpath)
+    dev = torch.device("cuda:0")
+    points = []
+    for n_si in (64, 256, 1024, 4000, 8000, 16000):
+        s = sio2_box(n_si, seed=2)
+        ctx = sn.Context(model, device=0, precision=args.precision)
+        pos = torch.tensor(s.pos, dtype=torch.float64, device=dev)
+        Z = torch.tensor(s.Z, dtype=torch.int32, device=dev)
+        energy = torch.zeros(1, dtype=torch.float64, device=dev)
+        forces = torch.zeros((s.n, 3), dtype=torch.float64, device=dev)
+        virial = torch.zeros(9, dtype=torch.float64, device=dev)
+        steps = max(5, min(200, int(4e5 / s.n)))
+        for k in range(3 + steps):
+            if k == 3:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            ctx.forward_device(pos, Z, s.cell, energy)
+            ctx.backward_device(1.0, forces, virial)
+        ctx.synchronize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        points.append({"n_atoms": s.n, "steps": steps, "ms_per_step": dt / steps * 1e3,
+                       "atom_steps_per_s": s.n * steps / dt})
+        print(f"size sweep: {s.n} atoms {dt / steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+        del ctx
+    return {"metric": "atom-steps/s (E+F) against atom count, 5-layer l<=2 model, SiO2",
+            "unit": "atom-steps/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
+            "config": {"workload": "SiO2 boxes at 2.2 g/cm^3, 192 to 48,000 atoms; one "
+                                   "evaluation = graph build + E + F + virial",
+                       "precision": args.precision},
+            "points": points}
+
+
+def bench_md(args):
+    """Molecular dynamics on device-resident arrays.  Default: 112,000-atom amorphous-density
+    Si3N4, velocity Verlet at dt = 1 fs from a 1500 K Maxwell-Boltzmann start, neighbour list
+    (skin 1 A) rebuilt every 10 steps.  Options: the 24k-atom SiO2 box or a 192-atom SiO2
+    box, a Nose-Hoover thermostat, the skin-triggered rebuild, and the paper's benchmark
+    protocol (NVT, 210 steps, the last 100 timed)."""
+    import torch
+
+    import paper_2402_03789_amd as sn
+    from paper_2402_03789_amd.md import NoseHoover, VelocityVerlet
+    from synth import config_structure, sio2_box
+
+    if args.paper_protocol:
+        args.thermostat, args.md_warmup, args.md_steps = "nh", 110, 100
+    if args.md_rebuild is None:
+        args.md_rebuild = "skin" if args.paper_protocol else "10"
     t0 = time.perf_counter()
-    small = args.md_system == "sio2_192"
-    s = sio2_box(64, seed=1) if small else config_structure("si3n4_112k")
+    system = args.md_system
+    if system == "sio2_192":
+        s = sio2_box(64, seed=1)
+    else:
+        s = config_structure(system)
     gen_s = time.perf_counter() - t0
-    species = (8, 14) if small else (7, 14)
-    ctx = sn.Context(sn.Model(_model_file(species, 102)), precision=args.precision, skin=1.0)
-    md = VelocityVerlet(ctx, s.pos, s.Z, s.cell, s.masses(), dt=1.0, rebuild_every=10,
-                        temperature=1500.0, seed=5, capture=args.capture)
+    species = (7, 14) if system == "si3n4_112k" else (8, 14)
+    temp = args.md_temperature or (300.0 if system == "sio2_24k" else 1500.0)
+    every = None if args.md_rebuild == "skin" else int(args.md_rebuild)
+    thermo = NoseHoover(temp, args.md_tau) if args.thermostat == "nh" else None
+    ctx = sn.Context(sn.Model(_model_file(species, 102)), precision=args.precision,
+                     skin=args.md_skin)
+    md = VelocityVerlet(ctx, s.pos, s.Z, s.cell, s.masses(), dt=1.0, rebuild_every=every,
+                        temperature=temp, seed=5, capture=args.capture, thermostat=thermo)
     md.run(args.md_warmup)
-    e0 = md.kinetic_energy() + md.potential_energy()
+    e0 = md.conserved_energy()
+    r0 = md.rebuilds
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     md.run(args.md_steps)
     ctx.synchronize()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
-    e1 = md.kinetic_energy() + md.potential_energy()
+    e1 = md.conserved_energy()
     n, g, e = ctx.graph_size()
-    workload = ("SiO2 192 atoms, 2.2 g/cm^3, periodic cubic 14.26 A" if small else
-                "Si3N4 112,000 atoms (48,000 Si + 64,000 N), 3.1 g/cm^3, periodic cubic 106.33 A")
-    return {"metric": f"atom-steps/s (E+F), 5-layer l<=2 model, {s.n}-atom velocity-Verlet MD",
+    workload = {"sio2_192": "SiO2 192 atoms, 2.2 g/cm^3, periodic cubic 14.26 A",
+                "sio2_24k": "SiO2 24,000 atoms (8,000 Si + 16,000 O), 2.2 g/cm^3, periodic "
+                            "cubic 71.32 A",
+                "si3n4_112k": "Si3N4 112,000 atoms (48,000 Si + 64,000 N), 3.1 g/cm^3, periodic "
+                              "cubic 106.33 A"}[system]
+    ens = (f"NVT Nose-Hoover {temp:g} K, tau {args.md_tau:g} fs" if thermo else
+           f"NVE from a {temp:g} K start")
+    reb = ("rebuild when an atom moved > skin/2" if every is None else
+           f"rebuild every {every} steps")
+    return {"metric": f"atom-steps/s (E+F), 5-layer l<=2 model, {s.n}-atom MD",
             "value": s.n * args.md_steps / dt, "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.md_steps, "warmup": args.md_warmup,
             "ms_per_step": dt / args.md_steps * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
             "data": "synthetic",
-            "config": {"workload": workload + "; dt 1 fs, 1500 K start, skin 1 A, rebuild every "
-                                   "10 steps", "n_atoms": n, "n_ghost": g, "n_edges": e,
-                       "precision": args.precision, "graph_replay": bool(args.capture)},
-            "energy_drift_eV_per_atom": (e1 - e0) / s.n, "generation_s": gen_s}
+            "config": {"workload": f"{workload}; dt 1 fs, {ens}, skin {args.md_skin:g} A, {reb}",
+                       "n_atoms": n, "n_ghost": g, "n_edges": e, "precision": args.precision,
+                       "graph_replay": bool(args.capture), "thermostat": args.thermostat,
+                       "rebuild": args.md_rebuild},
+            "rebuilds_timed": md.rebuilds - r0, "temperature_K": md.temperature(),
+            "conserved_energy_drift_eV_per_atom": (e1 - e0) / s.n, "generation_s": gen_s}
 
 
 if __name__ == "__main__":

@@ -182,6 +182,30 @@ int sn_ctx_set_capture(sn_ctx_t* ctx, int on);
 int sn_md_verlet(sn_ctx_t* ctx, int64_t n, double* d_pos, double* d_vel, const double* d_forces,
                  const double* d_inv_mass, double dt, int stage);
 
+/* Nose-Hoover thermostat for the NVT runs of the paper's MD benchmarks (section 4: NVT
+ * ensemble with the Nose-Hoover thermostat).  One thermostat on all particles:
+ *   dv/dt = a - xi v,  dxi/dt = (2K - dof kT) / Q,  deta/dt = xi,
+ * K = sum m v^2 / 2.  This call applies the half-step operator of the symmetric Trotter
+ * splitting  NH(dt/2) . Verlet(dt) . NH(dt/2):
+ *   xi += dt/4 G(K);  eta += dt/2 xi;  v *= exp(-xi dt/2);  xi += dt/4 G(K'),
+ * G(K) = (2K - dof kT)/Q, K' = K exp(-xi dt) the kinetic energy after scaling.  Stream-ordered,
+ * no host synchronisation.  d_vel: n x 3 float64 (angstrom/fs); d_inv_mass[n] as for
+ * sn_md_verlet (its reciprocal is the mass in eV fs^2 / angstrom^2, so K is in eV);
+ * kT in eV, dof the number of thermostatted degrees of freedom, Q > 0 in eV fs^2;
+ * d_state: 4 float64 in device memory owned by the caller, {xi (1/fs), eta, last scale
+ * factor, K after the call (eV)}, zero-initialised before the first call.  The conserved
+ * quantity is K + U + Q xi^2 / 2 + dof kT eta.  SN_EINVAL for n < 1, dt, kT or dof not
+ * positive, Q not positive or null pointers. */
+int sn_md_nh_half(sn_ctx_t* ctx, int64_t n, double* d_vel, const double* d_inv_mass, double dt,
+                  double kT, double dof, double Q, double* d_state);
+
+/* Largest displacement since the last neighbour-list build, for a skin-triggered rebuild:
+ * *max_disp (host, angstrom) = max_i |d_pos_i - d_ref_i| over the n x 3 float64 device arrays
+ * (unwrapped positions and the positions at the last build).  Synchronises the context's
+ * stream.  SN_EINVAL for n < 1 or null pointers. */
+int sn_md_max_displacement(sn_ctx_t* ctx, int64_t n, const double* d_pos, const double* d_ref,
+                           double* max_disp);
+
 /* Wait for every queued operation of the context. */
 int sn_ctx_synchronize(sn_ctx_t* ctx);
 

@@ -19,7 +19,9 @@ What it computes (paper sections 2-3):
   * the ghost-shell evaluation of one subdomain whose ghost features are
     refreshed from their owners before every layer after the first, with
     gradients and partial forces folded back (section 3.1), and a
-    multi-subdomain emulation of the same scheme.
+    multi-subdomain emulation of the same scheme;
+  * (oracle/md.py) velocity Verlet and the Nose-Hoover NVT integrator of the
+    paper's MD benchmarks (section 4), driven by any force function.
 
 Every floating-point quantity is float64.  Derivatives are taken with
 torch.autograd on CPU.  Pins (closed forms, invariances, finite differences,

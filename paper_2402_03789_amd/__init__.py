@@ -51,6 +51,14 @@ class Model:
             pass
 
 
+def _device_f64(t, shape):
+    """The MD entry points take raw device pointers: refuse anything but a contiguous
+    float64 tensor of the expected shape on a GPU."""
+    if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda
+            or not t.is_contiguous() or tuple(t.shape) != tuple(shape)):
+        raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {tuple(shape)}")
+
+
 class Context:
     """One model on one device, stream and precision form."""
 
@@ -58,6 +66,7 @@ class Context:
                  stream=None, hbm_budget: int = 0):
         self.model = model
         self.device = device
+        self.skin = float(skin)  # neighbour-list skin (angstrom) of graph reuse
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
@@ -158,8 +167,29 @@ class Context:
         check(lib().sn_ctx_set_graph_reuse(self._h, 1 if reuse else 0))
 
     def verlet(self, pos, vel, forces, inv_mass, dt: float, stage: int):
-        check(lib().sn_md_verlet(self._h, pos.shape[0], ptr(pos), ptr(vel), ptr(forces),
+        n = pos.shape[0]
+        for t, shape in ((pos, (n, 3)), (vel, (n, 3)), (forces, (n, 3)), (inv_mass, (n,))):
+            _device_f64(t, shape)
+        check(lib().sn_md_verlet(self._h, n, ptr(pos), ptr(vel), ptr(forces),
                                  ptr(inv_mass), float(dt), int(stage)), self._h)
+
+    def nh_half(self, vel, inv_mass, dt: float, kT: float, dof: float, Q: float, state):
+        """Thermostat half NH(dt/2) of a Nose-Hoover step of length dt on device velocities;
+        state: 4 float64 on the device ({xi, eta, scale, K}, zeros before the first call)."""
+        n = vel.shape[0]
+        for t, shape in ((vel, (n, 3)), (inv_mass, (n,)), (state, (4,))):
+            _device_f64(t, shape)
+        check(lib().sn_md_nh_half(self._h, n, ptr(vel), ptr(inv_mass), float(dt), float(kT),
+                                  float(dof), float(Q), ptr(state)), self._h)
+
+    def max_displacement(self, pos, ref) -> float:
+        """max_i |pos_i - ref_i| (angstrom) of two n x 3 float64 device arrays."""
+        n = pos.shape[0]
+        for t in (pos, ref):
+            _device_f64(t, (n, 3))
+        v = C.c_double()
+        check(lib().sn_md_max_displacement(self._h, n, ptr(pos), ptr(ref), C.byref(v)), self._h)
+        return v.value
 
     def memory(self) -> int:
         v = C.c_size_t()

@@ -78,6 +78,10 @@ _SIGS = {
     "sn_ctx_set_capture": (C.c_int, [C.c_void_p, C.c_int]),
     "sn_md_verlet": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_double, C.c_int]),
+    "sn_md_nh_half": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_double,
+                                C.c_double, C.c_double, C.c_double, C.c_void_p]),
+    "sn_md_max_displacement": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.POINTER(C.c_double)]),
     "sn_ctx_graph": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
     "sn_ctx_memory": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),

@@ -304,7 +304,99 @@ __global__ void k_verlet(int n, double* __restrict__ pos, double* __restrict__ v
   }
 }
 
+// Nose-Hoover thermostat (one thermostat on all particles), half-step operator of the
+// symmetric Trotter splitting of the equations of motion
+//   dv/dt = F/m - xi v,  dxi/dt = (2K - g kT) / Q,  deta/dt = xi:
+//   xi += dt/4 G(K);  eta += dt/2 xi;  v *= exp(-xi dt/2);  xi += dt/4 G(K exp(-xi dt)),
+// G(K) = (2K - g kT) / Q.  K = sum v^2 / (2 inv_mass) is formed from fixed-order block sums.
+// The state {xi, eta, scale, K} stays in device memory.
+constexpr int kKinBlock = 256;
+__global__ void k_kinetic_partial(int n, const double* __restrict__ vel,
+                                  const double* __restrict__ inv_mass, double* __restrict__ part) {
+  __shared__ double sh[kKinBlock];
+  const int i = blockIdx.x * kKinBlock + threadIdx.x;
+  double k = 0.0;
+  if (i < n)
+    k = 0.5 * (vel[3 * i] * vel[3 * i] + vel[3 * i + 1] * vel[3 * i + 1] +
+               vel[3 * i + 2] * vel[3 * i + 2]) / inv_mass[i];
+  sh[threadIdx.x] = k;
+  __syncthreads();
+  for (int o = kKinBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_nh_scalars(int nb, const double* __restrict__ part, double dt, double gkT,
+                             double Q, double* __restrict__ st) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double K = 0.0;
+  for (int b = 0; b < nb; ++b) K += part[b];
+  double xi = st[0];
+  xi += 0.25 * dt * (2.0 * K - gkT) / Q;
+  st[1] += 0.5 * dt * xi;
+  const double sc = exp(-0.5 * dt * xi);
+  K *= sc * sc;
+  xi += 0.25 * dt * (2.0 * K - gkT) / Q;
+  st[0] = xi;
+  st[2] = sc;
+  st[3] = K;
+}
+__global__ void k_scale_vel(int n, double* __restrict__ vel, const double* __restrict__ st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  vel[i] *= st[2];
+}
+
+// max over atoms of |pos - ref|^2: block maxima, then one block over those
+__global__ void k_disp_partial(int n, const double* __restrict__ pos, const double* __restrict__ ref,
+                               double* __restrict__ part) {
+  __shared__ double sh[kKinBlock];
+  const int i = blockIdx.x * kKinBlock + threadIdx.x;
+  double d = 0.0;
+  if (i < n) {
+    const double dx = pos[3 * i] - ref[3 * i], dy = pos[3 * i + 1] - ref[3 * i + 1],
+                 dz = pos[3 * i + 2] - ref[3 * i + 2];
+    d = dx * dx + dy * dy + dz * dz;
+  }
+  sh[threadIdx.x] = d;
+  __syncthreads();
+  for (int o = kKinBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_max_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[kKinBlock];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kKinBlock) m = fmax(m, part[b]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kKinBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 // ------------------------------------------------------------------ launchers
+int md_partials(int n) { return (int)nblk(n, kKinBlock); }
+void launch_nh_half(int n, double* vel, const double* inv_mass, double dt, double gkT, double Q,
+                    double* state, double* part, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = md_partials(n);
+  k_kinetic_partial<<<nb, kKinBlock, 0, s>>>(n, vel, inv_mass, part);
+  k_nh_scalars<<<1, 64, 0, s>>>(nb, part, dt, gkT, Q, state);
+  k_scale_vel<<<nblk(3 * (int64_t)n, 256), 256, 0, s>>>(n, vel, state);
+}
+void launch_max_disp2(int n, const double* pos, const double* ref, double* part, double* out,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = md_partials(n);
+  k_disp_partial<<<nb, kKinBlock, 0, s>>>(n, pos, ref, part);
+  k_max_final<<<1, kKinBlock, 0, s>>>(nb, part, out);
+}
 void launch_refresh_positions(int n, int n_ghost, const int* order, const double* pos,
                               const double* wrap_off, const int* owner, const int* shift,
                               const int* sid_ext, const StructParams* sp, double* pos_ext,

@@ -202,6 +202,15 @@ void launch_wrap_offsets(int n, const int* order, const double* pos, const doubl
 // Velocity-Verlet half step (stage 0: kick + drift, stage 1: kick); a = F * inv_mass.
 void launch_verlet(int n, double* pos, double* vel, const double* F, const double* inv_mass,
                    double dt, int stage, hipStream_t s);
+// Block-partial scratch (doubles) needed by the two kernels below for n atoms.
+int md_partials(int n);
+// Nose-Hoover half-step operator on vel (n x 3); state = {xi, eta, scale, K} in device memory;
+// gkT = degrees of freedom x kT (eV), Q the thermostat mass (eV fs^2).
+void launch_nh_half(int n, double* vel, const double* inv_mass, double dt, double gkT, double Q,
+                    double* state, double* part, hipStream_t s);
+// out[0] = max_i |pos_i - ref_i|^2 (device).
+void launch_max_disp2(int n, const double* pos, const double* ref, double* part, double* out,
+                      hipStream_t s);
 
 
 

@@ -1559,6 +1559,31 @@ int sn_md_verlet(sn_ctx_t* ctx, int64_t n, double* d_pos, double* d_vel, const d
   });
 }
 
+int sn_md_nh_half(sn_ctx_t* ctx, int64_t n, double* d_vel, const double* d_inv_mass, double dt,
+                  double kT, double dof, double Q, double* d_state) {
+  if (!ctx || !d_vel || !d_inv_mass || !d_state || n <= 0 || n > INT32_MAX / 3 || !(dt > 0) ||
+      !(kT > 0) || !(dof > 0) || !(Q > 0) || !std::isfinite(dt) || !std::isfinite(Q))
+    return SN_EINVAL;
+  return guarded(ctx, [&] {
+    double* part = ctx->get<double>("md_partials", md_partials((int)n));
+    launch_nh_half((int)n, d_vel, d_inv_mass, dt, dof * kT, Q, d_state, part, ctx->stream);
+  });
+}
+
+int sn_md_max_displacement(sn_ctx_t* ctx, int64_t n, const double* d_pos, const double* d_ref,
+                           double* max_disp) {
+  if (!ctx || !d_pos || !d_ref || !max_disp || n <= 0 || n > INT32_MAX / 3) return SN_EINVAL;
+  return guarded(ctx, [&] {
+    double* part = ctx->get<double>("md_partials", md_partials((int)n));
+    double* out = ctx->get<double>("md_max", 1);
+    launch_max_disp2((int)n, d_pos, d_ref, part, out, ctx->stream);
+    double h = 0;
+    HIPCHK(hipMemcpyAsync(&h, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *max_disp = std::sqrt(h);
+  });
+}
+
 int sn_ctx_memory(const sn_ctx_t* ctx, size_t* bytes) {
   if (!ctx || !bytes) return SN_EINVAL;
   *bytes = ctx->used + ctx->weight_bytes;
