@@ -9,7 +9,7 @@ different method.
 What it computes (paper sections 2-3):
   * E = sum_i E_i (eq 1), F_i = -grad_i E (eq 2);
   * NequIP message passing (eqs 3-4) with real spherical harmonics up to
-    l = 2, 8 Bessel radial functions under a p = 6 polynomial envelope, a
+    l = 2 (l = 3 for the benchmark models of section 4), 8 Bessel radial functions under a p = 6 polynomial envelope, a
     radial MLP, channel-wise Clebsch-Gordan tensor-product convolutions
     normalised by the average neighbour count, linear self-connections in
     place of the species-dependent tensor product, gated nonlinearities, and

@@ -15,5 +15,5 @@ from .structures import (  # noqa: F401
 )
 from .weights import (  # noqa: F401
     ModelSpec, make_weights, write_weights, read_weights_header,
-    model_spec_small, model_spec_real, ACT_SCALE,
+    model_spec_small, model_spec_real, model_spec_bench, ACT_SCALE,
 )

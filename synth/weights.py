@@ -151,6 +151,8 @@ SIGMA_REAL = 20.41
 
 # SiO2 at 2.2 g/cm^3 has 0.06615 atoms per cubic angstrom.
 _SIO2_NUMBER_DENSITY = 192 / 14.264434 ** 3
+# alpha-quartz, 2.65 g/cm^3
+_QUARTZ_NUMBER_DENSITY = _SIO2_NUMBER_DENSITY * 2.65 / 2.2
 
 
 def model_spec_small(species=(8, 14)) -> ModelSpec:
@@ -166,3 +168,13 @@ def model_spec_real(species=(8, 14)) -> ModelSpec:
     return ModelSpec(n_layers=5, muls=(128, 64, 32), l_sh=2, r_cut=5.0, species=tuple(species),
                      k_avg=_number_density_kavg(192, 192 / _SIO2_NUMBER_DENSITY, 5.0),
                      sigma=SIGMA_REAL)
+
+
+def model_spec_bench(channels: int, layers: int, species=(8, 14), sigma: float = 1.0) -> ModelSpec:
+    """One of the paper's benchmark models (section 4): `layers` interaction blocks,
+    `channels` channels at every degree l = 0..3 (l_max 3), 8 Bessel functions, r_c 4 A;
+    messages normalised by the neighbour count of SiO2 at the alpha-quartz density."""
+    return ModelSpec(n_layers=layers, muls=(channels,) * 4, l_sh=3, r_cut=4.0,
+                     species=tuple(species),
+                     k_avg=_number_density_kavg(192, 192 / _QUARTZ_NUMBER_DENSITY, 4.0),
+                     sigma=sigma)

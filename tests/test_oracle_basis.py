@@ -20,24 +20,24 @@ def _unit(n, seed):
 
 
 def test_sh_at_z_axis():
-    Y = real_sph_harm(torch.tensor([[0.0, 0.0, 1.0]], dtype=torch.float64), 2)
+    Y = real_sph_harm(torch.tensor([[0.0, 0.0, 1.0]], dtype=torch.float64), 3)
     got = torch.cat(Y, dim=1)[0].numpy()
-    want = [1, 0, math.sqrt(3), 0, 0, 0, math.sqrt(5), 0, 0]
+    want = [1, 0, math.sqrt(3), 0, 0, 0, math.sqrt(5), 0, 0, 0, 0, 0, math.sqrt(7), 0, 0, 0]
     np.testing.assert_allclose(got, want, atol=1e-15)
 
 
 def test_sh_component_normalisation():
-    Y = real_sph_harm(torch.tensor(_unit(200, 1)), 2)
-    for l in range(3):
+    Y = real_sph_harm(torch.tensor(_unit(200, 1)), 3)
+    for l in range(4):
         np.testing.assert_allclose((Y[l] ** 2).sum(1).numpy(), 2 * l + 1, rtol=1e-13)
 
 
 def test_sh_addition_theorem_legendre():
     a, b = _unit(100, 2), _unit(100, 3)
-    Ya = real_sph_harm(torch.tensor(a), 2)
-    Yb = real_sph_harm(torch.tensor(b), 2)
+    Ya = real_sph_harm(torch.tensor(a), 3)
+    Yb = real_sph_harm(torch.tensor(b), 3)
     cos = (a * b).sum(1)
-    for l in range(3):
+    for l in range(4):
         lhs = (Ya[l] * Yb[l]).sum(1).numpy()
         np.testing.assert_allclose(lhs, (2 * l + 1) * special.eval_legendre(l, cos), atol=1e-12)
 
@@ -50,9 +50,9 @@ def test_sh_orthogonal_on_sphere():
     st = np.sqrt(1 - ct ** 2)
     pts = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
     wts = (ws[:, None] * np.ones_like(phis)[None] * (2 * np.pi / 16)).reshape(-1) / (4 * np.pi)
-    Y = torch.cat(real_sph_harm(torch.tensor(pts), 2), dim=1).numpy()
+    Y = torch.cat(real_sph_harm(torch.tensor(pts), 3), dim=1).numpy()
     gram = (Y * wts[:, None]).T @ Y
-    np.testing.assert_allclose(gram, np.eye(9), atol=1e-13)
+    np.testing.assert_allclose(gram, np.eye(16), atol=1e-13)
 
 
 def test_sh_match_scipy_real_harmonics():
@@ -61,8 +61,8 @@ def test_sh_match_scipy_real_harmonics():
     pts = _unit(30, 4)
     theta = np.arccos(pts[:, 2])
     phi = np.arctan2(pts[:, 1], pts[:, 0])
-    Y = real_sph_harm(torch.tensor(pts), 2)
-    for l in range(3):
+    Y = real_sph_harm(torch.tensor(pts), 3)
+    for l in range(4):
         for m in range(-l, l + 1):
             c = special.sph_harm_y(l, abs(m), theta, phi)
             if m > 0:
@@ -78,9 +78,9 @@ def test_sh_match_scipy_real_harmonics():
 def test_sh_rotation_orthogonal():
     pts = _unit(40, 5)
     R = Rotation.random(random_state=7).as_matrix()
-    Y = real_sph_harm(torch.tensor(pts), 2)
-    Yr = real_sph_harm(torch.tensor(pts @ R.T), 2)
-    for l in range(1, 3):
+    Y = real_sph_harm(torch.tensor(pts), 3)
+    Yr = real_sph_harm(torch.tensor(pts @ R.T), 3)
+    for l in range(1, 4):
         D = np.linalg.lstsq(Y[l].numpy(), Yr[l].numpy(), rcond=None)[0].T
         np.testing.assert_allclose(D @ D.T, np.eye(2 * l + 1), atol=1e-12)
         np.testing.assert_allclose(Y[l].numpy() @ D.T, Yr[l].numpy(), atol=1e-12)

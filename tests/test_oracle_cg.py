@@ -9,16 +9,19 @@ from scipy.spatial.transform import Rotation
 from oracle.cg import real_cg, complex_cg
 from oracle.basis import real_sph_harm
 
-PATHS = [(l1, l2, l3) for l1 in range(3) for l2 in range(3)
-         for l3 in range(abs(l1 - l2), min(l1 + l2, 2) + 1)]
+PATHS2 = [(l1, l2, l3) for l1 in range(3) for l2 in range(3)
+          for l3 in range(abs(l1 - l2), min(l1 + l2, 2) + 1)]
+# the l_max = 3 benchmark models of the paper (section 4) use l <= 3
+PATHS = [(l1, l2, l3) for l1 in range(4) for l2 in range(4)
+         for l3 in range(abs(l1 - l2), min(l1 + l2, 3) + 1)]
 
 
 def test_racah_matches_sympy():
     sympy = pytest.importorskip("sympy")
     from sympy.physics.quantum.cg import CG
-    for j1 in range(3):
-        for j2 in range(3):
-            for J in range(abs(j1 - j2), j1 + j2 + 1):
+    for j1 in range(4):
+        for j2 in range(4):
+            for J in range(abs(j1 - j2), min(j1 + j2, 3) + 1):
                 for m1 in range(-j1, j1 + 1):
                     for m2 in range(-j2, j2 + 1):
                         M = m1 + m2
@@ -36,9 +39,10 @@ def test_textbook_values():
 
 
 def test_nonzero_counts():
-    counts = [int((np.abs(real_cg(*p)) > 1e-12).sum()) for p in PATHS]
+    counts = [int((np.abs(real_cg(*p)) > 1e-12).sum()) for p in PATHS2]
     assert counts == [1, 3, 5, 3, 3, 6, 11, 11, 16, 5, 11, 16, 5, 16, 25]
     assert sum(counts) == 137
+    assert len(PATHS) == 34
 
 
 @pytest.mark.parametrize("p", PATHS)
@@ -47,7 +51,7 @@ def test_orthonormal_columns(p):
     np.testing.assert_allclose(np.einsum("abc,abd->cd", C, C), np.eye(2 * p[2] + 1), atol=1e-13)
 
 
-@pytest.mark.parametrize("l1,l2", [(1, 1), (1, 2), (2, 2), (2, 1)])
+@pytest.mark.parametrize("l1,l2", [(1, 1), (1, 2), (2, 2), (2, 1), (3, 1), (3, 3)])
 def test_completeness(l1, l2):
     tot = np.zeros((2 * l1 + 1, 2 * l2 + 1, 2 * l1 + 1, 2 * l2 + 1))
     for l3 in range(abs(l1 - l2), l1 + l2 + 1):
@@ -58,7 +62,7 @@ def test_completeness(l1, l2):
 
 
 def test_closed_forms():
-    for l in range(3):
+    for l in range(4):
         np.testing.assert_allclose(real_cg(0, l, l)[0], np.eye(2 * l + 1), atol=1e-15)
         np.testing.assert_allclose(real_cg(l, 0, l)[:, 0, :], np.eye(2 * l + 1), atol=1e-15)
         np.testing.assert_allclose(real_cg(l, l, 0)[:, :, 0], np.eye(2 * l + 1) / math.sqrt(2 * l + 1),
@@ -74,8 +78,8 @@ def test_closed_forms():
 
 
 def _wigner(l, R, pts):
-    Y = real_sph_harm(torch.tensor(pts), 2)[l].numpy()
-    Yr = real_sph_harm(torch.tensor(pts @ R.T), 2)[l].numpy()
+    Y = real_sph_harm(torch.tensor(pts), 3)[l].numpy()
+    Yr = real_sph_harm(torch.tensor(pts @ R.T), 3)[l].numpy()
     return np.linalg.lstsq(Y, Yr, rcond=None)[0].T
 
 
@@ -87,7 +91,7 @@ def test_equivariance(p):
     C = real_cg(*p)
     for seed in range(3):
         R = Rotation.random(random_state=seed).as_matrix()
-        D = [_wigner(l, R, pts) for l in range(3)]
+        D = [_wigner(l, R, pts) for l in range(4)]
         u, v = rng.normal(size=2 * p[0] + 1), rng.normal(size=2 * p[1] + 1)
         lhs = np.einsum("abc,a,b->c", C, D[p[0]] @ u, D[p[1]] @ v)
         rhs = D[p[2]] @ np.einsum("abc,a,b->c", C, u, v)
