@@ -82,11 +82,16 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (HBM counter calibration)")
     ap.add_argument("--workload", default="sio2_24k",
-                    choices=["sio2_24k", "md", "serving", "fd", "size_sweep"],
+                    choices=["sio2_24k", "md", "serving", "fd", "size_sweep", "paper_models"],
                     help="sio2_24k: the headline line (plus a short serving replay); md: molecular "
                          "dynamics (default the 112k-atom Si3N4 Verlet run); serving: the full "
                          "2,000-request stream; fd: the differentiation and precision report; "
-                         "size_sweep: throughput against atom count")
+                         "size_sweep: throughput against atom count; paper_models: the 20 "
+                         "benchmark models (l_max 3) in NVT MD of alpha-quartz-density SiO2")
+    ap.add_argument("--models", default=None,
+                    help="paper_models: comma-separated CxT list (default all 20, e.g. 32x4)")
+    ap.add_argument("--sizes", default="4608,12960",
+                    help="paper_models: atom counts (multiples of 3)")
     ap.add_argument("--serve-requests", type=int, default=None,
                     help="requests of the serving stream to replay: default 400 beside the "
                          "headline line (0 to skip), 2,000 for --workload serving")
@@ -130,6 +135,9 @@ def main():
         return
     if args.workload == "size_sweep":
         print(json.dumps(bench_size_sweep(args)))
+        return
+    if args.workload == "paper_models":
+        print(json.dumps(bench_paper_models(args)))
         return
     if args.workload == "serving":
         count = 2000 if args.serve_requests is None else args.serve_requests
@@ -450,6 +458,74 @@ def bench_size_sweep(args):
                                    "evaluation = graph build + E + F + virial",
                        "precision": args.precision},
             "points": points}
+
+
+def bench_paper_models(args):
+    """The paper's benchmark models (section 4): channels C in {4, 8, 16, 32, 64} at every degree
+    l <= 3, T in {2, 3, 4, 5} interaction blocks, r_c 4 A, in NVT MD (Nose-Hoover, 300 K, dt 1 fs,
+    210 steps of which the last 100 are timed) of SiO2 at the alpha-quartz density 2.65 g/cm^3,
+    at the paper's one-GPU sizes of 4,608 atoms (the weak-scaling share) and 12,960 atoms (the
+    strong-scaling system).  The graph is built afresh every step.  Random-packed boxes stand in
+    for the crystal; each model's energy scale gives RMS forces of 1 eV/A on its start box."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import paper_2402_03789_amd as sn
+    from paper_2402_03789_amd.md import NoseHoover, VelocityVerlet
+    from synth import make_weights, model_spec_bench, sio2_box, write_weights
+
+    if args.models:
+        family = [tuple(int(v) for v in m.split("x")) for m in args.models.split(",")]
+    else:
+        family = [(c, t) for c in (4, 8, 16, 32, 64) for t in (2, 3, 4, 5)]
+    sizes = [int(v) for v in args.sizes.split(",")]
+    if any(n % 3 for n in sizes):
+        raise SystemExit("--sizes: SiO2 atom counts are multiples of 3")
+    boxes = {n: sio2_box(n // 3, density=2.65, seed=7) for n in sizes}
+    tmp = tempfile.mkdtemp()
+    rows = []
+    for c, t in family:
+        spec = model_spec_bench(c, t)
+        w = make_weights(spec, 300 + 10 * c + t)
+        path = os.path.join(tmp, f"bench_{c}x{t}.snw")
+        write_weights(path, spec, w)
+        s0 = boxes[sizes[0]]
+        f = sn.Context(sn.Model(path), precision=args.precision).compute(s0.pos, s0.Z, s0.cell)["forces"]
+        spec = dataclasses.replace(spec, sigma=1.0 / float(np.sqrt(np.mean(f ** 2))))
+        write_weights(path, spec, w)
+        model = sn.Model(path)
+        n_params = model.info()["n_params"]
+        for n in sizes:
+            s = boxes[n]
+            ctx = sn.Context(model, precision=args.precision, skin=0.0)
+            md = VelocityVerlet(ctx, s.pos, s.Z, s.cell, s.masses(), dt=1.0, rebuild_every=1,
+                                temperature=300.0, seed=5, thermostat=NoseHoover(300.0, 100.0))
+            md.run(110)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            md.run(100)
+            ctx.synchronize()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            _, g, e = ctx.graph_size()
+            rows.append({"channels": c, "layers": t, "n_atoms": n, "n_params": n_params,
+                         "ms_per_step": dt / 100 * 1e3, "atom_steps_per_s": n * 100 / dt,
+                         "n_ghost": g, "n_edges": e, "device_bytes": ctx.memory(),
+                         "temperature_K": md.temperature()})
+            print(f"paper models: C{c} T{t} {n} atoms {dt / 100 * 1e3:.2f} ms/step "
+                  f"{ctx.memory() / 2 ** 30:.2f} GiB", file=sys.stderr, flush=True)
+            del md, ctx
+        del model
+    return {"metric": "atom-steps/s (E+F) of NVT MD per benchmark model (l_max 3, r_c 4 A)",
+            "unit": "atom-steps/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
+            "config": {"workload": "SiO2 at 2.65 g/cm^3 (random packing, all pairs >= 1.4 A apart), "
+                                   "NVT Nose-Hoover 300 K, tau 100 fs, dt 1 fs, 110 warm-up + "
+                                   "100 timed steps, graph rebuilt every step",
+                       "sizes": sizes, "precision": args.precision},
+            "models": rows}
 
 
 def bench_md(args):

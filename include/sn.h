@@ -61,7 +61,7 @@ typedef struct sn_model_info {
   int n_layers;      /* interaction blocks T */
   int l_max;         /* highest feature degree */
   int l_sh;          /* highest edge spherical-harmonic degree */
-  int muls[3];       /* channels per degree l = 0..2 (0 when absent) */
+  int muls[4];       /* channels per degree l = 0..3 (0 when absent) */
   int n_basis;       /* radial Bessel functions */
   int hidden;        /* radial-MLP hidden width */
   int n_species;     /* rows of the embedding */
@@ -92,7 +92,7 @@ void sn_model_free(sn_model_t* model);
 int sn_model_info(const sn_model_t* model, sn_model_info_t* info);
 
 /* Real Clebsch-Gordan table used by the kernels for the coupling (l1, l2) -> l3
- * (l <= 2), written densely into out[(2l1+1)(2l2+1)(2l3+1)] in row-major
+ * (l <= 3), written densely into out[(2l1+1)(2l2+1)(2l3+1)] in row-major
  * (m1, m2, m3) order.  Needs no device.  SN_EINVAL for an invalid triple. */
 int sn_cg_table(int l1, int l2, int l3, double* out);
 

@@ -37,7 +37,7 @@ class Model:
     def info(self) -> dict:
         i = ModelInfo()
         check(lib().sn_model_info(self._h, C.byref(i)))
-        return dict(n_layers=i.n_layers, l_max=i.l_max, l_sh=i.l_sh, muls=list(i.muls),
+        return dict(n_layers=i.n_layers, l_max=i.l_max, l_sh=i.l_sh, muls=list(i.muls)[:i.l_max + 1],
                     n_basis=i.n_basis, hidden=i.hidden, n_species=i.n_species,
                     species=list(i.species_z[:i.n_species]), r_cut=i.r_cut, k_avg=i.k_avg,
                     sigma=i.sigma, n_params=i.n_params)

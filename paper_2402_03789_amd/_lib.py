@@ -27,7 +27,7 @@ class SNError(RuntimeError):
 
 class ModelInfo(C.Structure):
     _fields_ = [
-        ("n_layers", C.c_int), ("l_max", C.c_int), ("l_sh", C.c_int), ("muls", C.c_int * 3),
+        ("n_layers", C.c_int), ("l_max", C.c_int), ("l_sh", C.c_int), ("muls", C.c_int * 4),
         ("n_basis", C.c_int), ("hidden", C.c_int), ("n_species", C.c_int),
         ("species_z", C.c_int * 128), ("r_cut", C.c_double), ("k_avg", C.c_double),
         ("sigma", C.c_double), ("n_params", C.c_int64),

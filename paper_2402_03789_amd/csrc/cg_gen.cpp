@@ -1,7 +1,7 @@
 // Build-time generator of the real Clebsch-Gordan coupling tensors used by
 // the tensor-product kernels (the convolution block of the NequIP
-// interaction block, paper section 2.2; spherical harmonics up to l = 2,
-// section 5.1).
+// interaction block, paper section 2.2; spherical harmonics up to l = 2 for the
+// model of section 5.1 and up to l = 3 for the benchmark models of section 4).
 //
 // Method: the coupling C[m1][m2][m3] of degrees (l1, l2) into l3 is the
 // one-dimensional null space of the equivariance equations
@@ -12,7 +12,7 @@
 // sum_{a,b} C[a][b][c] C[a][b][c'] = delta(c, c'), and its sign is fixed so
 // that the first nonzero entry in row-major (m1, m2, m3) order is positive.
 //
-// Output: a header with, for each (l1, l2, l3) with l <= 2, a struct whose
+// Output: a header with, for each (l1, l2, l3) with l <= 3, a struct whose
 // static `each(f)` calls f(m1, m2, m3, value) for every nonzero entry, and a
 // dense table used by the library's table-export entry point.
 #include <cmath>
@@ -29,15 +29,27 @@ static void sh(int l, const double v[3], double* out) {
   } else if (l == 1) {
     const double s3 = std::sqrt(3.0);
     out[0] = s3 * y; out[1] = s3 * z; out[2] = s3 * x;
-  } else {
+  } else if (l == 2) {
     const double s15 = std::sqrt(15.0), s5 = std::sqrt(5.0);
     out[0] = s15 * x * y;
     out[1] = s15 * y * z;
     out[2] = 0.5 * s5 * (3.0 * z * z - 1.0);
     out[3] = s15 * x * z;
     out[4] = 0.5 * s15 * (x * x - y * y);
+  } else {  // l = 3, on the unit sphere
+    const double a = std::sqrt(70.0) / 4, b = std::sqrt(105.0), c = std::sqrt(42.0) / 4,
+                 d = std::sqrt(7.0) / 2;
+    out[0] = a * y * (3.0 * x * x - y * y);
+    out[1] = b * x * y * z;
+    out[2] = c * y * (5.0 * z * z - 1.0);
+    out[3] = d * z * (5.0 * z * z - 3.0);
+    out[4] = c * x * (5.0 * z * z - 1.0);
+    out[5] = 0.5 * b * z * (x * x - y * y);
+    out[6] = a * x * (x * x - 3.0 * y * y);
   }
 }
+
+constexpr int kL = 3;  // highest degree generated
 
 // Solve A X = B (n x n, n x m) by Gaussian elimination with partial pivoting.
 static void solve(int n, int m, std::vector<double> A, std::vector<double>& B) {
@@ -142,20 +154,30 @@ int main(int argc, char** argv) {
   double R[2][9];
   random_rotation(g, R[0]);
   random_rotation(g, R[1]);
-  std::vector<double> D[2][3];
+  std::vector<double> D[2][kL + 1];
   for (int k = 0; k < 2; ++k)
-    for (int l = 0; l <= 2; ++l) D[k][l] = wigner(l, R[k], g);
+    for (int l = 0; l <= kL; ++l) D[k][l] = wigner(l, R[k], g);
 
+  int n_triples = 0;
+  for (int l1 = 0; l1 <= kL; ++l1)
+    for (int l2 = 0; l2 <= kL; ++l2)
+      for (int l3 = std::abs(l1 - l2); l3 <= std::min(l1 + l2, kL); ++l3) ++n_triples;
+  const int dmax = (2 * kL + 1) * (2 * kL + 1) * (2 * kL + 1);
   std::string hdr;
-  hdr += "// Generated by cg_gen.cpp: real Clebsch-Gordan coupling tensors, l <= 2.\n";
+  char line[256];
+  hdr += "// Generated by cg_gen.cpp: real Clebsch-Gordan coupling tensors, l <= 3.\n";
   hdr += "// Do not edit.\n#pragma once\n\nnamespace sn {\n\n";
+  std::snprintf(line, sizeof line, "constexpr int kCGMaxL = %d;\nconstexpr int kCGTriples = %d;\n\n",
+                kL, n_triples);
+  hdr += line;
   hdr += "template <int L1, int L2, int L3> struct CG;\n\n";
-  std::string dense = "static const double kCGDense[15][125] = {\n";
+  std::snprintf(line, sizeof line, "static const double kCGDense[%d][%d] = {\n", n_triples, dmax);
+  std::string dense = line;
   int path_id = 0;
   int total_nnz = 0;
-  for (int l1 = 0; l1 <= 2; ++l1)
-    for (int l2 = 0; l2 <= 2; ++l2)
-      for (int l3 = std::abs(l1 - l2); l3 <= std::min(l1 + l2, 2); ++l3) {
+  for (int l1 = 0; l1 <= kL; ++l1)
+    for (int l2 = 0; l2 <= kL; ++l2)
+      for (int l3 = std::abs(l1 - l2); l3 <= std::min(l1 + l2, kL); ++l3) {
         const int d1 = 2 * l1 + 1, d2 = 2 * l2 + 1, d3 = 2 * l3 + 1, n = d1 * d2 * d3;
         std::vector<double> K;
         for (int k = 0; k < 2; ++k) {
@@ -200,8 +222,8 @@ int main(int argc, char** argv) {
         std::snprintf(buf, sizeof buf, "  }\n  static constexpr int nnz = %d;\n};\n\n", nnz);
         hdr += buf;
         dense += "  {";
-        for (int i = 0; i < 125; ++i) {
-          std::snprintf(buf, sizeof buf, "%.17g%s", i < n ? C[i] : 0.0, i < 124 ? ", " : "");
+        for (int i = 0; i < dmax; ++i) {
+          std::snprintf(buf, sizeof buf, "%.17g%s", i < n ? C[i] : 0.0, i < dmax - 1 ? ", " : "");
           dense += buf;
         }
         dense += "},\n";

@@ -9,14 +9,15 @@
 namespace sn {
 
 constexpr int kWave = 64;
+constexpr int kNumL = 4;  // feature and harmonic degrees l = 0..3
 
-// Layout of one feature row: degree blocks l = 0..2, each [m][channel] with
+// Layout of one feature row: degree blocks l = 0..kNumL-1, each [m][channel] with
 // the channel index innermost, so every (atom, m) pair is a contiguous row of
 // `mul` values and a per-degree channel mixing is a GEMM over those rows.
 struct IrrepLayout {
-  int mul[3];    // channels per degree (0 when absent)
-  int off[3];    // offset of each degree block within the row
-  int width;     // total floats per row
+  int mul[kNumL];  // channels per degree (0 when absent)
+  int off[kNumL];  // offset of each degree block within the row
+  int width;       // total floats per row
 };
 
 // A GEMM operand whose logical row r lives at

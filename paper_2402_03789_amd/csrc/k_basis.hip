@@ -7,6 +7,9 @@
 // component normalisation |Y^l|^2 = 2l+1 with m ordered -l..l:
 //   Y^0 = 1,  Y^1 = sqrt3 (y, z, x),
 //   Y^2 = (sqrt15 xy, sqrt15 yz, sqrt5/2 (3z^2-1), sqrt15 xz, sqrt15/2 (x^2-y^2)),
+//   Y^3 = (a y(3x^2-y^2), b xyz, c y(5z^2-1), d z(5z^2-3), c x(5z^2-1), b/2 z(x^2-y^2),
+//          a x(x^2-3y^2)),  a = sqrt70/4, b = sqrt105, c = sqrt42/4, d = sqrt7/2
+//   (l = 3 for the benchmark models of section 4),
 // and 8 radial Bessel functions (2/r_c) sin(n pi r / r_c) / r times the
 // polynomial envelope u(x) = 1 - (p+1)(p+2)/2 x^p + p(p+2) x^(p+1) - p(p+1)/2 x^(p+2).
 //
@@ -16,6 +19,12 @@
 #include "kernels.h"
 
 namespace sn {
+
+// l = 3 coefficients
+constexpr double kY3a = 2.0916500663351889;  // sqrt(70) / 4
+constexpr double kY3b = 10.246950765959598;  // sqrt(105)
+constexpr double kY3c = 1.6201851746019651;  // sqrt(42) / 4
+constexpr double kY3d = 1.3228756555322954;  // sqrt(7) / 2
 
 template <typename T>
 __global__ void k_edge_basis(int64_t E, const int* __restrict__ recv, const int* __restrict__ src,
@@ -45,6 +54,15 @@ __global__ void k_edge_basis(int64_t E, const int* __restrict__ recv, const int*
     Ye[6] = T(0.5 * s5 * (3.0 * z * z - 1.0));
     Ye[7] = T(s15 * x * z);
     Ye[8] = T(0.5 * s15 * (x * x - y * y));
+  }
+  if (l_sh >= 3) {
+    Ye[9] = T(kY3a * y * (3.0 * x * x - y * y));
+    Ye[10] = T(kY3b * x * y * z);
+    Ye[11] = T(kY3c * y * (5.0 * z * z - 1.0));
+    Ye[12] = T(kY3d * z * (5.0 * z * z - 3.0));
+    Ye[13] = T(kY3c * x * (5.0 * z * z - 1.0));
+    Ye[14] = T(0.5 * kY3b * z * (x * x - y * y));
+    Ye[15] = T(kY3a * x * (x * x - 3.0 * y * y));
   }
   double xr = r / r_cut;
   double c1 = (p + 1) * (p + 2) / 2.0, c2 = p * (p + 2.0), c3 = p * (p + 1) / 2.0;
@@ -106,6 +124,17 @@ __global__ void k_edge_grad(int64_t E, const int* __restrict__ recv, const int* 
     vx += s15 * (a4 * y + a7 * z + a8 * x);
     vy += s15 * (a4 * x + a5 * z - a8 * y);
     vz += s15 * (a5 * y + a7 * x) + 3.0 * s5 * a6 * z;
+  }
+  if (l_sh >= 3) {  // gradients of the l = 3 polynomials above
+    const double a9 = a[9], a10 = a[10], a11 = a[11], a12 = a[12], a13 = a[13], a14 = a[14],
+                 a15 = a[15];
+    const double q = 5.0 * z * z - 1.0;
+    vx += kY3a * (6.0 * x * y * a9 + 3.0 * (x * x - y * y) * a15) + kY3b * y * z * a10 +
+          kY3c * q * a13 + kY3b * x * z * a14;
+    vy += kY3a * (3.0 * (x * x - y * y) * a9 - 6.0 * x * y * a15) + kY3b * x * z * a10 +
+          kY3c * q * a11 - kY3b * y * z * a14;
+    vz += kY3b * x * y * a10 + 10.0 * kY3c * z * (y * a11 + x * a13) +
+          kY3d * (15.0 * z * z - 3.0) * a12 + 0.5 * kY3b * (x * x - y * y) * a14;
   }
   double vr = vx * x + vy * y + vz * z;
   g[3 * e] = dEdr * x + (vx - vr * x) / r;

@@ -48,7 +48,7 @@ __global__ void k_gate_fwd(int n, int last, IrrepLayout yl, IrrepLayout hl, cons
   for (int k = threadIdx.x; k < C0; k += blockDim.x) hr[hl.off[0] + k] = act(yr[yl.off[0] + k], c);
   if (last) return;
   int goff = C0;
-  for (int l = 1; l <= 2; ++l) {
+  for (int l = 1; l < kNumL; ++l) {
     const int mul = hl.mul[l];
     if (mul == 0) continue;
     const int nm = 2 * l + 1;
@@ -73,7 +73,7 @@ __global__ void k_gate_bwd(int n, int last, IrrepLayout yl, IrrepLayout hl, cons
     dyr[yl.off[0] + k] = dhr[hl.off[0] + k] * act_grad(yr[yl.off[0] + k], c);
   if (last) return;
   int goff = C0;
-  for (int l = 1; l <= 2; ++l) {
+  for (int l = 1; l < kNumL; ++l) {
     const int mul = hl.mul[l];
     if (mul == 0) continue;
     const int nm = 2 * l + 1;

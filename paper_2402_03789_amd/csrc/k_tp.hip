@@ -29,6 +29,7 @@
 #include "kernels.h"
 #include "cg_tables.h"
 
+#include <stdexcept>
 #include <utility>
 
 namespace sn {
@@ -75,7 +76,7 @@ __device__ inline void static_for(F&& f) {
 struct TPDeg {
   int xoff, mul, cpt, cpl;  // feature block offset, channels, lanes per edge slot, channels per lane
   int woff;                 // first radial weight of the paths with this l1
-  int mo[8], mw[8];         // per path: offset in the message row, width of its l3 block
+  int mo[kMaxPathsL1], mw[kMaxPathsL1];  // per path: offset in the message row, width of its l3 block
 };
 
 struct TPArgs {
@@ -93,18 +94,14 @@ struct CPL { static constexpr int value = L1 == 0 ? 2 : 1; };
 
 constexpr int kRecvPerBlock = 4;  // one wave per receiver
 
-// t[m3] of every path of degree l1 for one edge and one channel: sum_{m1,m2} C x[m1] Y[m2]
-template <typename T, int L1, class PL>
-__device__ inline void tp_paths(const T* xv, const T* Ye, T* t) {
+// t[m3] = sum_{m1,m2} C[m1,m2,m3] x[m1] Y[m2] of one path (l1, l2, l3) for one edge and one
+// channel; each path's t is formed where it is used, so at most 2 l3 + 1 of them are live
+template <typename T, int L1, int L2, int L3>
+__device__ inline void tp_path(const T* xv, const T* Ye, T (&t)[2 * L3 + 1]) {
 #pragma unroll
-  for (int q = 0; q < PL::NOUT; ++q) t[q] = T(0);
-  static_for<PL::count()>([&](auto P) {
-    constexpr int p = decltype(P)::value;
-    constexpr int l2 = PL::l2(p), l3 = PL::l3(p);
-    constexpr int oo = PL::ooff(p);
-    CG<L1, l2, l3>::each([&](int m1, int m2, int m3, double c) {
-      t[oo + m3] += T(c) * (xv[m1] * Ye[l2 * l2 + m2]);
-    });
+  for (int q = 0; q < 2 * L3 + 1; ++q) t[q] = T(0);
+  CG<L1, L2, L3>::each([&](int m1, int m2, int m3, double c) {
+    t[m3] += T(c) * (xv[m1] * Ye[L2 * L2 + m2]);
   });
 }
 
@@ -221,15 +218,15 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
           const bool active = beg + k * EI + ei < end;
 #pragma unroll
           for (int c = 0; c < KC; ++c) {
-            T t[NO];
-            tp_paths<T, L1, PL>(cur.x[c], cur.Y, t);
             static_for<NP>([&](auto P) {
               constexpr int p = decltype(P)::value;
-              constexpr int D3 = 2 * PL::l3(p) + 1;
+              constexpr int l3 = PL::l3(p);
               constexpr int oo = PL::ooff(p);
+              T t[2 * l3 + 1];
+              tp_path<T, L1, PL::l2(p), l3>(cur.x[c], cur.Y, t);
               const T wv = (active && ok[c]) ? cur.w[c][p] : T(0);
 #pragma unroll
-              for (int m3 = 0; m3 < D3; ++m3) acc[c][oo + m3] += wv * t[oo + m3];
+              for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) acc[c][oo + m3] += wv * t[m3];
             });
           }
         });
@@ -379,20 +376,20 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
             T dxv[D1];
 #pragma unroll
             for (int m1 = 0; m1 < D1; ++m1) dxv[m1] = T(0);
-            T t[NO];
-            tp_paths<T, L1, PL>(xv, cur.Y, t);
             static_for<NP>([&](auto P) {
               constexpr int p = decltype(P)::value;
               constexpr int l2 = PL::l2(p), l3 = PL::l3(p);
               constexpr int D3 = 2 * l3 + 1;
               constexpr int oo = PL::ooff(p);
+              T t[D3];
+              tp_path<T, L1, l2, l3>(xv, cur.Y, t);
               const T wv = cur.w[c][p];
               T dwv = T(0);
               T gg[D3];
 #pragma unroll
               for (int m3 = 0; m3 < D3; ++m3) {
                 const T gi = gin[c][oo + m3];
-                dwv += gi * t[oo + m3];
+                dwv += gi * t[m3];
                 gg[m3] = wv * gi;
               }
               dw[drow + p * a.mul + u] = sstore<S>(dwv);
@@ -446,7 +443,7 @@ static TPArgs make_args(const TPLayer& L, int l1, int n_recv, const int* row_ptr
   d.cpt = cpt;
   d.cpl = (mul + cpt - 1) / cpt;
   d.woff = L.woff[l1];
-  for (int p = 0; p < 8; ++p) {
+  for (int p = 0; p < kMaxPathsL1; ++p) {
     d.mo[p] = L.mo[l1][p];
     d.mw[p] = L.mw[l1][p];
   }
@@ -498,7 +495,12 @@ static void run(const TPLayer& L, bool fwd, int n_recv, const int* row_ptr, cons
     SN_TP_CASE(0, 1, 1, true) SN_TP_CASE(1, 1, 1, true)
     SN_TP_CASE(0, 2, 2, false) SN_TP_CASE(1, 2, 2, false) SN_TP_CASE(2, 2, 2, false)
     SN_TP_CASE(0, 2, 2, true) SN_TP_CASE(1, 2, 2, true) SN_TP_CASE(2, 2, 2, true)
+    SN_TP_CASE(0, 3, 3, false) SN_TP_CASE(1, 3, 3, false) SN_TP_CASE(2, 3, 3, false)
+    SN_TP_CASE(3, 3, 3, false)
+    SN_TP_CASE(0, 3, 3, true) SN_TP_CASE(1, 3, 3, true) SN_TP_CASE(2, 3, 3, true)
+    SN_TP_CASE(3, 3, 3, true)
 #undef SN_TP_CASE
+    throw std::invalid_argument("no tensor-product kernel for this degree combination");
   }
 }
 

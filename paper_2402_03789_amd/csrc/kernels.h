@@ -122,16 +122,18 @@ struct TPTask {  // one wave's work: one degree l1, 64 lanes over channels x edg
   int cpt;       // channels per edge slot (power of two <= 64)
 };
 
+constexpr int kMaxPathsL1 = 16;  // paths per input degree (11 at most for l <= 3)
+
 struct TPLayer {
   int lmax, lsh;
   bool scalar_only;     // last block: only l3 = 0 paths
   IrrepLayout xin;      // layout of the sender feature rows
   int P;                // radial weights per edge
-  int woff[3];          // first weight of the paths with each l1
+  int woff[kNumL];      // first weight of the paths with each l1
   int Dm;               // mid (message) row width
   // per l1, per local path index: offset of (l3 block + channel start) in M, and l3 mid width
-  int mo[3][8];
-  int mw[3][8];
+  int mo[kNumL][kMaxPathsL1];
+  int mw[kNumL][kMaxPathsL1];
   int n_tasks;
   TPTask tasks[16];
   int NY;               // (l_sh + 1)^2

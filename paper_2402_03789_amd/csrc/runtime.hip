@@ -64,24 +64,30 @@ struct LayerDesc {
   std::vector<int> ins, outs;
   std::vector<std::array<int, 3>> paths;
   int P = 0;
-  int gmul[3] = {0, 0, 0};
-  int mid[3] = {0, 0, 0};
+  int gmul[kNumL] = {};
+  int mid[kNumL] = {};
   IrrepLayout hin{}, yl{}, ml{}, hout{};
   TPLayer tp{};
-  int64_t w_lin1[3] = {-1, -1, -1}, w_linsc[3] = {-1, -1, -1}, w_lin2[3] = {-1, -1, -1};
+  int64_t w_lin1[kNumL] = {-1, -1, -1, -1}, w_linsc[kNumL] = {-1, -1, -1, -1},
+          w_lin2[kNumL] = {-1, -1, -1, -1};
   int64_t w_mlp[3] = {-1, -1, -1};
 };
 
-IrrepLayout make_layout(int m0, int m1, int m2) {
+// channels per degree (kNumL entries, zero where absent)
+IrrepLayout make_layout(const int* mul) {
   IrrepLayout L{};
-  L.mul[0] = m0; L.mul[1] = m1; L.mul[2] = m2;
   int off = 0;
-  for (int l = 0; l < 3; ++l) {
+  for (int l = 0; l < kNumL; ++l) {
+    L.mul[l] = mul[l];
     L.off[l] = off;
     off += (2 * l + 1) * L.mul[l];
   }
   L.width = off;
   return L;
+}
+IrrepLayout scalar_layout(int c) {
+  const int mul[kNumL] = {c, 0, 0, 0};
+  return make_layout(mul);
 }
 
 RowMap rows_of(const IrrepLayout& L, int l) {
@@ -92,7 +98,7 @@ RowMap rows_of(const IrrepLayout& L, int l) {
 
 struct sn_model {
   int T = 0, lmax = 0, lsh = 0, nb = 8, hidden = 64, p = 6;
-  int muls[3] = {0, 0, 0};
+  int muls[kNumL] = {};
   double rc = 0, kavg = 1, sigma = 1, act = 1;
   std::vector<int> species;
   std::vector<double> shift;
@@ -119,7 +125,7 @@ namespace {
 
 void build_layers(sn_model& m) {
   const int C0 = m.muls[0];
-  const IrrepLayout feat = make_layout(m.muls[0], m.muls[1], m.muls[2]);
+  const IrrepLayout feat = make_layout(m.muls);
   for (int t = 0; t < m.T; ++t) {
     LayerDesc L;
     L.last = (t == m.T - 1);
@@ -135,13 +141,13 @@ void build_layers(sn_model& m) {
     for (auto& pth : L.paths) L.P += m.muls[pth[0]];
     for (int l : L.outs) {
       if (L.last) L.gmul[l] = C0;
-      else L.gmul[l] = (l == 0) ? (m.muls[0] + m.muls[1] + m.muls[2]) : m.muls[l];
+      else L.gmul[l] = (l == 0) ? (m.muls[0] + m.muls[1] + m.muls[2] + m.muls[3]) : m.muls[l];
     }
     for (auto& pth : L.paths) L.mid[pth[2]] += m.muls[pth[0]];
-    L.hin = (t == 0) ? make_layout(C0, 0, 0) : feat;
-    L.yl = make_layout(L.gmul[0], L.gmul[1], L.gmul[2]);
-    L.ml = make_layout(L.mid[0], L.mid[1], L.mid[2]);
-    L.hout = L.last ? make_layout(C0, 0, 0) : feat;
+    L.hin = (t == 0) ? scalar_layout(C0) : feat;
+    L.yl = make_layout(L.gmul);
+    L.ml = make_layout(L.mid);
+    L.hout = L.last ? scalar_layout(C0) : feat;
     // weights
     for (int l : L.ins) {
       const int mu = m.muls[l];
@@ -164,8 +170,8 @@ void build_layers(sn_model& m) {
     tp.Dm = L.ml.width;
     tp.NY = (m.lsh + 1) * (m.lsh + 1);
     int woff = 0;
-    int kfill[3] = {0, 0, 0};
-    for (int l1 = 0; l1 <= 2; ++l1) {
+    int kfill[kNumL] = {};
+    for (int l1 = 0; l1 < kNumL; ++l1) {
       tp.woff[l1] = woff;
       int pi = 0;
       for (auto& pth : L.paths) {
@@ -209,7 +215,7 @@ std::unique_ptr<sn_model> load_model(const char* path) {
   const Json& c = j.at("config");
   m->T = c.at("n_layers").integer();
   const auto& muls = c.at("muls").array();
-  if (muls.empty() || muls.size() > 3) throw UnsupportedError("l_max must be 0..2");
+  if (muls.empty() || muls.size() > (size_t)kNumL) throw UnsupportedError("l_max must be 0..3");
   for (size_t l = 0; l < muls.size(); ++l) m->muls[l] = muls[l].integer();
   m->lmax = (int)muls.size() - 1;
   m->lsh = c.at("l_sh").integer();
@@ -227,12 +233,13 @@ std::unique_ptr<sn_model> load_model(const char* path) {
       m->shift.size() != m->species.size())
     throw ArgError("invalid model configuration");
   if (m->nb != 8 || m->hidden != 64) throw UnsupportedError("radial MLP must be 8 -> 64 -> 64");
-  if (!((m->lmax == 1 && m->lsh == 1) || (m->lmax == 2 && m->lsh == 2)))
-    throw UnsupportedError("supported (l_max, l_sh): (1, 1) and (2, 2)");
-  if (m->muls[0] % 4 != 0 || m->muls[1] % 4 != 0 || m->muls[2] % 4 != 0)
-    throw UnsupportedError("channel counts must be multiples of 4");
-  for (int l = 0; l < 3; ++l)
+  if (!((m->lmax == 1 && m->lsh == 1) || (m->lmax == 2 && m->lsh == 2) ||
+        (m->lmax == 3 && m->lsh == 3)))
+    throw UnsupportedError("supported (l_max, l_sh): (1, 1), (2, 2) and (3, 3)");
+  for (int l = 0; l < kNumL; ++l) {
+    if (m->muls[l] % 4 != 0) throw UnsupportedError("channel counts must be multiples of 4");
     if (m->muls[l] < 0 || m->muls[l] > 128) throw UnsupportedError("at most 128 channels per degree");
+  }
   std::fill(m->lut, m->lut + 128, -1);
   for (size_t s = 0; s < m->species.size(); ++s) {
     int z = m->species[s];
@@ -763,6 +770,7 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
   int hP = 0;
   HIPCHK(hipMemcpyAsync(&hP, fscan + E, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
   c->NP = hP;
 }
 
@@ -941,6 +949,8 @@ struct Pipe {
       const int* order = c->get<int>("order", N);
       launch_unpermute(N, order, ae, 1, d_atom_energy_orig, 1.0, s);
     }
+    // a launch refused by the runtime (resources, configuration) leaves its outputs unwritten
+    HIPCHK(hipGetLastError());
   }
 
   void backward(double grad_scale, double* d_forces_orig, double* d_virial) {
@@ -1048,6 +1058,7 @@ struct Pipe {
                         gE, part, s);
       launch_seg_finalize(c->B, c->get<int>("vfirst", c->B + 1), part, 9, d_virial, grad_scale, s);
     }
+    HIPCHK(hipGetLastError());
     c->mark("end");
   }
 };
@@ -1331,7 +1342,7 @@ int sn_model_info(const sn_model_t* m, sn_model_info_t* info) {
   info->n_layers = m->T;
   info->l_max = m->lmax;
   info->l_sh = m->lsh;
-  for (int l = 0; l < 3; ++l) info->muls[l] = m->muls[l];
+  for (int l = 0; l < kNumL; ++l) info->muls[l] = m->muls[l];
   info->n_basis = m->nb;
   info->hidden = m->hidden;
   info->n_species = (int)m->species.size();
@@ -1344,12 +1355,13 @@ int sn_model_info(const sn_model_t* m, sn_model_info_t* info) {
 }
 
 int sn_cg_table(int l1, int l2, int l3, double* out) {
-  if (!out || l1 < 0 || l2 < 0 || l3 < 0 || l1 > 2 || l2 > 2 || l3 > 2) return SN_EINVAL;
+  constexpr int L = sn::kCGMaxL;
+  if (!out || l1 < 0 || l2 < 0 || l3 < 0 || l1 > L || l2 > L || l3 > L) return SN_EINVAL;
   if (l3 < std::abs(l1 - l2) || l3 > l1 + l2) return SN_EINVAL;
   int id = 0;
-  for (int a = 0; a <= 2; ++a)
-    for (int b = 0; b <= 2; ++b)
-      for (int c = std::abs(a - b); c <= std::min(a + b, 2); ++c) {
+  for (int a = 0; a <= L; ++a)
+    for (int b = 0; b <= L; ++b)
+      for (int c = std::abs(a - b); c <= std::min(a + b, L); ++c) {
         if (a == l1 && b == l2 && c == l3) {
           const int n = (2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1);
           for (int i = 0; i < n; ++i) out[i] = sn::kCGDense[id][i];

@@ -36,9 +36,9 @@ def test_library_exports_every_declared_symbol():
 def test_cg_tables_match_oracle():
     import paper_2402_03789_amd as sn
     from oracle.cg import real_cg
-    for l1 in range(3):
-        for l2 in range(3):
-            for l3 in range(abs(l1 - l2), min(l1 + l2, 2) + 1):
+    for l1 in range(4):
+        for l2 in range(4):
+            for l3 in range(abs(l1 - l2), min(l1 + l2, 3) + 1):
                 np.testing.assert_allclose(sn.cg_table(l1, l2, l3), real_cg(l1, l2, l3), atol=1e-13)
     with pytest.raises(sn.SNError):
         sn.cg_table(1, 1, 3)
@@ -56,6 +56,13 @@ def test_model_load_and_parameter_count(tmp_path):
     spec = model_spec_small()
     write_weights(p, spec, make_weights(spec, 1))
     assert sn.Model(p).info()["n_params"] == 56_400
+    # a benchmark-family model (l_max 3 features and harmonics, section 4)
+    from synth import model_spec_bench
+    spec = model_spec_bench(32, 3)
+    write_weights(p, spec, make_weights(spec, 1))
+    info = sn.Model(p).info()
+    assert info["l_max"] == 3 and info["l_sh"] == 3 and info["muls"] == [32] * 4
+    assert info["n_params"] == sum(a.size for a in make_weights(spec, 1).values())
 
 
 def test_model_load_rejects_bad_files(tmp_path):
