@@ -90,6 +90,11 @@ def main():
                          "benchmark models (l_max 3) in NVT MD of alpha-quartz-density SiO2")
     ap.add_argument("--models", default=None,
                     help="paper_models: comma-separated CxT list (default all 20, e.g. 32x4)")
+    ap.add_argument("--sweep-channels", default=None,
+                    help="size_sweep: comma-separated channel counts of benchmark models (l_max 3) "
+                         "to sweep instead of the l <= 2 model")
+    ap.add_argument("--sweep-layers", type=int, default=4,
+                    help="size_sweep: interaction blocks of the benchmark models")
     ap.add_argument("--sizes", default="4608,12960",
                     help="paper_models: atom counts (multiples of 3)")
     ap.add_argument("--serve-requests", type=int, default=None,
@@ -416,48 +421,73 @@ def bench_fd(args):
 
 def bench_size_sweep(args):
     """One-GPU throughput against system size (the paper's single-GPU utilisation curve,
-    section 4.2): E+F+virial evaluations, graph build included, of SiO2 boxes at
-    2.2 g/cm^3 from 192 to 48,000 atoms with the 5-block l <= 2 model."""
+    section 4.2 and its supplementary figure): E+F+virial evaluations, graph build included.
+    Default: SiO2 boxes at 2.2 g/cm^3 from 192 to 48,000 atoms with the 5-block l <= 2 model.
+    With --sweep-channels: the benchmark models (l_max 3, r_c 4 A, --sweep-layers blocks) of
+    each channel count on SiO2 at the alpha-quartz density, from 96 to 73,728 atoms."""
     import torch
 
     import paper_2402_03789_amd as sn
-    from synth import model_spec_real, make_weights, write_weights, sio2_box
+    from synth import model_spec_bench, model_spec_real, make_weights, write_weights, sio2_box
 
-    spec = model_spec_real()
-    wpath = os.path.join(tempfile.mkdtemp(), "model.snw")
-    write_weights(wpath, spec, make_weights(spec, 102))
-    model = sn.Model(wpath)
+    tmp = tempfile.mkdtemp()
+    if args.sweep_channels:
+        density = 2.65
+        n_si = (32, 128, 512, 1536, 4320, 12288, 24576)
+        models = []
+        for c in (int(v) for v in args.sweep_channels.split(",")):
+            spec = model_spec_bench(c, args.sweep_layers)
+            models.append((f"{c} channels, {args.sweep_layers} blocks, l_max 3", spec,
+                           make_weights(spec, 300 + 10 * c + args.sweep_layers)))
+    else:
+        density = 2.2
+        n_si = (64, 256, 1024, 4000, 8000, 16000)
+        spec = model_spec_real()
+        models = [("5 blocks, 128x0e+64x1e+32x2e", spec, make_weights(spec, 102))]
     dev = torch.device("cuda:0")
-    points = []
-    for n_si in (64, 256, 1024, 4000, 8000, 16000):
-        s = sio2_box(n_si, seed=2)
-        ctx = sn.Context(model, device=0, precision=args.precision)
-        pos = torch.tensor(s.pos, dtype=torch.float64, device=dev)
-        Z = torch.tensor(s.Z, dtype=torch.int32, device=dev)
-        energy = torch.zeros(1, dtype=torch.float64, device=dev)
-        forces = torch.zeros((s.n, 3), dtype=torch.float64, device=dev)
-        virial = torch.zeros(9, dtype=torch.float64, device=dev)
-        steps = max(5, min(200, int(4e5 / s.n)))
-        for k in range(3 + steps):
-            if k == 3:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-            ctx.forward_device(pos, Z, s.cell, energy)
-            ctx.backward_device(1.0, forces, virial)
-        ctx.synchronize()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        points.append({"n_atoms": s.n, "steps": steps, "ms_per_step": dt / steps * 1e3,
-                       "atom_steps_per_s": s.n * steps / dt})
-        print(f"size sweep: {s.n} atoms {dt / steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
-        del ctx
-    return {"metric": "atom-steps/s (E+F) against atom count, 5-layer l<=2 model, SiO2",
+    boxes = {k: sio2_box(k, density=density, seed=2) for k in n_si}
+    curves = []
+    for label, spec, w in models:
+        wpath = os.path.join(tmp, "model.snw")
+        write_weights(wpath, spec, w)
+        model = sn.Model(wpath)
+        points = []
+        for k_si in n_si:
+            s = boxes[k_si]
+            ctx = sn.Context(model, device=0, precision=args.precision)
+            pos = torch.tensor(s.pos, dtype=torch.float64, device=dev)
+            Z = torch.tensor(s.Z, dtype=torch.int32, device=dev)
+            energy = torch.zeros(1, dtype=torch.float64, device=dev)
+            forces = torch.zeros((s.n, 3), dtype=torch.float64, device=dev)
+            virial = torch.zeros(9, dtype=torch.float64, device=dev)
+            steps = max(5, min(200, int(4e5 / s.n)))
+            for k in range(3 + steps):
+                if k == 3:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                ctx.forward_device(pos, Z, s.cell, energy)
+                ctx.backward_device(1.0, forces, virial)
+            ctx.synchronize()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            points.append({"n_atoms": s.n, "steps": steps, "ms_per_step": dt / steps * 1e3,
+                           "atom_steps_per_s": s.n * steps / dt, "device_bytes": ctx.memory()})
+            print(f"size sweep: {label}: {s.n} atoms {dt / steps * 1e3:.2f} ms/step",
+                  file=sys.stderr, flush=True)
+            del ctx
+        best = max(p["atom_steps_per_s"] for p in points)
+        for p in points:  # throughput relative to the largest this model reaches on the sweep
+            p["relative_throughput"] = p["atom_steps_per_s"] / best
+        curves.append({"model": label, "points": points})
+        del model
+    return {"metric": "atom-steps/s (E+F) against atom count, SiO2",
             "unit": "atom-steps/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
             "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
-            "config": {"workload": "SiO2 boxes at 2.2 g/cm^3, 192 to 48,000 atoms; one "
-                                   "evaluation = graph build + E + F + virial",
+            "config": {"workload": f"SiO2 boxes at {density} g/cm^3, {3 * n_si[0]} to "
+                                   f"{3 * n_si[-1]:,} atoms; one evaluation = graph build + E + F "
+                                   "+ virial",
                        "precision": args.precision},
-            "points": points}
+            "curves": curves, "points": curves[0]["points"]}
 
 
 def bench_paper_models(args):
