@@ -11,7 +11,7 @@ namespace sn {
 
 // ------------------------------------------------------------------ generic tiled GEMM
 constexpr int GT = 64;   // tile rows / cols
-constexpr int GK = 16;   // k step
+constexpr int GK = 32;   // k step
 
 template <typename TACC, typename T>
 __device__ inline TACC load_operand(T v, bool bf16) {
@@ -21,41 +21,64 @@ __device__ inline TACC load_operand(T v, bool bf16) {
 
 // C[M x N] (=|+=) alpha * A[M x K] op(B), with operand types TA/TB, result type TC
 // and accumulation in TACC.  64 x 64 tile per 256-thread block, 4 x 4 per thread.
+template <typename TACC>
+struct ValuLds {
+  TACC a[GK][GT + 4];
+  TACC b[GK][GT + 4];
+};
+
+// one 64 x 64 output tile (rows m0.., columns n0..)
 template <typename TA, typename TB, typename TC, typename TACC, bool BT>
-__global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, const TA* __restrict__ A,
-                                                    RowMap am, const TB* __restrict__ B, int ldb,
-                                                    TC* __restrict__ C, RowMap cm, TACC alpha,
-                                                    int accumulate, int bf16) {
-  __shared__ TACC As[GK][GT + 4];
-  __shared__ TACC Bs[GK][GT + 4];
+__device__ inline void gemm_valu_tile(int64_t M, int N, int K, const TA* __restrict__ A, RowMap am,
+                                      const TB* __restrict__ B, int ldb, TC* __restrict__ C,
+                                      RowMap cm, TACC alpha, int accumulate, int bf16, int64_t m0,
+                                      int n0, ValuLds<TACC>& L) {
+  auto& As = L.a;
+  auto& Bs = L.b;
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  const int64_t m0 = (int64_t)blockIdx.x * GT;
-  const int n0 = blockIdx.y * GT;
   TACC acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = TACC(0);
-  const int ar = tid >> 2, ak = (tid & 3) * 4;
+  // A: 8 consecutive k of row ar; B: k-rows bk and bk + 16, 4 consecutive n.  The next
+  // k-slab is loaded into registers while the current one is multiplied; every load is
+  // issued from a clamped address and masked afterwards (no load under a branch).
+  const int ar = tid >> 2, ak = (tid & 3) * 8;
   const int64_t agm = m0 + ar;
-  const int64_t arow = agm < M ? am(agm) : 0;
+  const bool a_ok = agm < M;
+  const int64_t arow = a_ok ? am(agm) : 0;
   const int bk = tid >> 4, bn = (tid & 15) * 4;
+  TACC ra[8], rb[2][4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + ak + j;
+      const TACC v = load_operand<TACC>(A[arow + min(k, K - 1)], bf16);
+      ra[j] = (a_ok && k < K) ? v : TACC(0);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + bn + j, k = k0 + bk + 16 * h;
+        const int nc = min(n, N - 1), kc = min(k, K - 1);
+        const TACC v =
+            load_operand<TACC>(BT ? B[(int64_t)nc * ldb + kc] : B[(int64_t)kc * ldb + nc], bf16);
+        rb[h][j] = (k < K && n < N) ? v : TACC(0);
+      }
+  };
+  if (K > 0) fetch(0);  // (K = 0: no loads; the tile is written as zeros)
   for (int k0 = 0; k0 < K; k0 += GK) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int k = k0 + ak + j;
-      As[ak + j][ar] = (agm < M && k < K) ? load_operand<TACC>(A[arow + k], bf16) : TACC(0);
-    }
+    for (int j = 0; j < 8; ++j) As[ak + j][ar] = ra[j];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int n = n0 + bn + j, k = k0 + bk;
-      TACC v = TACC(0);
-      if (k < K && n < N)
-        v = load_operand<TACC>(BT ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n], bf16);
-      Bs[bk][bn + j] = v;
-    }
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Bs[bk + 16 * h][bn + j] = rb[h][j];
     __syncthreads();
+    if (k0 + GK < K) fetch(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; ++kk) {
       TACC a[4], b[4];
@@ -85,6 +108,38 @@ __global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, cons
   }
 }
 
+template <typename TA, typename TB, typename TC, typename TACC, bool BT>
+__global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, const TA* __restrict__ A,
+                                                    RowMap am, const TB* __restrict__ B, int ldb,
+                                                    TC* __restrict__ C, RowMap cm, TACC alpha,
+                                                    int accumulate, int bf16) {
+  __shared__ ValuLds<TACC> lds;
+  gemm_valu_tile<TA, TB, TC, TACC, BT>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate, bf16,
+                                       (int64_t)blockIdx.x * GT, blockIdx.y * GT, lds);
+}
+
+// grouped launch: problem q owns blocks [tile0[q], tile0[q + 1]), nbn[q] column tiles per row
+template <typename TA, typename TB, typename TC>
+struct ValuGroupArgs {
+  GemmDesc<TA, TB, TC> d[kMaxGemmGroup];
+  int64_t tile0[kMaxGemmGroup + 1];
+  int nbn[kMaxGemmGroup];
+  int n;
+};
+
+template <typename TA, typename TB, typename TC, typename TACC, bool BT>
+__global__ __launch_bounds__(256) void k_gemm_valu_g(ValuGroupArgs<TA, TB, TC> g, int bf16) {
+  __shared__ ValuLds<TACC> lds;
+  const int64_t tile = blockIdx.x;
+  int q = 0;
+  while (q + 1 < g.n && tile >= g.tile0[q + 1]) ++q;
+  const GemmDesc<TA, TB, TC>& d = g.d[q];
+  const int64_t t = tile - g.tile0[q];
+  gemm_valu_tile<TA, TB, TC, TACC, BT>(d.M, d.N, d.K, d.A, d.am, d.B, d.ldb, d.C, d.cm,
+                                       (TACC)d.alpha, d.accumulate, bf16, (t / g.nbn[q]) * GT,
+                                       (int)(t % g.nbn[q]) * GT, lds);
+}
+
 template <typename TA, typename TB, typename TC, typename TACC>
 void launch_gemm(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, int ldb, bool bt,
                  TC* C, RowMap cm, TACC alpha, bool accumulate, bool bf16_operands, hipStream_t s) {
@@ -98,10 +153,40 @@ void launch_gemm(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, i
                                                               accumulate, bf16_operands);
 }
 
+template <typename TA, typename TB, typename TC, typename TACC>
+void launch_gemm_group(int n, const GemmDesc<TA, TB, TC>* d, bool bt, bool bf16_operands,
+                       hipStream_t s) {
+  ValuGroupArgs<TA, TB, TC> g{};
+  for (int q = 0; q < n && q < kMaxGemmGroup; ++q)
+    if (d[q].M > 0 && d[q].N > 0) g.d[g.n++] = d[q];
+  int64_t tiles = 0;
+  for (int q = 0; q < g.n; ++q)
+    tiles += ((g.d[q].M + GT - 1) / GT) * ((g.d[q].N + GT - 1) / GT);
+  if (n > kMaxGemmGroup || g.n <= 1 || tiles > kGroupMaxTiles) {  // one launch per problem
+    for (int q = 0; q < n; ++q)
+      launch_gemm<TA, TB, TC, TACC>(d[q].M, d[q].N, d[q].K, d[q].A, d[q].am, d[q].B, d[q].ldb, bt,
+                                    d[q].C, d[q].cm, (TACC)d[q].alpha, d[q].accumulate != 0,
+                                    bf16_operands, s);
+    return;
+  }
+  g.tile0[0] = 0;
+  for (int q = 0; q < g.n; ++q) {
+    g.nbn[q] = (g.d[q].N + GT - 1) / GT;
+    g.tile0[q + 1] = g.tile0[q] + ((g.d[q].M + GT - 1) / GT) * g.nbn[q];
+  }
+  const unsigned grid = (unsigned)g.tile0[g.n];
+  if (bt)
+    k_gemm_valu_g<TA, TB, TC, TACC, true><<<grid, 256, 0, s>>>(g, bf16_operands ? 1 : 0);
+  else
+    k_gemm_valu_g<TA, TB, TC, TACC, false><<<grid, 256, 0, s>>>(g, bf16_operands ? 1 : 0);
+}
+
 #define SN_GEMM_INST(TA, TB, TC, TACC)                                                          \
   template void launch_gemm<TA, TB, TC, TACC>(int64_t, int, int, const TA*, RowMap, const TB*,   \
                                               int, bool, TC*, RowMap, TACC, bool, bool,          \
-                                              hipStream_t);
+                                              hipStream_t);                                      \
+  template void launch_gemm_group<TA, TB, TC, TACC>(int, const GemmDesc<TA, TB, TC>*, bool, bool, \
+                                                    hipStream_t);
 SN_GEMM_INST(double, double, double, double)
 SN_GEMM_INST(double, double, float, double)
 SN_GEMM_INST(float, float, double, float)

@@ -12,6 +12,8 @@
 // emitted in bin-scan order, and sender segments are sorted by edge id.
 #include "kernels.h"
 
+#include <climits>
+
 namespace sn {
 
 // ------------------------------------------------------------------ exclusive scan
@@ -135,19 +137,55 @@ __global__ void k_scatter_keys(int n, const int* __restrict__ key, const int* __
   items[pos] = i;
 }
 
-// insertion sort of each segment (segments are short: bin or sender lists)
-__global__ void k_sort_segments(int nseg, const int* __restrict__ start, int* __restrict__ items) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
-  int a = start[s], b = start[s + 1];
-  for (int i = a + 1; i < b; ++i) {
-    int v = items[i];
-    int j = i - 1;
-    while (j >= a && items[j] > v) {
-      items[j + 1] = items[j];
-      --j;
+// Ascending sort of each segment (bin or sender lists: distinct item indices), one wave
+// per segment: every value's final position is the number of smaller values in the
+// segment (counted through cross-lane broadcasts), so each lane places its values
+// directly.  Segments of up to 64 * kSortChunks items; longer ones (none in practice)
+// fall back to an insertion sort by one lane.
+constexpr int kSortChunks = 8;
+__global__ __launch_bounds__(256) void k_sort_segments(int nseg, const int* __restrict__ start,
+                                                       int* __restrict__ items) {
+  const int sg = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (sg >= nseg) return;
+  const int lane = threadIdx.x & 63;
+  const int a = start[sg], n = start[sg + 1] - a;
+  if (n <= 1) return;
+  if (n > 64 * kSortChunks) {
+    if (lane == 0) {
+      for (int i = a + 1; i < a + n; ++i) {
+        const int v = items[i];
+        int j = i - 1;
+        while (j >= a && items[j] > v) {
+          items[j + 1] = items[j];
+          --j;
+        }
+        items[j + 1] = v;
+      }
     }
-    items[j + 1] = v;
+    return;
+  }
+  const int nc = (n + 63) >> 6;
+  int v[kSortChunks], rank[kSortChunks];
+#pragma unroll
+  for (int c = 0; c < kSortChunks; ++c) {
+    const int i = 64 * c + lane;
+    v[c] = (c < nc && i < n) ? items[a + i] : INT_MAX;
+    rank[c] = 0;
+  }
+#pragma unroll
+  for (int cs = 0; cs < kSortChunks; ++cs) {
+    if (cs >= nc) break;
+    const int m = min(64, n - 64 * cs);
+    for (int j = 0; j < m; ++j) {
+      const int w = __shfl(v[cs], j);
+#pragma unroll
+      for (int c = 0; c < kSortChunks; ++c) rank[c] += w < v[c] ? 1 : 0;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kSortChunks; ++c) {
+    const int i = 64 * c + lane;
+    if (c < nc && i < n) items[a + rank[c]] = v[c];
   }
 }
 
@@ -184,12 +222,13 @@ __device__ inline void for_each_ghost(const double* f, int own_region,
                                       const StructParams* __restrict__ sp, F&& emit) {
   const StructParams& P = sp[own_region];
   const int nreg = P.ndom[0] * P.ndom[1] * P.ndom[2];
-  const BinGrid& g0 = P.g;
-  for (int d = P.first_region; d < P.first_region + nreg; ++d) {
-    const BinGrid& g = sp[d].g;
-    for (int sx = -g0.nimg[0]; sx <= g0.nimg[0]; ++sx)
-      for (int sy = -g0.nimg[1]; sy <= g0.nimg[1]; ++sy)
-        for (int sz = -g0.nimg[2]; sz <= g0.nimg[2]; ++sz) {
+  const int first = P.first_region;
+  const int ni[3] = {P.g.nimg[0], P.g.nimg[1], P.g.nimg[2]};
+  for (int d = first; d < first + nreg; ++d) {
+    const BinGrid g = sp[d].g;  // one copy in registers for the image loop
+    for (int sx = -ni[0]; sx <= ni[0]; ++sx)
+      for (int sy = -ni[1]; sy <= ni[1]; ++sy)
+        for (int sz = -ni[2]; sz <= ni[2]; ++sz) {
           if (sx == 0 && sy == 0 && sz == 0 && d == own_region) continue;
           if (in_shell(f, sx, sy, sz, g)) emit(d, sx, sy, sz);
         }
@@ -244,46 +283,82 @@ __global__ void k_bin_keys(int n, const double* __restrict__ frac, const int* __
   key[i] = P.bin_base + bin_lin(f, P.g);
 }
 
+// Edges of receiver k: every extended point s != k of the 27 bins around k's bin with
+// |r_s - r_k|^2 < rc2, in bin order (x, then y, then z) and item order within a bin.  One
+// wave per receiver: lanes 0..26 take one neighbouring bin each, a wave prefix sum lays
+// the bins' items out as one candidate list, and the lanes test 64 candidates at a time;
+// hits are numbered by a ballot prefix, so the edge order is the same as a serial scan.
 template <bool FILL>
-__global__ void k_edges(int n, const double* __restrict__ pos_ext, const double* __restrict__ frac_ext,
-                        const int* __restrict__ sid, const StructParams* __restrict__ sp,
-                        const int* __restrict__ cell_start, const int* __restrict__ cell_items,
-                        double rc2, int* __restrict__ count, int* __restrict__ err,
-                        const int* __restrict__ row_ptr, int* __restrict__ src,
-                        int* __restrict__ recv) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_edges(int n, const double* __restrict__ pos_ext,
+                                               const double* __restrict__ frac_ext,
+                                               const int* __restrict__ sid,
+                                               const StructParams* __restrict__ sp,
+                                               const int* __restrict__ cell_start,
+                                               const int* __restrict__ cell_items, double rc2,
+                                               int* __restrict__ count, int* __restrict__ err,
+                                               const int* __restrict__ row_ptr,
+                                               int* __restrict__ src, int* __restrict__ recv) {
+  const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (k >= n) return;
+  const int lane = threadIdx.x & 63;
   const StructParams& P = sp[sid[k]];
-  const BinGrid& g = P.g;
-  double p[3] = {pos_ext[3 * k], pos_ext[3 * k + 1], pos_ext[3 * k + 2]};
-  double f[3] = {frac_ext[3 * k], frac_ext[3 * k + 1], frac_ext[3 * k + 2]};
+  const BinGrid g = P.g;
+  const double p0 = pos_ext[3 * k], p1 = pos_ext[3 * k + 1], p2 = pos_ext[3 * k + 2];
   int b[3];
-  for (int a = 0; a < 3; ++a) b[a] = bin_axis(f[a], g, a);
-  int c = 0;
+  for (int a = 0; a < 3; ++a) b[a] = bin_axis(frac_ext[3 * k + a], g, a);
+  // this lane's bin (lanes 0..26): offsets (dx, dy, dz) in lexicographic order
+  int c0 = 0, cn = 0;
+  if (lane < 27) {
+    const int bx = b[0] + lane / 9 - 1, by = b[1] + (lane / 3) % 3 - 1, bz = b[2] + lane % 3 - 1;
+    if (bx >= 0 && bx < g.nb[0] && by >= 0 && by < g.nb[1] && bz >= 0 && bz < g.nb[2]) {
+      const int cell = P.bin_base + (bx * g.nb[1] + by) * g.nb[2] + bz;
+      c0 = cell_start[cell];
+      cn = cell_start[cell + 1] - c0;
+    }
+  }
+  int incl = cn;  // inclusive prefix of the bin sizes over lanes
+  for (int o = 1; o < 32; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  const int total = __shfl(incl, 26);
   int w = FILL ? row_ptr[k] : 0;
-  for (int bx = max(b[0] - 1, 0); bx <= min(b[0] + 1, g.nb[0] - 1); ++bx)
-    for (int by = max(b[1] - 1, 0); by <= min(b[1] + 1, g.nb[1] - 1); ++by)
-      for (int bz = max(b[2] - 1, 0); bz <= min(b[2] + 1, g.nb[2] - 1); ++bz) {
-        int cell = P.bin_base + (bx * g.nb[1] + by) * g.nb[2] + bz;
-        for (int q = cell_start[cell]; q < cell_start[cell + 1]; ++q) {
-          int s = cell_items[q];
-          if (s == k) continue;
-          double dx = pos_ext[3 * s] - p[0], dy = pos_ext[3 * s + 1] - p[1],
-                 dz = pos_ext[3 * s + 2] - p[2];
-          double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < rc2) {
-            if (!FILL && r2 < 1e-16) atomicOr(err, 2);
-            if (FILL) {
-              src[w] = s;
-              recv[w] = k;
-              ++w;
-            } else {
-              ++c;
-            }
-          }
-        }
+  int c = 0;
+  for (int v0 = 0; v0 < total; v0 += 64) {
+    const int v = v0 + lane;
+    const int vc = min(v, total - 1);  // every lane takes part in the cross-lane reads
+    int j = 0;                          // first bin whose inclusive prefix exceeds vc
+    for (int step = 16; step > 0; step >>= 1) {
+      const int t = __shfl(incl, j + step - 1);
+      if (j + step - 1 < 27 && t <= vc) j += step;
+    }
+    const int first = __shfl(incl, j) - __shfl(cn, j);
+    const int q = __shfl(c0, j) + (vc - first);
+    bool hit = false;
+    int s = 0;
+    if (v < total) {
+      s = cell_items[q];
+      if (s != k) {
+        const double dx = pos_ext[3 * s] - p0, dy = pos_ext[3 * s + 1] - p1,
+                     dz = pos_ext[3 * s + 2] - p2;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        hit = r2 < rc2;
+        if (!FILL && hit && r2 < 1e-16) atomicOr(err, 2);
       }
-  if (!FILL) count[k] = c;
+    }
+    const unsigned long long m = __ballot(hit);
+    if (FILL) {
+      if (hit) {
+        const int at = w + __popcll(m & ((1ull << lane) - 1ull));
+        src[at] = s;
+        recv[at] = k;
+      }
+      w += __popcll(m);
+    } else {
+      c += __popcll(m);
+    }
+  }
+  if (!FILL && lane == 0) count[k] = c;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -301,7 +376,7 @@ void launch_scatter_keys(int n, const int* key, const int* start, int* cursor, i
   if (n > 0) k_scatter_keys<<<nblk(n, 256), 256, 0, s>>>(n, key, start, cursor, items);
 }
 void launch_sort_segments(int nseg, const int* start, int* items, hipStream_t s) {
-  if (nseg > 0) k_sort_segments<<<nblk(nseg, 128), 128, 0, s>>>(nseg, start, items);
+  if (nseg > 0) k_sort_segments<<<nblk(nseg, 4), 256, 0, s>>>(nseg, start, items);
 }
 void launch_gather_local(int n, const int* order, const double* posw, const double* frac,
                          const int* spec_orig, const int* sid_orig, double* pos_ext,
@@ -329,7 +404,7 @@ void launch_edge_count(int n, const double* pos_ext, const double* frac_ext, con
                        const StructParams* sp, const int* cell_start, const int* cell_items,
                        double rc2, int* count, int* err, hipStream_t s) {
   if (n > 0)
-    k_edges<false><<<nblk(n, 128), 128, 0, s>>>(n, pos_ext, frac_ext, sid, sp, cell_start,
+    k_edges<false><<<nblk(n, 4), 256, 0, s>>>(n, pos_ext, frac_ext, sid, sp, cell_start,
                                                  cell_items, rc2, count, err, nullptr, nullptr,
                                                  nullptr);
 }
@@ -337,7 +412,7 @@ void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, cons
                       const StructParams* sp, const int* cell_start, const int* cell_items,
                       double rc2, const int* row_ptr, int* src, int* recv, hipStream_t s) {
   if (n > 0)
-    k_edges<true><<<nblk(n, 128), 128, 0, s>>>(n, pos_ext, frac_ext, sid, sp, cell_start,
+    k_edges<true><<<nblk(n, 4), 256, 0, s>>>(n, pos_ext, frac_ext, sid, sp, cell_start,
                                                 cell_items, rc2, nullptr, nullptr, row_ptr, src,
                                                 recv);
 }
@@ -351,33 +426,42 @@ namespace sn {
 // image of i shifted by -shift(s) (the local atom i itself when s is local).  Found by a
 // scan of o's receiver segment; -1 when no such edge exists (possible only when the two
 // directions round to different sides of r_c).
-__global__ void k_reverse(int64_t E, int n_local, const int* __restrict__ recv,
-                          const int* __restrict__ src, const int* __restrict__ row_ptr,
-                          const int* __restrict__ owner, const int* __restrict__ shift,
-                          int* __restrict__ rev) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
-  const int i = recv[e], s = src[e];
-  int o = s, sx = 0, sy = 0, sz = 0;
-  if (s >= n_local) {
-    const int g = s - n_local;
-    o = owner[g];
-    sx = shift[3 * g];
-    sy = shift[3 * g + 1];
-    sz = shift[3 * g + 2];
-  }
-  int found = -1;
-  for (int q = row_ptr[o]; q < row_ptr[o + 1]; ++q) {
-    const int t = src[q];
-    if (t < n_local) {
-      if (t == i && sx == 0 && sy == 0 && sz == 0) { found = q; break; }
-    } else {
-      const int g = t - n_local;
-      if (owner[g] == i && shift[3 * g] == -sx && shift[3 * g + 1] == -sy &&
-          shift[3 * g + 2] == -sz) { found = q; break; }
+__global__ __launch_bounds__(256) void k_reverse(int64_t E, int n_local, const int* __restrict__ recv,
+                                                 const int* __restrict__ src,
+                                                 const int* __restrict__ row_ptr,
+                                                 const int* __restrict__ owner,
+                                                 const int* __restrict__ shift,
+                                                 int* __restrict__ rev) {
+  // 16 lanes per edge search o's segment together; the match is unique, the group keeps
+  // the smallest index found
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sub = threadIdx.x & 15;
+  int found = INT_MAX;
+  if (e < E) {
+    const int i = recv[e], s = src[e];
+    int o = s, sx = 0, sy = 0, sz = 0;
+    if (s >= n_local) {
+      const int g = s - n_local;
+      o = owner[g];
+      sx = shift[3 * g];
+      sy = shift[3 * g + 1];
+      sz = shift[3 * g + 2];
+    }
+    for (int q = row_ptr[o] + sub; q < row_ptr[o + 1]; q += 16) {
+      const int t = src[q];
+      bool match;
+      if (t < n_local) {
+        match = t == i && sx == 0 && sy == 0 && sz == 0;
+      } else {
+        const int g = t - n_local;
+        match = owner[g] == i && shift[3 * g] == -sx && shift[3 * g + 1] == -sy &&
+                shift[3 * g + 2] == -sz;
+      }
+      if (match) found = min(found, q);
     }
   }
-  rev[e] = found;
+  for (int off = 1; off < 16; off <<= 1) found = min(found, __shfl_xor(found, off));
+  if (e < E && sub == 0) rev[e] = found == INT_MAX ? -1 : found;
 }
 
 __global__ void k_canon_flags(int64_t E, const int* __restrict__ rev, int* __restrict__ flag) {
@@ -413,7 +497,8 @@ void launch_pairs(int64_t E, int n_local, const int* recv, const int* src, const
     return;
   }
   const unsigned g = (unsigned)((E + 255) / 256);
-  k_reverse<<<g, 256, 0, s>>>(E, n_local, recv, src, row_ptr, owner, shift, rev);
+  k_reverse<<<(unsigned)((16 * E + 255) / 256), 256, 0, s>>>(E, n_local, recv, src, row_ptr,
+                                                             owner, shift, rev);
   k_canon_flags<<<g, 256, 0, s>>>(E, rev, flag);
   scan_exclusive(flag, fscan, E, tmp, s);
   k_pairs<<<g, 256, 0, s>>>(E, rev, flag, fscan, pidx, pe1, pe2);

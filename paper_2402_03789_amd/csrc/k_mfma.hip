@@ -174,22 +174,26 @@ __device__ inline void ld4<double>(const double* p, float (&v)[4]) {
   v[0] = (float)a[0]; v[1] = (float)a[1]; v[2] = (float)b[0]; v[3] = (float)b[1];
 }
 
-template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN>
-__global__ __launch_bounds__(256) void k_gemm_mfma_v(int64_t M, int N, int K, const TA* __restrict__ A,
-                                                      RowMap am, const TB* __restrict__ B, int ldb,
-                                                      TC* __restrict__ C, RowMap cm, float alpha,
-                                                      int accumulate, int nbn, int64_t ntiles,
-                                                      int64_t chunk) {
-  constexpr int BM = 64, BK = 32;
-  constexpr int SP = BF16 ? BK + 8 : BK + 4;  // LDS row stride (16-byte aligned rows)
+template <bool BF16, int BN>
+struct VTileLds {
+  static constexpr int BM = 64, BK = 32;
+  static constexpr int SP = BF16 ? BK + 8 : BK + 4;  // LDS row stride (16-byte aligned rows)
   using ST = typename std::conditional<BF16, __bf16, float>::type;
-  __shared__ __attribute__((aligned(16))) ST As[2][BM][SP];
-  __shared__ __attribute__((aligned(16))) ST Bs[2][BN][SP];  // stored [n][k]
-  const int64_t p = blockIdx.x;
-  const int64_t tile = (p % 8) * chunk + p / 8;
-  if (tile >= ntiles) return;
-  const int64_t m0 = (tile / nbn) * BM;
-  const int n0 = (int)(tile % nbn) * BN;
+  ST a[2][BM][SP];
+  ST b[2][BN][SP];  // stored [n][k]
+};
+
+// one 64 x BN output tile (rows m0.., columns n0..) of C (=|+=) alpha * A op(B)
+template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN>
+__device__ inline void gemm_v_tile(int64_t M, int N, int K, const TA* __restrict__ A, RowMap am,
+                                   const TB* __restrict__ B, int ldb, TC* __restrict__ C, RowMap cm,
+                                   float alpha, int accumulate, int64_t m0, int n0,
+                                   VTileLds<BF16, BN>& L) {
+  constexpr int BM = 64, BK = 32;
+  using ST = typename VTileLds<BF16, BN>::ST;
+  auto& As = L.a;
+  auto& Bs = L.b;
+  (void)BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int TM = BN == 64 ? 2 : 1;  // 16-row tiles per wave
   const int wr = BN == 64 ? (wave >> 1) * 32 : wave * 16;
@@ -306,6 +310,45 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_v(int64_t M, int N, int K, co
     }
 }
 
+template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN>
+__global__ __launch_bounds__(256) void k_gemm_mfma_v(int64_t M, int N, int K, const TA* __restrict__ A,
+                                                      RowMap am, const TB* __restrict__ B, int ldb,
+                                                      TC* __restrict__ C, RowMap cm, float alpha,
+                                                      int accumulate, int nbn, int64_t ntiles,
+                                                      int64_t chunk) {
+  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN> lds;
+  const int64_t p = blockIdx.x;
+  const int64_t tile = (p % 8) * chunk + p / 8;
+  if (tile >= ntiles) return;
+  gemm_v_tile<TA, TB, TC, BT, BF16, BN>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
+                                        (tile / nbn) * 64, (int)(tile % nbn) * BN, lds);
+}
+
+// grouped launch: problem q owns tiles [tile0[q], tile0[q + 1])
+template <typename TA, typename TB, typename TC>
+struct GemmGroupArgs {
+  GemmDesc<TA, TB, TC> d[kMaxGemmGroup];
+  int64_t tile0[kMaxGemmGroup + 1];
+  int nbn[kMaxGemmGroup];
+  int n;
+  int64_t chunk;
+};
+
+template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN>
+__global__ __launch_bounds__(256) void k_gemm_mfma_vg(GemmGroupArgs<TA, TB, TC> g) {
+  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN> lds;
+  const int64_t p = blockIdx.x;
+  const int64_t tile = (p % 8) * g.chunk + p / 8;
+  if (tile >= g.tile0[g.n]) return;
+  int q = 0;
+  while (q + 1 < g.n && tile >= g.tile0[q + 1]) ++q;
+  const GemmDesc<TA, TB, TC>& d = g.d[q];
+  const int64_t t = tile - g.tile0[q];
+  gemm_v_tile<TA, TB, TC, BT, BF16, BN>(d.M, d.N, d.K, d.A, d.am, d.B, d.ldb, d.C, d.cm,
+                                        (float)d.alpha, d.accumulate, (t / g.nbn[q]) * 64,
+                                        (int)(t % g.nbn[q]) * BN, lds);
+}
+
 template <typename T>
 static bool aligned16(const T* p, int64_t a, int64_t b, int64_t c) {
   constexpr int64_t q = 16 / sizeof(T);
@@ -354,10 +397,56 @@ void launch_gemm_mfma(int64_t M, int N, int K, const TA* A, RowMap am, const TB*
 #undef SN_L
 }
 
+template <typename TA, typename TB, typename TC>
+void launch_gemm_mfma_group(int n, const GemmDesc<TA, TB, TC>* d, bool bt, bool bf16, hipStream_t s) {
+  GemmGroupArgs<TA, TB, TC> g{};
+  bool vec = n <= kMaxGemmGroup;
+  bool narrow = true;
+  for (int q = 0; q < n && vec; ++q) {
+    if (d[q].M <= 0 || d[q].N <= 0) continue;
+    vec = d[q].K % 8 == 0 && d[q].N % 8 == 0 &&
+          aligned16(d[q].A, d[q].am.stride, d[q].am.off, d[q].am.nm > 1 ? d[q].am.ld : 0) &&
+          aligned16(d[q].B, d[q].ldb, 0, 0);
+    narrow = narrow && d[q].N <= 32;
+    g.d[g.n++] = d[q];
+  }
+  int64_t tiles = 0;
+  for (int q = 0; q < g.n; ++q)
+    tiles += ((g.d[q].M + 63) / 64) * ((g.d[q].N + (narrow ? 31 : 63)) / (narrow ? 32 : 64));
+  // grouping pays where the problems are too small to fill the chip one at a time; larger
+  // ones keep their own launches (and the overlap with the second stream they were tuned for)
+  if (!vec || g.n <= 1 || tiles > kGroupMaxTiles) {  // one launch per problem
+    for (int q = 0; q < n; ++q)
+      launch_gemm_mfma<TA, TB, TC>(d[q].M, d[q].N, d[q].K, d[q].A, d[q].am, d[q].B, d[q].ldb, bt,
+                                   d[q].C, d[q].cm, (float)d[q].alpha, d[q].accumulate != 0, bf16,
+                                   s);
+    return;
+  }
+  const int bn = narrow ? 32 : 64;
+  g.tile0[0] = 0;
+  for (int q = 0; q < g.n; ++q) {
+    g.nbn[q] = (g.d[q].N + bn - 1) / bn;
+    g.tile0[q + 1] = g.tile0[q] + ((g.d[q].M + 63) / 64) * g.nbn[q];
+  }
+  g.chunk = (g.tile0[g.n] + 7) / 8;
+  const unsigned grid = (unsigned)(g.chunk * 8);
+#define SN_G(BTV, BFV, BNV) k_gemm_mfma_vg<TA, TB, TC, BTV, BFV, BNV><<<grid, 256, 0, s>>>(g)
+  if (bn == 32) {
+    if (bt) { if (bf16) SN_G(true, true, 32); else SN_G(true, false, 32); }
+    else { if (bf16) SN_G(false, true, 32); else SN_G(false, false, 32); }
+  } else {
+    if (bt) { if (bf16) SN_G(true, true, 64); else SN_G(true, false, 64); }
+    else { if (bf16) SN_G(false, true, 64); else SN_G(false, false, 64); }
+  }
+#undef SN_G
+}
+
 #define SN_MFMA_INST(TA, TB, TC)                                                               \
   template void launch_gemm_mfma<TA, TB, TC>(int64_t, int, int, const TA*, RowMap, const TB*,   \
                                              int, bool, TC*, RowMap, float, bool, bool,         \
-                                             hipStream_t);
+                                             hipStream_t);                                     \
+  template void launch_gemm_mfma_group<TA, TB, TC>(int, const GemmDesc<TA, TB, TC>*, bool, bool, \
+                                                   hipStream_t);
 SN_MFMA_INST(float, float, float)
 SN_MFMA_INST(float, float, double)
 SN_MFMA_INST(double, float, float)

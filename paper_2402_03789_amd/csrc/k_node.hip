@@ -173,26 +173,35 @@ __global__ void k_dY_reduce(int64_t E, int n_tasks, int NY, const T* __restrict_
 }
 
 // F_k = sum_{e: recv=k} g_e - sum_{e: send=k} g_e - sum_{ghosts of k} sum_{e: send=ghost} g_e
-__global__ void k_forces(int n_local, const int* __restrict__ row_ptr, const int* __restrict__ sptr,
-                         const int* __restrict__ sidx, const int* __restrict__ gptr,
-                         const double* __restrict__ g, double* __restrict__ F) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
+// F_k = sum of g over k's receiver edges - sum over the edges k and its ghost images send;
+// one wave per atom, lanes over the edge lists, combined by a fixed butterfly
+__global__ __launch_bounds__(256) void k_forces(int n_local, const int* __restrict__ row_ptr,
+                                                const int* __restrict__ sptr,
+                                                const int* __restrict__ sidx,
+                                                const int* __restrict__ gptr,
+                                                const double* __restrict__ g,
+                                                double* __restrict__ F) {
+  const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (k >= n_local) return;
+  const int lane = threadIdx.x & 63;
   double f[3] = {0, 0, 0};
-  for (int e = row_ptr[k]; e < row_ptr[k + 1]; ++e)
+  for (int e = row_ptr[k] + lane; e < row_ptr[k + 1]; e += 64)
     for (int a = 0; a < 3; ++a) f[a] += g[3 * (int64_t)e + a];
-  for (int q = sptr[k]; q < sptr[k + 1]; ++q) {
-    int64_t e = sidx[q];
+  for (int q = sptr[k] + lane; q < sptr[k + 1]; q += 64) {
+    const int64_t e = sidx[q];
     for (int a = 0; a < 3; ++a) f[a] -= g[3 * e + a];
   }
   for (int gh = gptr[k]; gh < gptr[k + 1]; ++gh) {
-    int s = n_local + gh;
-    for (int q = sptr[s]; q < sptr[s + 1]; ++q) {
-      int64_t e = sidx[q];
+    const int s = n_local + gh;
+    for (int q = sptr[s] + lane; q < sptr[s + 1]; q += 64) {
+      const int64_t e = sidx[q];
       for (int a = 0; a < 3; ++a) f[a] -= g[3 * e + a];
     }
   }
-  for (int a = 0; a < 3; ++a) F[3 * (int64_t)k + a] = f[a];
+  for (int off = 32; off > 0; off >>= 1)
+    for (int a = 0; a < 3; ++a) f[a] += __shfl_xor(f[a], off);
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) F[3 * (int64_t)k + a] = f[a];
 }
 
 constexpr int kRedThreads = 256;
@@ -459,7 +468,7 @@ void launch_dY_reduce(int64_t E, int n_tasks, int NY, const T* part, T* dY, bool
 }
 void launch_forces(int n_local, const int* row_ptr, const int* sptr, const int* sidx, const int* gptr,
                    const double* g, double* F, hipStream_t s) {
-  if (n_local > 0) k_forces<<<nblk(n_local, 128), 128, 0, s>>>(n_local, row_ptr, sptr, sidx, gptr, g, F);
+  if (n_local > 0) k_forces<<<nblk(n_local, 4), 256, 0, s>>>(n_local, row_ptr, sptr, sidx, gptr, g, F);
 }
 void launch_seg_energy(int nchunks, const int* chunks, const double* atom_e, double* partial,
                        hipStream_t s) {

@@ -84,6 +84,7 @@ struct TPArgs {
   const int* src;
   const int* pidx;  // 2 p + side: pair p holds the shared radial weights, 2 p + side the dE/dw row
   int n_recv;
+  int split_log;    // adjoint: 2^split_log waves share a receiver's edges (contiguous slices)
   int Dx, P, Dm, NY;
   TPDeg d;
 };
@@ -93,6 +94,7 @@ template <int L1>
 struct CPL { static constexpr int value = L1 == 0 ? 2 : 1; };
 
 constexpr int kRecvPerBlock = 4;  // one wave per receiver
+constexpr int kSplitWaves = 2048;  // adjoint waves wanted before a receiver's edges are split
 
 // t[m3] = sum_{m1,m2} C[m1,m2,m3] x[m1] Y[m2] of one path (l1, l2, l3) for one edge and one
 // channel; each path's t is formed where it is used, so at most 2 l3 + 1 of them are live
@@ -313,7 +315,11 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   constexpr int NO = PL::NOUT;
   constexpr int KC = CPL<L1>::value;
   // receiver of this wave (wave-uniform; kept in a scalar register)
-  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kRecvPerBlock + (threadIdx.x >> 6));
+  // receiver of this wave and its slice of the receiver's edges (wave-uniform; scalar
+  // registers).  Every edge's outputs depend on that edge and G alone, so slices need no
+  // combining; small graphs use several waves per receiver to fill the chip.
+  const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kRecvPerBlock + (threadIdx.x >> 6));
+  const int i = task >> g.split_log;
   if (i >= g.n_recv) return;
   const TPDeg& a = g.d;
   const int lane = threadIdx.x & 63;
@@ -334,7 +340,13 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
         gin[c][oo + m3] = ok ? G[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u] : T(0);
     });
   }
-  const int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
+  int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
+  if (g.split_log) {
+    const int len = (end - beg + (1 << g.split_log) - 1) >> g.split_log;
+    const int b0 = min(end, beg + (task & ((1 << g.split_log) - 1)) * len);
+    end = min(end, b0 + len);
+    beg = b0;
+  }
   const int n_it = (end - beg + EI - 1) / EI;
   if (n_it == 0) return;
   int uc[KC];
@@ -467,7 +479,8 @@ static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const 
     else launch_fwd<T, S, L1, LSH, LMX, SO, 0>(a, Y, x, w, M, inv_k, s);
     return;
   }
-  const unsigned grid = (unsigned)((a.n_recv + kRecvPerBlock - 1) / kRecvPerBlock);
+  const unsigned grid =
+      (unsigned)((((int64_t)a.n_recv << a.split_log) + kRecvPerBlock - 1) / kRecvPerBlock);
   const unsigned block = kWave * kRecvPerBlock;
   if (dxe)
     k_tp_bwd<T, S, L1, LSH, LMX, SO, true, 0><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
@@ -483,7 +496,10 @@ static void run(const TPLayer& L, bool fwd, int n_recv, const int* row_ptr, cons
   bool first = true;
   for (int l1 = 0; l1 <= L.lmax; ++l1) {
     if (L.xin.mul[l1] == 0) continue;
-    const TPArgs a = make_args(L, l1, n_recv, row_ptr, src, pidx);
+    TPArgs a = make_args(L, l1, n_recv, row_ptr, src, pidx);
+    // adjoint of a small graph: up to eight waves per receiver until about 2,048 waves run
+    if (!fwd)
+      while ((n_recv << a.split_log) < kSplitWaves && a.split_log < 3) ++a.split_log;
     const int acc = (accumulate || !first) ? 1 : 0;
     first = false;
 #define SN_TP_CASE(LL1, LSH, LMX, SO)                                                        \

@@ -85,6 +85,30 @@ template <typename TA, typename TB, typename TC>
 void launch_gemm_mfma(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, int ldb, bool bt,
                       TC* C, RowMap cm, float alpha, bool accumulate, bool bf16, hipStream_t s);
 
+// Several independent contractions of the same operand types and B layout in one launch
+// (the per-degree blocks of one channel-mixing layer): every problem's tiles are spread
+// over the grid together.  Each problem is computed exactly as by the single launches.
+template <typename TA, typename TB, typename TC>
+struct GemmDesc {
+  int64_t M;
+  int N, K;
+  const TA* A;
+  RowMap am;
+  const TB* B;
+  int ldb;
+  TC* C;
+  RowMap cm;
+  double alpha;
+  int accumulate;
+};
+constexpr int kMaxGemmGroup = 4;
+constexpr int64_t kGroupMaxTiles = 1024;  // larger groups launch problem by problem
+template <typename TA, typename TB, typename TC, typename TACC>
+void launch_gemm_group(int n, const GemmDesc<TA, TB, TC>* d, bool bt, bool bf16_operands,
+                       hipStream_t s);
+template <typename TA, typename TB, typename TC>
+void launch_gemm_mfma_group(int n, const GemmDesc<TA, TB, TC>* d, bool bt, bool bf16, hipStream_t s);
+
 // Vector-unit radial-MLP hidden layers over pairs (float64 form): rows of rho and drho
 // are taken at rows[p].
 template <typename T>

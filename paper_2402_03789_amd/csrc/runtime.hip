@@ -817,6 +817,23 @@ struct Pipe {
     }
   }
 
+  // the per-degree contractions of one channel-mixing layer as one grouped launch (same
+  // dispatch rule as gemm())
+  template <typename TA, typename TB, typename TC>
+  GemmDesc<TA, TB, TC> gd(int64_t rows, int N, int K, const TA* A, RowMap am, int64_t woff, int ldb,
+                          TC* C, RowMap cm, double alpha, bool acc) {
+    return GemmDesc<TA, TB, TC>{rows, N, K, A, am, W<TB>(c, woff), ldb, C, cm, alpha, acc ? 1 : 0};
+  }
+  template <typename TA, typename TB, typename TC, typename TACC>
+  void gemm_group(const std::vector<GemmDesc<TA, TB, TC>>& d, bool bt) {
+    if (d.empty()) return;
+    const int n = (int)d.size();
+    if (std::is_same<TC, bf16_t>::value || bf16 || std::is_same<TACC, float>::value)
+      launch_gemm_mfma_group<TA, TB, TC>(n, d.data(), bt, bf16, s);
+    else
+      launch_gemm_group<TA, TB, TC, TACC>(n, d.data(), bt, false, s);
+  }
+
   // panels of block L's output weights for the fused kernels (the transposed bfloat16
   // copy for the bfloat16 forward)
   template <typename WS>
@@ -907,30 +924,45 @@ struct Pipe {
       double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
       const int xrows = (t == 0) ? NE : N;  // block 1: ghosts from their own species
       // Lin1 accumulates in the edge type: x only feeds the tensor product, which runs in it
-      for (int l : L.ins)
-        gemm<double, T, S, T>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
-                              rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], false, x,
-                              rows_of(L.hin, l), T(1), false);
+      {
+        std::vector<GemmDesc<double, T, S>> g;
+        for (int l : L.ins)
+          g.push_back(gd<double, T, S>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
+                                       rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], x,
+                                       rows_of(L.hin, l), 1.0, false));
+        gemm_group<double, T, S, T>(g, false);
+      }
       if (t > 0) {
         c->mark("layer" + ts + ".ghost_refresh");
         launch_ghost_refresh<S>(N, G, owner, x, L.hin.width, s);
       }
       c->mark("layer" + ts + ".linsc");
-      for (int l : L.ins)
-        if (L.gmul[l] > 0)
-          gemm<double, double, double, double>((int64_t)N * (2 * l + 1), L.gmul[l], L.hin.mul[l], h,
-                                               rows_of(L.hin, l), L.w_linsc[l], L.gmul[l], false, y,
-                                               rows_of(L.yl, l), 1.0, false);
+      {
+        std::vector<GemmDesc<double, double, double>> g;
+        for (int l : L.ins)
+          if (L.gmul[l] > 0)
+            g.push_back(gd<double, double, double>((int64_t)N * (2 * l + 1), L.gmul[l],
+                                                   L.hin.mul[l], h, rows_of(L.hin, l),
+                                                   L.w_linsc[l], L.gmul[l], y, rows_of(L.yl, l),
+                                                   1.0, false));
+        gemm_group<double, double, double, double>(g, false);
+      }
       S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("layer" + ts + ".tp");
       HIPCHK(hipStreamWaitEvent(s, w_ready[t], 0));
       T* M = c->get<T>("M", (int64_t)N * L.ml.width);
       launch_tp_fwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, M, (T)(1.0 / m->kavg), s);
       c->mark("layer" + ts + ".linear_out");
-      for (int l : L.outs) {
-        const bool has_sc = std::find(L.ins.begin(), L.ins.end(), l) != L.ins.end() && L.gmul[l] > 0;
-        gemm<T, T, double, T>((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M, rows_of(L.ml, l),
-                              L.w_lin2[l], L.gmul[l], false, y, rows_of(L.yl, l), T(1), has_sc);
+      {
+        std::vector<GemmDesc<T, T, double>> g;
+        for (int l : L.outs) {
+          const bool has_sc =
+              std::find(L.ins.begin(), L.ins.end(), l) != L.ins.end() && L.gmul[l] > 0;
+          g.push_back(gd<T, T, double>((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M,
+                                       rows_of(L.ml, l), L.w_lin2[l], L.gmul[l], y,
+                                       rows_of(L.yl, l), 1.0, has_sc));
+        }
+        gemm_group<T, T, double, T>(g, false);
       }
       double* hn = c->get<double>(t % 2 ? "h_a" : "h_b", (int64_t)N * L.hout.width);
       launch_gate_fwd<double>(N, L.last, L.yl, L.hout, y, hn, m->act, s);
@@ -1004,10 +1036,14 @@ struct Pipe {
       const S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("bwd.layer" + ts + ".linear_out");
       launch_gate_bwd<double>(N, L.last, L.yl, L.hout, y, dh, dy, m->act, s);
-      for (int l : L.outs)
-        gemm<double, T, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy, rows_of(L.yl, l),
-                              L.w_lin2[l], L.gmul[l], true, Gm, rows_of(L.ml, l),
-                              (T)(1.0 / m->kavg), false);
+      {
+        std::vector<GemmDesc<double, T, T>> g;
+        for (int l : L.outs)
+          g.push_back(gd<double, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy,
+                                       rows_of(L.yl, l), L.w_lin2[l], L.gmul[l], Gm,
+                                       rows_of(L.ml, l), 1.0 / m->kavg, false));
+        gemm_group<double, T, T, T>(g, true);
+      }
       S* dw = dw_buf[t % 2];
       if (t + 2 < m->T) {  // dw_buf[t % 2] is free once the MLP adjoint of block t + 2 is done
         c->mark("bwd.layer" + ts + ".mlp_wait");
@@ -1031,14 +1067,20 @@ struct Pipe {
       launch_sender_reduce<S>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
       launch_ghost_fold<double>(N, gptr, dx_ext, dx, L.hin.width, s);
       c->mark("bwd.layer" + ts + ".linear_in");
-      for (int l : L.ins) {
-        gemm<double, T, double, T>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], dx,
-                                   rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], true, dh_other,
-                                   rows_of(L.hin, l), T(1), false);
-        if (L.gmul[l] > 0)
-          gemm<double, T, double, T>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], dy,
-                                     rows_of(L.yl, l), L.w_linsc[l], L.gmul[l], true, dh_other,
-                                     rows_of(L.hin, l), T(1), true);
+      {
+        // dh = dx Lin1^T (all degrees), then += dy Linsc^T (all degrees)
+        std::vector<GemmDesc<double, T, double>> g1, g2;
+        for (int l : L.ins) {
+          g1.push_back(gd<double, T, double>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l],
+                                             dx, rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l],
+                                             dh_other, rows_of(L.hin, l), 1.0, false));
+          if (L.gmul[l] > 0)
+            g2.push_back(gd<double, T, double>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l],
+                                               dy, rows_of(L.yl, l), L.w_linsc[l], L.gmul[l],
+                                               dh_other, rows_of(L.hin, l), 1.0, true));
+        }
+        gemm_group<double, T, double, T>(g1, true);
+        gemm_group<double, T, double, T>(g2, true);
       }
       std::swap(dh, dh_other);
     }
