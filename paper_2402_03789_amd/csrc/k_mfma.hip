@@ -174,26 +174,26 @@ __device__ inline void ld4<double>(const double* p, float (&v)[4]) {
   v[0] = (float)a[0]; v[1] = (float)a[1]; v[2] = (float)b[0]; v[3] = (float)b[1];
 }
 
-template <bool BF16, int BN>
+template <bool BF16, int BN, int BK>
 struct VTileLds {
-  static constexpr int BM = 64, BK = 32;
+  static constexpr int BM = 64;
   static constexpr int SP = BF16 ? BK + 8 : BK + 4;  // LDS row stride (16-byte aligned rows)
   using ST = typename std::conditional<BF16, __bf16, float>::type;
   ST a[2][BM][SP];
   ST b[2][BN][SP];  // stored [n][k]
 };
 
-// one 64 x BN output tile (rows m0.., columns n0..) of C (=|+=) alpha * A op(B)
-template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN>
+// one 64 x BN output tile (rows m0.., columns n0..) of C (=|+=) alpha * A op(B) in k-slabs of
+// BK (a multiple of 32); each output element accumulates over k in the same order for any
+// slab width.
+template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN, int BK>
 __device__ inline void gemm_v_tile(int64_t M, int N, int K, const TA* __restrict__ A, RowMap am,
                                    const TB* __restrict__ B, int ldb, TC* __restrict__ C, RowMap cm,
                                    float alpha, int accumulate, int64_t m0, int n0,
-                                   VTileLds<BF16, BN>& L) {
-  constexpr int BM = 64, BK = 32;
-  using ST = typename VTileLds<BF16, BN>::ST;
+                                   VTileLds<BF16, BN, BK>& L) {
+  using ST = typename VTileLds<BF16, BN, BK>::ST;
   auto& As = L.a;
   auto& Bs = L.b;
-  (void)BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int TM = BN == 64 ? 2 : 1;  // 16-row tiles per wave
   const int wr = BN == 64 ? (wave >> 1) * 32 : wave * 16;
@@ -203,12 +203,13 @@ __device__ inline void gemm_v_tile(int64_t M, int N, int K, const TA* __restrict
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // A: thread covers row tid/4, k = 8 (tid%4) .. +7
-  const int ar = tid >> 2, ak = (tid & 3) * 8;
+  // A: thread covers row tid/4, k = AE (tid%4) .. + AE - 1
+  constexpr int AE = BK / 4;
+  const int ar = tid >> 2, ak = (tid & 3) * AE;
   const bool a_ok = m0 + ar < M;
   const TA* a_src = A + (a_ok ? am(m0 + ar) : 0) + ak;
   // B: BN*BK/256 elements per thread
-  constexpr int BE = BN * BK / 256;  // 8 or 4
+  constexpr int BE = BN * BK / 256;  // 4, 8 or 16
   int bn, bk;
   if (BT) {  // B[n][k]: thread covers n, BE consecutive k
     bn = tid / (BK / BE);
@@ -217,39 +218,46 @@ __device__ inline void gemm_v_tile(int64_t M, int N, int K, const TA* __restrict
     bk = tid / (BN / BE);
     bn = (tid % (BN / BE)) * BE;
   }
-  const bool b_ok = BT ? (n0 + bn < N) : (n0 + bn < N);
   const TB* b_src = BT ? B + (int64_t)(n0 + bn) * ldb + bk : B + (int64_t)bk * ldb + n0 + bn;
-  float ra[8], rb[BE];
+  float ra[AE], rb[BE];
+  // K and N are multiples of 8, so each group of (up to) 8 values is all in or all out
   auto fetch = [&](int k0) {
     float t[4];
-    if (a_ok && k0 + ak < K) {  // K is a multiple of 8: a thread's 8 values are all in or out
-      ld4<TA>(a_src + k0, t);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ra[e] = t[e];
-      ld4<TA>(a_src + k0 + 4, t);
+    for (int h = 0; h < AE; h += 8) {
+      if (a_ok && k0 + ak + h < K) {
+        ld4<TA>(a_src + k0 + h, t);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ra[4 + e] = t[e];
-    } else {
+        for (int e = 0; e < 4; ++e) ra[h + e] = t[e];
+        ld4<TA>(a_src + k0 + h + 4, t);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ra[e] = 0.f;
-    }
-    const bool kin = k0 + bk < K;
-    if (b_ok && kin) {
-      const TB* q = BT ? b_src + k0 : b_src + (int64_t)k0 * ldb;
+        for (int e = 0; e < 4; ++e) ra[h + 4 + e] = t[e];
+      } else {
 #pragma unroll
-      for (int e = 0; e < BE; e += 4) {
-        ld4<TB>(q + e, t);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) rb[e + f] = t[f];
+        for (int e = 0; e < 8; ++e) ra[h + e] = 0.f;
       }
-    } else {
+    }
+    constexpr int CH = BE < 8 ? BE : 8;
 #pragma unroll
-      for (int e = 0; e < BE; ++e) rb[e] = 0.f;
+    for (int h = 0; h < BE; h += CH) {
+      const bool in = BT ? (n0 + bn < N && k0 + bk + h < K) : (k0 + bk < K && n0 + bn + h < N);
+      if (in) {
+        const TB* q = (BT ? b_src + k0 : b_src + (int64_t)k0 * ldb) + h;
+#pragma unroll
+        for (int e = 0; e < CH; e += 4) {
+          ld4<TB>(q + e, t);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) rb[h + e + f] = t[f];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < CH; ++e) rb[h + e] = 0.f;
+      }
     }
   };
   auto stage = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) As[buf][ar][ak + e] = (ST)ra[e];
+    for (int e = 0; e < AE; ++e) As[buf][ar][ak + e] = (ST)ra[e];
     if (BT) {
 #pragma unroll
       for (int e = 0; e < BE; ++e) Bs[buf][bn][bk + e] = (ST)rb[e];
@@ -266,16 +274,21 @@ __device__ inline void gemm_v_tile(int64_t M, int N, int K, const TA* __restrict
     if (k0 + BK < K) fetch(k0 + BK);
     if constexpr (BF16) {
       const int r = lane & 15, kq = (lane >> 4) * 8;
-      bf16x8 a[TM], b[2];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wr + i * 16 + r][kq]);
+      for (int kb = 0; kb < BK; kb += 32) {
+        bf16x8 a[TM], b[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wc + j * 16 + r][kq]);
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
+          a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wr + i * 16 + r][kb + kq]);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+          b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wc + j * 16 + r][kb + kq]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
     } else {
       const int r = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -316,12 +329,12 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_v(int64_t M, int N, int K, co
                                                       TC* __restrict__ C, RowMap cm, float alpha,
                                                       int accumulate, int nbn, int64_t ntiles,
                                                       int64_t chunk) {
-  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN> lds;
+  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN, 32> lds;
   const int64_t p = blockIdx.x;
   const int64_t tile = (p % 8) * chunk + p / 8;
   if (tile >= ntiles) return;
-  gemm_v_tile<TA, TB, TC, BT, BF16, BN>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
-                                        (tile / nbn) * 64, (int)(tile % nbn) * BN, lds);
+  gemm_v_tile<TA, TB, TC, BT, BF16, BN, 32>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
+                                            (tile / nbn) * 64, (int)(tile % nbn) * BN, lds);
 }
 
 // grouped launch: problem q owns tiles [tile0[q], tile0[q + 1])
@@ -336,7 +349,7 @@ struct GemmGroupArgs {
 
 template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN>
 __global__ __launch_bounds__(256) void k_gemm_mfma_vg(GemmGroupArgs<TA, TB, TC> g) {
-  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN> lds;
+  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN, 32> lds;
   const int64_t p = blockIdx.x;
   const int64_t tile = (p % 8) * g.chunk + p / 8;
   if (tile >= g.tile0[g.n]) return;
@@ -344,9 +357,9 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_vg(GemmGroupArgs<TA, TB, TC> 
   while (q + 1 < g.n && tile >= g.tile0[q + 1]) ++q;
   const GemmDesc<TA, TB, TC>& d = g.d[q];
   const int64_t t = tile - g.tile0[q];
-  gemm_v_tile<TA, TB, TC, BT, BF16, BN>(d.M, d.N, d.K, d.A, d.am, d.B, d.ldb, d.C, d.cm,
-                                        (float)d.alpha, d.accumulate, (t / g.nbn[q]) * 64,
-                                        (int)(t % g.nbn[q]) * BN, lds);
+  gemm_v_tile<TA, TB, TC, BT, BF16, BN, 32>(d.M, d.N, d.K, d.A, d.am, d.B, d.ldb, d.C, d.cm,
+                                            (float)d.alpha, d.accumulate, (t / g.nbn[q]) * 64,
+                                            (int)(t % g.nbn[q]) * BN, lds);
 }
 
 template <typename T>

@@ -28,6 +28,7 @@
 // that the 64 lanes of a fragment read hit distinct banks.
 #include "kernels.h"
 
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -209,12 +210,17 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   __shared__ __attribute__((aligned(16))) float sW[2][HID * WP];  // Wb, then Wc panels
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
+  // output panels of this block: all of them, or (few pairs) one of gridDim.y panel groups;
+  // each group recomputes the pairs' hidden layers, which are cheap next to the panels
+  const int npan = (P + HID - 1) / HID;
+  const int ppg = (npan + gridDim.y - 1) / gridDim.y;
+  const int pan0 = blockIdx.y * ppg, pan1 = min(npan, pan0 + ppg);
+  if (pan0 >= pan1) return;
   stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sW[1], sRho);
   __shared__ __attribute__((aligned(16))) __bf16 sWbT[BF16 ? HID * BP : 8];
   if (BF16) stage_wb_bf16(Wb, sWbT, nullptr);
-  const int npan = (P + HID - 1) / HID;
   PanelRegs<BF16> pr;
-  fetch_panel<BF16>(Wcp, 0, npan, tid, pr);
+  fetch_panel<BF16>(Wcp, pan0, npan, tid, pr);
   __syncthreads();
   float* Z = sZ[wave];
   floatx4 acc[4];
@@ -242,7 +248,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
     for (int s = 0; s < HID / 4; ++s) za[s] = Z[r * ZP + 4 * s + q];
   }
   int buf = 0;
-  for (int n0 = 0; n0 < P; n0 += HID) {
+  for (int n0 = pan0 * HID; n0 < min(P, pan1 * HID); n0 += HID) {
     fetch_panel<BF16>(Wcp, n0 / HID + 1, npan, tid, pr);  // in flight during the MFMAs
     __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
     const float* sf = sW[buf];
@@ -515,8 +521,11 @@ void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const fl
                           const float* Wb, const WS* Wcp, int P, float c, WS* w, hipStream_t s) {
   if (np <= 0) return;
   const unsigned grid = (unsigned)((np + EB - 1) / EB);
+  // few pairs: split the output panels over blocks until about 512 blocks run
+  const int npan = (P + HID - 1) / HID;
+  const unsigned groups = (unsigned)std::max(1, std::min<int>(npan, (int)((512 + grid - 1) / grid)));
   constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
-  k_mlp_fused_fwd<BF16><<<grid, 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wcp, P, c, w);
+  k_mlp_fused_fwd<BF16><<<dim3(grid, groups), 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wcp, P, c, w);
 }
 
 template <typename WS>

@@ -94,7 +94,6 @@ template <int L1>
 struct CPL { static constexpr int value = L1 == 0 ? 2 : 1; };
 
 constexpr int kRecvPerBlock = 4;  // one wave per receiver
-constexpr int kSplitWaves = 2048;  // adjoint waves wanted before a receiver's edges are split
 
 // t[m3] = sum_{m1,m2} C[m1,m2,m3] x[m1] Y[m2] of one path (l1, l2, l3) for one edge and one
 // channel; each path's t is formed where it is used, so at most 2 l3 + 1 of them are live
@@ -497,9 +496,7 @@ static void run(const TPLayer& L, bool fwd, int n_recv, const int* row_ptr, cons
   for (int l1 = 0; l1 <= L.lmax; ++l1) {
     if (L.xin.mul[l1] == 0) continue;
     TPArgs a = make_args(L, l1, n_recv, row_ptr, src, pidx);
-    // adjoint of a small graph: up to eight waves per receiver until about 2,048 waves run
-    if (!fwd)
-      while ((n_recv << a.split_log) < kSplitWaves && a.split_log < 3) ++a.split_log;
+    if (!fwd) a.split_log = tp_split_log(n_recv);
     const int acc = (accumulate || !first) ? 1 : 0;
     first = false;
 #define SN_TP_CASE(LL1, LSH, LMX, SO)                                                        \

@@ -170,6 +170,17 @@ template <typename T, typename S>
 void launch_tp_fwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
                    const int* pidx, const T* Y, const S* x, const S* w, T* M, T inv_k,
                    hipStream_t s);
+// The adjoint of a small graph runs 2^tp_split_log(n_recv) waves per receiver, each over a
+// contiguous slice of its edges (until about 2,048 waves run; at most 8 per receiver).
+// Every edge's adjoint outputs are computed whole by one wave, so results do not depend on
+// the split.  (The forward is not split: partial message sums would make a structure's
+// result depend on the size of the packed graph it is evaluated in.)
+constexpr int kTPSplitWaves = 2048;
+inline int tp_split_log(int n_recv) {
+  int k = 0;
+  while (n_recv > 0 && ((int64_t)n_recv << k) < kTPSplitWaves && k < 3) ++k;
+  return k;
+}
 // Adjoint: writes dE/dw [E x P], per-edge dE/dx_sender rows dxe [E x Dx] (skipped when dxe is
 // null), and dE/dY [E x NY] (added to the existing values when accumulate is set).
 template <typename T, typename S>
