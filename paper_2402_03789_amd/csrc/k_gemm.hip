@@ -7,6 +7,8 @@
 // addresses those rows inside the interleaved feature rows.
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace sn {
 
 // ------------------------------------------------------------------ generic tiled GEMM
@@ -108,6 +110,119 @@ __device__ inline void gemm_valu_tile(int64_t M, int N, int K, const TA* __restr
   }
 }
 
+// ------------------------------------------------------------------ float64 matrix cores
+// The float64-accumulated contractions (the self-connection Linsc of every form; every
+// contraction of the FP64 form) on v_mfma_f64_16x16x4_f64: 64 x 64 block tile, four waves
+// of 32 x 32 (2 x 2 MFMA tiles of 16 x 16), k-slabs of 16 staged in double-buffered LDS
+// with the next slab loaded into registers while the current one is multiplied.  Operand
+// layout (lane l): A[row l%16][k l/16], B[k l/16][col l%16]; result register r of lane l
+// holds row l/16 + 4 r of column l%16 (rows interleaved, unlike the float32 16x16x4 form).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int DK = 16;
+struct F64Lds {
+  double a[2][64][DK + 1];
+  double b[2][64][DK + 1];  // stored [n][k]
+};
+
+template <typename TA, typename TB, typename TC, bool BT>
+__device__ inline void gemm_f64_tile(int64_t M, int N, int K, const TA* __restrict__ A, RowMap am,
+                                     const TB* __restrict__ B, int ldb, TC* __restrict__ C,
+                                     RowMap cm, double alpha, int accumulate, int64_t m0, int n0,
+                                     F64Lds& L) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  // A: row tid/4, k = 4 (tid%4) .. +3; B: 64 x 16 values, 4 per thread (n tid/4, k 4 (tid%4)
+  // .. +3 when B is [n][k]; k tid/16, n 4 (tid%16) .. +3 when B is [k][n]).  Loads come from
+  // clamped addresses and are masked afterwards.
+  const int ar = tid >> 2, ak = (tid & 3) * 4;
+  const bool a_ok = m0 + ar < M;
+  const int64_t arow = a_ok ? am(m0 + ar) : 0;
+  const int bn = BT ? tid >> 2 : (tid & 15) * 4;
+  const int bk = BT ? (tid & 3) * 4 : tid >> 4;
+  double ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + ak + e;
+      const double v = (double)A[arow + min(k, K - 1)];
+      ra[e] = (a_ok && k < K) ? v : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int n = n0 + bn + (BT ? 0 : e), k = k0 + bk + (BT ? e : 0);
+      const int nc = min(n, N - 1), kc = min(k, K - 1);
+      const double v = (double)(BT ? B[(int64_t)nc * ldb + kc] : B[(int64_t)kc * ldb + nc]);
+      rb[e] = (n < N && k < K) ? v : 0.0;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) L.a[buf][ar][ak + e] = ra[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (BT) L.b[buf][bn][bk + e] = rb[e];
+      else L.b[buf][bn + e][bk] = rb[e];
+    }
+  };
+  if (K > 0) fetch(0);
+  int buf = 0;
+  const int r = lane & 15, kq = lane >> 4;
+  for (int k0 = 0; k0 < K; k0 += DK) {
+    stage(buf);
+    __syncthreads();
+    if (k0 + DK < K) fetch(k0 + DK);
+#pragma unroll
+    for (int kk = 0; kk < DK; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = L.a[buf][wr + i * 16 + r][kk + kq];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = L.b[buf][wc + j * 16 + r][kk + kq];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    buf ^= 1;
+  }
+  const int row_q = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wc + j * 16 + r;
+      if (col >= N) continue;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int64_t row = m0 + wr + i * 16 + row_q + 4 * rr;
+        if (row >= M) continue;
+        TC* c = C + cm(row) + col;
+        const double v = alpha * acc[i][j][rr];
+        *c = accumulate ? (TC)((double)*c + v) : (TC)v;
+      }
+    }
+}
+
+template <typename TA, typename TB, typename TC, bool BT>
+__global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int N, int K, const TA* __restrict__ A,
+                                                   RowMap am, const TB* __restrict__ B, int ldb,
+                                                   TC* __restrict__ C, RowMap cm, double alpha,
+                                                   int accumulate, int nbn, int64_t ntiles,
+                                                   int64_t chunk) {
+  __shared__ F64Lds lds;
+  const int64_t p = blockIdx.x;
+  const int64_t tile = (p % 8) * chunk + p / 8;  // XCD-contiguous tile order
+  if (tile >= ntiles) return;
+  gemm_f64_tile<TA, TB, TC, BT>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
+                                (tile / nbn) * 64, (int)(tile % nbn) * 64, lds);
+}
+
 template <typename TA, typename TB, typename TC, typename TACC, bool BT>
 __global__ __launch_bounds__(256) void k_gemm_valu(int64_t M, int N, int K, const TA* __restrict__ A,
                                                     RowMap am, const TB* __restrict__ B, int ldb,
@@ -127,6 +242,18 @@ struct ValuGroupArgs {
   int n;
 };
 
+template <typename TA, typename TB, typename TC, bool BT>
+__global__ __launch_bounds__(256) void k_gemm_f64_g(ValuGroupArgs<TA, TB, TC> g) {
+  __shared__ F64Lds lds;
+  const int64_t tile = blockIdx.x;
+  int q = 0;
+  while (q + 1 < g.n && tile >= g.tile0[q + 1]) ++q;
+  const GemmDesc<TA, TB, TC>& d = g.d[q];
+  const int64_t t = tile - g.tile0[q];
+  gemm_f64_tile<TA, TB, TC, BT>(d.M, d.N, d.K, d.A, d.am, d.B, d.ldb, d.C, d.cm, d.alpha,
+                                d.accumulate, (t / g.nbn[q]) * GT, (int)(t % g.nbn[q]) * GT, lds);
+}
+
 template <typename TA, typename TB, typename TC, typename TACC, bool BT>
 __global__ __launch_bounds__(256) void k_gemm_valu_g(ValuGroupArgs<TA, TB, TC> g, int bf16) {
   __shared__ ValuLds<TACC> lds;
@@ -144,6 +271,19 @@ template <typename TA, typename TB, typename TC, typename TACC>
 void launch_gemm(int64_t M, int N, int K, const TA* A, RowMap am, const TB* B, int ldb, bool bt,
                  TC* C, RowMap cm, TACC alpha, bool accumulate, bool bf16_operands, hipStream_t s) {
   if (M <= 0 || N <= 0) return;
+  if (std::is_same<TACC, double>::value && !bf16_operands) {  // float64 matrix cores
+    const int nbn = (N + 63) / 64;
+    const int64_t ntiles = ((M + 63) / 64) * nbn;
+    const int64_t chunk = (ntiles + 7) / 8;
+    const unsigned g = (unsigned)(chunk * 8);
+    if (bt)
+      k_gemm_f64<TA, TB, TC, true><<<g, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, (double)alpha,
+                                                     accumulate ? 1 : 0, nbn, ntiles, chunk);
+    else
+      k_gemm_f64<TA, TB, TC, false><<<g, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, (double)alpha,
+                                                      accumulate ? 1 : 0, nbn, ntiles, chunk);
+    return;
+  }
   dim3 grid((unsigned)((M + GT - 1) / GT), (unsigned)((N + GT - 1) / GT));
   if (bt)
     k_gemm_valu<TA, TB, TC, TACC, true><<<grid, 256, 0, s>>>(M, N, K, A, am, B, ldb, C, cm, alpha,
@@ -175,6 +315,11 @@ void launch_gemm_group(int n, const GemmDesc<TA, TB, TC>* d, bool bt, bool bf16_
     g.tile0[q + 1] = g.tile0[q] + ((g.d[q].M + GT - 1) / GT) * g.nbn[q];
   }
   const unsigned grid = (unsigned)g.tile0[g.n];
+  if (std::is_same<TACC, double>::value && !bf16_operands) {
+    if (bt) k_gemm_f64_g<TA, TB, TC, true><<<grid, 256, 0, s>>>(g);
+    else k_gemm_f64_g<TA, TB, TC, false><<<grid, 256, 0, s>>>(g);
+    return;
+  }
   if (bt)
     k_gemm_valu_g<TA, TB, TC, TACC, true><<<grid, 256, 0, s>>>(g, bf16_operands ? 1 : 0);
   else
