@@ -56,6 +56,21 @@ def _tp_blocks(spec):
     return out
 
 
+def _tp_adjoint_flops(spec, cg_nnz):
+    """Algorithmic arithmetic of the tensor-product adjoint per edge of each block: per path
+    (l1, l2, l3) and channel, t = C x Y (3 flops per CG nonzero), dE/dw = G . t (2 (2 l3 + 1)),
+    gg = w G (2 l3 + 1), dE/dx += C Y gg and dE/dY += C x gg (3 flops per nonzero each; no
+    dE/dx in the first block)."""
+    out = []
+    for t in range(spec.n_layers):
+        f = 0
+        for (l1, l2, l3) in spec._paths(t):
+            per_nz = 9 if t > 0 else 6
+            f += spec.muls[l1] * (per_nz * cg_nnz(l1, l2, l3) + 3 * (2 * l3 + 1))
+        out.append(f)
+    return out
+
+
 def _roofline_entry(kernel, nbytes, nflops, ms, traffic, peak_tf):
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
     e = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
@@ -220,6 +235,39 @@ def main():
         bytes_tp, None, tp_ms,
         _traffic("k_tp_bwd", os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_tp.hip"),
                  args.precision), None)
+    # Practical streaming ceiling of this part: a 1 GiB device-to-device copy (reads and
+    # writes 1 GiB each), timed with events on the current stream after the timed steps.
+    cbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cdst = torch.empty_like(cbuf)
+    cdst.copy_(cbuf)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        cdst.copy_(cbuf)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * cbuf.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del cbuf, cdst
+    if roofline["achieved"]:
+        roofline["copy_GBps"] = copy_gbps
+        roofline["frac_of_copy"] = roofline["achieved"] / copy_gbps
+    # The same launches against the vector ALUs: algorithmic flops per block (CG nonzeros
+    # from the library's own tables), against the published vector peak (fp32 157.3 TFLOP/s
+    # counts packed two-wide FP32 instructions, which this build does not emit, so 78.6 is
+    # the attainable ceiling; fp64 78.6).
+    import numpy as np
+
+    def cg_nnz(l1, l2, l3):
+        return int(np.count_nonzero(np.abs(sn.cg_table(l1, l2, l3)) > 1e-12))
+    flops_tp = sum(e * f for f in _tp_adjoint_flops(spec, cg_nnz)) / len(blocks)
+    alu_peak, alu_attainable = (78.6, 78.6) if args.precision == "fp64" else (157.3, 78.6)
+    alu_tf = flops_tp / (tp_ms * 1e-3) / 1e12 if tp_ms > 0 else None
+    roofline_alu = {"bound": "alu", "kernel": "k_tp_bwd (same unit)", "achieved": alu_tf,
+                    "peak": alu_peak, "unit": "TFLOP/s",
+                    "frac": alu_tf / alu_peak if alu_tf else None,
+                    "attainable_peak": alu_attainable,
+                    "attainable_frac": alu_tf / alu_attainable if alu_tf else None,
+                    "algorithmic_flops_per_launch": flops_tp, "launch_ms": tp_ms}
 
     # The radial-MLP adjoint (one launch per block, "bwd.layer<t>.mlp" on the MLP stream):
     # read dE/dw of both edges of every pair (2 b P), read rho and write drho (2 x 32 bytes).
@@ -300,6 +348,7 @@ def main():
                    "n_atoms": n, "n_ghost": g, "n_edges": e, "precision": args.precision,
                    "subdomains": list(domains)},
         "roofline": roofline,
+        "roofline_alu": roofline_alu,
         "roofline_mlp_adjoint": roofline_mlp,
         "cpu_baseline": cpu,
         "phases_ms": {k: v / args.steps for k, v in phase_ms.items()},

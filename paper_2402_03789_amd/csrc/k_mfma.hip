@@ -174,24 +174,26 @@ __device__ inline void ld4<double>(const double* p, float (&v)[4]) {
   v[0] = (float)a[0]; v[1] = (float)a[1]; v[2] = (float)b[0]; v[3] = (float)b[1];
 }
 
-template <bool BF16, int BN, int BK>
+// NBUF LDS stages: 2 (one barrier per slab) or 1 (two barriers per slab, half the LDS, so
+// twice the resident blocks per CU; the next slab is in registers either way)
+template <bool BF16, int BN, int BK, int NBUF = 2>
 struct VTileLds {
   static constexpr int BM = 64;
   static constexpr int SP = BF16 ? BK + 8 : BK + 4;  // LDS row stride (16-byte aligned rows)
   using ST = typename std::conditional<BF16, __bf16, float>::type;
-  ST a[2][BM][SP];
-  ST b[2][BN][SP];  // stored [n][k]
+  ST a[NBUF][BM][SP];
+  ST b[NBUF][BN][SP];  // stored [n][k]
 };
 
 // one 64 x BN output tile (rows m0.., columns n0..) of C (=|+=) alpha * A op(B) in k-slabs of
 // BK (a multiple of 32); each output element accumulates over k in the same order for any
 // slab width.
-template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN, int BK>
+template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN, int BK, int NBUF>
 __device__ inline void gemm_v_tile(int64_t M, int N, int K, const TA* __restrict__ A, RowMap am,
                                    const TB* __restrict__ B, int ldb, TC* __restrict__ C, RowMap cm,
                                    float alpha, int accumulate, int64_t m0, int n0,
-                                   VTileLds<BF16, BN, BK>& L) {
-  using ST = typename VTileLds<BF16, BN, BK>::ST;
+                                   VTileLds<BF16, BN, BK, NBUF>& L) {
+  using ST = typename VTileLds<BF16, BN, BK, NBUF>::ST;
   auto& As = L.a;
   auto& Bs = L.b;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -305,7 +307,8 @@ __device__ inline void gemm_v_tile(int64_t M, int N, int K, const TA* __restrict
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     }
-    buf ^= 1;
+    if (NBUF == 1) __syncthreads();  // every wave is done with the stage before it is refilled
+    buf ^= NBUF - 1;
   }
   const int col_l = lane & 15, row_q = (lane >> 4) * 4;
 #pragma unroll
@@ -329,12 +332,12 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_v(int64_t M, int N, int K, co
                                                       TC* __restrict__ C, RowMap cm, float alpha,
                                                       int accumulate, int nbn, int64_t ntiles,
                                                       int64_t chunk) {
-  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN, 32> lds;
+  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN, 32, 1> lds;
   const int64_t p = blockIdx.x;
   const int64_t tile = (p % 8) * chunk + p / 8;
   if (tile >= ntiles) return;
-  gemm_v_tile<TA, TB, TC, BT, BF16, BN, 32>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
-                                            (tile / nbn) * 64, (int)(tile % nbn) * BN, lds);
+  gemm_v_tile<TA, TB, TC, BT, BF16, BN, 32, 1>(M, N, K, A, am, B, ldb, C, cm, alpha, accumulate,
+                                               (tile / nbn) * 64, (int)(tile % nbn) * BN, lds);
 }
 
 // grouped launch: problem q owns tiles [tile0[q], tile0[q + 1])
@@ -349,7 +352,7 @@ struct GemmGroupArgs {
 
 template <typename TA, typename TB, typename TC, bool BT, bool BF16, int BN>
 __global__ __launch_bounds__(256) void k_gemm_mfma_vg(GemmGroupArgs<TA, TB, TC> g) {
-  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN, 32> lds;
+  __shared__ __attribute__((aligned(16))) VTileLds<BF16, BN, 32, 2> lds;
   const int64_t p = blockIdx.x;
   const int64_t tile = (p % 8) * g.chunk + p / 8;
   if (tile >= g.tile0[g.n]) return;
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_vg(GemmGroupArgs<TA, TB, TC> 
   while (q + 1 < g.n && tile >= g.tile0[q + 1]) ++q;
   const GemmDesc<TA, TB, TC>& d = g.d[q];
   const int64_t t = tile - g.tile0[q];
-  gemm_v_tile<TA, TB, TC, BT, BF16, BN, 32>(d.M, d.N, d.K, d.A, d.am, d.B, d.ldb, d.C, d.cm,
+  gemm_v_tile<TA, TB, TC, BT, BF16, BN, 32, 2>(d.M, d.N, d.K, d.A, d.am, d.B, d.ldb, d.C, d.cm,
                                             (float)d.alpha, d.accumulate, (t / g.nbn[q]) * 64,
                                             (int)(t % g.nbn[q]) * BN, lds);
 }
