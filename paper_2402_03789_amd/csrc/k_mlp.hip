@@ -307,6 +307,126 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   }
 }
 
+// ------------------------------------------------------------------ forward, split form
+// The FP32 form's output layer in three-part bfloat16 arithmetic: every float32 operand x
+// is written as x0 + x1 + x2 with x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1)
+// (each difference exact in float32), which carries x's 24-bit significand.  The product
+// a b is the sum of the six part products a_i b_j with i + j <= 2 (the dropped ones are
+// below 2^-24 relative), each exact in the float32 accumulation of the bfloat16 matrix
+// cores: float32-level results in 6 bfloat16 MFMAs per 32-wide k step instead of 8 float32
+// ones at an eighth of the rate.  The hidden layers (6 % of the work) stay float32.
+// Wc3 holds per panel the three parts, each transposed [c][j] (a 64 x 64 bfloat16 block).
+constexpr int kPanel3 = 3 * HID * HID;  // elements per split panel
+struct Panel3Regs {
+  u32x4 v[6];
+};
+__device__ inline void fetch_panel3(const bf16_t* __restrict__ pan, int panel, int npan, int tid,
+                                    Panel3Regs& r) {
+  const bf16_t* src = pan + (int64_t)min(panel, npan - 1) * kPanel3;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) r.v[j] = *reinterpret_cast<const u32x4*>(src + (tid + 256 * j) * 8);
+}
+// parts at lds + part * HID * BP, rows of stride BP
+__device__ inline void store_panel3(const Panel3Regs& r, int tid, __bf16* lds) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int i = (tid + 256 * j) * 8, part = i / kPanel, ii = i % kPanel;
+    *reinterpret_cast<u32x4*>(lds + part * HID * BP + (ii / HID) * BP + ii % HID) = r.v[j];
+  }
+}
+__device__ inline void split3(float v, __bf16& h0, __bf16& h1, __bf16& h2) {
+  h0 = __float2bfloat16(v);
+  const float r1 = v - (float)h0;
+  h1 = __float2bfloat16(r1);
+  h2 = __float2bfloat16(r1 - (float)h1);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fused_fwd_split(int64_t np, const int* __restrict__ pe1,
+                                                              const float* __restrict__ rho,
+                                                              const float* __restrict__ Wa,
+                                                              const float* __restrict__ Wb,
+                                                              const bf16_t* __restrict__ Wc3, int P,
+                                                              float c, float* __restrict__ w) {
+  __shared__ float sWa[NBAS * HID];
+  __shared__ float sRho[EB * (NBAS + 1)];
+  __shared__ float sZ[4][16 * ZP];
+  // two split-panel stages; the second one holds Wb (k-major, float32) until the hidden
+  // layers are done
+  __shared__ __attribute__((aligned(16))) __bf16 sS[2][3 * HID * BP];
+  static_assert(sizeof(float) * HID * WP <= sizeof(__bf16) * 3 * HID * BP, "Wb fits a stage");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * EB;
+  const int npan = (P + HID - 1) / HID;
+  const int ppg = (npan + gridDim.y - 1) / gridDim.y;
+  const int pan0 = blockIdx.y * ppg, pan1 = min(npan, pan0 + ppg);
+  if (pan0 >= pan1) return;
+  float* sWb = reinterpret_cast<float*>(sS[1]);
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
+  Panel3Regs pr;
+  fetch_panel3(Wc3, pan0, npan, tid, pr);
+  __syncthreads();
+  float* Z = sZ[wave];
+  floatx4 acc[4];
+  first_layer(sRho + wave * 16 * (NBAS + 1), sWa, acc, lane);
+  acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  store_panel3(pr, tid, sS[0]);
+  __syncthreads();
+  zero4(acc);
+  panel_kn(Z, sWb, acc, lane);
+  __syncthreads();
+  acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  __syncthreads();
+  // z2 of pair r in three parts: eight consecutive k per lane and 32-wide step
+  const int r = lane & 15, q = lane >> 4;
+  bf16x8 z0[HID / 32], z1[HID / 32], z2[HID / 32];
+#pragma unroll
+  for (int st = 0; st < HID / 32; ++st)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 h0, h1, h2;
+      split3(Z[r * ZP + 32 * st + 8 * q + e], h0, h1, h2);
+      z0[st][e] = h0;
+      z1[st][e] = h1;
+      z2[st][e] = h2;
+    }
+  // w^T = Wc^T z2^T with the bfloat16 form's row order: row i of tile t is panel column
+  // 16 (i / 4) + 4 t + i % 4, so acc[t] = w[pair r][n0 + 16 q + 4 t + 0..3]
+  const int ca = 16 * (r >> 2) + (r & 3);
+  int buf = 0;
+  for (int n0 = pan0 * HID; n0 < min(P, pan1 * HID); n0 += HID) {
+    fetch_panel3(Wc3, n0 / HID + 1, npan, tid, pr);  // in flight during the MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+    const __bf16* sh = sS[buf];
+    zero4(acc);
+#pragma unroll
+    for (int st = 0; st < HID / 32; ++st)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int off = (ca + 4 * t) * BP + 32 * st + 8 * q;
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sh + off);
+        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sh + HID * BP + off);
+        const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(sh + 2 * HID * BP + off);
+        acc[t] = mfma32(a2, z0[st], acc[t]);  // smaller part products first
+        acc[t] = mfma32(a1, z1[st], acc[t]);
+        acc[t] = mfma32(a0, z2[st], acc[t]);
+        acc[t] = mfma32(a1, z0[st], acc[t]);
+        acc[t] = mfma32(a0, z1[st], acc[t]);
+        acc[t] = mfma32(a0, z0[st], acc[t]);
+      }
+    store_panel3(pr, tid, sS[buf ^ 1]);  // unconditionally, as in the other forms
+    const int64_t p = p0 + wave * 16 + r;
+    if (p < np) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = n0 + 16 * q + 4 * t;
+        if (col < P) *reinterpret_cast<floatx4*>(&w[p * P + col]) = acc[t];  // P % 4 == 0
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
 // dE/dw of the 16 pairs of a wave for one 64-wide k panel, loaded row-coalesced: the
 // float32 form covers rows 4 i + l / 16 (i = 0..3) and columns 4 (l % 16) .. + 3 of the
 // panel (each load is four full 256-byte row segments); the bfloat16 form covers rows
@@ -526,6 +646,16 @@ void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const fl
   const unsigned groups = (unsigned)std::max(1, std::min<int>(npan, (int)((512 + grid - 1) / grid)));
   constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
   k_mlp_fused_fwd<BF16><<<dim3(grid, groups), 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wcp, P, c, w);
+}
+
+void launch_mlp_fused_fwd_split(int64_t np, const int* pe1, const float* rho, const float* Wa,
+                                const float* Wb, const bf16_t* Wc3, int P, float c, float* w,
+                                hipStream_t s) {
+  if (np <= 0) return;
+  const unsigned grid = (unsigned)((np + EB - 1) / EB);
+  const int npan = (P + HID - 1) / HID;
+  const unsigned groups = (unsigned)std::max(1, std::min<int>(npan, (int)((512 + grid - 1) / grid)));
+  k_mlp_fused_fwd_split<<<dim3(grid, groups), 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wc3, P, c, w);
 }
 
 template <typename WS>

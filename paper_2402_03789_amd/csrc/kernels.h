@@ -134,6 +134,12 @@ void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const T* dw, in
 template <typename WS>
 void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
                           const float* Wb, const WS* Wcp, int P, float c, WS* w, hipStream_t s);
+// FP32 form of the forward with the output layer in three-part bfloat16 arithmetic
+// (float32-level results): Wc3 holds per panel the three bfloat16 parts x0, x1, x2 of every
+// weight (x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1)), each [c][j].
+void launch_mlp_fused_fwd_split(int64_t np, const int* pe1, const float* rho, const float* Wa,
+                                const float* Wb, const bf16_t* Wc3, int P, float c, float* w,
+                                hipStream_t s);
 template <typename WS>
 void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
                           const float* Wa, const float* Wb, const WS* Wcp, int P, float c,

@@ -295,7 +295,7 @@ struct sn_ctx {
   // per block: the radial MLP's output weights as 64-column panels (wc_panels)
   void* d_wpan = nullptr;
   std::vector<const float*> wc_pan;
-  std::vector<const bf16_t*> wc_pan16, wc_panT16;
+  std::vector<const bf16_t*> wc_pan16, wc_panT16, wc_panT3;
   size_t weight_bytes = 0;
   double* d_v = nullptr;
   double* d_shift = nullptr;
@@ -459,7 +459,8 @@ void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
     total += (size_t)((L.P + H - 1) / H) * K;
   }
   std::vector<float> f(total, 0.f);
-  std::vector<bf16_t> h(total), ht(total);
+  std::vector<bf16_t> h(total), ht(total), h3(3 * total);
+  auto widen = [](bf16_t b) { return __builtin_bit_cast(float, (uint32_t)b.u << 16); };
   for (size_t t = 0; t < m->layers.size(); ++t) {
     const LayerDesc& L = m->layers[t];
     const float* wc = w32.data() + L.w_mlp[2];
@@ -472,21 +473,33 @@ void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
           f[b + j * H + q] = v;
           h[b + j * H + q] = sstore<bf16_t>(v);
           ht[b + q * H + j] = sstore<bf16_t>(v);
+          // three bfloat16 parts of v (each remainder is exact in float32), each [c][j]
+          const bf16_t x0 = sstore<bf16_t>(v);
+          const float r1 = v - widen(x0);
+          const bf16_t x1 = sstore<bf16_t>(r1);
+          const bf16_t x2 = sstore<bf16_t>(r1 - widen(x1));
+          const size_t b3 = 3 * off[t] + (size_t)pan * 3 * K + q * H + j;
+          h3[b3] = x0;
+          h3[b3 + K] = x1;
+          h3[b3 + 2 * K] = x2;
         }
   }
-  const size_t bytes = total * (sizeof(float) + 2 * sizeof(bf16_t));
+  const size_t bytes = total * (sizeof(float) + 5 * sizeof(bf16_t));
   HIPCHK(hipMalloc(&c->d_wpan, bytes));
   char* d = static_cast<char*>(c->d_wpan);
   float* df = reinterpret_cast<float*>(d);
   bf16_t* dh = reinterpret_cast<bf16_t*>(d + total * sizeof(float));
   bf16_t* dht = dh + total;
+  bf16_t* dh3 = dht + total;
   HIPCHK(hipMemcpy(df, f.data(), total * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dh, h.data(), total * sizeof(bf16_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dht, ht.data(), total * sizeof(bf16_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dh3, h3.data(), 3 * total * sizeof(bf16_t), hipMemcpyHostToDevice));
   for (size_t t = 0; t < m->layers.size(); ++t) {
     c->wc_pan.push_back(df + off[t]);
     c->wc_pan16.push_back(dh + off[t]);
     c->wc_panT16.push_back(dht + off[t]);
+    c->wc_panT3.push_back(dh3 + 3 * off[t]);
   }
   c->weight_bytes += bytes;
 }
@@ -850,8 +863,13 @@ struct Pipe {
     const int* pe1 = c->get<int>("pair_e1", c->E);
     if constexpr (std::is_same<T, float>::value) {
       if (L.P % 8) throw UnsupportedError("radial weight count not a multiple of 8");
-      launch_mlp_fused_fwd<S>(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
-                              wc_panel<S>(L, true), L.P, (float)m->act, w, s);
+      if constexpr (std::is_same<S, float>::value)  // FP32 form: split-bfloat16 output layer
+        launch_mlp_fused_fwd_split(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
+                                   c->wc_panT3[(size_t)(&L - m->layers.data())], L.P,
+                                   (float)m->act, w, s);
+      else
+        launch_mlp_fused_fwd<S>(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
+                                wc_panel<S>(L, true), L.P, (float)m->act, w, s);
     } else {
       T* z2 = c->get<T>("z2", NPr * m->hidden);
       launch_mlp_hidden_fwd<T>(NPr, pe1, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]),
