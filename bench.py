@@ -237,18 +237,21 @@ def main():
                  args.precision), None)
     # Practical streaming ceiling of this part: a 1 GiB device-to-device copy (reads and
     # writes 1 GiB each), timed with events on the current stream after the timed steps.
-    cbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-    cdst = torch.empty_like(cbuf)
-    cdst.copy_(cbuf)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(5):
+    # (Skipped in counter runs, whose calibration is the one 256 MiB copy of --calib-copy.)
+    copy_gbps = None
+    if not args.calib_copy:
+        cbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        cdst = torch.empty_like(cbuf)
         cdst.copy_(cbuf)
-    ev1.record()
-    torch.cuda.synchronize()
-    copy_gbps = 5 * 2 * cbuf.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
-    del cbuf, cdst
-    if roofline["achieved"]:
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            cdst.copy_(cbuf)
+        ev1.record()
+        torch.cuda.synchronize()
+        copy_gbps = 5 * 2 * cbuf.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+        del cbuf, cdst
+    if roofline["achieved"] and copy_gbps:
         roofline["copy_GBps"] = copy_gbps
         roofline["frac_of_copy"] = roofline["achieved"] / copy_gbps
     # The same launches against the vector ALUs: algorithmic flops per block (CG nonzeros

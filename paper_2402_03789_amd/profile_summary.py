@@ -7,7 +7,8 @@ Usage:
 
 The traffic summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by the
 readings of the same counters for the 256 MiB device copy that the benchmark
-runs first with --calib-copy (a copy reads and writes exactly 256 MiB).  A kernel
+runs first with --calib-copy (a copy reads and writes exactly 256 MiB; the largest
+copy issued before the first library kernel).  A kernel
 given as NAME@UNIT is reported per dispatch of UNIT: the bytes of all NAME
 dispatches divided by the number of UNIT dispatches (k_tp_bwd@k_mlp_fused_bwd: per
 interaction block, since the radial-MLP adjoint runs once per block).
@@ -44,8 +45,10 @@ def stats(d, steps, out, cmd):
                      f"{float(r['TotalDurationNs']) / 1e6 / steps:.3f} | {float(r['Percentage']):.2f} |")
     lines += ["", f"Total GPU time per step: {total / 1e6 / steps:.3f} ms", "",
               "Per interaction block (sum over the kernel's instantiations per step / 5 blocks):", ""]
+    # (the FP32 form's radial-MLP forward is the non-template k_mlp_fused_fwd_split)
     for k in ("k_tp_bwd", "k_tp_fwd", "k_mlp_fused_bwd", "k_mlp_fused_fwd"):
-        t = sum(float(r["TotalDurationNs"]) for r in rows if f"::{k}<" in r["Name"])
+        t = sum(float(r["TotalDurationNs"]) for r in rows
+                if f"::{k}<" in r["Name"] or f"::{k}_split(" in r["Name"])
         lines.append(f"- `{k}`: {t / 1e3 / steps / 5:.1f} us")
     open(out, "w").write("\n".join(lines) + "\n")
 
@@ -55,9 +58,13 @@ def traffic(fetch_dir, write_dir, kernel, source, precision, out, cmd):
     w_rows = _rows(write_dir, "*counter_collection.csv")
 
     def calib(rows, counter):
+        # the 256 MiB calibration copy runs before the first library kernel (copies issued
+        # later, of other sizes, are not calibration)
+        first = min(int(r["Dispatch_Id"]) for r in rows if "sn::" in r["Kernel_Name"])
         vals = [float(r["Counter_Value"]) for r in rows
-                if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
-        return max(vals)  # the 256 MiB copy is the largest
+                if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]
+                and int(r["Dispatch_Id"]) < first]
+        return max(vals)
     cf = calib(f_rows, "FETCH_SIZE") / (256 * 1024)
     cw = calib(w_rows, "WRITE_SIZE") / (256 * 1024)
     kernel, _, unit = kernel.partition("@")
