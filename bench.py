@@ -10,8 +10,9 @@ Workload: 24,000-atom SiO2 (8,000 Si + 16,000 O) in a periodic cubic box at
 5-layer model with 128x0e+64x1e+32x2e features, l <= 2, 8 Bessel functions,
 r_c = 5 A, radial MLP 8-64-64, seeded N(0, 1/fan_in) weights.
 
-Prints one JSON line (rank 0).  --gpus above 1 exits: this build runs one
-GPU (the multi-GPU decomposition is a design in the design doc, not code).
+Prints one JSON line (rank 0).  --gpus above 1 exits: the library evaluates the
+subdomains of one GPU's share on that GPU; the multi-GPU decomposition is not
+implemented.
 """
 from __future__ import annotations
 
@@ -143,7 +144,7 @@ def main():
                          "of which the last 100 are timed; the list is rebuilt on the skin trigger")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build evaluates one subdomain on one GPU; "
+        print(json.dumps({"error": "the library evaluates one GPU's share on one GPU; "
                                    "--gpus must be 1"}))
         sys.exit(2)
 
@@ -256,7 +257,7 @@ def main():
         roofline["frac_of_copy"] = roofline["achieved"] / copy_gbps
     # The same launches against the vector ALUs: algorithmic flops per block (CG nonzeros
     # from the library's own tables), against the published vector peak (fp32 157.3 TFLOP/s
-    # counts packed two-wide FP32 instructions, which this build does not emit, so 78.6 is
+    # counts packed two-wide FP32 instructions, which the library's kernels do not emit, so 78.6 is
     # the attainable ceiling; fp64 78.6).
     import numpy as np
 

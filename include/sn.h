@@ -41,7 +41,7 @@ extern "C" {
 #define SN_EINVAL (-1)        /* bad argument: shape, NaN/Inf, singular cell, unknown Z, r = 0 pair */
 #define SN_ENOMEM (-2)        /* device memory or HBM budget exhausted */
 #define SN_EHIP (-3)          /* HIP runtime error; the context is no longer usable */
-#define SN_EUNSUPPORTED (-4)  /* valid request that this build does not implement */
+#define SN_EUNSUPPORTED (-4)  /* valid request that the library does not implement */
 #define SN_EBUSY (-5)         /* resource in use (e.g. backward without a pending forward) */
 
 /* ---- precision forms -------------------------------------------------------------- */

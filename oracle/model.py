@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE (see oracle/__init__.py).
 
-Model (paper section 2.2 and section 5.1; readings of the points the paper
-leaves open are listed in the design doc):
+Model (paper section 2.2 and section 5.1; where the paper leaves a point open,
+the reading taken is the one written here):
 
   h^(1)_i = W_emb[s_i]                               (scalars only)
   for each interaction block t:

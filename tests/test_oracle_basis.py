@@ -1,7 +1,7 @@
 """Pins of the oracle's edge basis against closed forms and library routines.
 
 Section 5.1 of the paper: spherical harmonics up to l = 2 and 8 radial Bessel
-functions; the envelope is a p = 6 polynomial (reading listed in the design doc).
+functions; the envelope is a p = 6 polynomial (the paper does not print it).
 """
 import math
 
