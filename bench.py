@@ -111,6 +111,9 @@ def main():
                          "to sweep instead of the l <= 2 model")
     ap.add_argument("--sweep-layers", type=int, default=4,
                     help="size_sweep: interaction blocks of the benchmark models")
+    ap.add_argument("--sweep-sizes", default=None,
+                    help="size_sweep: comma-separated atom counts (multiples of 3) instead of the "
+                         "default ladder")
     ap.add_argument("--sizes", default="4608,12960",
                     help="paper_models: atom counts (multiples of 3)")
     ap.add_argument("--serve-requests", type=int, default=None,
@@ -487,6 +490,8 @@ def bench_size_sweep(args):
     if args.sweep_channels:
         density = 2.65
         n_si = (32, 128, 512, 1536, 4320, 12288, 24576)
+        if args.sweep_sizes:
+            n_si = tuple(int(v) // 3 for v in args.sweep_sizes.split(","))
         models = []
         for c in (int(v) for v in args.sweep_channels.split(",")):
             spec = model_spec_bench(c, args.sweep_layers)
@@ -495,6 +500,8 @@ def bench_size_sweep(args):
     else:
         density = 2.2
         n_si = (64, 256, 1024, 4000, 8000, 16000)
+        if args.sweep_sizes:
+            n_si = tuple(int(v) // 3 for v in args.sweep_sizes.split(","))
         spec = model_spec_real()
         models = [("5 blocks, 128x0e+64x1e+32x2e", spec, make_weights(spec, 102))]
     dev = torch.device("cuda:0")
