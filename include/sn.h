@@ -40,16 +40,20 @@ extern "C" {
 #define SN_OK 0
 #define SN_EINVAL (-1)        /* bad argument: shape, NaN/Inf, singular cell, unknown Z, r = 0 pair */
 #define SN_ENOMEM (-2)        /* device memory or HBM budget exhausted */
-#define SN_EHIP (-3)          /* HIP runtime error; the context is no longer usable */
+#define SN_EHIP (-3)          /* HIP runtime error, including a kernel launch the runtime
+                                 refused; the context is no longer usable */
 #define SN_EUNSUPPORTED (-4)  /* valid request that the library does not implement */
 #define SN_EBUSY (-5)         /* resource in use (e.g. backward without a pending forward) */
 
 /* ---- precision forms -------------------------------------------------------------- */
 #define SN_FP64 0  /* everything in float64 (reference-grade; for tests and finite differences) */
 #define SN_FP32 1  /* per-edge work in float32 (basis, radial MLP, tensor product, edge
-                      gradients), edge vectors from float64 positions; the node-state chain
-                      (features, self-connection, gate, readout, node gradients) in float64;
-                      energy and virial reductions in float64 */
+                      gradients; the forward radial MLP's output layer as sums of products of
+                      three-part bfloat16 splits of its float32 operands, float32-level
+                      error), edge vectors from float64 positions; the node-state chain
+                      (features, self-connection, gate, readout, node gradients) in float64,
+                      its float64 contractions on the float64 matrix cores; energy and virial
+                      reductions in float64 */
 #define SN_BF16 2  /* as SN_FP32, but the radial MLP and the channel-mixing linears take
                       bfloat16 operands with float32 accumulation on the matrix cores; tensor
                       product in float32; float64 energy and virial reductions */

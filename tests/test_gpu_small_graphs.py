@@ -45,3 +45,21 @@ def test_small_graph_regimes_match_oracle(real_model, n_si):
         else:
             assert err["e_rel"] < TOL_E_REL_FP32 and err["f_abs"] < TOL_F_ABS_FP32
             assert err["w_rel"] < TOL_W_REL_FP32
+
+
+@pytest.mark.parametrize("precision,w_asym", [("fp64", 1e-12), ("fp32", 1e-8), ("bf16", 1e-4)])
+def test_force_sum_and_virial_symmetry(real_model, precision, w_asym):
+    # every edge gradient g_e enters its receiver's force with + and its sender's owner's
+    # with -, so the forces sum to zero up to rounding of float64 sums in every form; the
+    # virial is symmetric as far as the arithmetic keeps the energy rotation-invariant
+    import numpy as np
+    path, _ = real_model
+    s = sio2_box(200, seed=31)
+    got = sn.Context(sn.Model(path), precision=precision).compute(s.pos, s.Z, s.cell)
+    f, w = got["forces"], got["virial"]
+    f_rms = float(np.sqrt(np.mean(f ** 2)))
+    sum_f = np.abs(f.sum(axis=0)).max()
+    asym = np.linalg.norm(w - w.T) / np.linalg.norm(w)
+    log(f"{precision}: |sum F| {sum_f:.3g} (rms F {f_rms:.3g}), virial asymmetry {asym:.3g}")
+    assert sum_f < 1e-9 * f_rms * len(f)
+    assert asym < w_asym
