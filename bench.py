@@ -93,7 +93,7 @@ def main():
     ap.add_argument("--no-isolated", action="store_true",
                     help="skip the single-stream context that times the roofline kernels in "
                          "isolation (for kernel traces of the overlapped steps alone)")
-    ap.add_argument("--cpu-sample-si", type=int, default=512,
+    ap.add_argument("--cpu-sample-si", type=int, default=800,
                     help="Si count of the SiO2 sample box timed with the CPU oracle")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (HBM counter calibration)")
