@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 outputs for profiles/ (kernel-trace stats and HBM counters).
 
 Usage:
-  python -m paper_2402_03789_amd.profile_summary stats <rocprof_dir> <steps> <out.md> <command...>
+  python -m paper_2402_03789_amd.profile_summary stats <rocprof_dir> <steps[:blocks]> <out.md> <command...>
   python -m paper_2402_03789_amd.profile_summary traffic <fetch_dir> <write_dir> <kernel> \
         <source.hip> <precision> <out.json> <command...>
 
@@ -14,7 +14,8 @@ dispatches divided by the number of UNIT dispatches (k_tp_bwd@k_mlp_fused_bwd: p
 interaction block, since the radial-MLP adjoint runs once per block).
 
 The stats summary also gives, for the tensor-product and radial-MLP kernels, the
-GPU time per interaction block (all their dispatches of a step / 5 blocks).
+GPU time per interaction block (all their dispatches of a step / the model's blocks,
+5 unless given as steps:blocks).
 """
 from __future__ import annotations
 
@@ -32,7 +33,7 @@ def _rows(d, pattern):
     return list(csv.DictReader(open(files[0])))
 
 
-def stats(d, steps, out, cmd):
+def stats(d, steps, out, cmd, blocks=5):
     rows = _rows(d, "*kernel_stats.csv")
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     total = sum(float(r["TotalDurationNs"]) for r in rows)
@@ -44,12 +45,13 @@ def stats(d, steps, out, cmd):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / 1e6 / steps:.3f} | {float(r['Percentage']):.2f} |")
     lines += ["", f"Total GPU time per step: {total / 1e6 / steps:.3f} ms", "",
-              "Per interaction block (sum over the kernel's instantiations per step / 5 blocks):", ""]
+              f"Per interaction block (sum over the kernel's instantiations per step / {blocks} "
+              "blocks):", ""]
     # (the FP32 form's radial-MLP forward is the non-template k_mlp_fused_fwd_split)
     for k in ("k_tp_bwd", "k_tp_fwd", "k_mlp_fused_bwd", "k_mlp_fused_fwd"):
         t = sum(float(r["TotalDurationNs"]) for r in rows
                 if f"::{k}<" in r["Name"] or f"::{k}_split(" in r["Name"])
-        lines.append(f"- `{k}`: {t / 1e3 / steps / 5:.1f} us")
+        lines.append(f"- `{k}`: {t / 1e3 / steps / blocks:.1f} us")
     open(out, "w").write("\n".join(lines) + "\n")
 
 
@@ -87,6 +89,8 @@ def traffic(fetch_dir, write_dir, kernel, source, precision, out, cmd):
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        stats(sys.argv[2], float(sys.argv[3]), sys.argv[4], " ".join(sys.argv[5:]))
+        steps, _, blocks = sys.argv[3].partition(":")
+        stats(sys.argv[2], float(steps), sys.argv[4], " ".join(sys.argv[5:]),
+              int(blocks) if blocks else 5)
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:8], " ".join(sys.argv[8:]))

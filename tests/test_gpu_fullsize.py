@@ -62,3 +62,37 @@ def test_sio2_24k_sampled_parity(tmp_path, golden, precision):
         assert de <= TOL_E_REL_FP32 and df <= TOL_F_ABS_FP32 and dw <= TOL_W_REL_FP32
     else:
         assert df_rms <= TOL_F_RMS_BF16
+
+
+QUARTZ = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "quartz_4608_32x4.json")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_benchmark_model_4608_sampled_parity(tmp_path, precision):
+    # one of the paper's benchmark models (32 channels at every l <= 3, 4 blocks, r_c 4 A)
+    # on its per-GPU share of 4,608 atoms at the alpha-quartz density
+    if not os.path.exists(QUARTZ):
+        pytest.skip("golden file missing")
+    with open(QUARTZ) as fh:
+        gold = json.load(fh)
+    from synth import model_spec_bench, sio2_box
+    spec = model_spec_bench(32, 4, sigma=gold["sigma"])
+    path, _ = write_model(tmp_path, spec, gold["weights_seed"])
+    s = sio2_box(gold["n_atoms"] // 3, density=2.65, seed=gold["structure_seed"])
+    log(f"benchmark-model parity precision={precision} n={s.n}")
+    ctx = sn.Context(sn.Model(path), precision=precision)
+    r = ctx.compute(s.pos, s.Z, s.cell)
+    assert ctx.graph_size()[2] == gold["n_edges"]
+    idx = np.array(gold["sample_index"])
+    de = np.abs(r["atom_energy"][idx] - np.array(gold["sample_atom_energy"])).max() / gold["atom_energy_rms"]
+    df = np.abs(r["forces"][idx] - np.array(gold["sample_forces"])).max()
+    df_rms = (np.sqrt(np.mean((r["forces"][idx] - np.array(gold["sample_forces"])) ** 2))
+              / gold["force_rms"])
+    dw = np.linalg.norm(r["virial"].reshape(-1) - np.array(gold["virial"])) / np.linalg.norm(gold["virial"])
+    log(f"e_rel={de:.2e} f_abs={df:.2e} f_rms_rel={df_rms:.2e} w_rel={dw:.2e}")
+    if precision == "fp64":
+        assert de <= 1e-10 and df <= 1e-10 and dw <= 1e-10
+    elif precision == "fp32":
+        assert de <= TOL_E_REL_FP32 and df <= TOL_F_ABS_FP32 and dw <= TOL_W_REL_FP32
+    else:
+        assert df_rms <= TOL_F_RMS_BF16
