@@ -8,8 +8,9 @@
 // only their nonzeros become instructions and no coupling table occupies LDS.
 //
 // Work decomposition (MI355X-native): one kernel per input degree l1 (so each
-// gets its own register budget), one 64-lane wavefront per receiver, four
-// receivers per block.  A wave covers the degree's channels with lanes (two
+// gets its own register budget), one 64-lane wavefront per receiver and one
+// wave per block (measured faster than two or four per block: the waves of a
+// launch are placed one by one).  A wave covers the degree's channels with lanes (two
 // channels per lane for a 128-channel scalar block); a degree with fewer than
 // 64 channels processes 64/cpt edges at once (lanes = channel x edge slot) and
 // combines the slots with cross-lane shuffles at the end.  The radial weights
@@ -93,7 +94,7 @@ struct TPArgs {
 template <int L1>
 struct CPL { static constexpr int value = L1 == 0 ? 2 : 1; };
 
-constexpr int kRecvPerBlock = 4;  // one wave per receiver
+constexpr int kRecvPerBlock = 1;  // receivers (waves) per block
 
 // t[m3] = sum_{m1,m2} C[m1,m2,m3] x[m1] Y[m2] of one path (l1, l2, l3) for one edge and one
 // channel; each path's t is formed where it is used, so at most 2 l3 + 1 of them are live
