@@ -72,6 +72,68 @@ def _tp_adjoint_flops(spec, cg_nnz):
     return out
 
 
+def _tp_forward_flops(spec, cg_nnz):
+    """Algorithmic arithmetic of the tensor-product forward per edge of each block: per path
+    (l1, l2, l3) and channel, t = C x Y (3 flops per CG nonzero) and m += w t (2 (2 l3 + 1))."""
+    return [sum(spec.muls[l1] * (3 * cg_nnz(l1, l2, l3) + 2 * (2 * l3 + 1))
+                for (l1, l2, l3) in spec._paths(t)) for t in range(spec.n_layers)]
+
+
+def _step_roofline(spec, cg_nnz, n, g, e, npairs, precision, ms, iso):
+    """Lower bound of one evaluation from the algorithmic work of its modelled kernels:
+    the sum over them of max(flops / peak, bytes / 8 TB/s), against the measured step.
+
+    Modelled per interaction block (b = storage bytes of w, dE/dw, x and dE/dx rows; tb = 4,
+    8 in FP64): radial-MLP forward (2 (8 64 + 64 64 + 64 P) flops per pair on the matrix
+    cores; writes w, reads rho: b P + 32 bytes per pair); tensor-product forward (per edge
+    the pair's w slice and Y, b P + nY tb; every sender row once and every message row
+    written once; vector-ALU peak); tensor-product adjoint (the same unit as the headline
+    roofline); radial-MLP adjoint (2 64 P + 2 (8 64 + 2 64 64 + 64 8) flops and 2 b P + 64
+    bytes per pair); per-edge dE/dx rows summed per sender and folded onto owners (read
+    E Dx b, write and read (n + g) Dx 8, write n Dx 8).  Node GEMMs, gates, graph build,
+    basis, readout and forces are not modelled and add nothing to the bound, so the
+    fraction is a lower estimate; `modelled_share` is the modelled phases' part of the
+    single-stream (isolated) phase time."""
+    b = {"fp32": 4, "bf16": 2, "fp64": 8}[precision]
+    tb = 8 if precision == "fp64" else 4
+    mlp_peak = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[precision] * 1e12
+    alu_peak = (78.6 if precision == "fp64" else 157.3) * 1e12
+    hbm = 8000e9
+    ny = (spec.l_sh + 1) ** 2
+    fwd_f = _tp_forward_flops(spec, cg_nnz)
+    bwd_f = _tp_adjoint_flops(spec, cg_nnz)
+    kinds = {}
+
+    def add(kind, phase, flops, nbytes, peak):
+        t = max(flops / peak if flops else 0.0, nbytes / hbm) * 1e3
+        k = kinds.setdefault(kind, {"flops": 0.0, "bytes": 0.0, "bound_ms": 0.0, "isolated_ms": 0.0})
+        k["flops"] += flops
+        k["bytes"] += nbytes
+        k["bound_ms"] += t
+        k["isolated_ms"] += iso.get(phase, 0.0)
+
+    for t, (P, Dx, Dm, wdx) in enumerate(_tp_blocks(spec)):
+        add("mlp_fwd", f"layer{t}.mlp", npairs * 2 * (8 * 64 + 64 * 64 + 64 * P),
+            npairs * (b * P + 32), mlp_peak)
+        add("tp_fwd", f"layer{t}.tp", e * fwd_f[t],
+            e * (b * P + ny * tb) + (n + g) * Dx * b + n * Dm * tb, alu_peak)
+        add("tp_bwd", f"bwd.layer{t}.tp", e * bwd_f[t],
+            e * (2 * b * P + (b * Dx if wdx else 0) + 3 * 3 * ny * tb) + n * Dm * tb
+            + (n + g) * Dx * b, alu_peak)
+        add("mlp_bwd", f"bwd.layer{t}.mlp",
+            npairs * (2 * 64 * P + 2 * (8 * 64 + 2 * 64 * 64 + 64 * 8)),
+            npairs * (2 * b * P + 64), mlp_peak)
+        if wdx:
+            add("sender_fold", f"bwd.layer{t}.sender_fold", 0,
+                e * Dx * b + 2 * (n + g) * Dx * 8 + n * Dx * 8, alu_peak)
+    bound = sum(k["bound_ms"] for k in kinds.values())
+    iso_all = sum(iso.values())
+    iso_mod = sum(k["isolated_ms"] for k in kinds.values())
+    return {"bound": "per kernel max(flops/peak, bytes/HBM), summed", "lower_bound_ms": bound,
+            "ms_per_step": ms, "frac": bound / ms if ms > 0 else None,
+            "modelled_share": iso_mod / iso_all if iso_all > 0 else None, "kernels": kinds}
+
+
 def _roofline_entry(kernel, nbytes, nflops, ms, traffic, peak_tf):
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
     e = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
@@ -322,6 +384,8 @@ def main():
             if nflops:
                 entry["isolated"]["mfma_frac"] = nflops / (iso_ms * 1e-3) / 1e12 / peak_tf
 
+    roofline_step = _step_roofline(spec, cg_nnz, n, g, e, npairs, args.precision, ms, iso)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle.model import OracleModel, evaluate
@@ -357,6 +421,7 @@ def main():
         "roofline": roofline,
         "roofline_alu": roofline_alu,
         "roofline_mlp_adjoint": roofline_mlp,
+        "roofline_step": roofline_step,
         "cpu_baseline": cpu,
         "phases_ms": {k: v / args.steps for k, v in phase_ms.items()},
         "serving": serving,

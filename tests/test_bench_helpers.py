@@ -81,3 +81,23 @@ def test_stats_counts_the_split_forward_per_block(tmp_path):
     text = out.read_text()
     assert "- `k_mlp_fused_fwd`: 500.0 us" in text   # 7.5 ms / 3 steps / 5 blocks
     assert "- `k_tp_bwd`: 1000.0 us" in text
+
+
+def test_step_roofline_small_model_by_hand():
+    import bench
+    spec = model_spec_small()  # radial weights per edge: 64, 160, 64 over the three blocks
+    n, g, e, npairs = 10, 5, 100, 50
+    r = bench._step_roofline(spec, _nnz, n, g, e, npairs, "fp32", 1.0, {})
+    k = r["kernels"]
+    # forward MLP: 2 (8 64 + 64 64 + 64 P) flops and 4 P + 32 bytes per pair, summed over blocks
+    assert k["mlp_fwd"]["flops"] == npairs * 2 * (3 * (8 * 64 + 64 * 64) + 64 * 288)
+    assert k["mlp_fwd"]["bytes"] == npairs * (4 * 288 + 3 * 32)
+    # each kernel bounded by the slower of its arithmetic and its HBM bytes
+    for kind in k.values():
+        assert kind["bound_ms"] >= kind["bytes"] / 8e12 * 1e3 - 1e-15
+    # dE/dx rows exist from the second block on; sender rows: the first block's are the
+    # 32 scalars, then 32 scalars + 32 vectors (128 floats)
+    assert k["sender_fold"]["bytes"] == sum(e * D * 4 + 2 * (n + g) * D * 8 + n * D * 8
+                                            for D in (128, 128))
+    assert r["frac"] == pytest.approx(r["lower_bound_ms"] / 1.0)
+    assert r["modelled_share"] is None
