@@ -153,10 +153,13 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-isolated", action="store_true",
-                    help="skip the single-stream context that times the roofline kernels in "
-                         "isolation (for kernel traces of the overlapped steps alone)")
+                    help="skip the evaluations after the timed steps (the single-stream context "
+                         "that times the roofline kernels in isolation, the host-buffer entry "
+                         "point), for kernel traces of the overlapped steps alone")
     ap.add_argument("--cpu-sample-si", type=int, default=800,
                     help="Si count of the SiO2 sample box timed with the CPU oracle")
+    ap.add_argument("--host-steps", type=int, default=5,
+                    help="evaluations timed through the host-buffer entry point (0 to skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (HBM counter calibration)")
     ap.add_argument("--workload", default="sio2_24k",
@@ -278,6 +281,20 @@ def main():
     ms = dt / args.steps * 1e3
     n, g, e = ctx.graph_size()
     value = s.n * args.steps / dt
+
+    # The same evaluation through the host-buffer entry point (positions in, energies,
+    # forces and virial out over PCIe, one synchronisation per call): reported beside the
+    # device-resident rate, never as the value.
+    host_buffers = None
+    if args.host_steps > 0 and not args.no_isolated:
+        ctx.compute(s.pos, s.Z, s.cell)
+        t1 = time.perf_counter()
+        for _ in range(args.host_steps):
+            ctx.compute(s.pos, s.Z, s.cell)
+        hdt = time.perf_counter() - t1
+        host_buffers = {"entry_point": "sn_compute (host buffers)", "steps": args.host_steps,
+                        "ms_per_step": hdt / args.host_steps * 1e3,
+                        "value": s.n * args.host_steps / hdt, "unit": "atom-steps/s"}
 
     # Roofline of the dominant kernel, the tensor-product adjoint (k_tp_bwd, about a third
     # of the GPU time of a step).  Unit: the adjoint of one interaction block, i.e. its
@@ -422,6 +439,7 @@ def main():
         "roofline_alu": roofline_alu,
         "roofline_mlp_adjoint": roofline_mlp,
         "roofline_step": roofline_step,
+        "host_buffers": host_buffers,
         "cpu_baseline": cpu,
         "phases_ms": {k: v / args.steps for k, v in phase_ms.items()},
         "serving": serving,
