@@ -154,8 +154,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-isolated", action="store_true",
                     help="skip the evaluations after the timed steps (the single-stream context "
-                         "that times the roofline kernels in isolation, the host-buffer entry "
-                         "point), for kernel traces of the overlapped steps alone")
+                         "that times the roofline kernels in isolation, the kept-list steps, "
+                         "the host-buffer entry point), for kernel traces of the overlapped "
+                         "steps alone")
     ap.add_argument("--cpu-sample-si", type=int, default=800,
                     help="Si count of the SiO2 sample box timed with the CPU oracle")
     ap.add_argument("--host-steps", type=int, default=5,
@@ -281,6 +282,26 @@ def main():
     ms = dt / args.steps * 1e3
     n, g, e = ctx.graph_size()
     value = s.n * args.steps / dt
+
+    # The same evaluation with the neighbour list kept from the last build (positions
+    # unchanged, so the kept graph is exact): every step without the graph build.
+    list_reused = None
+    if not args.no_isolated:
+        f_ref = forces.clone()
+        ctx.set_graph_reuse(True)
+        step()
+        ctx.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+            ctx.synchronize()
+        torch.cuda.synchronize()
+        rdt = time.perf_counter() - t1
+        ctx.set_graph_reuse(False)
+        list_reused = {"steps": args.steps, "ms_per_step": rdt / args.steps * 1e3,
+                       "value": s.n * args.steps / rdt, "unit": "atom-steps/s",
+                       "max_abs_dF_vs_rebuild": float((forces - f_ref).abs().max())}
+        del f_ref
 
     # The same evaluation through the host-buffer entry point (positions in, energies,
     # forces and virial out over PCIe, one synchronisation per call): reported beside the
@@ -439,6 +460,7 @@ def main():
         "roofline_alu": roofline_alu,
         "roofline_mlp_adjoint": roofline_mlp,
         "roofline_step": roofline_step,
+        "list_reused": list_reused,
         "host_buffers": host_buffers,
         "cpu_baseline": cpu,
         "phases_ms": {k: v / args.steps for k, v in phase_ms.items()},
