@@ -60,6 +60,9 @@ class OracleModel:
         if config.get("gate", "silu") != "silu":
             raise ValueError("only SiLU gates are defined")
         self.C0 = self.muls[0]
+        # receivers are processed in chunks of about this many edges when a structure has
+        # more (memory bound of the autograd graph; the result does not depend on it)
+        self.chunk_edges = 200_000
         self.W = {k: torch.as_tensor(np.asarray(v), dtype=DT) for k, v in weights.items()}
         self.layers = []
         for t in range(self.T):
@@ -130,9 +133,11 @@ class OracleModel:
             off += mul
         return tuple(torch.cat(parts[l], dim=1) / self.kavg for l in L["outs"])
 
-    def conv(self, t, x_send: dict, recv, send, n_recv, Y, rho, chunk_edges=200_000):
+    def conv(self, t, x_send: dict, recv, send, n_recv, Y, rho, chunk_edges=None):
         """Aggregated messages M[l3] for receivers 0..n_recv-1 (edges sorted by receiver)."""
         L = self.layers[t]
+        if chunk_edges is None:
+            chunk_edges = self.chunk_edges
         xs = [x_send[l] for l in L["ins"]]
         E = recv.shape[0]
         if E <= chunk_edges:
