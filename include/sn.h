@@ -105,10 +105,28 @@ int sn_cg_table(int l1, int l2, int l3, double* out);
  * and one precision form, and owns the device workspace.  hbm_budget caps the
  * workspace in bytes (0 = no cap beyond the device); a request that would exceed
  * it fails with SN_ENOMEM before any launch.  skin widens the ghost shell to
- * r_cut + skin so that a neighbour list can be reused while atoms move less than
- * skin / 2 (0 for a fresh list every call). */
+ * r_cut + skin (paper section 3.1: the shell that holds every sender within reach of a
+ * subdomain's receivers) so that a neighbour list can be reused while atoms move less
+ * than skin / 2 (0 for a fresh list every call).
+ *
+ * alloc (may be NULL) supplies every device allocation of the context -- weights and
+ * workspace -- so that a framework can serve them from its own pool (the Python layer
+ * binds torch's caching allocator).  NULL uses hipMalloc / hipFree.  The library calls
+ * alloc(user, bytes, device, stream) with the context's device current and its stream;
+ * it must return memory aligned to at least 256 bytes and valid on that device, or NULL
+ * on failure (the call then fails with SN_ENOMEM).  free(user, ptr, bytes, device,
+ * stream) is called only after every use of ptr on the context's streams has completed
+ * (the library synchronises those streams first), and for every block at sn_ctx_free.
+ * The allocator must outlive the context and may be called from the host thread that
+ * makes the library call. */
+typedef struct sn_allocator {
+  void* (*alloc)(void* user, size_t bytes, int device, void* hip_stream);
+  void (*free)(void* user, void* ptr, size_t bytes, int device, void* hip_stream);
+  void* user;
+} sn_allocator_t;
+
 int sn_ctx_create(const sn_model_t* model, int device, void* hip_stream, size_t hbm_budget,
-                  int precision, double skin, sn_ctx_t** out);
+                  int precision, double skin, const sn_allocator_t* alloc, sn_ctx_t** out);
 /* A context also owns a second HIP stream on which the radial MLPs of every block run,
  * overlapped with the node-feature chain (the MLP forward needs only the edge basis; the
  * MLP adjoint of a block only that block's dE/dw).  Every call joins that stream back into
@@ -118,16 +136,26 @@ int sn_ctx_create(const sn_model_t* model, int device, void* hip_stream, size_t 
 void sn_ctx_free(sn_ctx_t* ctx);
 
 /* ---- single structure, host buffers -------------------------------------------------
+ * One evaluation of the potential (paper section 2: atomic numbers and positions in; the
+ * per-atom energies E_i whose sum is E, eq 1; the forces F_i = -dE/dr_i, eq 2, assembled
+ * from the edge gradients by eqs 5-6; the virial for the stress of section 3.2), run as
+ * one subdomain with its ghost shell (section 3.1).
  * n atoms; pos[n*3] angstrom; Z[n] atomic numbers known to the model; cell[9]
  * rows a1 a2 a3; pbc[3] must all be nonzero (periodic in every direction; other
  * cases return SN_EUNSUPPORTED).  Outputs (any may be NULL except energy):
  * energy[1] eV; atom_energy[n] eV; forces[n*3] eV/angstrom; virial[9] eV,
- * W = -sum_e d_e (x) dE/dd_e (stress = -W / volume).  Blocks until done. */
+ * W = -sum_e d_e (x) dE/dd_e (stress = -W / volume).  Blocks until done.  The inputs are
+ * copied to device memory and the results back (two PCIe transfers beside the device
+ * entry points below).  SN_EINVAL for an unknown atomic number, non-finite positions, a
+ * singular cell or two atoms at one position; SN_ENOMEM when the workspace would exceed
+ * the budget (the context stays usable). */
 int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, const double* cell,
                const uint8_t* pbc, double* energy, double* atom_energy, double* forces,
                double* virial);
 
 /* ---- several structures in one packed graph, host buffers --------------------------
+ * The evaluation of sn_compute (paper section 2, eqs 1-2, 5-6) for a batch: the graph of
+ * section 3.1 built once over all structures, with edges inside each structure only.
  * B structures; offsets[B+1] (offsets[0] = 0) delimit each structure's atoms in pos[n*3]
  * and Z[n] (n = offsets[B]); cells[B*9] holds each structure's cell (all periodic).  The
  * structures are evaluated together as one graph (the kernels run once over all atoms
@@ -139,18 +167,39 @@ int sn_compute_batch(sn_ctx_t* ctx, int B, const int64_t* offsets, const double*
                      double* atom_energies, double* forces, double* virials);
 
 /* ---- device buffers, stream-ordered (the autograd pair) -----------------------------
- * sn_forward_device builds the graph, runs every interaction block and the
- * readout, and keeps the activations the backward pass needs inside ctx.
- * d_pos[n*3] float64 and d_Z[n] int32 are device pointers; cell[9] is a host
- * array.  d_energy[1] (float64) and d_atom_energy[n] (float64, may be NULL) are
- * device outputs.  sn_backward_device consumes the pending forward: with the
- * upstream gradient g = dL/dE (host scalar) it writes d_forces[n*3] = -g dE/dr
- * (float64, device; i.e. the forces scaled by g) and d_virial[9] = g W (float64,
- * device, may be NULL).  Both return as soon as the work is queued on the
- * context's stream.  SN_EBUSY if backward is called without a pending forward. */
-int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32_t* d_Z,
-                      const double* cell, double* d_energy, double* d_atom_energy);
-int sn_backward_device(sn_ctx_t* ctx, double grad_energy, double* d_forces, double* d_virial);
+ * One packed batch of B periodic structures resident in device memory.  The atoms of
+ * structure b are offsets[b] .. offsets[b+1]-1 of d_pos (n x 3 float64, angstrom) and
+ * d_Z (n int32 atomic numbers), n = offsets[B]; offsets (B+1 int64, offsets[0] = 0,
+ * strictly increasing) and cells (B x 9 float64, rows a1 a2 a3 of each cell) are host
+ * arrays read during the call.  The caller owns every buffer. */
+typedef struct sn_batch {
+  int32_t n_structures;    /* B >= 1 */
+  const int64_t* offsets;  /* host, B + 1 */
+  const double* cells;     /* host, B x 9 */
+  const double* d_pos;     /* device, n x 3 */
+  const int32_t* d_Z;      /* device, n */
+} sn_batch_t;
+
+/* sn_forward_device evaluates the energy of every structure of the batch as one packed
+ * graph (paper Fig 3a: graph build, edge basis, the interaction blocks of section 2.2 with
+ * the per-block ghost refresh of section 3.1, readout and E_b = sum of E_i over the
+ * structure's atoms, eq 1, in float64) and keeps the activations the backward pass needs
+ * inside ctx (one pending forward per context).  Outputs (device, float64): d_energy[B];
+ * d_atom_energy[n] (may be NULL).  sn_backward_device consumes the pending forward with
+ * the upstream gradients d_grad_energy[B] = dL/dE_b (device, float64, read when the work
+ * runs) and writes the position gradients through the hand-written adjoint (eqs 5-8:
+ * edge gradients dE/dd_e summed over blocks, the sender-side sums and ghost folds of the
+ * reverse communication, F = -dE/dr by eq 6):
+ *   d_forces[i]  = g_b F_i = -dL/dr_i   for the atoms i of structure b (n x 3, device);
+ *   d_virial[b]  = g_b W_b, W_b = -sum_e d_e (x) dE_b/dd_e (B x 9, device, may be NULL).
+ * Both return once the work is queued on the context's stream (no host synchronisation
+ * after the graph build).  SN_EINVAL for a malformed batch, an atomic number outside the
+ * model or non-finite positions (checked before the kernels that depend on them);
+ * SN_EBUSY for a backward without a pending forward. */
+int sn_forward_device(sn_ctx_t* ctx, const sn_batch_t* batch, double* d_energy,
+                      double* d_atom_energy);
+int sn_backward_device(sn_ctx_t* ctx, const double* d_grad_energy, double* d_forces,
+                       double* d_virial);
 
 /* Neighbour-list reuse for molecular dynamics.  With reuse enabled, a forward call whose
  * atom count and cell equal those of the previous build keeps that graph (ghost shell and
@@ -174,12 +223,14 @@ int sn_ctx_set_domains(sn_ctx_t* ctx, int nx, int ny, int nz);
 /* hipGraph replay for molecular dynamics.  With capture on and graph reuse enabled, a
  * forward/backward pair that reuses the kept neighbour list is recorded once into a HIP
  * graph (all launches on one stream, no timing events) and replayed on later reuse calls
- * with the same device pointers and upstream gradient; a rebuild, other pointers or another
- * gradient record a new graph.  The first reuse call after a build runs eagerly (it sizes
+ * with the same device pointers (the upstream gradients are read from device memory at
+ * replay, so their values may change); a rebuild or other pointers record a new graph.  The first reuse call after a build runs eagerly (it sizes
  * the workspace).  Results are bitwise those of the eager launches. */
 int sn_ctx_set_capture(sn_ctx_t* ctx, int on);
 
-/* Velocity-Verlet half step on device arrays (harness of the MD workload), stream-ordered:
+/* Velocity-Verlet half step on device arrays (harness of the MD workload: the 1 fs
+ * velocity-Verlet runs of the large-box section 5.2 and the benchmarks of section 4),
+ * stream-ordered:
  * stage 0: v += dt/2 a, x += dt v;  stage 1: v += dt/2 a;  a = F * inv_mass.
  * d_pos, d_vel, d_forces are n x 3 float64; d_inv_mass[n] carries the unit conversion
  * (for eV, angstrom, amu and fs: 0.0096485 / mass). */
@@ -214,6 +265,8 @@ int sn_md_max_displacement(sn_ctx_t* ctx, int64_t n, const double* d_pos, const 
 int sn_ctx_synchronize(sn_ctx_t* ctx);
 
 /* ---- serving: continuous batching of structures of uneven size --------------------
+ * Inference serving of the general-purpose potential (paper section 5: one model over
+ * many chemistries and cell shapes), each request one evaluation as in sn_compute.
  * A server runs n_streams worker threads on one device, each with its own HIP stream and
  * context (sharing the model).  Requests enter a FIFO queue; a free worker packs requests
  * from the head of the queue into one graph while the batch stays within
@@ -252,7 +305,12 @@ typedef struct sn_result {
 int sn_server_create(const sn_model_t* model, int device, int n_streams, int precision,
                      size_t hbm_budget, int64_t max_batch_atoms, int max_batch_structures,
                      sn_server_t** out);
-/* Queue one structure; *ticket identifies its result.  SN_EHIP when no worker is alive. */
+/* Queue one structure; *ticket identifies its result.  The request is checked here:
+ * SN_EINVAL for an atomic number outside the model, non-finite positions or cell, or a
+ * singular cell, so that a bad request cannot fail its batch mates.  A batch that fails on
+ * what only the device finds (two atoms at one position) is re-run one structure at a time,
+ * and only the offending request completes with the error.  SN_EHIP when no worker is
+ * alive. */
 int sn_server_submit(sn_server_t* server, const sn_request_t* request, uint64_t* ticket);
 /* Move up to max finished results into out[]; *n_out receives the count.  Waits up to
  * timeout_ms for the first one (0: do not wait, negative: wait without limit). */

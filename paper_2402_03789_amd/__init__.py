@@ -7,12 +7,44 @@ to a CPU or PyTorch implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 import torch
 
-from ._lib import lib, check, ptr, PRECISIONS, SNError, ModelInfo, EXPORTED  # noqa: F401
+from ._lib import (lib, check, ptr, PRECISIONS, SNError, ModelInfo, EXPORTED,  # noqa: F401
+                   Allocator, Batch, ALLOC_FN, FREE_FN)
+
+# contexts still open at interpreter exit are closed while torch (whose allocator may hold
+# their memory) is still usable
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for c in list(_LIVE):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+def _torch_allocator():
+    """sn_allocator_t over torch's caching allocator (memory shows in torch's statistics
+    and is reused by torch once the context frees it)."""
+    def _alloc(_user, nbytes, device, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+        except Exception:  # out of memory: the library reports SN_ENOMEM
+            return None
+
+    def _free(_user, p, _nbytes, _device, _stream):
+        torch.cuda.caching_allocator_delete(int(p))
+
+    fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+    return Allocator(fa, ff, None), (fa, ff)
 
 
 def cg_table(l1: int, l2: int, l3: int) -> np.ndarray:
@@ -63,18 +95,29 @@ class Context:
     """One model on one device, stream and precision form."""
 
     def __init__(self, model: Model, device: int = 0, precision: str = "fp32", skin: float = 0.0,
-                 stream=None, hbm_budget: int = 0):
+                 stream=None, hbm_budget: int = 0, allocator: str | None = "torch"):
+        """allocator: "torch" serves the context's device memory from torch's caching
+        allocator; None lets the library call hipMalloc."""
         self.model = model
         self.device = device
         self.skin = float(skin)  # neighbour-list skin (angstrom) of graph reuse
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
+        self._alloc = None
+        alloc_ref = None
+        if allocator == "torch":
+            self._alloc, self._alloc_keep = _torch_allocator()  # kept alive with the context
+            alloc_ref = C.byref(self._alloc)
+        elif allocator is not None:
+            raise ValueError(f"unknown allocator {allocator!r}")
+        self._ones = None
         h = C.c_void_p()
         st = lib().sn_ctx_create(model.handle, device, C.c_void_p(stream.cuda_stream), hbm_budget,
-                                 PRECISIONS[precision], float(skin), C.byref(h))
+                                 PRECISIONS[precision], float(skin), alloc_ref, C.byref(h))
         check(st)
         self._h = h
+        _LIVE.add(self)
 
     @property
     def handle(self):
@@ -139,13 +182,41 @@ class Context:
         return out
 
     def forward_device(self, pos: torch.Tensor, Z: torch.Tensor, cell, energy: torch.Tensor,
-                       atom_energy: torch.Tensor | None = None):
-        cell = np.ascontiguousarray(cell, dtype=np.float64)
-        check(lib().sn_forward_device(self._h, pos.shape[0], ptr(pos), ptr(Z), ptr(cell), ptr(energy),
-                                      ptr(atom_energy)), self._h)
+                       atom_energy: torch.Tensor | None = None, offsets=None):
+        """Energies of a packed batch in device memory.  pos [n,3] float64 and Z [n] int32 on
+        the context's device; offsets (B+1, host) delimit the structures (None: one structure
+        of all n atoms); cell: 3x3 or B x 3 x 3 (host).  energy [B] and atom_energy [n]
+        (optional) are float64 device outputs."""
+        n = int(pos.shape[0])
+        offs = np.array([0, n] if offsets is None else offsets, dtype=np.int64)
+        B = len(offs) - 1
+        cells = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(B, 9))
+        for t, dt in ((pos, torch.float64), (Z, torch.int32), (energy, torch.float64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"expected a contiguous {dt} device tensor")
+        if energy.numel() < B or (atom_energy is not None and atom_energy.numel() < n):
+            raise ValueError("output tensor too small")
+        b = Batch(B, offs.ctypes.data, cells.ctypes.data, pos.data_ptr(), Z.data_ptr())
+        check(lib().sn_forward_device(self._h, C.byref(b), ptr(energy), ptr(atom_energy)), self._h)
+        self._pending_B = B
 
-    def backward_device(self, grad_energy: float, forces: torch.Tensor, virial: torch.Tensor | None):
-        check(lib().sn_backward_device(self._h, float(grad_energy), ptr(forces), ptr(virial)), self._h)
+    def backward_device(self, grad_energy, forces: torch.Tensor, virial: torch.Tensor | None):
+        """Consume the pending forward.  grad_energy: dL/dE_b as a float64 device tensor [B],
+        or a float (every structure).  forces [n,3] <- g_b F_i; virial [B,9] <- g_b W_b."""
+        B = getattr(self, "_pending_B", 1)
+        if not isinstance(grad_energy, torch.Tensor):
+            g = float(grad_energy)
+            if g == 1.0:  # kept on the device: MD loops and graph replays reuse it
+                if self._ones is None or self._ones.numel() < B:
+                    self._ones = torch.ones(max(B, 64), dtype=torch.float64, device=forces.device)
+                grad_energy = self._ones
+            else:
+                grad_energy = torch.full((B,), g, dtype=torch.float64, device=forces.device)
+        if grad_energy.dtype != torch.float64 or not grad_energy.is_cuda or grad_energy.numel() < B:
+            raise ValueError(f"grad_energy must be a float64 device tensor of at least {B} values")
+        grad_energy = grad_energy.contiguous()
+        self._g_keep = grad_energy  # alive until the queued backward has read it
+        check(lib().sn_backward_device(self._h, ptr(grad_energy), ptr(forces), ptr(virial)), self._h)
 
     def synchronize(self):
         check(lib().sn_ctx_synchronize(self._h), self._h)
@@ -221,31 +292,42 @@ class Context:
 
 
 class SevenNetEnergy(torch.autograd.Function):
-    """E(pos) with forces from the library's hand-written adjoint.
+    """Energies of a packed batch with forces from the library's hand-written adjoint.
 
-    forward(pos [n,3] float64 cuda, Z [n] int32 cuda, cell (3x3 host), ctx) -> E (float64 scalar);
-    backward gives dL/dpos = g dE/dpos = -g F.  The virial of the last backward is
-    stored on the context object as `last_virial` (g W).
+    forward(pos [n,3] float64 cuda, Z [n] int32 cuda, cells (B x 3 x 3 host), offsets (B+1 host
+    int64, or None for one structure), ctx) -> E [B] float64; backward takes dL/dE [B] on the
+    device (no host synchronisation) and gives dL/dpos = -g_b F_i.  The virials of the last
+    backward (g_b W_b, [B,9]) are stored on the context object as `last_virial`.
     """
 
     @staticmethod
-    def forward(actx, pos, Z, cell, ctx: Context):
-        energy = torch.zeros(1, dtype=torch.float64, device=pos.device)
-        ctx.forward_device(pos.contiguous(), Z.contiguous(), cell, energy)
+    def forward(actx, pos, Z, cells, offsets, ctx: Context):
+        n = int(pos.shape[0])
+        offs = np.array([0, n] if offsets is None else offsets, dtype=np.int64)
+        B = len(offs) - 1
+        energy = torch.zeros(B, dtype=torch.float64, device=pos.device)
+        ctx.forward_device(pos.contiguous(), Z.contiguous(), cells, energy, offsets=offs)
         actx.sn = ctx
-        actx.n = pos.shape[0]
-        return energy[0]
+        actx.n = n
+        actx.B = B
+        return energy
 
     @staticmethod
     def backward(actx, grad_e):
         ctx = actx.sn
-        g = float(grad_e)
-        f = torch.zeros((actx.n, 3), dtype=torch.float64, device=grad_e.device)
-        w = torch.zeros(9, dtype=torch.float64, device=grad_e.device)
+        g = grad_e.to(torch.float64).contiguous()
+        f = torch.empty((actx.n, 3), dtype=torch.float64, device=grad_e.device)
+        w = torch.empty((actx.B, 9), dtype=torch.float64, device=grad_e.device)
         ctx.backward_device(g, f, w)
         ctx.last_virial = w
-        return -f, None, None, None
+        return -f, None, None, None, None
 
 
 def energy(pos, Z, cell, ctx: Context):
-    return SevenNetEnergy.apply(pos, Z, cell, ctx)
+    """Total energy of one structure (scalar) through SevenNetEnergy."""
+    return SevenNetEnergy.apply(pos, Z, cell, None, ctx)[0]
+
+
+def energies(pos, Z, cells, offsets, ctx: Context):
+    """Energies [B] of a packed batch through SevenNetEnergy."""
+    return SevenNetEnergy.apply(pos, Z, cells, offsets, ctx)

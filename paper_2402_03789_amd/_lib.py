@@ -49,6 +49,23 @@ class Result(C.Structure):
     ]
 
 
+class Batch(C.Structure):
+    """sn_batch_t: a packed batch of structures in device memory."""
+    _fields_ = [
+        ("n_structures", C.c_int32), ("offsets", C.c_void_p), ("cells", C.c_void_p),
+        ("d_pos", C.c_void_p), ("d_Z", C.c_void_p),
+    ]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """sn_allocator_t: device allocations of a context through caller callbacks."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -60,15 +77,14 @@ _SIGS = {
     "sn_model_info": (C.c_int, [C.c_void_p, C.POINTER(ModelInfo)]),
     "sn_cg_table": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "sn_ctx_create": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_int, C.c_double,
-                                C.POINTER(C.c_void_p)]),
+                                C.POINTER(Allocator), C.POINTER(C.c_void_p)]),
     "sn_ctx_free": (None, [C.c_void_p]),
     "sn_compute": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sn_compute_batch": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
-    "sn_forward_device": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
-                                    C.c_void_p, C.c_void_p]),
-    "sn_backward_device": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "sn_forward_device": (C.c_int, [C.c_void_p, C.POINTER(Batch), C.c_void_p, C.c_void_p]),
+    "sn_backward_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sn_ctx_synchronize": (C.c_int, [C.c_void_p]),
     "sn_ctx_graph_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64)]),

@@ -249,21 +249,27 @@ __global__ void k_seg_virial(const int* __restrict__ chunks, const int* __restri
     for (int q = 0; q < 9; ++q) partial[blockIdx.x * 9 + q] = s[0][q];
 }
 
+// gscale (device, one value per structure, or null for 1) multiplies structure b's sums:
+// the upstream gradient dL/dE_b of a backward pass
 __global__ void k_seg_finalize(int B, const int* __restrict__ first, const double* __restrict__ partial,
-                               int width, double* __restrict__ out, double scale) {
+                               int width, double* __restrict__ out, const double* __restrict__ gscale) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= B * width) return;
   int b = idx / width, q = idx % width;
   double v = 0;
   for (int c = first[b]; c < first[b + 1]; ++c) v += partial[c * width + q];
-  out[idx] = scale * v;
+  out[idx] = (gscale ? gscale[b] : 1.0) * v;
 }
 
+// rows back to the caller's atom order; with gscale, row o is multiplied by the value of
+// its structure, sid_orig[o] / regions_per_struct
 __global__ void k_unpermute(int n, const int* __restrict__ order, const double* __restrict__ in_rows,
-                            int width, double* __restrict__ out_rows, double scale) {
+                            int width, double* __restrict__ out_rows, const double* __restrict__ gscale,
+                            const int* __restrict__ sid_orig, int regions_per_struct) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int o = order[k];
+  const double scale = gscale ? gscale[sid_orig[o] / regions_per_struct] : 1.0;
   for (int a = 0; a < width; ++a) out_rows[(int64_t)o * width + a] = scale * in_rows[(int64_t)k * width + a];
 }
 
@@ -479,12 +485,16 @@ void launch_seg_virial(int nchunks, const int* chunks, const int* recv, const in
   if (nchunks > 0) k_seg_virial<<<nchunks, kRedThreads, 0, s>>>(chunks, recv, src, pos_ext, g, partial);
 }
 void launch_seg_finalize(int B, const int* first, const double* partial, int width, double* out,
-                         double scale, hipStream_t s) {
-  if (B > 0) k_seg_finalize<<<nblk((int64_t)B * width, 128), 128, 0, s>>>(B, first, partial, width, out, scale);
+                         const double* gscale, hipStream_t s) {
+  if (B > 0)
+    k_seg_finalize<<<nblk((int64_t)B * width, 128), 128, 0, s>>>(B, first, partial, width, out, gscale);
 }
 void launch_unpermute(int n, const int* order, const double* in_rows, int width, double* out_rows,
-                      double scale, hipStream_t s) {
-  if (n > 0) k_unpermute<<<nblk(n, 256), 256, 0, s>>>(n, order, in_rows, width, out_rows, scale);
+                      const double* gscale, const int* sid_orig, int regions_per_struct,
+                      hipStream_t s) {
+  if (n > 0)
+    k_unpermute<<<nblk(n, 256), 256, 0, s>>>(n, order, in_rows, width, out_rows, gscale, sid_orig,
+                                             regions_per_struct);
 }
 
 #define SN_INST(T)                                                                                \

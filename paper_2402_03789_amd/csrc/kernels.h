@@ -229,10 +229,12 @@ void launch_seg_energy(int nchunks, const int* chunks, const double* atom_e, dou
                        hipStream_t s);
 void launch_seg_virial(int nchunks, const int* chunks, const int* recv, const int* src,
                        const double* pos_ext, const double* g, double* partial, hipStream_t s);
+// gscale: per-structure factors in device memory (null: 1)
 void launch_seg_finalize(int B, const int* first, const double* partial, int width, double* out,
-                         double scale, hipStream_t s);
+                         const double* gscale, hipStream_t s);
 void launch_unpermute(int n, const int* order, const double* in_rows, int width,
-                      double* out_rows, double scale, hipStream_t s);
+                      double* out_rows, const double* gscale, const int* sid_orig,
+                      int regions_per_struct, hipStream_t s);
 
 // Kept graph, moved atoms: local rows from pos[order[k]] + wrap_off[k], ghost rows from
 // owner row + shift . H.  wrap_off is recorded at build time by launch_wrap_offsets.

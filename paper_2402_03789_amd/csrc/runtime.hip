@@ -282,6 +282,9 @@ struct sn_ctx {
   const sn_model* m = nullptr;
   int device = 0;
   hipStream_t stream = nullptr;
+  // device allocations come from the caller's allocator when one was given at creation
+  sn_allocator_t alloc{nullptr, nullptr, nullptr};
+  std::map<void*, size_t> weight_blocks;  // weight buffers and their sizes (for free)
   size_t budget = 0;
   int precision = SN_FP32;
   double skin = 0;
@@ -326,7 +329,6 @@ struct sn_ctx {
     hipGraphExec_t exec = nullptr;
     uint64_t version = ~0ull;
     const void* key[3] = {nullptr, nullptr, nullptr};
-    double g = 0;
   } rp_fwd, rp_bwd;
   std::vector<double> graph_cells;
   // second stream for the radial MLPs, which depend only on the edge basis (forward) or
@@ -341,6 +343,32 @@ struct sn_ctx {
   std::vector<hipEvent_t> event_pool;
   size_t event_next = 0;
 
+  // device memory from the caller's allocator, or hipMalloc; nullptr on failure
+  void* dev_alloc(size_t bytes) {
+    if (alloc.alloc) return alloc.alloc(alloc.user, bytes, device, stream);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  // the caller guarantees that no queued work still uses p
+  bool dev_free(void* p, size_t bytes) {
+    if (!p) return true;
+    if (alloc.free) {
+      alloc.free(alloc.user, p, bytes, device, stream);
+      return true;
+    }
+    return hipFree(p) == hipSuccess;
+  }
+  // a weight buffer (released only by sn_ctx_free)
+  void* weight_alloc(size_t bytes) {
+    void* p = dev_alloc(bytes);
+    if (!p) throw MemError("device allocation failed for the model weights");
+    weight_blocks[p] = bytes;
+    return p;
+  }
   void* raw(const std::string& name, size_t bytes) {
     Buf& b = bufs[name];
     if (bytes <= b.cap) return b.p;
@@ -350,17 +378,13 @@ struct sn_ctx {
     if (b.p) {
       HIPCHK(hipStreamSynchronize(stream));
       if (aux) HIPCHK(hipStreamSynchronize(aux));
-      HIPCHK(hipFree(b.p));
+      if (!dev_free(b.p, b.cap)) throw HipError("device free failed for " + name);
       used -= b.cap;
       b.p = nullptr;
       b.cap = 0;
     }
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      b.p = nullptr;
-      throw MemError("device allocation failed for " + name);
-    }
+    b.p = dev_alloc(want);
+    if (!b.p) throw MemError("device allocation failed for " + name);
     b.cap = want;
     used += want;
     return b.p;
@@ -485,7 +509,7 @@ void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
         }
   }
   const size_t bytes = total * (sizeof(float) + 5 * sizeof(bf16_t));
-  HIPCHK(hipMalloc(&c->d_wpan, bytes));
+  c->d_wpan = c->weight_alloc(bytes);
   char* d = static_cast<char*>(c->d_wpan);
   float* df = reinterpret_cast<float*>(d);
   bf16_t* dh = reinterpret_cast<bf16_t*>(d + total * sizeof(float));
@@ -513,14 +537,14 @@ void upload_weights(sn_ctx* c) {
   else HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
   std::vector<float> w32(m->flat.size());
   for (size_t i = 0; i < w32.size(); ++i) w32[i] = (float)m->flat[i];
-  HIPCHK(hipMalloc(&c->d_w, m->flat.size() * sizeof(double)));
+  c->d_w = c->weight_alloc(m->flat.size() * sizeof(double));
   HIPCHK(hipMemcpy(c->d_w, m->flat.data(), m->flat.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(hipMalloc(&c->d_w32, w32.size() * sizeof(float)));
+  c->d_w32 = c->weight_alloc(w32.size() * sizeof(float));
   HIPCHK(hipMemcpy(c->d_w32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice));
-  HIPCHK(hipMalloc(&c->d_v, m->readout_v.size() * sizeof(double)));
+  c->d_v = static_cast<double*>(c->weight_alloc(m->readout_v.size() * sizeof(double)));
   HIPCHK(hipMemcpy(c->d_v, m->readout_v.data(), m->readout_v.size() * sizeof(double),
                    hipMemcpyHostToDevice));
-  HIPCHK(hipMalloc(&c->d_shift, m->shift.size() * sizeof(double)));
+  c->d_shift = static_cast<double*>(c->weight_alloc(m->shift.size() * sizeof(double)));
   HIPCHK(hipMemcpy(c->d_shift, m->shift.data(), m->shift.size() * sizeof(double),
                    hipMemcpyHostToDevice));
   c->weight_bytes = m->flat.size() * (sizeof(double) + sizeof(float)) +
@@ -994,16 +1018,18 @@ struct Pipe {
     // per-structure energies (eq 1): fixed-order segmented sums
     double* part = c->get<double>("partial_e", c->n_echunk);
     launch_seg_energy(c->n_echunk, c->get<int>("echunks", 3 * c->n_echunk), ae, part, s);
-    launch_seg_finalize(c->B, c->get<int>("efirst", c->B + 1), part, 1, d_energy, 1.0, s);
+    launch_seg_finalize(c->B, c->get<int>("efirst", c->B + 1), part, 1, d_energy, nullptr, s);
     if (d_atom_energy_orig) {
       const int* order = c->get<int>("order", N);
-      launch_unpermute(N, order, ae, 1, d_atom_energy_orig, 1.0, s);
+      launch_unpermute(N, order, ae, 1, d_atom_energy_orig, nullptr, nullptr, 1, s);
     }
     // a launch refused by the runtime (resources, configuration) leaves its outputs unwritten
     HIPCHK(hipGetLastError());
   }
 
-  void backward(double grad_scale, double* d_forces_orig, double* d_virial) {
+  // d_grad: dL/dE_b per structure in device memory (null: 1), applied to the outputs (the
+  // adjoint is linear in the seed and structures share no edges)
+  void backward(const double* d_grad, double* d_forces_orig, double* d_virial) {
     const int N = c->N, G = c->G, NE = N + G;
     (void)G;
     const int64_t E = c->E;
@@ -1110,13 +1136,14 @@ struct Pipe {
     launch_forces(N, row_ptr, sptr, sidx, gptr, gE, F, s);
     if (d_forces_orig) {
       const int* order = c->get<int>("order", N);
-      launch_unpermute(N, order, F, 3, d_forces_orig, grad_scale, s);
+      launch_unpermute(N, order, F, 3, d_forces_orig, d_grad, c->get<int>("sid_orig", N),
+                       c->R / c->B, s);
     }
     if (d_virial) {
       double* part = c->get<double>("partial_w", 9 * (int64_t)c->n_vchunk);
       launch_seg_virial(c->n_vchunk, c->get<int>("vchunks", 3 * c->n_vchunk), recv, src, pos_ext,
                         gE, part, s);
-      launch_seg_finalize(c->B, c->get<int>("vfirst", c->B + 1), part, 9, d_virial, grad_scale, s);
+      launch_seg_finalize(c->B, c->get<int>("vfirst", c->B + 1), part, 9, d_virial, d_grad, s);
     }
     HIPCHK(hipGetLastError());
     c->mark("end");
@@ -1132,7 +1159,7 @@ bool release_workspace(sn_ctx* c) {
   destroy_replays(c);
   if (c->aux && hipStreamSynchronize(c->aux) != hipSuccess) ok = false;
   for (auto& kv : c->bufs)
-    if (kv.second.p && hipFree(kv.second.p) != hipSuccess) ok = false;
+    if (kv.second.p && !c->dev_free(kv.second.p, kv.second.cap)) ok = false;
   c->bufs.clear();
   c->used = 0;
   c->have_graph = false;
@@ -1255,9 +1282,8 @@ void launch_replay(sn_ctx* c, hipGraphExec_t exec) {
   if (cs != c->stream) c->join(c->stream, cs);
 }
 bool replay_hit(const sn_ctx::Replay& r, uint64_t version, const void* k0, const void* k1,
-                const void* k2, double g) {
-  return r.exec && r.version == version && r.key[0] == k0 && r.key[1] == k1 && r.key[2] == k2 &&
-         r.g == g;
+                const void* k2) {
+  return r.exec && r.version == version && r.key[0] == k0 && r.key[1] == k1 && r.key[2] == k2;
 }
 
 template <typename T, typename S>
@@ -1291,7 +1317,7 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
     sn_ctx::Replay& r = c->rp_fwd;
     // replay once an eager run on this graph has sized every buffer
     if (c->capture && c->reuse_runs >= 1) {
-      if (!replay_hit(r, c->graph_version, d_pos, d_energy, d_atom_energy, 0.0)) {
+      if (!replay_hit(r, c->graph_version, d_pos, d_energy, d_atom_energy)) {
         if (r.exec) (void)hipGraphExecDestroy(r.exec);
         r.exec = nullptr;
         r.exec = record_graph(c, body);
@@ -1299,7 +1325,6 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
         r.key[0] = d_pos;
         r.key[1] = d_energy;
         r.key[2] = d_atom_energy;
-        r.g = 0.0;
       }
       launch_replay(c, r.exec);
       return;
@@ -1324,24 +1349,23 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
 }
 
 template <typename T, typename S>
-void backward_impl(sn_ctx* c, double g, double* d_forces, double* d_virial) {
+void backward_impl(sn_ctx* c, const double* d_grad, double* d_forces, double* d_virial) {
   if (!c->pending) throw std::logic_error("busy");
   auto body = [&] {
     Pipe<T, S> p(c);
-    p.backward(g, d_forces, d_virial);
+    p.backward(d_grad, d_forces, d_virial);
   };
   c->pending = false;
   sn_ctx::Replay& r = c->rp_bwd;
   if (c->capture && c->last_fwd_reused && c->reuse_runs >= 1) {
-    if (!replay_hit(r, c->graph_version, d_forces, d_virial, nullptr, g)) {
+    if (!replay_hit(r, c->graph_version, d_forces, d_virial, d_grad)) {
       if (r.exec) (void)hipGraphExecDestroy(r.exec);
       r.exec = nullptr;
       r.exec = record_graph(c, body);
       r.version = c->graph_version;
       r.key[0] = d_forces;
       r.key[1] = d_virial;
-      r.key[2] = nullptr;
-      r.g = g;
+      r.key[2] = d_grad;
     }
     launch_replay(c, r.exec);
     return;
@@ -1433,19 +1457,22 @@ int sn_cg_table(int l1, int l2, int l3, double* out) {
 }
 
 int sn_ctx_create(const sn_model_t* model, int device, void* hip_stream, size_t hbm_budget,
-                  int precision, double skin, sn_ctx_t** out) {
+                  int precision, double skin, const sn_allocator_t* alloc, sn_ctx_t** out) {
   if (!model || !out || skin < 0 || !std::isfinite(skin)) return SN_EINVAL;
   if (precision != SN_FP64 && precision != SN_FP32 && precision != SN_BF16) return SN_EINVAL;
+  if (alloc && (!alloc->alloc || !alloc->free)) return SN_EINVAL;
   auto c = std::make_unique<sn_ctx>();
   c->m = model;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (alloc) c->alloc = *alloc;
   c->budget = hbm_budget;
   c->precision = precision;
   c->skin = skin;
   int st = guarded(c.get(), [&] { upload_weights(c.get()); });
   if (st != SN_OK) {
     g_load_error = c->err;
+    sn_ctx_free(c.release());  // what upload_weights allocated before failing
     return st;
   }
   *out = c.release();
@@ -1458,12 +1485,9 @@ void sn_ctx_free(sn_ctx_t* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   for (auto& kv : ctx->bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
-  if (ctx->d_w) (void)hipFree(ctx->d_w);
-  if (ctx->d_w32) (void)hipFree(ctx->d_w32);
-  if (ctx->d_wpan) (void)hipFree(ctx->d_wpan);
-  if (ctx->d_v) (void)hipFree(ctx->d_v);
-  if (ctx->d_shift) (void)hipFree(ctx->d_shift);
+    if (kv.second.p) (void)ctx->dev_free(kv.second.p, kv.second.cap);
+  for (auto& kv : ctx->weight_blocks) (void)ctx->dev_free(kv.first, kv.second);
+  ctx->weight_blocks.clear();
   destroy_replays(ctx);
   if (ctx->cap_stream) {
     (void)hipStreamSynchronize(ctx->cap_stream);
@@ -1478,50 +1502,68 @@ void sn_ctx_free(sn_ctx_t* ctx) {
   delete ctx;
 }
 
-int sn_forward_device(sn_ctx_t* ctx, int64_t n, const double* d_pos, const int32_t* d_Z,
-                      const double* cell, double* d_energy, double* d_atom_energy) {
-  if (!ctx || !d_pos || !d_Z || !cell || !d_energy || n <= 0) return SN_EINVAL;
+int sn_forward_device(sn_ctx_t* ctx, const sn_batch_t* batch, double* d_energy,
+                      double* d_atom_energy) {
+  if (!ctx || !batch || !d_energy) return SN_EINVAL;
+  const int B = batch->n_structures;
+  const int64_t* off = batch->offsets;
+  if (B < 1 || !off || !batch->cells || !batch->d_pos || !batch->d_Z || off[0] != 0) {
+    ctx->err = "malformed batch";
+    return SN_EINVAL;
+  }
+  for (int b = 0; b < B; ++b)
+    if (off[b + 1] <= off[b]) {
+      ctx->err = "empty structure in batch";
+      return SN_EINVAL;
+    }
+  const int64_t n = off[B];
   return guarded(ctx, [&] {
-    const int64_t off[2] = {0, n};
-    const bool reusable = ctx->reuse && ctx->have_graph && ctx->B == 1 && ctx->N == n &&
-                          std::memcmp(ctx->graph_cells.data(), cell, sizeof(double) * 9) == 0;
-    if (reusable) {  // the species of the kept graph stay (reuse contract): no host round trip
-      const int* d_spec = ctx->get<int>("spec_orig", n);
+    auto run = [&](const int* d_spec) {
       if (ctx->precision == SN_FP64)
-        forward_impl<double, double>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+        forward_impl<double, double>(ctx, B, off, batch->d_pos, d_spec, batch->cells, d_energy,
+                                     d_atom_energy);
       else if (ctx->precision == SN_BF16)
-        forward_impl<float, bf16_t>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+        forward_impl<float, bf16_t>(ctx, B, off, batch->d_pos, d_spec, batch->cells, d_energy,
+                                    d_atom_energy);
       else
-        forward_impl<float, float>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+        forward_impl<float, float>(ctx, B, off, batch->d_pos, d_spec, batch->cells, d_energy,
+                                   d_atom_energy);
+    };
+    const bool reusable = ctx->reuse && ctx->have_graph && ctx->B == B && ctx->N == n &&
+                          std::equal(off, off + B + 1, ctx->atom_off.begin()) &&
+                          std::memcmp(ctx->graph_cells.data(), batch->cells,
+                                      sizeof(double) * 9 * B) == 0;
+    if (reusable) {  // the species of the kept graph stay (reuse contract): no host round trip
+      run(ctx->get<int>("spec_orig", n));
       return;
     }
     // map atomic numbers to embedding rows on the host (validation before any launch)
     std::vector<int32_t> hz((size_t)n);
-    HIPCHK(hipMemcpyAsync(hz.data(), d_Z, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(hz.data(), batch->d_Z, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                          ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     std::vector<int> spec;
     map_species(ctx->m, n, hz.data(), spec);
     int* d_spec = ctx->get<int>("spec_orig", n);
     HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx->stream));
-    if (ctx->precision == SN_FP64)
-      forward_impl<double, double>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
-    else if (ctx->precision == SN_BF16)
-      forward_impl<float, bf16_t>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
-    else
-      forward_impl<float, float>(ctx, 1, off, d_pos, d_spec, cell, d_energy, d_atom_energy);
+    run(d_spec);
   });
 }
 
-int sn_backward_device(sn_ctx_t* ctx, double grad_energy, double* d_forces, double* d_virial) {
-  if (!ctx) return SN_EINVAL;
+int sn_backward_device(sn_ctx_t* ctx, const double* d_grad_energy, double* d_forces,
+                       double* d_virial) {
+  if (!ctx || !d_grad_energy) return SN_EINVAL;
   if (!ctx->pending) {
     ctx->err = "backward without a pending forward";
     return SN_EBUSY;
   }
   return guarded(ctx, [&] {
-    if (ctx->precision == SN_FP64) backward_impl<double, double>(ctx, grad_energy, d_forces, d_virial);
-    else if (ctx->precision == SN_BF16) backward_impl<float, bf16_t>(ctx, grad_energy, d_forces, d_virial);
-    else backward_impl<float, float>(ctx, grad_energy, d_forces, d_virial);
+    if (ctx->precision == SN_FP64)
+      backward_impl<double, double>(ctx, d_grad_energy, d_forces, d_virial);
+    else if (ctx->precision == SN_BF16)
+      backward_impl<float, bf16_t>(ctx, d_grad_energy, d_forces, d_virial);
+    else
+      backward_impl<float, float>(ctx, d_grad_energy, d_forces, d_virial);
   });
 }
 
@@ -1561,13 +1603,13 @@ int sn_compute_batch(sn_ctx_t* ctx, int B, const int64_t* offsets, const double*
     const bool need_bwd = forces || virials;
     if (ctx->precision == SN_FP64) {
       forward_impl<double, double>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
-      if (need_bwd) backward_impl<double, double>(ctx, 1.0, d_f, d_w);
+      if (need_bwd) backward_impl<double, double>(ctx, nullptr, d_f, d_w);
     } else if (ctx->precision == SN_BF16) {
       forward_impl<float, bf16_t>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
-      if (need_bwd) backward_impl<float, bf16_t>(ctx, 1.0, d_f, d_w);
+      if (need_bwd) backward_impl<float, bf16_t>(ctx, nullptr, d_f, d_w);
     } else {
       forward_impl<float, float>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
-      if (need_bwd) backward_impl<float, float>(ctx, 1.0, d_f, d_w);
+      if (need_bwd) backward_impl<float, float>(ctx, nullptr, d_f, d_w);
     }
     ctx->pending = false;
     std::vector<double> h((size_t)(10 * (int64_t)B + 4 * n));

@@ -10,7 +10,12 @@
 // are on the device join the next batch of whichever worker frees up first, so
 // batches of different workers overlap on the device.  A batch that still runs out
 // of its budget is split in half and retried; a single structure that cannot fit
-// completes with SN_ENOMEM.
+// completes with SN_ENOMEM.  A request is validated at submit (known species, finite
+// positions and cell, nonzero cell volume); a batch that fails on what only the device
+// finds (two atoms at one position, an unsupported geometry) is re-run one structure at
+// a time, so only the offending request fails and every other result is the one it
+// would get alone.
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,6 +56,7 @@ struct sn_server {
   size_t slice = 0;  // HBM bytes per worker (0 = no cap)
   int64_t max_batch_atoms = 0;
   int max_batch_structures = 0;
+  bool known_z[128] = {};  // atomic numbers of the model's species table
   Clock::time_point t0;
 
   std::mutex mu;
@@ -74,28 +80,46 @@ namespace {
 // upper estimate for dense condensed-phase cells under a five-block l <= 2 model.
 constexpr double kInitialBytesPerAtom = 96.0 * 1024.0;
 
-void complete(sn_server* s, std::vector<std::unique_ptr<Request>>& batch, int status,
-              const std::vector<double>& e, const std::vector<double>& w, double t_start,
-              double t_end, int64_t atoms) {
+// results of batch[first .. first + count) (e and w indexed from 0 for that range)
+void complete(sn_server* s, std::vector<std::unique_ptr<Request>>& batch, size_t first,
+              size_t count, int status, const std::vector<double>& e,
+              const std::vector<double>& w, double t_start, double t_end, int64_t atoms) {
   std::lock_guard<std::mutex> lk(s->mu);
-  for (size_t b = 0; b < batch.size(); ++b) {
+  for (size_t k = 0; k < count; ++k) {
+    const Request& q = *batch[first + k];
     sn_result_t r;
     std::memset(&r, 0, sizeof(r));
-    r.ticket = batch[b]->ticket;
+    r.ticket = q.ticket;
     r.status = status;
     if (status == SN_OK) {
-      r.energy = e[b];
-      for (int k = 0; k < 9; ++k) r.virial[k] = w[9 * b + k];
+      r.energy = e[k];
+      for (int a = 0; a < 9; ++a) r.virial[a] = w[9 * k + a];
     }
-    r.t_submit = batch[b]->t_submit;
+    r.t_submit = q.t_submit;
     r.t_start = t_start;
     r.t_done = t_end;
-    r.batch_structures = (int)batch.size();
+    r.batch_structures = (int)count;
     r.batch_atoms = atoms;
     s->done.push_back(r);
   }
-  s->in_flight -= (int64_t)batch.size();
+  s->in_flight -= (int64_t)count;
   s->cv_done.notify_all();
+}
+
+// host-side checks of one request (what a batch mate must not be able to fail)
+bool valid_request(const sn_server* s, const sn_request_t* q) {
+  for (int64_t i = 0; i < q->n; ++i) {
+    const int z = q->Z[i];
+    if (z < 0 || z >= 128 || !s->known_z[z]) return false;
+  }
+  for (int64_t i = 0; i < 3 * q->n; ++i)
+    if (!std::isfinite(q->pos[i])) return false;
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(q->cell[k])) return false;
+  const double* H = q->cell;
+  const double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                     H[2] * (H[3] * H[7] - H[4] * H[6]);
+  return std::isfinite(det) && std::fabs(det) > 1e-6;
 }
 
 }  // namespace
@@ -106,7 +130,7 @@ void sn_server::worker(int w) {
   sn_ctx_t* ctx = nullptr;
   bool ok = hipSetDevice(device) == hipSuccess &&
             hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess &&
-            sn_ctx_create(model, device, stream, slice, precision, 0.0, &ctx) == SN_OK;
+            sn_ctx_create(model, device, stream, slice, precision, 0.0, nullptr, &ctx) == SN_OK;
   size_t base = 0;
   if (ok) sn_ctx_memory(ctx, &base);
   size_t high_water = base;
@@ -166,6 +190,32 @@ void sn_server::worker(int w) {
       continue;
     }
     atom_cap = max_batch_atoms;
+    if ((st == SN_EINVAL || st == SN_EUNSUPPORTED) && B > 1) {
+      // a structure the device rejected: evaluate each alone, so only that one fails
+      bool dead = false;
+      for (int b = 0; b < B && !dead; ++b) {
+        Request& r = *batch[b];
+        const int64_t o1[2] = {0, r.n};
+        std::vector<double> e1(1, 0.0), w1(9, 0.0);
+        const double t1 = now();
+        const int s1 = sn_compute_batch(ctx, 1, o1, r.pos.data(), r.Z.data(), r.cell, e1.data(),
+                                        ae.data(), f.data(), w1.data());
+        if (s1 == SN_OK) {
+          if (r.atom_energy) std::memcpy(r.atom_energy, ae.data(), sizeof(double) * r.n);
+          if (r.forces) std::memcpy(r.forces, f.data(), sizeof(double) * 3 * r.n);
+        }
+        complete(this, batch, (size_t)b, 1, s1, e1, w1, t1, now(), r.n);
+        if (s1 == SN_EHIP) {
+          // the context is gone: what is left of the batch cannot run here
+          std::vector<double> none;
+          if (b + 1 < B) complete(this, batch, (size_t)b + 1, (size_t)(B - b - 1), SN_EHIP, none,
+                                  none, t1, now(), 0);
+          dead = true;
+        }
+      }
+      if (dead) break;
+      continue;
+    }
     if (st == SN_OK) {
       for (int b = 0; b < B; ++b) {
         Request& r = *batch[b];
@@ -181,7 +231,7 @@ void sn_server::worker(int w) {
         bytes_per_atom = std::max(1024.0, (double)(used - base) / (double)n);
       }
     }
-    complete(this, batch, st, e, vir, t_start, t_end, n);
+    complete(this, batch, 0, (size_t)B, st, e, vir, t_start, t_end, n);
     if (st == SN_EHIP) break;  // the context is no longer usable
   }
   if (ctx) sn_ctx_free(ctx);
@@ -221,6 +271,10 @@ int sn_server_create(const sn_model_t* model, int device, int n_streams, int pre
   s->slice = hbm_budget / (size_t)n_streams;
   s->max_batch_atoms = max_batch_atoms;
   s->max_batch_structures = max_batch_structures;
+  sn_model_info_t info;
+  if (sn_model_info(model, &info) != SN_OK) return SN_EINVAL;
+  for (int k = 0; k < info.n_species; ++k)
+    if (info.species_z[k] >= 0 && info.species_z[k] < 128) s->known_z[info.species_z[k]] = true;
   s->t0 = Clock::now();
   s->live_workers = n_streams;
   try {
@@ -240,6 +294,7 @@ int sn_server_create(const sn_model_t* model, int device, int n_streams, int pre
 
 int sn_server_submit(sn_server_t* s, const sn_request_t* req, uint64_t* ticket) {
   if (!s || !req || !ticket || req->n <= 0 || !req->pos || !req->Z || !req->cell) return SN_EINVAL;
+  if (!valid_request(s, req)) return SN_EINVAL;
   auto r = std::make_unique<Request>();
   r->n = req->n;
   try {

@@ -52,6 +52,11 @@ class VelocityVerlet:
         dev = torch.device(device)
         if rebuild_every is None and ctx.skin <= 0:
             raise ValueError("a displacement-triggered rebuild needs a context with a skin")
+        if rebuild_every is not None and rebuild_every > 1 and ctx.skin <= 0:
+            # a kept list without a skin would silently drop pairs that move inside r_c
+            raise ValueError("keeping a neighbour list between rebuilds needs a context with a skin")
+        if rebuild_every is not None and rebuild_every < 1:
+            raise ValueError("rebuild_every must be at least 1")
         self.ctx = ctx
         ctx.set_capture(capture)  # replay the steps between rebuilds from a HIP graph
         self.cell = np.ascontiguousarray(cell, dtype=np.float64)

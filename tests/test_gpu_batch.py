@@ -68,3 +68,41 @@ def test_batch_rejects_empty_structure(model_path):
     # the context stays usable after the rejected call
     r = ctx.compute_batch([(s.pos, s.Z, s.cell)])
     assert np.isfinite(r[0]["energy"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_device_batch_autograd_equals_host_batch(model_path, precision):
+    """A packed batch resident in device memory through the autograd Function (forward:
+    energies [B]; backward: per-structure upstream gradients on the device) gives the
+    host-buffer batch entry point's results bit for bit, scaled by each structure's
+    upstream gradient."""
+    mix = _mix()[:3]
+    log(f"device batch autograd precision={precision} sizes={[len(z) for _, z, _ in mix]}")
+    model = sn.Model(model_path)
+    ref = sn.Context(model, precision=precision, allocator=None).compute_batch(mix)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    ctx = sn.Context(model, precision=precision)  # workspace from torch's caching allocator
+    dev = torch.device("cuda:0")
+    offs = np.cumsum([0] + [len(z) for _, z, _ in mix])
+    pos = torch.tensor(np.concatenate([p for p, _, _ in mix]), device=dev, requires_grad=True)
+    Z = torch.tensor(np.concatenate([z for _, z, _ in mix]).astype(np.int32), device=dev)
+    cells = np.stack([c for _, _, c in mix])
+    E = sn.energies(pos, Z, cells, offs, ctx)
+    assert E.shape == (3,)
+    g = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device=dev)
+    (E * g).sum().backward()
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated() - before
+    log(f"  context memory {ctx.memory() / 2**20:.1f} MiB, torch allocator grew {held / 2**20:.1f} MiB")
+    assert held >= ctx.memory() > 0  # weights and workspace came through torch
+    grad = pos.grad.cpu().numpy()
+    W = ctx.last_virial.cpu().numpy().reshape(3, 3, 3)
+    for b in range(3):
+        assert float(E[b]) == ref[b]["energy"]
+        gb = float(g[b])
+        np.testing.assert_array_equal(-grad[offs[b]:offs[b + 1]], gb * ref[b]["forces"])
+        np.testing.assert_array_equal(W[b], gb * ref[b]["virial"])
+    ctx.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - before < held  # released back to torch

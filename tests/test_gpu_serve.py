@@ -86,3 +86,38 @@ def test_structure_too_large_for_budget(model):
     srv.close()
     assert res[t_big]["status"] == sn._lib.SN_ENOMEM
     assert res[t_small]["status"] == 0
+
+
+def test_bad_request_fails_alone(model):
+    """A request the device rejects (two atoms at one position) fails by itself; the
+    requests batched with it get the results they get alone.  One with an atomic number
+    outside the model is refused at submit."""
+    from synth import sio2_box
+    good = [sio2_box(n, seed=40 + n) for n in (8, 12, 16)]
+    bad = sio2_box(10, seed=45)
+    bad_pos = bad.pos.copy()
+    bad_pos[3] = bad_pos[7]  # r = 0 pair: found only by the graph build on the device
+    log("serve: one r = 0 request among good ones")
+    srv = Server(model, n_streams=1, precision="fp32", max_batch_atoms=4000)
+    with pytest.raises(sn.SNError):
+        srv.submit(good[0].pos, np.full(good[0].n, 120, np.int32), good[0].cell)
+    with pytest.raises(sn.SNError):
+        p = good[0].pos.copy()
+        p[0, 0] = np.nan
+        srv.submit(p, good[0].Z, good[0].cell)
+    # hold the worker on a first request so the next four queue up and form one batch
+    first = srv.submit(good[0].pos, good[0].Z, good[0].cell)
+    tickets = [srv.submit(s.pos, s.Z, s.cell) for s in good[1:2]]
+    t_bad = srv.submit(bad_pos, bad.Z, bad.cell)
+    tickets += [srv.submit(s.pos, s.Z, s.cell) for s in good[2:]]
+    res = _drain(srv, 4, timeout_s=60)
+    srv.close()
+    log(f"  batch sizes: {[res[t]['batch_structures'] for t in [first] + tickets + [t_bad]]}")
+    assert res[t_bad]["status"] == sn._lib.SN_EINVAL
+    assert res[first]["status"] == 0
+    ctx = sn.Context(model, precision="fp32")
+    for tk, s in zip(tickets, good[1:]):
+        assert res[tk]["status"] == 0
+        alone = ctx.compute(s.pos, s.Z, s.cell)
+        assert res[tk]["energy"] == alone["energy"]
+        np.testing.assert_array_equal(res[tk]["forces"], alone["forces"])
