@@ -153,6 +153,23 @@ int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, co
                const uint8_t* pbc, double* energy, double* atom_energy, double* forces,
                double* virial);
 
+/* ---- the same evaluation without allocating device memory ------------------------
+ * For callers that cannot allocate device memory (code around HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sn_compute with the same arguments,
+ * outputs and errors, whose every device buffer is a slice of a fixed array of 512 MiB
+ * that the library holds per device (allocated with the library's code object and kept
+ * until the process ends).  The call allocates and frees nothing on the device; it always
+ * builds its own graph and keeps no state after it returns (a later sn_ctx_graph sees no
+ * graph).  A structure whose workspace does not fit the array fails with SN_ENOMEM and a
+ * message naming the size (the context stays usable; roughly 500 atoms of the five-block
+ * l <= 2 model of section 5.1 fit).  The array is shared by every context and thread on a
+ * device and keeps the last call's contents: calls that overlap on one device (other
+ * threads, other contexts' streams) race and must be serialised by the caller.
+ * Blocks until done. */
+int sn_compute_noalloc(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z,
+                       const double* cell, const uint8_t* pbc, double* energy,
+                       double* atom_energy, double* forces, double* virial);
+
 /* ---- several structures in one packed graph, host buffers --------------------------
  * The evaluation of sn_compute (paper section 2, eqs 1-2, 5-6) for a batch: the graph of
  * section 3.1 built once over all structures, with edges inside each structure only.

@@ -134,8 +134,9 @@ class Context:
         except Exception:
             pass
 
-    def compute(self, pos, Z, cell, forces=True, virial=True) -> dict:
-        """Host-buffer evaluation: E, per-atom E, F, W (float64)."""
+    def compute(self, pos, Z, cell, forces=True, virial=True, noalloc=False) -> dict:
+        """Host-buffer evaluation: E, per-atom E, F, W (float64).  noalloc=True runs
+        sn_compute_noalloc (no device allocation: the library's static scratch)."""
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         Z = np.ascontiguousarray(Z, dtype=np.int32)
         cell = np.ascontiguousarray(cell, dtype=np.float64)
@@ -145,8 +146,9 @@ class Context:
         f = np.zeros((n, 3)) if forces else None
         w = np.zeros((3, 3)) if virial else None
         pbc = (C.c_uint8 * 3)(1, 1, 1)
-        check(lib().sn_compute(self._h, n, ptr(pos), ptr(Z), ptr(cell), C.cast(pbc, C.c_void_p),
-                               ptr(e), ptr(ae), ptr(f), ptr(w)), self._h)
+        fn = lib().sn_compute_noalloc if noalloc else lib().sn_compute
+        check(fn(self._h, n, ptr(pos), ptr(Z), ptr(cell), C.cast(pbc, C.c_void_p),
+                 ptr(e), ptr(ae), ptr(f), ptr(w)), self._h)
         out = dict(energy=float(e[0]), atom_energy=ae)
         if forces:
             out["forces"] = f

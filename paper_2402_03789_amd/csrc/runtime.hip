@@ -22,6 +22,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <stdexcept>
 #include <string>
@@ -47,6 +48,10 @@ struct MemError : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
 struct UnsupportedError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+// the static scratch of sn_compute_noalloc is too small for the request
+struct ScratchError : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
 
@@ -369,7 +374,36 @@ struct sn_ctx {
     weight_blocks[p] = bytes;
     return p;
   }
+  // Fixed-arena mode (sn_compute_noalloc): every buffer is a slice of caller-provided device
+  // memory, handed out in request order; growing a buffer moves it to a new slice (its
+  // contents are dropped, as when a pool buffer grows).  Nothing is allocated or freed.
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_top = 0;
+  std::map<std::string, std::pair<size_t, size_t>> arena_slots;  // name -> (offset, bytes)
+  void* arena_raw(const std::string& name, size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    auto it = arena_slots.find(name);
+    if (it != arena_slots.end()) {
+      if (bytes <= it->second.second) return arena + it->second.first;
+      if (it->second.first + it->second.second == arena_top &&
+          it->second.first + bytes <= arena_cap) {  // the newest slice grows in place
+        arena_top = it->second.first + bytes;
+        it->second.second = bytes;
+        return arena + it->second.first;
+      }
+    }
+    if (arena_top + bytes > arena_cap)
+      throw ScratchError("the request needs more than the " + std::to_string(arena_cap >> 20) +
+                         " MiB static scratch (buffer " + name + " of " +
+                         std::to_string(bytes) + " bytes at offset " +
+                         std::to_string(arena_top) + ")");
+    arena_slots[name] = {arena_top, bytes};
+    void* p = arena + arena_top;
+    arena_top += bytes;
+    return p;
+  }
   void* raw(const std::string& name, size_t bytes) {
+    if (arena) return arena_raw(name, bytes);
     Buf& b = bufs[name];
     if (bytes <= b.cap) return b.p;
     size_t want = std::max(bytes + bytes / 4, (size_t)256);
@@ -1205,6 +1239,19 @@ int guarded(sn_ctx* c, F&& f) {
   } catch (const ArgError& e) {
     if (c) c->err = e.what();
     return SN_EINVAL;
+  } catch (const ScratchError& e) {
+    if (c) {
+      c->err = e.what();
+      // kernels of the refused call may still run on either stream over the shared scratch:
+      // let them finish before another call reuses it
+      bool ok = hipStreamSynchronize(c->stream) == hipSuccess;
+      if (c->aux && hipStreamSynchronize(c->aux) != hipSuccess) ok = false;
+      if (!ok) {
+        c->dead = true;
+        return SN_EHIP;
+      }
+    }
+    return SN_ENOMEM;
   } catch (const MemError& e) {
     if (c) {
       c->err = e.what();
@@ -1380,6 +1427,78 @@ void map_species(const sn_model* m, int64_t n, const int32_t* Z, std::vector<int
     if (z < 0 || z >= 128 || m->lut[z] < 0) throw ArgError("atomic number not in the model");
     out[i] = m->lut[z];
   }
+}
+
+// The host-buffer evaluation of B packed structures (sn_compute_batch, sn_compute and
+// sn_compute_noalloc): inputs copied in, forward and adjoint, results copied out.
+void compute_batch_host(sn_ctx_t* ctx, int B, const int64_t* offsets, const double* pos,
+                     const int32_t* Z, const double* cells, double* energies,
+                     double* atom_energies, double* forces, double* virials) {
+  const int64_t n = offsets[B];
+  {
+    std::vector<int> spec;
+    map_species(ctx->m, n, Z, spec);
+    for (int64_t i = 0; i < 3 * n; ++i)
+      if (!std::isfinite(pos[i])) throw ArgError("non-finite positions");
+    hipStream_t s = ctx->stream;
+    double* d_pos = ctx->get<double>("in_pos", 3 * n);
+    int* d_spec = ctx->get<int>("spec_orig", n);
+    // staging for the results: B energies, B virials, n atom energies, n x 3 forces
+    double* d_out = ctx->get<double>("out_host_stage", 10 * (int64_t)B + 4 * n);
+    HIPCHK(hipMemcpyAsync(d_pos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    double* d_e = d_out;
+    double* d_w = d_out + B;
+    double* d_ae = d_out + 10 * (int64_t)B;
+    double* d_f = d_ae + n;
+    const bool need_bwd = forces || virials;
+    if (ctx->precision == SN_FP64) {
+      forward_impl<double, double>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
+      if (need_bwd) backward_impl<double, double>(ctx, nullptr, d_f, d_w);
+    } else if (ctx->precision == SN_BF16) {
+      forward_impl<float, bf16_t>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
+      if (need_bwd) backward_impl<float, bf16_t>(ctx, nullptr, d_f, d_w);
+    } else {
+      forward_impl<float, float>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
+      if (need_bwd) backward_impl<float, float>(ctx, nullptr, d_f, d_w);
+    }
+    ctx->pending = false;
+    std::vector<double> h((size_t)(10 * (int64_t)B + 4 * n));
+    HIPCHK(hipMemcpyAsync(h.data(), d_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    collect_timings(ctx);
+    std::memcpy(energies, &h[0], B * sizeof(double));
+    if (virials) std::memcpy(virials, &h[B], 9 * (size_t)B * sizeof(double));
+    if (atom_energies) std::memcpy(atom_energies, &h[10 * (size_t)B], n * sizeof(double));
+    if (forces) std::memcpy(forces, &h[10 * (size_t)B + n], 3 * n * sizeof(double));
+  }
+}
+
+
+// ------------------------------------------------------------------ static scratch
+// Device memory of sn_compute_noalloc: one array per device, allocated with the code object
+// and held until the process ends.  Host code never passes the symbol itself to a kernel:
+// it uses the device address that hipGetSymbolAddress returns, looked up once per device
+// with that device current.
+}  // namespace
+
+constexpr size_t kScratchBytes = (size_t)512 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;  // device -> address of its scratch
+
+char* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));  // the caller made device current
+  if (!p || (reinterpret_cast<uintptr_t>(p) & 255)) throw HipError("static scratch not aligned");
+  g_scratch_ptr[device] = static_cast<char*>(p);
+  return static_cast<char*>(p);
 }
 
 }  // namespace
@@ -1583,43 +1702,8 @@ int sn_compute_batch(sn_ctx_t* ctx, int B, const int64_t* offsets, const double*
   if (offsets[0] != 0) return SN_EINVAL;
   for (int b = 0; b < B; ++b)
     if (offsets[b + 1] <= offsets[b]) return SN_EINVAL;
-  const int64_t n = offsets[B];
   return guarded(ctx, [&] {
-    std::vector<int> spec;
-    map_species(ctx->m, n, Z, spec);
-    for (int64_t i = 0; i < 3 * n; ++i)
-      if (!std::isfinite(pos[i])) throw ArgError("non-finite positions");
-    hipStream_t s = ctx->stream;
-    double* d_pos = ctx->get<double>("in_pos", 3 * n);
-    int* d_spec = ctx->get<int>("spec_orig", n);
-    // staging for the results: B energies, B virials, n atom energies, n x 3 forces
-    double* d_out = ctx->get<double>("out_host_stage", 10 * (int64_t)B + 4 * n);
-    HIPCHK(hipMemcpyAsync(d_pos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-    double* d_e = d_out;
-    double* d_w = d_out + B;
-    double* d_ae = d_out + 10 * (int64_t)B;
-    double* d_f = d_ae + n;
-    const bool need_bwd = forces || virials;
-    if (ctx->precision == SN_FP64) {
-      forward_impl<double, double>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
-      if (need_bwd) backward_impl<double, double>(ctx, nullptr, d_f, d_w);
-    } else if (ctx->precision == SN_BF16) {
-      forward_impl<float, bf16_t>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
-      if (need_bwd) backward_impl<float, bf16_t>(ctx, nullptr, d_f, d_w);
-    } else {
-      forward_impl<float, float>(ctx, B, offsets, d_pos, d_spec, cells, d_e, d_ae);
-      if (need_bwd) backward_impl<float, float>(ctx, nullptr, d_f, d_w);
-    }
-    ctx->pending = false;
-    std::vector<double> h((size_t)(10 * (int64_t)B + 4 * n));
-    HIPCHK(hipMemcpyAsync(h.data(), d_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    collect_timings(ctx);
-    std::memcpy(energies, &h[0], B * sizeof(double));
-    if (virials) std::memcpy(virials, &h[B], 9 * (size_t)B * sizeof(double));
-    if (atom_energies) std::memcpy(atom_energies, &h[10 * (size_t)B], n * sizeof(double));
-    if (forces) std::memcpy(forces, &h[10 * (size_t)B + n], 3 * n * sizeof(double));
+    compute_batch_host(ctx, B, offsets, pos, Z, cells, energies, atom_energies, forces, virials);
   });
 }
 
@@ -1633,6 +1717,40 @@ int sn_compute(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z, co
   }
   const int64_t off[2] = {0, n};
   return sn_compute_batch(ctx, 1, off, pos, Z, cell, energy, atom_energy, forces, virial);
+}
+
+int sn_compute_noalloc(sn_ctx_t* ctx, int64_t n, const double* pos, const int32_t* Z,
+                       const double* cell, const uint8_t* pbc, double* energy,
+                       double* atom_energy, double* forces, double* virial) {
+  if (!ctx || !pos || !Z || !cell || !energy || n <= 0) return SN_EINVAL;
+  if (pbc && !(pbc[0] && pbc[1] && pbc[2])) {
+    ctx->err = "only fully periodic cells are supported";
+    return SN_EUNSUPPORTED;
+  }
+  const int64_t off[2] = {0, n};
+  return guarded(ctx, [&] {
+    char* base = scratch_address(ctx->device);  // guarded() made the device current
+    // every buffer of this call is a slice of the device's scratch; the call always builds
+    // its own graph, and none of its state survives it
+    struct ArenaScope {
+      sn_ctx* c;
+      ArenaScope(sn_ctx* cc, char* b) : c(cc) {
+        c->arena = b;
+        c->arena_cap = kScratchBytes;
+        c->arena_top = 0;
+        c->arena_slots.clear();
+        c->have_graph = false;
+        c->pending = false;
+      }
+      ~ArenaScope() {
+        c->arena = nullptr;
+        c->arena_slots.clear();
+        c->have_graph = false;
+        c->pending = false;
+      }
+    } scope(ctx, base);
+    compute_batch_host(ctx, 1, off, pos, Z, cell, energy, atom_energy, forces, virial);
+  });
 }
 
 int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, int64_t* n_edge) {
@@ -1714,6 +1832,10 @@ int sn_ctx_graph(const sn_ctx_t* cctx, int32_t* recv, int32_t* send_owner, int32
                  int32_t* ghost_owner, int32_t* ghost_shift) {
   sn_ctx_t* ctx = const_cast<sn_ctx_t*>(cctx);
   if (!ctx) return SN_EINVAL;
+  if (!ctx->have_graph) {  // none built, or released, or built in the static scratch
+    ctx->err = "no graph is held by the context";
+    return SN_EBUSY;
+  }
   return guarded(ctx, [&] {
     const int N = ctx->N, G = ctx->G;
     const int64_t E = ctx->E;
