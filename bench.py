@@ -79,70 +79,88 @@ def _tp_forward_flops(spec, cg_nnz):
                 for (l1, l2, l3) in spec._paths(t)) for t in range(spec.n_layers)]
 
 
-def _step_roofline(spec, cg_nnz, n, g, e, npairs, precision, ms, iso):
-    """Lower bound of one evaluation from the algorithmic work of its modelled kernels:
-    the sum over them of max(flops / peak, bytes / 8 TB/s), against the measured step.
+def _linear_flops(spec, n, g):
+    """Channel-mixing GEMM flops of one evaluation (forward and the adjoint's input
+    gradients): Lin1 (block 1 also on the ghost rows), Linsc and Lin2 per degree, rows =
+    atoms x (2l + 1); the adjoint repeats Lin2 in every block and Lin1, Linsc in blocks
+    after the first (the first block's inputs are the species embedding); readout."""
+    f = 0
+    for t in range(spec.n_layers):
+        paths = spec._paths(t)
+        rows1 = (n + g) if t == 0 else n
+        for l in spec._in_ls(t):
+            m = spec.muls[l]
+            fl1 = 2 * rows1 * (2 * l + 1) * m * m
+            fsc = 2 * n * (2 * l + 1) * m * spec._gate_mul(t, l)
+            f += fl1 + fsc + ((2 * n * (2 * l + 1) * m * m + fsc) if t > 0 else 0)
+        for l in spec._out_ls(t):
+            mid = sum(spec.muls[l1] for (l1, _, l3) in paths if l3 == l)
+            f += 2 * 2 * n * (2 * l + 1) * mid * spec._gate_mul(t, l)
+    C0 = spec.muls[0]
+    return f + 2 * 2 * n * C0 * (C0 // 2)
 
-    Modelled per interaction block (b = storage bytes of w, dE/dw, x and dE/dx rows; tb = 4,
-    8 in FP64): radial-MLP forward (2 (8 64 + 64 64 + 64 P) flops per pair on the matrix
-    cores; writes w, reads rho: b P + 32 bytes per pair); tensor-product forward (per edge
-    the pair's w slice and Y, b P + nY tb; every sender row once and every message row
-    written once; vector-ALU peak); tensor-product adjoint (the same unit as the headline
-    roofline); radial-MLP adjoint (2 64 P + 2 (8 64 + 2 64 64 + 64 8) flops and 2 b P + 64
-    bytes per pair); per-edge dE/dx rows summed per sender and folded onto owners (read
-    E Dx b, write and read (n + g) Dx 8, write n Dx 8).  Node GEMMs, gates, graph build,
-    basis, readout and forces are not modelled and add nothing to the bound, so the
-    fraction is a lower estimate; `modelled_share` is the modelled phases' part of the
-    single-stream (isolated) phase time."""
+
+def _algorithmic_work(spec, cg_nnz, n, g, e, npairs, precision):
+    """Algorithmic flops F and minimum HBM bytes B of one E + F evaluation by work class,
+    as the hot-path measurement section prices them:
+      radial MLP  -- 8 -> 64 -> 64 -> P_t per undirected pair (w depends on |d| only), forward
+                     and input-gradient adjoint: 2 x 2 (8 64 + 64 64 + 64 P_t) flops per pair
+                     and block; bytes: the radial basis of every edge read once;
+      tensor product -- per edge and block, forward 3 flops per CG nonzero and channel plus
+                     2 (2 l3 + 1) per path and channel, adjoint 9 per nonzero and channel plus
+                     3 (2 l3 + 1) (6 per nonzero in the first block, which has no dE/dx);
+                     bytes: every sender feature row read, every message row written and its
+                     adjoint read (float32), every sender's dE/dx row written (float64);
+      linears     -- the channel-mixing GEMMs (forward and adjoint); bytes: node state read
+                     and written once per block in each direction (float64).
+    Peaks: radial MLP and linears on the matrix cores of the form's operand type (float32
+    157.3 TFLOP/s; bfloat16 2,500), the tensor product on the float32 vector units (157.3),
+    float64 78.6; HBM 8 TB/s."""
     b = {"fp32": 4, "bf16": 2, "fp64": 8}[precision]
     tb = 8 if precision == "fp64" else 4
-    mlp_peak = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[precision] * 1e12
+    mm_peak = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[precision] * 1e12
     alu_peak = (78.6 if precision == "fp64" else 157.3) * 1e12
-    hbm = 8000e9
-    ny = (spec.l_sh + 1) ** 2
     fwd_f = _tp_forward_flops(spec, cg_nnz)
     bwd_f = _tp_adjoint_flops(spec, cg_nnz)
-    kinds = {}
-
-    def add(kind, phase, flops, nbytes, peak):
-        t = max(flops / peak if flops else 0.0, nbytes / hbm) * 1e3
-        k = kinds.setdefault(kind, {"flops": 0.0, "bytes": 0.0, "bound_ms": 0.0, "isolated_ms": 0.0})
-        k["flops"] += flops
-        k["bytes"] += nbytes
-        k["bound_ms"] += t
-        k["isolated_ms"] += iso.get(phase, 0.0)
-
+    mlp_f = tp_f = tp_b = lin_b = 0
     for t, (P, Dx, Dm, wdx) in enumerate(_tp_blocks(spec)):
-        add("mlp_fwd", f"layer{t}.mlp", npairs * 2 * (8 * 64 + 64 * 64 + 64 * P),
-            npairs * (b * P + 32), mlp_peak)
-        add("tp_fwd", f"layer{t}.tp", e * fwd_f[t],
-            e * (b * P + ny * tb) + (n + g) * Dx * b + n * Dm * tb, alu_peak)
-        add("tp_bwd", f"bwd.layer{t}.tp", e * bwd_f[t],
-            e * (2 * b * P + (b * Dx if wdx else 0) + 3 * 3 * ny * tb) + n * Dm * tb
-            + (n + g) * Dx * b, alu_peak)
-        add("mlp_bwd", f"bwd.layer{t}.mlp",
-            npairs * (2 * 64 * P + 2 * (8 * 64 + 2 * 64 * 64 + 64 * 8)),
-            npairs * (2 * b * P + 64), mlp_peak)
-        if wdx:
-            add("sender_fold", f"bwd.layer{t}.sender_fold", 0,
-                e * Dx * b + 2 * (n + g) * Dx * 8 + n * Dx * 8, alu_peak)
-    bound = sum(k["bound_ms"] for k in kinds.values())
-    iso_all = sum(iso.values())
-    iso_mod = sum(k["isolated_ms"] for k in kinds.values())
-    return {"bound": "per kernel max(flops/peak, bytes/HBM), summed", "lower_bound_ms": bound,
-            "ms_per_step": ms, "frac": bound / ms if ms > 0 else None,
-            "modelled_share": iso_mod / iso_all if iso_all > 0 else None, "kernels": kinds}
+        mlp_f += npairs * 2 * 2 * (8 * 64 + 64 * 64 + 64 * P)
+        tp_f += e * (fwd_f[t] + bwd_f[t])
+        tp_b += (n + g) * Dx * b + 2 * n * Dm * tb + ((n + g) * Dx * 8 if wdx else 0)
+        hin = sum(spec.muls[l] * (2 * l + 1) for l in spec._in_ls(t))
+        yw = sum(spec._gate_mul(t, l) * (2 * l + 1) for l in spec._out_ls(t))
+        lin_b += 2 * n * (hin + 2 * yw) * 8
+    return {
+        "radial_mlp": {"flops": mlp_f, "bytes": e * 8 * tb, "peak_flops": mm_peak},
+        "tensor_product": {"flops": tp_f, "bytes": tp_b, "peak_flops": alu_peak},
+        "linears": {"flops": _linear_flops(spec, n, g), "bytes": lin_b, "peak_flops": mm_peak},
+    }
 
 
-def _roofline_entry(kernel, nbytes, nflops, ms, traffic, peak_tf):
+def _step_roofline(work, ms):
+    """Whole-step fraction of roofline: sum over work classes of max(F/P, B/BW) against the
+    measured step time (inputs resident in HBM, graph build included in the step)."""
+    hbm = 8000e9
+    kinds = {}
+    bound = 0.0
+    for k, w in work.items():
+        t = max(w["flops"] / w["peak_flops"], w["bytes"] / hbm) * 1e3
+        kinds[k] = {"flops": w["flops"], "bytes": w["bytes"], "peak_TFLOPs": w["peak_flops"] / 1e12,
+                    "bound_ms": t}
+        bound += t
+    return {"bound": "sum over work classes of max(flops/peak, bytes/8 TB/s)",
+            "lower_bound_ms": bound, "ms_per_step": ms, "frac": bound / ms if ms > 0 else None,
+            "classes": kinds}
+
+
+def _impl_traffic_entry(kernel, nbytes, ms, traffic):
+    """The dominant kernel against HBM with the bytes this implementation's data layout
+    makes it move (per-edge weight, dE/dw and dE/dx rows): how close the kernel runs to the
+    bandwidth its own traffic needs, not an algorithmic bound."""
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
-    e = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-         "frac": (achieved / 8000.0) if achieved else None, "traffic": traffic,
-         "launch_ms": ms, "algorithmic_bytes_per_launch": nbytes}
-    if nflops:
-        e["algorithmic_flops_per_launch"] = nflops
-        e["mfma_frac"] = nflops / (ms * 1e-3) / 1e12 / peak_tf if ms > 0 else None
-    return e
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+            "frac": (achieved / 8000.0) if achieved else None, "traffic": traffic,
+            "launch_ms": ms, "implementation_bytes_per_launch": nbytes}
 
 
 def main():
@@ -152,6 +170,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the BF16-form steps timed beside the FP32 headline")
     ap.add_argument("--no-isolated", action="store_true",
                     help="skip the evaluations after the timed steps (the single-stream context "
                          "that times the roofline kernels in isolation, the kept-list steps, "
@@ -186,6 +206,8 @@ def main():
                     help="requests of the serving stream to replay: default 400 beside the "
                          "headline line (0 to skip), 2,000 for --workload serving")
     ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--serve-high-rate", type=float, default=5000.0,
+                    help="second replay of the serving stream at this arrival rate (per s)")
     ap.add_argument("--domains", default="1,1,1",
                     help="nx,ny,nz spatial subdomains of the 24k-atom box, each with its own "
                          "ghost shell (halo refresh and fold in device memory)")
@@ -245,10 +267,61 @@ def main():
     tmp = tempfile.mkdtemp()
     wpath = os.path.join(tmp, "model.snw")
     write_weights(wpath, spec, weights)
+    domains = tuple(int(v) for v in args.domains.split(","))
+
+    head = _run_form(args, sn, torch, wpath, spec, s, args.precision, domains, extras=True)
+    bf16 = None
+    if args.precision == "fp32" and not args.no_bf16:
+        torch.cuda.empty_cache()
+        r = _run_form(args, sn, torch, wpath, spec, s, "bf16", domains, extras=False)
+        bf16 = {k: r[k] for k in ("value", "unit", "ms_per_step", "steps", "roofline",
+                                  "roofline_step")}
+        bf16["dtype"] = "bf16"
+
+    cpu = None if args.no_cpu_baseline else _cpu_baseline(args, spec, weights)
+
+    serving = None
+    count = 400 if args.serve_requests is None else args.serve_requests
+    if count > 0:
+        torch.cuda.empty_cache()
+        serving = bench_serving(args, count, args.precision, full=False)
+
+    out = {
+        "metric": "atom-steps/s (E+F), 5-layer l<=2 model, 24k-atom SiO2",
+        "value": head["value"], "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "SiO2 24,000 atoms (8,000 Si + 16,000 O), 2.2 g/cm^3, periodic cubic "
+                               "71.32 A; 5 blocks 128x0e+64x1e+32x2e, l<=2, r_c 5 A; E+F+virial "
+                               "as one subdomain + r_c ghost shell",
+                   "n_atoms": head["n"], "n_ghost": head["g"], "n_edges": head["e"],
+                   "precision": args.precision, "subdomains": list(domains)},
+        "roofline": head["roofline"],
+        "roofline_step": head["roofline_step"],
+        "bf16": bf16,
+        "cpu_baseline": cpu,
+        "implementation_traffic": head.get("implementation_traffic"),
+        "roofline_mlp_adjoint": head.get("roofline_mlp_adjoint"),
+        "list_reused": head.get("list_reused"),
+        "host_buffers": head.get("host_buffers"),
+        "phases_ms": head["phases_ms"],
+        "serving": serving,
+    }
+    print(json.dumps(out))
+
+
+def _run_form(args, sn, torch, wpath, spec, s, precision, domains, extras):
+    """Time `args.steps` evaluations (graph build, forward, adjoint, forces, virial) of the
+    24k-atom box in one precision form on device-resident inputs, after `args.warmup`
+    untimed ones, and price them against the algorithmic roofline.  With `extras`: also
+    the kept-list steps, the host-buffer entry point, the single-stream (isolated) kernel
+    times and the implementation-traffic figures."""
+    import numpy as np
 
     dev = torch.device("cuda:0")
-    ctx = sn.Context(sn.Model(wpath), device=0, precision=args.precision)
-    domains = tuple(int(v) for v in args.domains.split(","))
+    ctx = sn.Context(sn.Model(wpath), device=0, precision=precision)
     if domains != (1, 1, 1):
         ctx.set_domains(*domains)
     pos = torch.tensor(s.pos, dtype=torch.float64, device=dev)
@@ -261,7 +334,7 @@ def main():
         ctx.forward_device(pos, Z, s.cell, energy)
         ctx.backward_device(1.0, forces, virial)
 
-    if args.calib_copy:
+    if args.calib_copy and extras:
         buf = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         buf.fill_(1.0)
         out_buf = buf.clone()
@@ -281,11 +354,48 @@ def main():
     dt = time.perf_counter() - t0
     ms = dt / args.steps * 1e3
     n, g, e = ctx.graph_size()
-    value = s.n * args.steps / dt
+    npairs = ctx.n_pairs()
+    print(f"bench: {precision} {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    def cg_nnz(l1, l2, l3):
+        return int(np.count_nonzero(np.abs(sn.cg_table(l1, l2, l3)) > 1e-12))
+
+    # Headline roofline object: the dominant kernel, the tensor-product adjoint (k_tp_bwd).
+    # Unit: the adjoint of one interaction block, i.e. its per-degree launches, which form
+    # exactly the "bwd.layer<t>.tp" phase timed by HIP events on the context's stream
+    # (averaged over the blocks).  Its work is vector-ALU arithmetic: per edge and block,
+    # 9 flops per CG nonzero and channel (t = C x Y, dE/dx += C Y gg, dE/dY += C x gg; 6 in
+    # the first block, which writes no dE/dx) plus 3 (2 l3 + 1) per path and channel
+    # (dE/dw = G . t, gg = w G), nonzeros from the library's own tables, against the
+    # published float32 vector peak (157.3 TFLOP/s, which counts packed two-wide FP32
+    # instructions; the library builds without them, so 78.6 is what it can reach).
+    blocks = _tp_blocks(spec)
+    tp_phases = [f"bwd.layer{t}.tp" for t in range(len(blocks))]
+    tp_ms = sum(phase_ms.get(k, 0.0) for k in tp_phases) / (len(tp_phases) * args.steps)
+    flops_tp = sum(e * f for f in _tp_adjoint_flops(spec, cg_nnz)) / len(blocks)
+    alu_peak = 78.6 if precision == "fp64" else 157.3
+    alu_tf = flops_tp / (tp_ms * 1e-3) / 1e12 if tp_ms > 0 else None
+    tp_src = os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_tp.hip")
+    roofline = {"bound": "alu", "kernel": "k_tp_bwd (tensor-product adjoint; one interaction "
+                                          "block = its degree launches)",
+                "achieved": alu_tf, "peak": alu_peak, "unit": "TFLOP/s",
+                "frac": alu_tf / alu_peak if alu_tf else None,
+                "traffic": _traffic("k_tp_bwd", tp_src, precision),
+                "launch_ms": tp_ms, "algorithmic_flops_per_launch": flops_tp,
+                "attainable_peak_unpacked": 78.6,
+                "attainable_frac": alu_tf / 78.6 if alu_tf else None}
+    work = _algorithmic_work(spec, cg_nnz, n, g, e, npairs, precision)
+    out = {"value": s.n * args.steps / dt, "unit": "atom-steps/s", "ms_per_step": ms,
+           "steps": args.steps, "n": n, "g": g, "e": e, "roofline": roofline,
+           "roofline_step": _step_roofline(work, ms),
+           "phases_ms": {k: v / args.steps for k, v in phase_ms.items()}}
+    if not extras:
+        del ctx
+        return out
 
     # The same evaluation with the neighbour list kept from the last build (positions
     # unchanged, so the kept graph is exact): every step without the graph build.
-    list_reused = None
+    list_reused = host_buffers = None
     if not args.no_isolated:
         f_ref = forces.clone()
         ctx.set_graph_reuse(True)
@@ -302,11 +412,8 @@ def main():
                        "value": s.n * args.steps / rdt, "unit": "atom-steps/s",
                        "max_abs_dF_vs_rebuild": float((forces - f_ref).abs().max())}
         del f_ref
-
-    # The same evaluation through the host-buffer entry point (positions in, energies,
-    # forces and virial out over PCIe, one synchronisation per call): reported beside the
-    # device-resident rate, never as the value.
-    host_buffers = None
+    # The host-buffer entry point (positions in, energies, forces and virial out over PCIe,
+    # one synchronisation per call): reported beside the device-resident rate, never as it.
     if args.host_steps > 0 and not args.no_isolated:
         ctx.compute(s.pos, s.Z, s.cell)
         t1 = time.perf_counter()
@@ -317,32 +424,17 @@ def main():
                         "ms_per_step": hdt / args.host_steps * 1e3,
                         "value": s.n * args.host_steps / hdt, "unit": "atom-steps/s"}
 
-    # Roofline of the dominant kernel, the tensor-product adjoint (k_tp_bwd, about a third
-    # of the GPU time of a step).  Unit: the adjoint of one interaction block, i.e. its
-    # per-degree launches, which are exactly the "bwd.layer<t>.tp" phase timed by HIP events
-    # on the context's stream; averaged over the five blocks.  Algorithmic bytes of block t
-    # (b = storage bytes of w, dE/dw and the dE/dx rows: 4 in FP32, 2 in BF16, 8 in FP64):
-    # per edge, read the pair's w slice and write dE/dw (2 b P_t), write the dE/dx row
-    # (b Dx_t, not in the first block) and, per degree launch, read Y and read and write
-    # dE/dY (3 x 9 x 4 bytes each); per receiver, read G (Dm_t x 4 bytes); every sender row
-    # once (NE x Dx_t x b: the per-edge gathers of x hit the caches).
-    wbytes = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
-    tbytes = 8 if args.precision == "fp64" else 4
-    blocks = _tp_blocks(spec)
+    # Implementation traffic of the dominant kernel: per edge the pair's w slice read and
+    # dE/dw written (2 b P_t), the dE/dx row written (b Dx_t, not in the first block), per
+    # degree launch Y read and dE/dY read and written; per receiver its G rows; every
+    # sender row once.  b = storage bytes of w, dE/dw, x and dE/dx (4 FP32, 2 BF16, 8 FP64).
+    wbytes = {"fp32": 4, "bf16": 2, "fp64": 8}[precision]
+    tbytes = 8 if precision == "fp64" else 4
     tp_bytes = [e * (2 * wbytes * P + (wbytes * Dx if wdx else 0) + 3 * 3 * 9 * tbytes)
                 + n * Dm * tbytes + (n + g) * Dx * wbytes for (P, Dx, Dm, wdx) in blocks]
-    bytes_tp = sum(tp_bytes) / len(tp_bytes)
-    tp_phases = [f"bwd.layer{t}.tp" for t in range(len(blocks))]
-    tp_ms = sum(phase_ms.get(k, 0.0) for k in tp_phases) / (len(tp_phases) * args.steps)
-    roofline = _roofline_entry(
-        "k_tp_bwd (tensor-product adjoint; one interaction block = its degree launches)",
-        bytes_tp, None, tp_ms,
-        _traffic("k_tp_bwd", os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_tp.hip"),
-                 args.precision), None)
-    # Practical streaming ceiling of this part: a 1 GiB device-to-device copy (reads and
-    # writes 1 GiB each), timed with events on the current stream after the timed steps.
-    # (Skipped in counter runs, whose calibration is the one 256 MiB copy of --calib-copy.)
-    copy_gbps = None
+    impl = _impl_traffic_entry("k_tp_bwd (same unit)", sum(tp_bytes) / len(tp_bytes), tp_ms,
+                               roofline["traffic"])
+    # practical streaming ceiling: a 1 GiB device copy timed with events (not in counter runs)
     if not args.calib_copy:
         cbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         cdst = torch.empty_like(cbuf)
@@ -353,52 +445,35 @@ def main():
             cdst.copy_(cbuf)
         ev1.record()
         torch.cuda.synchronize()
-        copy_gbps = 5 * 2 * cbuf.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+        impl["copy_GBps"] = 5 * 2 * cbuf.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+        impl["frac_of_copy"] = impl["achieved"] / impl["copy_GBps"] if impl["achieved"] else None
         del cbuf, cdst
-    if roofline["achieved"] and copy_gbps:
-        roofline["copy_GBps"] = copy_gbps
-        roofline["frac_of_copy"] = roofline["achieved"] / copy_gbps
-    # The same launches against the vector ALUs: algorithmic flops per block (CG nonzeros
-    # from the library's own tables), against the published vector peak (fp32 157.3 TFLOP/s
-    # counts packed two-wide FP32 instructions, which the library's kernels do not emit, so 78.6 is
-    # the attainable ceiling; fp64 78.6).
-    import numpy as np
 
-    def cg_nnz(l1, l2, l3):
-        return int(np.count_nonzero(np.abs(sn.cg_table(l1, l2, l3)) > 1e-12))
-    flops_tp = sum(e * f for f in _tp_adjoint_flops(spec, cg_nnz)) / len(blocks)
-    alu_peak, alu_attainable = (78.6, 78.6) if args.precision == "fp64" else (157.3, 78.6)
-    alu_tf = flops_tp / (tp_ms * 1e-3) / 1e12 if tp_ms > 0 else None
-    roofline_alu = {"bound": "alu", "kernel": "k_tp_bwd (same unit)", "achieved": alu_tf,
-                    "peak": alu_peak, "unit": "TFLOP/s",
-                    "frac": alu_tf / alu_peak if alu_tf else None,
-                    "attainable_peak": alu_attainable,
-                    "attainable_frac": alu_tf / alu_attainable if alu_tf else None,
-                    "algorithmic_flops_per_launch": flops_tp, "launch_ms": tp_ms}
-
-    # The radial-MLP adjoint (one launch per block, "bwd.layer<t>.mlp" on the MLP stream):
-    # read dE/dw of both edges of every pair (2 b P), read rho and write drho (2 x 32 bytes).
-    npairs = ctx.n_pairs()
-    Ps = [b[0] for b in blocks]
+    # The radial-MLP adjoint (one launch per block on the MLP stream): per pair, dE/dw of
+    # both edges read (2 b P), rho read and drho written; matrix-core flops of
+    # dz2 = dE/dw Wc^T and the two hidden layers' adjoints.
+    Ps = [bk[0] for bk in blocks]
     mlp_phases = [f"bwd.layer{t}.mlp" for t in range(len(blocks))]
     mlp_ms = sum(phase_ms.get(k, 0.0) for k in mlp_phases) / (len(mlp_phases) * args.steps)
     P_mean = sum(Ps) / len(Ps)
     bytes_mlp = npairs * (2 * wbytes * P_mean + 64)
     flops_mlp = npairs * (2 * 64 * P_mean + 2 * (8 * 64 + 64 * 64 + 64 * 64 + 64 * 8))
-    peak_tf = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[args.precision]
-    roofline_mlp = _roofline_entry(
-        "k_mlp_fused_bwd (radial-MLP adjoint over edge pairs)", bytes_mlp, flops_mlp, mlp_ms,
-        _traffic("k_mlp_fused_bwd", os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_mlp.hip"),
-                 args.precision), peak_tf)
+    peak_tf = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}[precision]
+    mlp_src = os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_mlp.hip")
+    roofline_mlp = _impl_traffic_entry("k_mlp_fused_bwd (radial-MLP adjoint over edge pairs)",
+                                       bytes_mlp, mlp_ms,
+                                       _traffic("k_mlp_fused_bwd", mlp_src, precision))
+    roofline_mlp["algorithmic_flops_per_launch"] = flops_mlp
+    roofline_mlp["mfma_frac"] = flops_mlp / (mlp_ms * 1e-3) / 1e12 / peak_tf if mlp_ms > 0 else None
 
     # The same kernels timed in isolation: a second context created with SN_SERIAL=1 runs
-    # every launch on one stream (the timed steps above overlap the radial MLPs with the
+    # every launch on one stream (the timed steps overlap the radial MLPs with the
     # node-feature chain, which stretches the launches of both while they share the GPU).
-    iso = {}
     if not args.no_isolated:
+        iso = {}
         prev = os.environ.get("SN_SERIAL")
         os.environ["SN_SERIAL"] = "1"
-        sctx = sn.Context(sn.Model(wpath), device=0, precision=args.precision)
+        sctx = sn.Context(sn.Model(wpath), device=0, precision=precision)
         if prev is None:
             del os.environ["SN_SERIAL"]
         else:
@@ -413,60 +488,68 @@ def main():
                 for kk, v in sctx.timings().items():
                     iso[kk] = iso.get(kk, 0.0) + v / 2
         del sctx
-    for entry, phases, nbytes, nflops in ((roofline, tp_phases, bytes_tp, None),
-                                          (roofline_mlp, mlp_phases, bytes_mlp, flops_mlp)):
-        iso_ms = sum(iso.get(kk, 0.0) for kk in phases) / len(phases)
-        if iso_ms > 0:
-            entry["isolated"] = {"launch_ms": iso_ms, "achieved": nbytes / (iso_ms * 1e-3) / 1e9,
-                                 "frac": nbytes / (iso_ms * 1e-3) / 1e9 / 8000.0}
-            if nflops:
-                entry["isolated"]["mfma_frac"] = nflops / (iso_ms * 1e-3) / 1e12 / peak_tf
+        iso_tp = sum(iso.get(kk, 0.0) for kk in tp_phases) / len(tp_phases)
+        if iso_tp > 0:
+            roofline["isolated"] = {"launch_ms": iso_tp,
+                                    "achieved": flops_tp / (iso_tp * 1e-3) / 1e12,
+                                    "frac": flops_tp / (iso_tp * 1e-3) / 1e12 / alu_peak}
+        iso_mlp = sum(iso.get(kk, 0.0) for kk in mlp_phases) / len(mlp_phases)
+        if iso_mlp > 0:
+            roofline_mlp["isolated"] = {"launch_ms": iso_mlp,
+                                        "mfma_frac": flops_mlp / (iso_mlp * 1e-3) / 1e12 / peak_tf,
+                                        "hbm_frac": bytes_mlp / (iso_mlp * 1e-3) / 8000e9}
+        out["isolated_phases_ms"] = iso
+    out.update(implementation_traffic=impl, roofline_mlp_adjoint=roofline_mlp,
+               list_reused=list_reused, host_buffers=host_buffers)
+    del ctx
+    return out
 
-    roofline_step = _step_roofline(spec, cg_nnz, n, g, e, npairs, args.precision, ms, iso)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle.model import OracleModel, evaluate
-        from synth import sio2_box
-        om = OracleModel(spec.config(), weights)
-        sample = sio2_box(args.cpu_sample_si, seed=2)
-        t1 = time.perf_counter()
-        evaluate(om, sample.pos, sample.Z, sample.cell)
-        cdt = time.perf_counter() - t1
-        cpu = {"value": sample.n / cdt, "unit": "atom-steps/s", "cores": torch.get_num_threads(),
-               "kind": "oracle",
-               "sample": f"one FP64 E+F+virial evaluation of a {sample.n}-atom SiO2 box at the "
-                         f"same density with the same model ({cdt:.1f} s)"}
+def _cpu_baseline(args, spec, weights):
+    """The FP64 oracle on this machine's host cores (every core the process may use): the
+    hot path's own model on a bounded sample of the workload (an SiO2 box at the same
+    density, one evaluation after a warm-up), plus the small configuration (192-atom SiO2,
+    3-block l <= 1 model) timed over 5 runs.  A full 24,000-atom oracle evaluation takes
+    about 9 minutes on 8 cores, so the sample keeps the benchmark within minutes."""
+    import subprocess
 
-    serving = None
-    count = 400 if args.serve_requests is None else args.serve_requests
-    if count > 0:
-        del ctx
-        torch.cuda.empty_cache()
-        serving = bench_serving(args, count, args.precision, full=False)
+    import torch
 
-    out = {
-        "metric": "atom-steps/s (E+F), 5-layer l<=2 model, 24k-atom SiO2",
-        "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
-        "data": "synthetic",
-        "config": {"workload": "SiO2 24,000 atoms (8,000 Si + 16,000 O), 2.2 g/cm^3, periodic cubic "
-                               "71.32 A; 5 blocks 128x0e+64x1e+32x2e, l<=2, r_c 5 A; E+F+virial "
-                               "as one subdomain + r_c ghost shell",
-                   "n_atoms": n, "n_ghost": g, "n_edges": e, "precision": args.precision,
-                   "subdomains": list(domains)},
-        "roofline": roofline,
-        "roofline_alu": roofline_alu,
-        "roofline_mlp_adjoint": roofline_mlp,
-        "roofline_step": roofline_step,
-        "list_reused": list_reused,
-        "host_buffers": host_buffers,
-        "cpu_baseline": cpu,
-        "phases_ms": {k: v / args.steps for k, v in phase_ms.items()},
-        "serving": serving,
-    }
-    print(json.dumps(out))
+    from oracle.model import OracleModel, evaluate
+    from synth import sio2_box, model_spec_small, make_weights as mk
+
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    model_name = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model_name = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    # small configuration: 1 warm-up + 5 timed runs
+    sspec = model_spec_small()
+    som = OracleModel(sspec.config(), mk(sspec, 101))
+    small = sio2_box(64, seed=1)
+    evaluate(som, small.pos, small.Z, small.cell)
+    t1 = time.perf_counter()
+    for _ in range(5):
+        evaluate(som, small.pos, small.Z, small.cell)
+    sdt = (time.perf_counter() - t1) / 5
+    # the workload's model on a bounded sample
+    om = OracleModel(spec.config(), weights)
+    sample = sio2_box(args.cpu_sample_si, seed=2)
+    t1 = time.perf_counter()
+    evaluate(om, sample.pos, sample.Z, sample.cell)
+    cdt = time.perf_counter() - t1
+    return {"value": sample.n / cdt, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model_name,
+            "sample": f"FP64 E+F+virial of a {sample.n}-atom SiO2 box at 2.2 g/cm^3 with the "
+                      f"5-block model ({cdt:.1f} s, after the small runs warmed the process); "
+                      f"FP64 reference on {cores} host cores, not an optimized CPU code",
+            "small_config": {"n_atoms": small.n, "runs": 5, "s_per_run": sdt,
+                             "value": small.n / sdt, "unit": "atom-steps/s"}}
 
 
 def _model_file(species, seed):
@@ -492,6 +575,8 @@ def bench_serving(args, count, precision, full):
     warm = serving_stream(count=24, seed=60)
     out = {"requests": count, "offered_rate_per_s": 200.0, "precision": precision,
            "stream_seed": 6, "generation_s": gen_s}
+    # the stream's own arrival rate (200/s), then the same requests arriving 25 times faster
+    # (5,000/s, more work than the GPU serves), where continuous batching has to carry the load
     for name, kw in (("batched", dict(n_streams=args.serve_streams, max_batch_atoms=16384,
                                       max_batch_structures=256)),
                      ("single", dict(n_streams=1, max_batch_atoms=1 << 40,
@@ -499,10 +584,14 @@ def bench_serving(args, count, precision, full):
         srv = Server(model, precision=precision, **kw)
         replay(srv, [(0.0, s) for _, s in warm])  # allocate workspaces, load kernels
         rep = replay(srv, stream)
-        srv.close()
         summ = latency_summary(rep)
         summ.update(kw)
         out[name] = summ
+        rep = replay(srv, stream, time_scale=200.0 / args.serve_high_rate)
+        srv.close()
+        summ = latency_summary(rep)
+        summ["offered_rate_per_s"] = args.serve_high_rate
+        out[name + "_high_rate"] = summ
     if not full:
         return out
     atoms = out["batched"]["atoms"]

@@ -9,8 +9,9 @@ import numpy as np
 TOL_E_REL_FP32 = 1e-6
 TOL_F_ABS_FP32 = 1e-4
 TOL_W_REL_FP32 = 1e-5
-# BF16 form: relative RMS force error.
+# BF16 form: relative RMS force error; relative Frobenius virial error.
 TOL_F_RMS_BF16 = 2e-2
+TOL_W_REL_BF16 = 2e-2
 # FP64 form: both sides compute the same sums in float64.
 TOL_E_REL_FP64 = 1e-10
 TOL_F_ABS_FP64 = 1e-10

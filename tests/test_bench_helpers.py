@@ -83,21 +83,62 @@ def test_stats_counts_the_split_forward_per_block(tmp_path):
     assert "- `k_tp_bwd`: 1000.0 us" in text
 
 
-def test_step_roofline_small_model_by_hand():
+def test_algorithmic_work_small_model_by_hand():
     import bench
     spec = model_spec_small()  # radial weights per edge: 64, 160, 64 over the three blocks
     n, g, e, npairs = 10, 5, 100, 50
-    r = bench._step_roofline(spec, _nnz, n, g, e, npairs, "fp32", 1.0, {})
-    k = r["kernels"]
-    # forward MLP: 2 (8 64 + 64 64 + 64 P) flops and 4 P + 32 bytes per pair, summed over blocks
-    assert k["mlp_fwd"]["flops"] == npairs * 2 * (3 * (8 * 64 + 64 * 64) + 64 * 288)
-    assert k["mlp_fwd"]["bytes"] == npairs * (4 * 288 + 3 * 32)
-    # each kernel bounded by the slower of its arithmetic and its HBM bytes
-    for kind in k.values():
-        assert kind["bound_ms"] >= kind["bytes"] / 8e12 * 1e3 - 1e-15
-    # dE/dx rows exist from the second block on; sender rows: the first block's are the
-    # 32 scalars, then 32 scalars + 32 vectors (128 floats)
-    assert k["sender_fold"]["bytes"] == sum(e * D * 4 + 2 * (n + g) * D * 8 + n * D * 8
-                                            for D in (128, 128))
-    assert r["frac"] == pytest.approx(r["lower_bound_ms"] / 1.0)
-    assert r["modelled_share"] is None
+    w = bench._algorithmic_work(spec, _nnz, n, g, e, npairs, "fp32")
+    # radial MLP once per undirected pair, forward and input-gradient adjoint
+    assert w["radial_mlp"]["flops"] == npairs * 2 * 2 * (3 * (8 * 64 + 64 * 64) + 64 * 288)
+    # tensor product: forward + adjoint flops per edge
+    fwd = bench._tp_forward_flops(spec, _nnz)
+    bwd = bench._tp_adjoint_flops(spec, _nnz)
+    assert w["tensor_product"]["flops"] == e * (sum(fwd) + sum(bwd))
+    # first-block forward by hand: paths (0,0,0), (0,1,1): 3 flops per nonzero + 2 (2 l3 + 1)
+    assert fwd[0] == 32 * (3 * 1 + 2) + 32 * (3 * 3 + 6)
+    # linears: Lin1 on 15 rows in block 1, Linsc 32 -> 64 gate inputs, Lin2 mid -> outputs...
+    C0 = 32
+    lin1 = 2 * (n + g) * 32 * 32
+    sc1 = 2 * n * 32 * 64
+    assert w["linears"]["flops"] > lin1 + sc1
+    r = bench._step_roofline(w, 2.0)
+    for c in r["classes"].values():
+        assert c["bound_ms"] == pytest.approx(max(c["flops"] / (c["peak_TFLOPs"] * 1e12),
+                                                  c["bytes"] / 8e12) * 1e3)
+    assert r["frac"] == pytest.approx(r["lower_bound_ms"] / 2.0)
+
+
+def test_algorithmic_work_real_size_matches_the_survey_estimate():
+    """At the 24k-atom configuration (818,560 edges, 409,280 pairs, 11,633 ghosts) the
+    pair-shared radial MLP is 0.40 TFLOP, the tensor product about 0.22-0.26 TFLOP and the
+    linears about 0.095 TFLOP per evaluation."""
+    import bench
+    from synth import model_spec_real
+    w = bench._algorithmic_work(model_spec_real(), _nnz, 24000, 11633, 818560, 409280, "fp32")
+    assert w["radial_mlp"]["flops"] / 1e12 == pytest.approx(0.40, rel=0.02)
+    assert 0.21 <= w["tensor_product"]["flops"] / 1e12 <= 0.27
+    assert w["linears"]["flops"] / 1e12 == pytest.approx(0.095, rel=0.05)
+
+
+def test_tp_resource_guard_parses_remarks(tmp_path):
+    """The build's guard over the tensor-product kernels' compiler resource remarks: float32
+    kernels with harmonics up to l = 2 may use no scratch; the others stay within limits."""
+    from paper_2402_03789_amd import build as b
+
+    def rec(name, vgpr, spill, scratch):
+        return (f"k.hip:1:1: remark: Function Name: {name} [-Rpass-analysis=kernel-resource-usage]\n"
+                f"k.hip:1:1: remark:     VGPRs: {vgpr} [-Rpass-analysis=kernel-resource-usage]\n"
+                f"k.hip:1:1: remark:     AGPRs: 0 [-Rpass-analysis=kernel-resource-usage]\n"
+                f"k.hip:1:1: remark:     ScratchSize [bytes/lane]: {scratch} [-Rpass-analysis=kernel-resource-usage]\n"
+                f"k.hip:1:1: remark:     VGPRs Spill: {spill} [-Rpass-analysis=kernel-resource-usage]\n")
+    fp32_l2 = "_ZN2sn8k_tp_bwdIffLi1ELi2ELi2ELb0ELb1ELi0EEEvNS_6TPArgsE"
+    bf16_l2 = "_ZN2sn8k_tp_fwdIfNS_6bf16_tELi2ELi2ELi2ELb0ELi64EEEvNS_6TPArgsE"
+    fp64_l3 = "_ZN2sn8k_tp_fwdIddLi3ELi3ELi3ELb0ELi0EEEvNS_6TPArgsE"
+    assert b._tp_kernel_kind(fp32_l2) == (True, 2)
+    assert b._tp_kernel_kind(bf16_l2) == (True, 2)
+    assert b._tp_kernel_kind(fp64_l3) == (False, 3)
+    ok = rec(fp32_l2, 120, 0, 0) + rec(bf16_l2, 90, 0, 0) + rec(fp64_l3, 256, 10, 68)
+    assert b.check_tp_resources(ok, str(tmp_path / "r.tsv")) == []
+    assert (tmp_path / "r.tsv").read_text().count("\n") == 4
+    bad = rec(fp32_l2, 120, 0, 36) + rec(fp64_l3, 256, 40, 200)
+    assert [r["name"] for r in b.check_tp_resources(bad, str(tmp_path / "r.tsv"))] == [fp32_l2, fp64_l3]

@@ -1,11 +1,13 @@
 """Spatial decomposition on one device: k subdomains, each with its own ghost shell whose
 owners are local atoms of other subdomains (halo refresh and fold in device memory).
-Energies, forces and virials equal the undivided evaluation; ghost and edge counts equal
+Energies, forces and virials equal the FP64 oracle's whole-box evaluation (paper section
+3.1: the decomposition does not change the model's outputs); ghost and edge counts equal
 the oracle's subdomain construction."""
 import numpy as np
 import pytest
 
-from gpu_common import log, write_model
+from gpu_common import (log, write_model, errors, TOL_E_REL_FP32, TOL_F_ABS_FP32,
+                        TOL_W_REL_FP32)
 
 pytestmark = pytest.mark.gpu
 
@@ -15,6 +17,7 @@ if not torch.cuda.is_available():
 
 import paper_2402_03789_amd as sn  # noqa: E402
 from oracle.graph import subdomains, wrap  # noqa: E402
+from oracle.model import OracleModel, evaluate  # noqa: E402
 from synth import model_spec_real, sio2_box, rsa_box  # noqa: E402
 
 
@@ -22,6 +25,13 @@ from synth import model_spec_real, sio2_box, rsa_box  # noqa: E402
 def model(tmp_path_factory):
     path, _ = write_model(tmp_path_factory.mktemp("m"), model_spec_real(), 107)
     return sn.Model(path)
+
+
+@pytest.fixture(scope="module")
+def oracle_model():
+    from synth import make_weights
+    spec = model_spec_real()
+    return OracleModel(spec.config(), make_weights(spec, 107))
 
 
 def _triclinic():
@@ -40,44 +50,43 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_domains_equal_whole_box_fp64(model, name):
+def test_domains_equal_whole_box_fp64(model, oracle_model, name):
     make, splits = CASES[name]
     pos, Z, cell = make()
     log(f"domains {name} splits={splits} n={len(Z)}")
-    one = sn.Context(model, precision="fp64")
-    ref = one.compute(pos, Z, cell)
-    n1, g1, e1 = one.graph_size()
+    ref = evaluate(oracle_model, pos, Z, cell)
     ctx = sn.Context(model, precision="fp64")
     ctx.set_domains(*splits)
     got = ctx.compute(pos, Z, cell)
     n, g, e = ctx.graph_size()
     doms = subdomains(wrap(pos, cell), cell, 5.0, splits)
-    assert n == n1 == len(Z)
+    assert n == len(Z)
     assert g == sum(len(D["ghost_owner"]) for D in doms)
-    assert e == e1 == sum(len(D["recv"]) for D in doms)
-    log(f"  ghosts {g1} -> {g}, edges {e}")
+    assert e == len(ref["graph"][0]) == sum(len(D["recv"]) for D in doms)
+    log(f"  ghosts {g}, edges {e}")
     assert abs(got["energy"] - ref["energy"]) <= 1e-10 * abs(ref["energy"])
     np.testing.assert_allclose(got["atom_energy"], ref["atom_energy"], rtol=0, atol=1e-10)
     np.testing.assert_allclose(got["forces"], ref["forces"], rtol=0, atol=1e-10)
     np.testing.assert_allclose(got["virial"], ref["virial"], rtol=0, atol=1e-9)
 
 
-def test_domains_fp32_and_batch(model):
+def test_domains_fp32_and_batch(model, oracle_model):
     s = sio2_box(300, seed=8)  # 900 atoms
     t = sio2_box(20, seed=9)
-    one = sn.Context(model, precision="fp32")
-    ref = [one.compute(s.pos, s.Z, s.cell), one.compute(t.pos, t.Z, t.cell)]
+    log("domains 2x2x2 fp32, packed batch of 900 + 60 atoms, against the oracle")
+    ref = [evaluate(oracle_model, s.pos, s.Z, s.cell), evaluate(oracle_model, t.pos, t.Z, t.cell)]
     ctx = sn.Context(model, precision="fp32")
     ctx.set_domains(2, 2, 2)
     got = ctx.compute_batch([(s.pos, s.Z, s.cell), (t.pos, t.Z, t.cell)])
     for g, r in zip(got, ref):
-        rms = np.sqrt(np.mean(r["atom_energy"] ** 2))
-        assert np.abs(g["atom_energy"] - r["atom_energy"]).max() / rms < 1e-6
-        assert np.abs(g["forces"] - r["forces"]).max() < 1e-4
-    # back to one subdomain per structure: identical to the undivided context
+        err = errors(g, r)
+        log(f"  {err}")
+        assert err["e_rel"] <= TOL_E_REL_FP32 and err["f_abs"] <= TOL_F_ABS_FP32
+        assert err["w_rel"] <= TOL_W_REL_FP32
+    # back to one subdomain per structure: identical to an undivided context
     ctx.set_domains(1, 1, 1)
     again = ctx.compute(s.pos, s.Z, s.cell)
-    assert again["energy"] == ref[0]["energy"]
+    assert again["energy"] == sn.Context(model, precision="fp32").compute(s.pos, s.Z, s.cell)["energy"]
 
 
 def test_domains_rejects_bad_counts(model):

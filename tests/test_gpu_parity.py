@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from gpu_common import (log, write_model, errors, TOL_E_REL_FP32, TOL_F_ABS_FP32, TOL_W_REL_FP32,
-                        TOL_E_REL_FP64, TOL_F_ABS_FP64, TOL_F_RMS_BF16)
+                        TOL_E_REL_FP64, TOL_F_ABS_FP64, TOL_F_RMS_BF16, TOL_W_REL_BF16)
 
 pytestmark = pytest.mark.gpu
 
@@ -97,7 +97,7 @@ def test_real_model_medium_box(real_model, precision):
         assert err["e_rel"] <= TOL_E_REL_FP32 and err["f_abs"] <= TOL_F_ABS_FP32
         assert err["w_rel"] <= TOL_W_REL_FP32
     else:
-        assert err["f_rms_rel"] <= TOL_F_RMS_BF16
+        assert err["f_rms_rel"] <= TOL_F_RMS_BF16 and err["w_rel"] <= TOL_W_REL_BF16
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
