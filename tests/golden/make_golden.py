@@ -6,6 +6,7 @@ oracle (paper eqs 1-2 and the virial), for use by the GPU parity tests at full s
 
     python tests/golden/make_golden.py sio2_24k
     python tests/golden/make_golden.py quartz_4608_32x4
+    python tests/golden/make_golden.py si3n4_112k     (about 80 minutes on 6 threads, 30 GB)
 
 quartz_4608_32x4 is one of the paper's benchmark models (section 4: 32 channels at every
 degree l <= 3, 4 interaction blocks, r_c 4 A) on a 4,608-atom SiO2 box at the alpha-quartz
