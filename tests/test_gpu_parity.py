@@ -100,6 +100,30 @@ def test_real_model_medium_box(real_model, precision):
         assert err["f_rms_rel"] <= TOL_F_RMS_BF16 and err["w_rel"] <= TOL_W_REL_BF16
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_si3n4_box_with_skin(tmp_path, precision):
+    """The large-box configuration's chemistry and list at a size the oracle evaluates in
+    seconds: Si3N4 at 3.1 g/cm^3 (48 Si + 64 N, RSA 1.5 A plus 0.05 A jitter), the real-size
+    model with N/Si species, and the r_c + 1 A skin list of the MD runs."""
+    spec = model_spec_real((7, 14))
+    path, w = write_model(tmp_path, spec, 102)
+    om = OracleModel(spec.config(), w)
+    s = si3n4_box(48, seed=9)
+    log(f"Si3N4 box precision={precision} n={s.n}")
+    got = sn.Context(sn.Model(path), precision=precision, skin=1.0).compute(s.pos, s.Z, s.cell)
+    ref = evaluate(om, s.pos, s.Z, s.cell)
+    err = errors(got, ref)
+    log(str(err))
+    if precision == "fp64":
+        assert err["e_rel"] < TOL_E_REL_FP64 and err["f_abs"] < TOL_F_ABS_FP64
+        assert err["w_rel"] < 1e-10
+    elif precision == "fp32":
+        assert err["e_rel"] <= TOL_E_REL_FP32 and err["f_abs"] <= TOL_F_ABS_FP32
+        assert err["w_rel"] <= TOL_W_REL_FP32
+    else:
+        assert err["f_rms_rel"] <= TOL_F_RMS_BF16
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_real_model_triclinic_small_cell(real_model, precision):
     spec, path, w, om = real_model
