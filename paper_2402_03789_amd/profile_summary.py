@@ -4,6 +4,7 @@ Usage:
   python -m paper_2402_03789_amd.profile_summary stats <rocprof_dir> <steps[:blocks]> <out.md> <command...>
   python -m paper_2402_03789_amd.profile_summary traffic <fetch_dir> <write_dir> <kernel> \
         <source.hip> <precision> <out.json> <command...>
+  python -m paper_2402_03789_amd.profile_summary utilization <pmc_dir> <out.md> <command...>
 
 The traffic summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by the
 readings of the same counters for the 256 MiB device copy that the benchmark
@@ -92,6 +93,45 @@ def traffic(fetch_dir, write_dir, kernel, source, precision, out, cmd):
     json.dump(rec, open(out, "w"), indent=1)
 
 
+def utilization(d, out, cmd, top=24):
+    """Per-kernel matrix-core and vector-ALU utilisation from a `--pmc MfmaUtil VALUBusy
+    SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU_MFMA_MOPS_*` run: the mean over a kernel's
+    dispatches of MfmaUtil (matrix-core busy cycles over GPU-active cycles of every SIMD)
+    and VALUBusy (vector-ALU instruction cycles over GPU-active cycles of every CU), the
+    raw float32 VALU flop counter and the matrix-core MOPs per dispatch (1 MOP = 512
+    flops)."""
+    rows = _rows(d, "*counter_collection.csv")
+    per = {}
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        k = per.setdefault(name, {})
+        k.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    cols = ["MfmaUtil", "VALUBusy", "SQ_INSTS_VALU_FLOPS_FP32", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+            "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F64"]
+
+    def mean(v):
+        return sum(v) / len(v) if v else 0.0
+    def work(n):  # all flops of the kernel's dispatches
+        return sum(per[n].get(cols[2], [0])) + 512 * sum(sum(per[n].get(c, [0])) for c in cols[3:])
+    order = sorted(per, key=lambda n: -work(n))
+    lines = ["# Matrix-core and vector-ALU utilisation per kernel", "", f"Command: `{cmd}`", "",
+             "MfmaUtil and VALUBusy: percent, mean over the kernel's dispatches (rocprofv3 derived "
+             "counters: SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) and "
+             "SQ_ACTIVE_INST_VALU / (CUs x GRBM_GUI_ACTIVE)); the float32 VALU flop counter "
+             "(SQ_INSTS_VALU_FLOPS_FP32, raw, 1e9 counts) and the matrix-core MOPs (x 512 flops) "
+             "per dispatch.", "",
+             "| kernel | dispatches | MfmaUtil % | VALUBusy % | FP32 VALU counter (G) | MFMA F32 GFLOP "
+             "| MFMA BF16 GFLOP | MFMA F64 GFLOP |", "|---|---|---|---|---|---|---|---|"]
+    for n in order[:top]:
+        k = per[n]
+        nd = max(len(v) for v in k.values())
+        lines.append(f"| `{n}` | {nd} | {mean(k.get('MfmaUtil', [])):.1f} | "
+                     f"{mean(k.get('VALUBusy', [])):.1f} | "
+                     f"{mean(k.get('SQ_INSTS_VALU_FLOPS_FP32', [])) / 1e9:.2f} | "
+                     + " | ".join(f"{512 * mean(k.get(c, [])) / 1e9:.2f}" for c in cols[3:]) + " |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         steps, _, blocks = sys.argv[3].partition(":")
@@ -99,3 +139,5 @@ if __name__ == "__main__":
               int(blocks) if blocks else 5)
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:8], " ".join(sys.argv[8:]))
+    elif sys.argv[1] == "utilization":
+        utilization(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
