@@ -21,7 +21,9 @@ What it computes (paper sections 2-3):
     gradients and partial forces folded back (section 3.1), and a
     multi-subdomain emulation of the same scheme;
   * (oracle/md.py) velocity Verlet and the Nose-Hoover NVT integrator of the
-    paper's MD benchmarks (section 4), driven by any force function.
+    paper's MD benchmarks (section 4), driven by any force function;
+  * (oracle/train.py) the energy term of the training loss (eq 9, Huber on per-atom
+    energies) and its gradient with respect to every weight tensor.
 
 Every floating-point quantity is float64.  Derivatives are taken with
 torch.autograd on CPU.  Pins (closed forms, invariances, finite differences,

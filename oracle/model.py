@@ -207,8 +207,10 @@ def _finish(model, E_i, ds, pos_t, recv, owner_of_send, n_atoms):
                 d=d.detach().numpy())
 
 
-def evaluate(model: OracleModel, pos, Z, cell, pbc=(True, True, True), graph=None):
-    """E, per-atom E, F (eq 6 assembly), F (autograd), W for one periodic structure."""
+def atom_energies(model: OracleModel, pos, Z, cell, pbc=(True, True, True), graph=None):
+    """Per-atom energies E_i (paper eq 1) of one periodic structure as a tensor that carries
+    the autograd graph back to the positions and the model's weight tensors.  Returns
+    (E_i, edge vectors d, positions tensor, graph)."""
     cell = np.asarray(cell, dtype=np.float64)
     posw = wrap(np.asarray(pos, dtype=np.float64), cell, pbc)
     if graph is None:
@@ -232,8 +234,14 @@ def evaluate(model: OracleModel, pos, Z, cell, pbc=(True, True, True), graph=Non
             if l in sc:
                 y[l] = y[l] + sc[l]
         h = model.gate(t, y)
-    E_i = model.readout(h[0], s_idx)
-    out = _finish(model, E_i, [d], pos_t, recv, send, N)
+    return model.readout(h[0], s_idx), d, pos_t, graph
+
+
+def evaluate(model: OracleModel, pos, Z, cell, pbc=(True, True, True), graph=None):
+    """E, per-atom E, F (eq 6 assembly), F (autograd), W for one periodic structure."""
+    E_i, d, pos_t, graph = atom_energies(model, pos, Z, cell, pbc, graph)
+    recv, send = (torch.as_tensor(a) for a in graph[:2])
+    out = _finish(model, E_i, [d], pos_t, recv, send, pos_t.shape[0])
     out["graph"] = (graph[0], graph[1], graph[2])
     return out
 
