@@ -184,7 +184,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (HBM counter calibration)")
     ap.add_argument("--workload", default="sio2_24k",
-                    choices=["sio2_24k", "md", "serving", "fd", "size_sweep", "paper_models"],
+                    choices=["sio2_24k", "md", "serving", "fd", "size_sweep", "paper_models",
+                             "train"],
                     help="sio2_24k: the headline line (plus a short serving replay); md: molecular "
                          "dynamics (default the 112k-atom Si3N4 Verlet run); serving: the full "
                          "2,000-request stream; fd: the differentiation and precision report; "
@@ -244,6 +245,9 @@ def main():
         return
     if args.workload == "fd":
         print(json.dumps(bench_fd(args)))
+        return
+    if args.workload == "train":
+        print(json.dumps(bench_train(args)))
         return
     if args.workload == "size_sweep":
         print(json.dumps(bench_size_sweep(args)))
@@ -666,6 +670,51 @@ def bench_fd(args):
                          "virial_rel": float(np.linalg.norm(r["virial"].ravel() - np.array(gold["virial"]))
                                              / np.linalg.norm(gold["virial"]))}
             del c
+    return out
+
+
+def bench_train(args):
+    """Training steps of the energy term of eq 9 (paper section 5.1: batches of 16): forward in
+    training mode, the Huber loss of per-atom energies against labels, and the adjoint with
+    every weight gradient, on (a) 16-structure batches from the serving stream's distribution
+    with the 89-species model and (b) the 24k-atom SiO2 box.  Labels are the model's own
+    energies shifted by a seeded per-atom offset (synthetic: no DFT data)."""
+    import numpy as np
+    import torch
+
+    import paper_2402_03789_amd as sn
+    from paper_2402_03789_amd.train import energy_loss_and_grads
+    from synth import config_structure, serving_stream
+
+    out = {"metric": "training steps (energy term of eq 9, weight gradients)", "unit": "steps/s",
+           "n_gpus": 1, "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
+           "data": "synthetic", "cases": []}
+    rng = np.random.Generator(np.random.PCG64(8))
+    cases = [("batch of 16 serving-stream structures, 89-species model",
+              [s for _, s in serving_stream(count=16 * (args.steps + args.warmup), seed=9)],
+              tuple(range(1, 90)), 16),
+             ("SiO2 24,000 atoms", [config_structure("sio2_24k")], (8, 14), 1)]
+    for label, pool, species, bsz in cases:
+        ctx = sn.Context(sn.Model(_model_file(species, 102)), precision=args.precision)
+        times, atoms = [], 0
+        for k in range(args.warmup + args.steps):
+            batch = [(s.pos, s.Z, s.cell) for s in pool[(k * bsz) % len(pool):(k * bsz) % len(pool) + bsz]]
+            labels = [0.0] * len(batch)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = energy_loss_and_grads(ctx, batch, labels)
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(time.perf_counter() - t0)
+                atoms += sum(len(z) for _, z, _ in batch)
+            del r
+        dt = sum(times)
+        out["cases"].append({"workload": label, "steps": len(times), "ms_per_step": dt / len(times) * 1e3,
+                             "steps_per_s": len(times) / dt, "atoms_per_s": atoms / dt})
+        print(f"train: {label}: {dt / len(times) * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+        del ctx
+        torch.cuda.empty_cache()
+    out["value"] = out["cases"][0]["steps_per_s"]
     return out
 
 

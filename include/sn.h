@@ -218,6 +218,44 @@ int sn_forward_device(sn_ctx_t* ctx, const sn_batch_t* batch, double* d_energy,
 int sn_backward_device(sn_ctx_t* ctx, const double* d_grad_energy, double* d_forces,
                        double* d_virial);
 
+/* ---- training: weight gradients of the energy term of the loss ----------------------
+ * Paper section 5.1 trains with the loss of eq 9: a Huber loss of per-atom energies, forces
+ * and stresses.  These calls give the energy term and its gradient with respect to every
+ * model weight; the force and stress terms need second derivatives through the force
+ * adjoint and are not provided.
+ *
+ * sn_ctx_set_training(ctx, 1): later forwards keep every interaction block's input features
+ * and messages (about (Dx + Dm) float64/float32 values per atom and block more device
+ * memory), which the weight gradients need.  Graph replay is off while it is set. */
+int sn_ctx_set_training(sn_ctx_t* ctx, int on);
+
+/* Consumes a pending training-mode forward (SN_EBUSY otherwise).  With the upstream
+ * gradients d_grad_energy[B] = dL/dE_b (device, float64) it writes
+ *   d_weight_grad = sum_b g_b dE_b/dW for every weight W (device, float64), sn_model_info's
+ *     n_params values laid out as the weights file's tensors (offsets from sn_model_tensor):
+ *     embedding, every block's Lin1, self-connection, radial MLP (Wa, Wb, Wc) and Lin2, and
+ *     the readout;
+ *   d_forces, d_virial as sn_backward_device (each may be NULL).
+ * The radial MLP's adjoint runs unfused here (its hidden activations and pre-activation
+ * gradients are needed per pair), so forces agree with sn_backward_device to rounding, not
+ * bit for bit.  Every weight gradient is a fixed-order float64 reduction over atoms or edge
+ * pairs: bitwise reproducible.  SN_EUNSUPPORTED for a weights file with gaps. */
+int sn_backward_train_device(sn_ctx_t* ctx, const double* d_grad_energy, double* d_forces,
+                             double* d_virial, double* d_weight_grad);
+
+/* Name, offset (in float64 values from the start of the weights) and element count of the
+ * index-th tensor of the model (tensors in name order).  SN_EINVAL past the last one.  The
+ * name points into the model and lives as long as it. */
+int sn_model_tensor(const sn_model_t* model, int index, const char** name, int64_t* offset,
+                    int64_t* count);
+
+/* Energy term of eq 9 on host arrays: loss = (1/B) sum_b huber(E_b/N_b - ref_b/N_b; delta),
+ * huber(r) = r^2/2 for |r| < delta, delta (|r| - delta/2) otherwise (squared error below the
+ * threshold, absolute error above; the paper takes delta = 0.01), and dloss_denergy[b] =
+ * dloss/dE_b (may be NULL).  SN_EINVAL for B < 1, a structure without atoms or delta <= 0. */
+int sn_huber_energy_loss(int B, const double* energy, const double* ref, const int64_t* natoms,
+                         double delta, double* loss, double* dloss_denergy);
+
 /* Neighbour-list reuse for molecular dynamics.  With reuse enabled, a forward call whose
  * atom count and cell equal those of the previous build keeps that graph (ghost shell and
  * edges out to r_cut + skin) and only refreshes local and ghost positions from d_pos; the

@@ -74,6 +74,18 @@ class Model:
                     species=list(i.species_z[:i.n_species]), r_cut=i.r_cut, k_avg=i.k_avg,
                     sigma=i.sigma, n_params=i.n_params)
 
+    def tensors(self) -> list:
+        """[(name, offset, count)] of every weight tensor (offsets in float64 values; the
+        layout of the weights file and of the training weight gradients)."""
+        out = []
+        i = 0
+        while True:
+            name, off, cnt = C.c_char_p(), C.c_int64(), C.c_int64()
+            if lib().sn_model_tensor(self._h, i, C.byref(name), C.byref(off), C.byref(cnt)) != 0:
+                return out
+            out.append((name.value.decode(), off.value, cnt.value))
+            i += 1
+
     def __del__(self):
         try:
             if getattr(self, "_h", None):
@@ -222,6 +234,23 @@ class Context:
 
     def synchronize(self):
         check(lib().sn_ctx_synchronize(self._h), self._h)
+
+    def set_training(self, on: bool):
+        """Later forwards keep what the weight gradients need (sn_ctx_set_training)."""
+        check(lib().sn_ctx_set_training(self._h, 1 if on else 0), self._h)
+
+    def backward_train_device(self, grad_energy: torch.Tensor, weight_grad: torch.Tensor,
+                              forces: torch.Tensor | None = None, virial: torch.Tensor | None = None):
+        """Consume a training-mode forward: weight_grad (float64 device, n_params) <- sum_b g_b
+        dE_b/dW with g = grad_energy [B] (float64 device); forces and virial as
+        backward_device."""
+        for t in (grad_energy, weight_grad):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("expected contiguous float64 device tensors")
+        if weight_grad.numel() < self.model.info()["n_params"]:
+            raise ValueError("weight_grad too small")
+        check(lib().sn_backward_train_device(self._h, ptr(grad_energy), ptr(forces), ptr(virial),
+                                             ptr(weight_grad)), self._h)
 
     def graph_size(self):
         n, g, e = C.c_int64(), C.c_int64(), C.c_int64()

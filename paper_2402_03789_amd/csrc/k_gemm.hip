@@ -374,12 +374,16 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(int64_t E, const int* __restric
   }
 }
 
+// With z1o, da1o, da2o (training): also the per-pair hidden activation z1 = phi(a1) and the
+// pre-activation gradients da1 = dE/da1, da2 = dE/da2 that the weight gradients need.
 template <typename T, int NB, int H>
 __global__ __launch_bounds__(256) void k_mlp_bwd(int64_t E, const int* __restrict__ rows,
                                                   const T* __restrict__ rho,
                                                   const T* __restrict__ Wa, const T* __restrict__ Wb,
                                                   T c, const T* __restrict__ dz2,
-                                                  T* __restrict__ drho, int accumulate) {
+                                                  T* __restrict__ drho, int accumulate,
+                                                  T* __restrict__ z1o, T* __restrict__ da1o,
+                                                  T* __restrict__ da2o) {
   __shared__ T sWa[NB * H];
   __shared__ T sWb[H * H];
   for (int i = threadIdx.x; i < NB * H; i += blockDim.x) sWa[i] = Wa[i];
@@ -398,12 +402,14 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int64_t E, const int* __restric
     for (int k = 0; k < NB; ++k) a += r[k] * sWa[k * H + j];
     z1[j] = act(a, c);
     dz1[j] = T(0);
+    if (z1o) z1o[e * H + j] = z1[j];
   }
   for (int j2 = 0; j2 < H; ++j2) {
     T a = T(0);
 #pragma unroll
     for (int j = 0; j < H; ++j) a += z1[j] * sWb[j * H + j2];
     T da = dz2[e * H + j2] * act_grad(a, c);
+    if (da2o) da2o[e * H + j2] = da;
 #pragma unroll
     for (int j = 0; j < H; ++j) dz1[j] += da * sWb[j * H + j2];
   }
@@ -416,6 +422,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int64_t E, const int* __restric
 #pragma unroll
     for (int k = 0; k < NB; ++k) a += r[k] * sWa[k * H + j];
     T da = dz1[j] * act_grad(a, c);
+    if (da1o) da1o[e * H + j] = da;
 #pragma unroll
     for (int k = 0; k < NB; ++k) dr[k] += da * sWa[k * H + j];
   }
@@ -436,37 +443,41 @@ void launch_mlp_hidden_fwd(int64_t E, const int* rows, const T* rho, int nb, int
 template <typename T>
 void launch_mlp_hidden_bwd(int64_t E, const int* rows, const T* rho, int nb, int hidden,
                            const T* Wa, const T* Wb, T c, const T* dz2, T* drho, bool accumulate,
-                           hipStream_t s) {
+                           hipStream_t s, T* z1, T* da1, T* da2) {
   if (E <= 0) return;
-  k_mlp_bwd<T, 8, 64><<<(unsigned)((E + 255) / 256), 256, 0, s>>>(E, rows, rho, Wa, Wb, c, dz2,
-                                                                  drho, accumulate ? 1 : 0);
+  k_mlp_bwd<T, 8, 64><<<(unsigned)((E + 255) / 256), 256, 0, s>>>(
+      E, rows, rho, Wa, Wb, c, dz2, drho, accumulate ? 1 : 0, z1, da1, da2);
 }
 
-template <typename T>
+template <typename S, typename T>
 __global__ void k_pair_sum(int64_t np, const int* __restrict__ pe1, const int* __restrict__ pe2,
-                           const T* __restrict__ dw, int P, T* __restrict__ out) {
+                           const S* __restrict__ dw, int P, T* __restrict__ out) {
   // dE/dw is pair-major: rows 2p and 2p + 1 hold the pair's two directions
   const int64_t p = blockIdx.x;
   const int64_t a = 2 * p * P;
   const int b = pe2[p];
   for (int k = threadIdx.x; k < P; k += blockDim.x)
-    out[p * P + k] = dw[a + k] + (b >= 0 ? dw[a + P + k] : T(0));
+    out[p * P + k] = T(sload(dw[a + k])) + (b >= 0 ? T(sload(dw[a + P + k])) : T(0));
 }
 
-template <typename T>
-void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const T* dw, int P, T* out,
+template <typename S, typename T>
+void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const S* dw, int P, T* out,
                      hipStream_t s) {
-  if (np > 0) k_pair_sum<T><<<(unsigned)np, 128, 0, s>>>(np, pe1, pe2, dw, P, out);
+  if (np > 0) k_pair_sum<S, T><<<(unsigned)np, 128, 0, s>>>(np, pe1, pe2, dw, P, out);
 }
 
 #define SN_MLPV_INST(T)                                                                          \
   template void launch_mlp_hidden_fwd<T>(int64_t, const int*, const T*, int, int, const T*,      \
                                          const T*, T, T*, hipStream_t);                          \
   template void launch_mlp_hidden_bwd<T>(int64_t, const int*, const T*, int, int, const T*,      \
-                                         const T*, T, const T*, T*, bool, hipStream_t);          \
-  template void launch_pair_sum<T>(int64_t, const int*, const int*, const T*, int, T*, hipStream_t);
+                                         const T*, T, const T*, T*, bool, hipStream_t, T*, T*,   \
+                                         T*);                                                    \
+  template void launch_pair_sum<T, T>(int64_t, const int*, const int*, const T*, int, T*,        \
+                                      hipStream_t);
 SN_MLPV_INST(float)
 SN_MLPV_INST(double)
 #undef SN_MLPV_INST
+template void launch_pair_sum<bf16_t, float>(int64_t, const int*, const int*, const bf16_t*, int,
+                                             float*, hipStream_t);
 
 }  // namespace sn

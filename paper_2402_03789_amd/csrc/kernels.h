@@ -114,14 +114,33 @@ void launch_gemm_mfma_group(int n, const GemmDesc<TA, TB, TC>* d, bool bt, bool 
 template <typename T>
 void launch_mlp_hidden_fwd(int64_t np, const int* rows, const T* rho, int nb, int hidden,
                            const T* Wa, const T* Wb, T c, T* z2, hipStream_t s);
+// With z1, da1, da2 (may be null): also the per-pair hidden activation and pre-activation
+// gradients [np x hidden] for the weight gradients.
 template <typename T>
 void launch_mlp_hidden_bwd(int64_t np, const int* rows, const T* rho, int nb, int hidden,
                            const T* Wa, const T* Wb, T c, const T* dz2, T* drho, bool accumulate,
-                           hipStream_t s);
-// out[p] = dw[pe1[p]] + dw[pe2[p]] (second term absent when pe2[p] < 0), rows of width P
-template <typename T>
-void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const T* dw, int P, T* out,
+                           hipStream_t s, T* z1 = nullptr, T* da1 = nullptr, T* da2 = nullptr);
+// out[p] = dw[2p] + dw[2p+1] (second term absent when pe2[p] < 0), rows of width P, stored
+// type S widened to T
+template <typename S, typename T>
+void launch_pair_sum(int64_t np, const int* pe1, const int* pe2, const S* dw, int P, T* out,
                      hipStream_t s);
+
+// ---------------------------------------------------------------- training (weight gradients)
+// dW[k][n] = scale * sum_r A[r'][k] B[r][n] over `rows` rows, float64 accumulation, fixed
+// chunk order: r' = aidx[r] when aidx is given (else r); with onehot, A[r'][k] = (onehot[r'] == k).
+// partial needs wgrad_chunks(rows) * K * N doubles.
+int64_t wgrad_chunks(int64_t rows);
+template <typename TA, typename TB>
+void launch_wgrad(int64_t rows, int K, int N, const TA* A, RowMap am, const int* aidx,
+                  const int* onehot, const TB* B, RowMap bm, double scale, double* partial,
+                  double* out, hipStream_t s);
+void launch_atom_grad(int n, const int* region, int regions_per_struct, const double* grad,
+                      double* g_atom, hipStream_t s);
+void launch_seed_rows(int n, const double* v, int C0, double sigma, const double* g_atom,
+                      double* dh, int ldh, hipStream_t s);
+void launch_readout_wgrad(int C0, const double* u, const double* wr1, const double* wr2,
+                          double sigma, double* g_wr1, double* g_wr2, hipStream_t s);
 
 // Fused radial MLP (hidden layers + output layer) on the matrix cores.  WS = float: float32
 // operands and storage; WS = bf16_t: bfloat16 operands for the two P-wide contractions and

@@ -321,6 +321,8 @@ struct sn_ctx {
   int nbins = 0;
   int n_echunk = 0, n_vchunk = 0;
   bool pending = false;
+  bool train = false;       // forwards keep every block's inputs and messages (weight gradients)
+  bool fwd_train = false;   // the pending forward kept them
   bool reuse = false;       // keep the graph of the previous call when n and the cell match
   bool have_graph = false;
   // hipGraph replay of the reused-graph evaluation (see sn_ctx_set_capture)
@@ -954,6 +956,44 @@ struct Pipe {
     }
   }
 
+  // Training: the radial-MLP adjoint unfused (pair sums of dE/dw, dz2 = dE/dw Wc^T, the
+  // hidden layers' adjoint) with the MLP's weight gradients, pairs as rows:
+  //   dWc = z2^T dE/dw,  dWb = z1^T da2,  dWa = rho^T da1
+  void mlp_backward_train(const LayerDesc& L, const T* rho, const S* dw, T* drho, double* gw) {
+    const int64_t NPr = c->NP;
+    const int* pe1 = c->get<int>("pair_e1", c->E);
+    const int* pe2 = c->get<int>("pair_e2", c->E);
+    const int H = m->hidden, NB = m->nb;
+    T* dws = c->get<T>("dw_pair", NPr * L.P);
+    launch_pair_sum<S, T>(NPr, pe1, pe2, dw, L.P, dws, s);
+    T* dz2 = c->get<T>("dz2", NPr * H);
+    gemm<T, T, T, T>(NPr, H, L.P, dws, plain_rows(L.P), L.w_mlp[2], L.P, true, dz2, plain_rows(H),
+                     T(1), false);
+    T* z1 = c->get<T>("tr_z1", NPr * H);
+    T* z2 = c->get<T>("tr_z2", NPr * H);
+    T* da1 = c->get<T>("tr_da1", NPr * H);
+    T* da2 = c->get<T>("tr_da2", NPr * H);
+    launch_mlp_hidden_bwd<T>(NPr, pe1, rho, NB, H, W<T>(c, L.w_mlp[0]), W<T>(c, L.w_mlp[1]),
+                             (T)m->act, dz2, drho, true, s, z1, da1, da2);
+    launch_mlp_hidden_fwd<T>(NPr, pe1, rho, NB, H, W<T>(c, L.w_mlp[0]), W<T>(c, L.w_mlp[1]),
+                             (T)m->act, z2, s);
+    double* part = c->get<double>("wg_part_aux", wgrad_chunks(NPr) * (int64_t)H * std::max(L.P, H));
+    launch_wgrad<T, T>(NPr, H, L.P, z2, plain_rows(H), nullptr, nullptr, dws, plain_rows(L.P), 1.0,
+                       part, gw + L.w_mlp[2], s);
+    launch_wgrad<T, T>(NPr, H, H, z1, plain_rows(H), nullptr, nullptr, da2, plain_rows(H), 1.0, part,
+                       gw + L.w_mlp[1], s);
+    launch_wgrad<T, T>(NPr, NB, H, rho, plain_rows(NB), pe1, nullptr, da1, plain_rows(H), 1.0, part,
+                       gw + L.w_mlp[0], s);
+  }
+
+  // weight gradient of a channel mixing over `rows` rows into the tensor at offset woff
+  template <typename TA, typename TB>
+  void wgrad(int64_t rows, int K, int N, const TA* A, RowMap am, const TB* B, RowMap bm,
+             int64_t woff, double* gw) {
+    double* part = c->get<double>("wg_part", wgrad_chunks(rows) * (int64_t)K * N);
+    launch_wgrad<TA, TB>(rows, K, N, A, am, nullptr, nullptr, B, bm, 1.0, part, gw + woff, s);
+  }
+
   void forward(double* d_energy, double* d_atom_energy_orig) {
     const int N = c->N, G = c->G, NE = N + G;
     const int64_t E = c->E;
@@ -1026,7 +1066,7 @@ struct Pipe {
       S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("layer" + ts + ".tp");
       HIPCHK(hipStreamWaitEvent(s, w_ready[t], 0));
-      T* M = c->get<T>("M", (int64_t)N * L.ml.width);
+      T* M = c->get<T>(c->fwd_train ? "M" + ts : std::string("M"), (int64_t)N * L.ml.width);
       launch_tp_fwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, M, (T)(1.0 / m->kavg), s);
       c->mark("layer" + ts + ".linear_out");
       {
@@ -1040,7 +1080,9 @@ struct Pipe {
         }
         gemm_group<T, T, double, T>(g, false);
       }
-      double* hn = c->get<double>(t % 2 ? "h_a" : "h_b", (int64_t)N * L.hout.width);
+      // block outputs alternate between two buffers, or stay per block for weight gradients
+      double* hn = c->get<double>(c->fwd_train ? "h_out" + ts : std::string(t % 2 ? "h_a" : "h_b"),
+                                  (int64_t)N * L.hout.width);
       launch_gate_fwd<double>(N, L.last, L.yl, L.hout, y, hn, m->act, s);
       h = hn;
     }
@@ -1062,9 +1104,13 @@ struct Pipe {
   }
 
   // d_grad: dL/dE_b per structure in device memory (null: 1), applied to the outputs (the
-  // adjoint is linear in the seed and structures share no edges)
-  void backward(const double* d_grad, double* d_forces_orig, double* d_virial) {
+  // adjoint is linear in the seed and structures share no edges).  With gw (training; the
+  // forward kept every block's inputs and messages) the seed itself carries each atom's
+  // dL/dE_b and gw receives dL/dW of every weight, laid out as the weights file.
+  void backward(const double* d_grad, double* d_forces_orig, double* d_virial,
+                double* gw = nullptr) {
     const int N = c->N, G = c->G, NE = N + G;
+    const bool train = gw != nullptr;
     (void)G;
     const int64_t E = c->E;
     const int* row_ptr = c->get<int>("row_ptr", N + 1);
@@ -1104,8 +1150,24 @@ struct Pipe {
     T* drho = c->get<T>("drho", E * m->nb);
     zero(drho, sizeof(T) * E * m->nb, s);  // only the first edge of each pair receives drho
     c->mark("bwd.readout");
-    // dE/dh^(T+1) = sigma (Wr1 Wr2): the same vector for every atom
-    launch_fill_rows<double>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
+    const double* g_atom = nullptr;
+    if (train) {
+      zero(gw, sizeof(double) * m->flat.size(), s);
+      double* ga = c->get<double>("g_atom", N);
+      launch_atom_grad(N, c->get<int>("sid_local", N), c->R / c->B, d_grad, ga, s);
+      g_atom = ga;
+      // dE/dh^(T+1)_i = sigma g_i (Wr1 Wr2); readout weights from u = sum_i g_i h_i
+      const int wlast = m->layers.back().hout.width;
+      launch_seed_rows(N, c->d_v, C0, m->sigma, g_atom, dh, wlast, s);
+      const double* hT = c->get<double>("h_out" + std::to_string(m->T - 1), (int64_t)N * wlast);
+      double* u = c->get<double>("tr_u", C0);
+      wgrad<double, double>(N, C0, 1, hT, plain_rows(wlast), g_atom, plain_rows(1), 0, u);
+      const int64_t r0 = m->tensors.at("readout.0").first, r1 = m->tensors.at("readout.1").first;
+      launch_readout_wgrad(C0, u, W<double>(c, r0), W<double>(c, r1), m->sigma, gw + r0, gw + r1, s);
+    } else {
+      // dE/dh^(T+1) = sigma (Wr1 Wr2): the same vector for every atom
+      launch_fill_rows<double>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
+    }
     for (int t = m->T - 1; t >= 0; --t) {
       const LayerDesc& L = m->layers[t];
       const std::string ts = std::to_string(t);
@@ -1114,6 +1176,22 @@ struct Pipe {
       const S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("bwd.layer" + ts + ".linear_out");
       launch_gate_bwd<double>(N, L.last, L.yl, L.hout, y, dh, dy, m->act, s);
+      // the block's input features (NE rows in block 1, whose ghosts carry their own species)
+      const double* h_in =
+          train ? c->get<double>(t == 0 ? std::string("h_cur") : "h_out" + std::to_string(t - 1),
+                                 (int64_t)(t == 0 ? NE : N) * L.hin.width)
+                : nullptr;
+      if (train) {
+        // Lin2: dW = M^T dy;  Linsc: dW = h^T dy
+        const T* Mt = c->get<T>("M" + ts, (int64_t)N * L.ml.width);
+        for (int l : L.outs)
+          wgrad<T, double>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], Mt, rows_of(L.ml, l), dy,
+                           rows_of(L.yl, l), L.w_lin2[l], gw);
+        for (int l : L.ins)
+          if (L.gmul[l] > 0)
+            wgrad<double, double>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], h_in,
+                                  rows_of(L.hin, l), dy, rows_of(L.yl, l), L.w_linsc[l], gw);
+      }
       {
         std::vector<GemmDesc<double, T, T>> g;
         for (int l : L.outs)
@@ -1128,22 +1206,47 @@ struct Pipe {
         HIPCHK(hipStreamWaitEvent(s, mlp_done[t + 2], 0));
       }
       c->mark("bwd.layer" + ts + ".tp");
-      launch_tp_bwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, Gm, dw, t > 0 ? dxe : nullptr, dY,
-                          t != m->T - 1, s);
+      launch_tp_bwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, Gm, dw,
+                          (t > 0 || train) ? dxe : nullptr, dY, t != m->T - 1, s);
       c->join(c->aux, s);
       c->aux_begin("bwd.layer" + ts + ".mlp");
       {
         OnStream os(this, c->aux);
-        mlp_backward(L, rho, dw, dz2, drho);
+        if (train) mlp_backward_train(L, rho, dw, drho, gw);
+        else mlp_backward(L, rho, dw, dz2, drho);
       }
       c->aux_end();
       mlp_done[t] = c->sync_event();
       HIPCHK(hipEventRecord(mlp_done[t], c->aux));
-      if (t == 0) break;
+      if (t == 0 && !train) break;
       c->mark("bwd.layer" + ts + ".sender_fold");
-      // sender-side sums over every extended row, then fold ghost rows onto owners
+      // sender-side sums over every extended row
       launch_sender_reduce<S>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
+      if (t == 0) {
+        // block 1 (training): x = Lin1(h^(1)) on every extended row, each ghost from its own
+        // species, so nothing folds: dW = h^T dx over all rows, then dE/dh^(1) on all rows
+        // (plus the self-connection's share on local rows) feeds the embedding gradient
+        wgrad<double, double>(NE, C0, C0, h_in, rows_of(L.hin, 0), dx_ext, rows_of(L.hin, 0),
+                              L.w_lin1[0], gw);
+        double* dh1 = c->get<double>("tr_dh1", (int64_t)NE * C0);
+        gemm<double, T, double, T>(NE, C0, C0, dx_ext, rows_of(L.hin, 0), L.w_lin1[0], C0, true, dh1,
+                                   rows_of(L.hin, 0), T(1), false);
+        if (L.gmul[0] > 0)
+          gemm<double, T, double, T>(N, C0, L.gmul[0], dy, rows_of(L.yl, 0), L.w_linsc[0],
+                                     L.gmul[0], true, dh1, rows_of(L.hin, 0), T(1), true);
+        const int S_ = (int)m->species.size();
+        double* part = c->get<double>("wg_part", wgrad_chunks(NE) * (int64_t)S_ * C0);
+        launch_wgrad<double, double>(NE, S_, C0, nullptr, plain_rows(0), nullptr,
+                                     c->get<int>("spec_ext", NE), dh1, plain_rows(C0), 1.0, part,
+                                     gw + m->tensors.at("embed").first, s);
+        break;
+      }
+      // fold ghost rows onto owners
       launch_ghost_fold<double>(N, gptr, dx_ext, dx, L.hin.width, s);
+      if (train)  // Lin1: dW = h^T dx
+        for (int l : L.ins)
+          wgrad<double, double>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h_in,
+                                rows_of(L.hin, l), dx, rows_of(L.hin, l), L.w_lin1[l], gw);
       c->mark("bwd.layer" + ts + ".linear_in");
       {
         // dh = dx Lin1^T (all degrees), then += dy Linsc^T (all degrees)
@@ -1168,16 +1271,18 @@ struct Pipe {
     launch_edge_grad<T>(E, recv, src, pos_ext, m->rc, m->nb, m->p, m->lsh, dY, drho, gE, s);
     double* F = c->get<double>("F_local", 3 * (int64_t)N);
     launch_forces(N, row_ptr, sptr, sidx, gptr, gE, F, s);
+    // (with training seeds the edge gradients already carry each structure's dL/dE_b)
+    const double* out_scale = train ? nullptr : d_grad;
     if (d_forces_orig) {
       const int* order = c->get<int>("order", N);
-      launch_unpermute(N, order, F, 3, d_forces_orig, d_grad, c->get<int>("sid_orig", N),
+      launch_unpermute(N, order, F, 3, d_forces_orig, out_scale, c->get<int>("sid_orig", N),
                        c->R / c->B, s);
     }
     if (d_virial) {
       double* part = c->get<double>("partial_w", 9 * (int64_t)c->n_vchunk);
       launch_seg_virial(c->n_vchunk, c->get<int>("vchunks", 3 * c->n_vchunk), recv, src, pos_ext,
                         gE, part, s);
-      launch_seg_finalize(c->B, c->get<int>("vfirst", c->B + 1), part, 9, d_virial, d_grad, s);
+      launch_seg_finalize(c->B, c->get<int>("vfirst", c->B + 1), part, 9, d_virial, out_scale, s);
     }
     HIPCHK(hipGetLastError());
     c->mark("end");
@@ -1338,6 +1443,7 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
                   const double* cells, double* d_energy, double* d_atom_energy) {
   const int64_t n = offsets[B];
   if (n <= 0 || n > (1 << 28)) throw ArgError("atom count out of range");
+  c->fwd_train = c->train;
   c->marks.clear();
   c->aux_marks.clear();
   c->event_next = 0;
@@ -1362,8 +1468,9 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
     c->last_fwd_reused = true;
     c->pending = true;
     sn_ctx::Replay& r = c->rp_fwd;
-    // replay once an eager run on this graph has sized every buffer
-    if (c->capture && c->reuse_runs >= 1) {
+    // replay once an eager run on this graph has sized every buffer (not in training mode,
+    // whose forwards keep other buffers)
+    if (c->capture && !c->train && c->reuse_runs >= 1) {
       if (!replay_hit(r, c->graph_version, d_pos, d_energy, d_atom_energy)) {
         if (r.exec) (void)hipGraphExecDestroy(r.exec);
         r.exec = nullptr;
@@ -1396,15 +1503,16 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
 }
 
 template <typename T, typename S>
-void backward_impl(sn_ctx* c, const double* d_grad, double* d_forces, double* d_virial) {
+void backward_impl(sn_ctx* c, const double* d_grad, double* d_forces, double* d_virial,
+                   double* d_wgrad = nullptr) {
   if (!c->pending) throw std::logic_error("busy");
   auto body = [&] {
     Pipe<T, S> p(c);
-    p.backward(d_grad, d_forces, d_virial);
+    p.backward(d_grad, d_forces, d_virial, d_wgrad);
   };
   c->pending = false;
   sn_ctx::Replay& r = c->rp_bwd;
-  if (c->capture && c->last_fwd_reused && c->reuse_runs >= 1) {
+  if (!d_wgrad && c->capture && c->last_fwd_reused && c->reuse_runs >= 1) {
     if (!replay_hit(r, c->graph_version, d_forces, d_virial, d_grad)) {
       if (r.exec) (void)hipGraphExecDestroy(r.exec);
       r.exec = nullptr;
@@ -1684,6 +1792,63 @@ int sn_backward_device(sn_ctx_t* ctx, const double* d_grad_energy, double* d_for
     else
       backward_impl<float, float>(ctx, d_grad_energy, d_forces, d_virial);
   });
+}
+
+int sn_ctx_set_training(sn_ctx_t* ctx, int on) {
+  if (!ctx) return SN_EINVAL;
+  ctx->train = on != 0;
+  return SN_OK;
+}
+
+int sn_backward_train_device(sn_ctx_t* ctx, const double* d_grad_energy, double* d_forces,
+                             double* d_virial, double* d_weight_grad) {
+  if (!ctx || !d_grad_energy || !d_weight_grad) return SN_EINVAL;
+  if (!ctx->pending || !ctx->fwd_train) {
+    ctx->err = ctx->pending ? "the pending forward did not run in training mode"
+                            : "backward without a pending forward";
+    return SN_EBUSY;
+  }
+  if ((int64_t)ctx->m->flat.size() != ctx->m->n_params) {
+    ctx->err = "weights file with gaps between tensors";
+    return SN_EUNSUPPORTED;
+  }
+  return guarded(ctx, [&] {
+    if (ctx->precision == SN_FP64)
+      backward_impl<double, double>(ctx, d_grad_energy, d_forces, d_virial, d_weight_grad);
+    else if (ctx->precision == SN_BF16)
+      backward_impl<float, bf16_t>(ctx, d_grad_energy, d_forces, d_virial, d_weight_grad);
+    else
+      backward_impl<float, float>(ctx, d_grad_energy, d_forces, d_virial, d_weight_grad);
+  });
+}
+
+int sn_model_tensor(const sn_model_t* model, int index, const char** name, int64_t* offset,
+                    int64_t* count) {
+  if (!model || index < 0 || index >= (int)model->tensors.size()) return SN_EINVAL;
+  auto it = model->tensors.begin();
+  std::advance(it, index);
+  int64_t n = 1;
+  for (int d : it->second.second) n *= d;
+  if (name) *name = it->first.c_str();
+  if (offset) *offset = it->second.first;
+  if (count) *count = n;
+  return SN_OK;
+}
+
+int sn_huber_energy_loss(int B, const double* energy, const double* ref, const int64_t* natoms,
+                         double delta, double* loss, double* dloss_denergy) {
+  if (B < 1 || !energy || !ref || !natoms || !loss || !(delta > 0)) return SN_EINVAL;
+  double acc = 0.0;
+  for (int b = 0; b < B; ++b) {
+    if (natoms[b] < 1) return SN_EINVAL;
+    const double nb = (double)natoms[b];
+    const double r = energy[b] / nb - ref[b] / nb;
+    const double a = std::fabs(r);
+    acc += a < delta ? 0.5 * r * r : delta * (a - 0.5 * delta);
+    if (dloss_denergy) dloss_denergy[b] = (a < delta ? r : (r > 0 ? delta : -delta)) / (B * nb);
+  }
+  *loss = acc / B;
+  return SN_OK;
 }
 
 int sn_ctx_synchronize(sn_ctx_t* ctx) {
