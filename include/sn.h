@@ -220,9 +220,9 @@ int sn_backward_device(sn_ctx_t* ctx, const double* d_grad_energy, double* d_for
 
 /* ---- training: weight gradients of the energy term of the loss ----------------------
  * Paper section 5.1 trains with the loss of eq 9: a Huber loss of per-atom energies, forces
- * and stresses.  These calls give the energy term and its gradient with respect to every
- * model weight; the force and stress terms need second derivatives through the force
- * adjoint and are not provided.
+ * and stresses.  sn_backward_train_device gives the exact weight gradient of any linear
+ * function of the energies (the energy term); sn_train_loss_grad gives the gradient of the
+ * whole loss.
  *
  * sn_ctx_set_training(ctx, 1): later forwards keep every interaction block's input features
  * and messages (about (Dx + Dm) float64/float32 values per atom and block more device
@@ -242,6 +242,27 @@ int sn_ctx_set_training(sn_ctx_t* ctx, int on);
  * pairs: bitwise reproducible.  SN_EUNSUPPORTED for a weights file with gaps. */
 int sn_backward_train_device(sn_ctx_t* ctx, const double* d_grad_energy, double* d_forces,
                              double* d_virial, double* d_weight_grad);
+
+/* Gradient of the whole loss of eq 9 for one packed batch (blocking; host labels):
+ *   Gamma = (1/M) sum_b huber(E_b/N_b - refE_b/N_b)
+ *         + mu_f / (3 M N) sum_{b,j,k} huber(F_bjk - refF_bjk)        (N: atoms of the batch)
+ *         + mu_s / (6 M) sum_{b,l} huber(S_bl - refS_bl)
+ * with S = -W / V in GPa from the symmetrised virial (components xx yy zz yz xz xy).
+ * ref_energy[B] eV, ref_forces[n*3] eV/angstrom (batch order), ref_stress[B*6] GPa (host).
+ * Writes *loss and d_weight_grad (device, n_params float64, layout as sn_backward_train_device).
+ * The energy term's weight gradient is the exact adjoint.  The force and stress terms are
+ * second derivatives: with v_i = dGamma/dF_i and the symmetric U_b = dGamma/dW_b, and since
+ * F = -dE/dr and W_ab = -dE/de_ab for a strain e, their weight gradient is minus the weight
+ * gradient of the derivative of E along the deformation r -> r + eps (v + U r), cell rows
+ * a -> a + eps U a.  That is taken as a four-point central difference of exact weight
+ * gradients at eps = +-h, +-2h (error O(h^4)), h chosen so the largest displacement is
+ * fd_step angstrom (0: 1e-3 in the FP64 form, 2e-2 otherwise).  Costs six evaluations with
+ * adjoints; with mu_f = mu_s = 0 the difference quotient is skipped (the energy term alone).
+ * SN_EINVAL for a malformed batch, delta <= 0 or negative weights. */
+int sn_train_loss_grad(sn_ctx_t* ctx, const sn_batch_t* batch, const double* ref_energy,
+                       const double* ref_forces, const double* ref_stress, double delta,
+                       double mu_f, double mu_s, double fd_step, double* loss,
+                       double* d_weight_grad);
 
 /* Name, offset (in float64 values from the start of the weights) and element count of the
  * index-th tensor of the model (tensors in name order).  SN_EINVAL past the last one.  The

@@ -91,6 +91,9 @@ _SIGS = {
     "sn_ctx_set_training": (C.c_int, [C.c_void_p, C.c_int]),
     "sn_backward_train_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p]),
+    "sn_train_loss_grad": (C.c_int, [C.c_void_p, C.POINTER(Batch), C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.POINTER(C.c_double), C.c_void_p]),
     "sn_model_tensor": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_char_p),
                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sn_huber_energy_loss": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,

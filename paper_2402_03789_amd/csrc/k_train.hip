@@ -135,6 +135,43 @@ void launch_readout_wgrad(int C0, const double* u, const double* wr1, const doub
   k_readout_wgrad<<<1, 256, 0, s>>>(C0, u, wr1, wr2, sigma, g_wr1, g_wr2);
 }
 
+// positions moved along a direction: out_i = pos_i + eps (v_i + U_b pos_i), b the structure of
+// atom i (U row-major 3 x 3 per structure)
+__global__ void k_perturb(int64_t n, const double* __restrict__ pos, const double* __restrict__ v,
+                          const double* __restrict__ U, const int* __restrict__ atom_struct,
+                          double eps, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* u = U + 9 * atom_struct[i];
+  const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  out[3 * i] = x + eps * (v[3 * i] + u[0] * x + u[1] * y + u[2] * z);
+  out[3 * i + 1] = y + eps * (v[3 * i + 1] + u[3] * x + u[4] * y + u[5] * z);
+  out[3 * i + 2] = z + eps * (v[3 * i + 2] + u[6] * x + u[7] * y + u[8] * z);
+}
+
+// y += a x (float64)
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+__global__ void k_fill_f64(int64_t n, double v, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+void launch_perturb(int64_t n, const double* pos, const double* v, const double* U,
+                    const int* atom_struct, double eps, double* out, hipStream_t s) {
+  if (n > 0)
+    k_perturb<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, pos, v, U, atom_struct, eps, out);
+}
+void launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  if (n > 0) k_axpy<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, x, y);
+}
+void launch_fill_f64(int64_t n, double v, double* y, hipStream_t s) {
+  if (n > 0) k_fill_f64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, v, y);
+}
+
 #define SN_WG_INST(TA, TB)                                                                      \
   template void launch_wgrad<TA, TB>(int64_t, int, int, const TA*, RowMap, const int*,           \
                                      const int*, const TB*, RowMap, double, double*, double*,     \

@@ -141,6 +141,11 @@ void launch_seed_rows(int n, const double* v, int C0, double sigma, const double
                       double* dh, int ldh, hipStream_t s);
 void launch_readout_wgrad(int C0, const double* u, const double* wr1, const double* wr2,
                           double sigma, double* g_wr1, double* g_wr2, hipStream_t s);
+// out_i = pos_i + eps (v_i + U_b pos_i) with b = atom_struct[i] and U[b] row-major 3 x 3
+void launch_perturb(int64_t n, const double* pos, const double* v, const double* U,
+                    const int* atom_struct, double eps, double* out, hipStream_t s);
+void launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);
+void launch_fill_f64(int64_t n, double v, double* y, hipStream_t s);
 
 // Fused radial MLP (hidden layers + output layer) on the matrix cores.  WS = float: float32
 // operands and storage; WS = bf16_t: bfloat16 operands for the two P-wide contractions and

@@ -1611,6 +1611,143 @@ char* scratch_address(int device) {
 
 }  // namespace
 
+namespace {
+
+// The gradient of the whole training loss (sn_train_loss_grad).
+template <typename T, typename S>
+void train_loss_grad(sn_ctx* c, const sn_batch_t* bt, const double* refE, const double* refF,
+                     const double* refS, double delta, double mu_f, double mu_s, double fd_step,
+                     double* loss, double* gw) {
+  const int B = bt->n_structures;
+  const int64_t* off = bt->offsets;
+  const int64_t n = off[B];
+  hipStream_t s = c->stream;
+  const int64_t np = c->m->n_params;
+  std::vector<int> spec;
+  {
+    std::vector<int32_t> hz((size_t)n);
+    HIPCHK(hipMemcpyAsync(hz.data(), bt->d_Z, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    map_species(c->m, n, hz.data(), spec);
+  }
+  int* d_spec = c->get<int>("spec_orig", n);
+  HIPCHK(hipMemcpyAsync(d_spec, spec.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  // (1) energies, forces and virials of the batch
+  double* d_E = c->get<double>("tr_E", B);
+  double* d_F = c->get<double>("tr_F", 3 * n);
+  double* d_W = c->get<double>("tr_W", 9 * (int64_t)B);
+  double* d_one = c->get<double>("tr_one", B);
+  launch_fill_f64(B, 1.0, d_one, s);
+  const bool was_train = c->train, was_reuse = c->reuse;
+  c->train = false;
+  c->reuse = false;  // every evaluation below builds its own graph
+  forward_impl<T, S>(c, B, off, bt->d_pos, d_spec, bt->cells, d_E, nullptr);
+  backward_impl<T, S>(c, d_one, d_F, d_W);
+  std::vector<double> E(B), F(3 * n), Wv(9 * (size_t)B);
+  HIPCHK(hipMemcpyAsync(E.data(), d_E, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(F.data(), d_F, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(Wv.data(), d_W, sizeof(double) * 9 * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // (2) the loss and its derivatives with respect to E_b, F_i and the virials W_b
+  auto hub = [&](double r) { const double a = std::fabs(r); return a < delta ? 0.5 * r * r : delta * (a - 0.5 * delta); };
+  auto dhub = [&](double r) { return std::fabs(r) < delta ? r : (r > 0 ? delta : -delta); };
+  constexpr double kGPa = 160.21766208;  // GPa per eV / A^3
+  const double cf = mu_f / (3.0 * B * (double)n), cs = mu_s / (6.0 * B);
+  double le = 0, lf = 0, ls = 0;
+  std::vector<double> gE(B), v(3 * n, 0.0), U(9 * (size_t)B, 0.0);
+  std::vector<int> atom_struct((size_t)n);
+  for (int b = 0; b < B; ++b) {
+    const double nb = (double)(off[b + 1] - off[b]);
+    const double r = E[b] / nb - refE[b] / nb;
+    le += hub(r);
+    gE[b] = dhub(r) / (B * nb);
+    for (int64_t i = off[b]; i < off[b + 1]; ++i) {
+      atom_struct[i] = b;
+      for (int k = 0; k < 3; ++k) {
+        const double rf = F[3 * i + k] - refF[3 * i + k];
+        lf += hub(rf);
+        v[3 * i + k] = cf * dhub(rf);
+      }
+    }
+    const double* H = bt->cells + 9 * b;
+    const double V = std::fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                               H[2] * (H[3] * H[7] - H[4] * H[6]));
+    const double* w = &Wv[9 * b];
+    // S = -sym(W) / V in GPa, components xx yy zz yz xz xy
+    const int ia[6] = {0, 1, 2, 1, 0, 0}, ib[6] = {0, 1, 2, 2, 2, 1};
+    for (int l = 0; l < 6; ++l) {
+      const double Wab = 0.5 * (w[3 * ia[l] + ib[l]] + w[3 * ib[l] + ia[l]]);
+      const double Sl = -Wab / V * kGPa;
+      const double rs = Sl - refS[6 * b + l];
+      ls += hub(rs);
+      const double gS = cs * dhub(rs) * (-kGPa / V);  // dL/dW_ab (symmetric part)
+      if (ia[l] == ib[l]) U[9 * b + 4 * ia[l]] += gS;
+      else {
+        U[9 * b + 3 * ia[l] + ib[l]] += 0.5 * gS;
+        U[9 * b + 3 * ib[l] + ia[l]] += 0.5 * gS;
+      }
+    }
+  }
+  *loss = le / B + cf * lf + cs * ls;
+  // (3) the energy term's weight gradient: the adjoint seeded with dL/dE_b
+  double* d_gE = c->get<double>("tr_gE", B);
+  HIPCHK(hipMemcpyAsync(d_gE, gE.data(), sizeof(double) * B, hipMemcpyHostToDevice, s));
+  c->train = true;
+  forward_impl<T, S>(c, B, off, bt->d_pos, d_spec, bt->cells, d_E, nullptr);
+  backward_impl<T, S>(c, d_gE, nullptr, nullptr, gw);
+  // (4) force and stress terms: sum_i v_i . dF_i/dW + sum_b U_b : dW_b/dW = -d/dW of the
+  // directional derivative of E along (v, U); four-point central difference of exact weight
+  // gradients along r + eps (v + U r), cells H (I + eps U)^T
+  double m = 0;
+  std::vector<double> pos(3 * n);
+  HIPCHK(hipMemcpyAsync(pos.data(), bt->d_pos, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < n; ++i) {
+    const double* u = &U[9 * atom_struct[i]];
+    for (int a = 0; a < 3; ++a) {
+      const double d = v[3 * i + a] + u[3 * a] * pos[3 * i] + u[3 * a + 1] * pos[3 * i + 1] +
+                       u[3 * a + 2] * pos[3 * i + 2];
+      m = std::max(m, std::fabs(d));
+    }
+  }
+  if (m > 0) {
+    const double step = fd_step > 0 ? fd_step : (c->precision == SN_FP64 ? 1e-3 : 2e-2);
+    const double h = step / m;
+    double* d_v = c->get<double>("tr_v", 3 * n);
+    double* d_U = c->get<double>("tr_U", 9 * (int64_t)B);
+    int* d_as = c->get<int>("tr_as", n);
+    double* d_pp = c->get<double>("tr_pos", 3 * n);
+    double* d_G = c->get<double>("tr_G", np);
+    HIPCHK(hipMemcpyAsync(d_v, v.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_U, U.data(), sizeof(double) * 9 * B, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_as, atom_struct.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    std::vector<double> cells(9 * (size_t)B);
+    const double steps[4] = {1.0, -1.0, 2.0, -2.0};
+    const double wts[4] = {8.0, -8.0, -1.0, 1.0};  // (8 (G+ - G-) - (G++ - G--)) / 12h
+    for (int q = 0; q < 4; ++q) {
+      const double eps = steps[q] * h;
+      launch_perturb(n, bt->d_pos, d_v, d_U, d_as, eps, d_pp, s);
+      for (int b = 0; b < B; ++b)
+        for (int k = 0; k < 3; ++k)  // cell row k: a_k + eps U a_k
+          for (int a = 0; a < 3; ++a) {
+            double t = bt->cells[9 * b + 3 * k + a];
+            for (int j = 0; j < 3; ++j) t += eps * U[9 * b + 3 * a + j] * bt->cells[9 * b + 3 * k + j];
+            cells[9 * b + 3 * k + a] = t;
+          }
+      forward_impl<T, S>(c, B, off, d_pp, d_spec, cells.data(), d_E, nullptr);
+      backward_impl<T, S>(c, d_one, nullptr, nullptr, d_G);
+      launch_axpy(np, -wts[q] / (12.0 * h), d_G, gw, s);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  c->train = was_train;
+  c->reuse = was_reuse;
+  c->pending = false;
+  c->have_graph = false;  // the last graph is the perturbed one
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -1820,6 +1957,40 @@ int sn_backward_train_device(sn_ctx_t* ctx, const double* d_grad_energy, double*
     else
       backward_impl<float, float>(ctx, d_grad_energy, d_forces, d_virial, d_weight_grad);
   });
+}
+
+
+int sn_train_loss_grad(sn_ctx_t* ctx, const sn_batch_t* batch, const double* ref_energy,
+                       const double* ref_forces, const double* ref_stress, double delta,
+                       double mu_f, double mu_s, double fd_step, double* loss,
+                       double* d_weight_grad) {
+  if (!ctx || !batch || !ref_energy || !ref_forces || !ref_stress || !loss || !d_weight_grad ||
+      !(delta > 0) || mu_f < 0 || mu_s < 0 || fd_step < 0)
+    return SN_EINVAL;
+  const int B = batch->n_structures;
+  const int64_t* off = batch->offsets;
+  if (B < 1 || !off || !batch->cells || !batch->d_pos || !batch->d_Z || off[0] != 0) return SN_EINVAL;
+  for (int b = 0; b < B; ++b)
+    if (off[b + 1] <= off[b]) return SN_EINVAL;
+  if ((int64_t)ctx->m->flat.size() != ctx->m->n_params) {
+    ctx->err = "weights file with gaps between tensors";
+    return SN_EUNSUPPORTED;
+  }
+  const bool was_train = ctx->train, was_reuse = ctx->reuse;
+  const int st = guarded(ctx, [&] {
+    if (ctx->precision == SN_FP64)
+      train_loss_grad<double, double>(ctx, batch, ref_energy, ref_forces, ref_stress, delta, mu_f,
+                                      mu_s, fd_step, loss, d_weight_grad);
+    else if (ctx->precision == SN_BF16)
+      train_loss_grad<float, bf16_t>(ctx, batch, ref_energy, ref_forces, ref_stress, delta, mu_f,
+                                     mu_s, fd_step, loss, d_weight_grad);
+    else
+      train_loss_grad<float, float>(ctx, batch, ref_energy, ref_forces, ref_stress, delta, mu_f,
+                                    mu_s, fd_step, loss, d_weight_grad);
+  });
+  ctx->train = was_train;
+  ctx->reuse = was_reuse;
+  return st;
 }
 
 int sn_model_tensor(const sn_model_t* model, int index, const char** name, int64_t* offset,

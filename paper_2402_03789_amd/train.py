@@ -79,3 +79,27 @@ def energy_loss_and_grads(ctx, structures, labels, delta: float = 0.01, device: 
     flat = wg.cpu().numpy()
     grads = {name: flat[off:off + cnt] for name, off, cnt in ctx.model.tensors()}
     return dict(loss=loss, energies=e, dloss_dE=g, grads=grads)
+
+
+def full_loss_and_grads(ctx, structures, labels_E, labels_F, labels_S, delta: float = 0.01,
+                        mu_f: float = 0.1, mu_s: float = 0.01, fd_step: float = 0.0,
+                        device: int = 0) -> dict:
+    """All three terms of eq 9 and dloss/dW per weight tensor (sn_train_loss_grad) for a batch
+    of (pos, Z, cell) structures; labels_F: one [N_b, 3] array per structure, labels_S [M, 6]
+    (GPa)."""
+    from ._lib import Batch
+    dev = torch.device(f"cuda:{device}")
+    offs, pos, Z, cells = _pack(structures, dev)
+    cells = np.ascontiguousarray(cells)
+    rE = np.ascontiguousarray(labels_E, dtype=np.float64)
+    rF = np.ascontiguousarray(np.concatenate([np.asarray(f, np.float64).reshape(-1, 3) for f in labels_F]))
+    rS = np.ascontiguousarray(labels_S, dtype=np.float64).reshape(-1, 6)
+    wg = torch.zeros(ctx.model.info()["n_params"], dtype=torch.float64, device=dev)
+    b = Batch(len(structures), offs.ctypes.data, cells.ctypes.data, pos.data_ptr(), Z.data_ptr())
+    loss = C.c_double()
+    check(lib().sn_train_loss_grad(ctx.handle, C.byref(b), ptr(rE), ptr(rF), ptr(rS), float(delta),
+                                   float(mu_f), float(mu_s), float(fd_step), C.byref(loss),
+                                   ptr(wg)), ctx.handle)
+    flat = wg.cpu().numpy()
+    return dict(loss=loss.value,
+                grads={name: flat[off:off + cnt] for name, off, cnt in ctx.model.tensors()})

@@ -100,3 +100,40 @@ def test_training_backward_needs_training_forward(setup):
     wg = torch.zeros(ctx.model.info()["n_params"], dtype=torch.float64, device=dev)
     with pytest.raises(sn.SNError):
         ctx.backward_train_device(torch.ones(1, dtype=torch.float64, device=dev), wg)
+
+
+@pytest.fixture(scope="module")
+def full_setup(setup):
+    from oracle.train import full_loss
+    which, path, batch, labels, _ = setup
+    spec = model_spec_small() if which == "small" else model_spec_real()
+    from synth import make_weights
+    om = OracleModel(spec.config(), make_weights(spec, 21))
+    pred = full_loss(om, batch, [0.0] * len(batch), [np.zeros((len(z), 3)) for _, z, _ in batch],
+                     np.zeros((len(batch), 6)), grads=False)
+    rng = np.random.Generator(np.random.PCG64(17))
+    lF = [f + rng.normal(0.0, 0.02, f.shape) for f in pred["forces"]]
+    lS = pred["stress"] + rng.normal(0.0, 0.05, pred["stress"].shape)
+    ref = full_loss(om, batch, labels, lF, lS)
+    return which, path, batch, labels, lF, lS, ref
+
+
+# the force and stress terms come from a four-point difference quotient of exact weight
+# gradients (O(h^4) with a 1e-3 A step in float64; 2e-2 A in float32, where the gradients'
+# own rounding over the step dominates)
+TOL_FULL = {"fp64": 1e-10, "fp32": 1e-4}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_loss_gradients_match_oracle(full_setup, precision):
+    from paper_2402_03789_amd.train import full_loss_and_grads
+    which, path, batch, labels, lF, lS, ref = full_setup
+    ctx = sn.Context(sn.Model(path), precision=precision)
+    got = full_loss_and_grads(ctx, batch, labels, lF, lS)
+    worst = _worst(got["grads"], ref["grads"])
+    log(f"full loss {which} {precision}: loss {got['loss']:.12e} (oracle {ref['loss']:.12e}); "
+        f"worst tensor {worst[0]} {worst[1]:.2e}")
+    if precision == "fp64":
+        assert abs(got["loss"] - ref["loss"]) <= 1e-10 * abs(ref["loss"])
+    assert worst[1] <= TOL_FULL[precision], worst
+    ctx.close()
