@@ -55,8 +55,10 @@ extern "C" {
                       its float64 contractions on the float64 matrix cores; energy and virial
                       reductions in float64 */
 #define SN_BF16 2  /* as SN_FP32, but the radial MLP and the channel-mixing linears take
-                      bfloat16 operands with float32 accumulation on the matrix cores; tensor
-                      product in float32; float64 energy and virial reductions */
+                      bfloat16 operands with float32 accumulation on the matrix cores; sender
+                      features, radial weights and per-edge gradients stored in bfloat16;
+                      tensor product in float32; node-state chain in float32; float64
+                      positions, edge gradients, forces, energy and virial reductions */
 
 typedef struct sn_model sn_model_t;
 typedef struct sn_ctx sn_ctx_t;

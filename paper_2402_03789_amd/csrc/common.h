@@ -51,9 +51,14 @@ __host__ __device__ inline S sstore(T v) {
 }
 template <>
 __host__ __device__ inline bf16_t sstore<bf16_t, float>(float v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // gfx950 rounds to nearest even in one instruction (v_cvt_pk_bf16_f32)
+  return bf16_t{__builtin_bit_cast(uint16_t, (__bf16)v)};
+#else
   uint32_t u = __builtin_bit_cast(uint32_t, v);
   u += 0x7fffu + ((u >> 16) & 1u);
   return bf16_t{(uint16_t)(u >> 16)};
+#endif
 }
 template <>
 __host__ __device__ inline bf16_t sstore<bf16_t, double>(double v) {

@@ -470,6 +470,7 @@ SN_MFMA_INST(double, float, double)
 SN_MFMA_INST(double, double, float)
 SN_MFMA_INST(double, double, double)
 SN_MFMA_INST(double, float, bf16_t)
+SN_MFMA_INST(float, float, bf16_t)
 #undef SN_MFMA_INST
 
 }  // namespace sn

@@ -114,15 +114,16 @@ __global__ void k_fill_rows(int n, const double* __restrict__ v, int C0, double 
 }
 
 // One row per block; each thread owns 4 consecutive columns (one 16-byte load per edge
-// in float32) and accumulates in float64.  The edge loop is unrolled for memory-level
-// parallelism; the summation order stays the sender segment's order.
-template <typename T>
+// in float32) and accumulates in the output type H (float64, or float32 in the bfloat16
+// form).  The edge loop is unrolled for memory-level parallelism; the summation order
+// stays the sender segment's order.
+template <typename T, typename H>
 __global__ void k_sender_reduce(int n_rows, const int* __restrict__ sptr, const int* __restrict__ sidx,
-                                const T* __restrict__ dxe, int width, double* __restrict__ dx) {
+                                const T* __restrict__ dxe, int width, H* __restrict__ dx) {
   const int s = blockIdx.x;
   const int a = sptr[s], b = sptr[s + 1];
   for (int c = threadIdx.x * 4; c < width; c += blockDim.x * 4) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    H acc[4] = {H(0), H(0), H(0), H(0)};
     int q = a;
     for (; q + 4 <= b; q += 4) {
       T v[4][4];
@@ -135,12 +136,12 @@ __global__ void k_sender_reduce(int n_rows, const int* __restrict__ sptr, const 
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] += (double)sload(v[k][j]);
+        for (int j = 0; j < 4; ++j) acc[j] += (H)sload(v[k][j]);
     }
     for (; q < b; ++q) {
       const T* row = dxe + (int64_t)sidx[q] * width + c;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] += (double)sload(row[j]);
+      for (int j = 0; j < 4; ++j) acc[j] += (H)sload(row[j]);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) dx[(int64_t)s * width + c + j] = acc[j];
@@ -457,10 +458,10 @@ template <typename T>
 void launch_fill_rows(int n, const double* v, int C0, double scale, T* dh, int ldh, hipStream_t s) {
   if (n > 0) k_fill_rows<T><<<n, 128, 0, s>>>(n, v, C0, scale, dh, ldh);
 }
-template <typename T>
+template <typename T, typename H>
 void launch_sender_reduce(int n_rows, const int* sptr, const int* sidx, const T* dxe, int width,
-                          double* dx, hipStream_t s) {
-  if (n_rows > 0) k_sender_reduce<T><<<n_rows, 128, 0, s>>>(n_rows, sptr, sidx, dxe, width, dx);
+                          H* dx, hipStream_t s) {
+  if (n_rows > 0) k_sender_reduce<T, H><<<n_rows, 128, 0, s>>>(n_rows, sptr, sidx, dxe, width, dx);
 }
 template <typename T>
 void launch_ghost_fold(int n_local, const int* gptr, const T* dx_ext, T* dx, int width, hipStream_t s) {
@@ -507,8 +508,8 @@ void launch_unpermute(int n, const int* order, const double* in_rows, int width,
   template void launch_readout<T>(int, const T*, int, const double*, int, double, const double*,  \
                                   const int*, double*, hipStream_t);                              \
   template void launch_fill_rows<T>(int, const double*, int, double, T*, int, hipStream_t);       \
-  template void launch_sender_reduce<T>(int, const int*, const int*, const T*, int, double*,      \
-                                        hipStream_t);                                             \
+  template void launch_sender_reduce<T, double>(int, const int*, const int*, const T*, int,       \
+                                                double*, hipStream_t);                            \
   template void launch_ghost_fold<T>(int, const int*, const T*, T*, int, hipStream_t);            \
   template void launch_dY_reduce<T>(int64_t, int, int, const T*, T*, bool, hipStream_t);
 SN_INST(float)
@@ -516,7 +517,7 @@ SN_INST(double)
 #undef SN_INST
 // bfloat16 storage of sender features and per-edge sender gradient rows
 template void launch_ghost_refresh<bf16_t>(int, int, const int*, bf16_t*, int, hipStream_t);
-template void launch_sender_reduce<bf16_t>(int, const int*, const int*, const bf16_t*, int, double*,
-                                           hipStream_t);
+template void launch_sender_reduce<bf16_t, float>(int, const int*, const int*, const bf16_t*, int,
+                                                  float*, hipStream_t);
 
 }  // namespace sn

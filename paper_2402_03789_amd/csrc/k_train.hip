@@ -100,11 +100,13 @@ __global__ void k_atom_grad(int n, const int* __restrict__ region, int regions_p
 }
 
 // dE/dh of the last block's outputs, seeded per row: sigma g_i v (v = Wr1 Wr2), zero beyond C0
+template <typename H>
 __global__ void k_seed_rows(int n, const double* __restrict__ v, int C0, double sigma,
-                            const double* __restrict__ g_atom, double* __restrict__ dh, int ldh) {
+                            const double* __restrict__ g_atom, H* __restrict__ dh, int ldh) {
   const int r = blockIdx.x;
   const double g = sigma * g_atom[r];
-  for (int k = threadIdx.x; k < ldh; k += blockDim.x) dh[(int64_t)r * ldh + k] = k < C0 ? g * v[k] : 0.0;
+  for (int k = threadIdx.x; k < ldh; k += blockDim.x)
+    dh[(int64_t)r * ldh + k] = (H)(k < C0 ? g * v[k] : 0.0);
 }
 
 // readout weights from u = sum_i g_i h_i (C0): E_i = sigma (h_i Wr1) Wr2 + mu, so
@@ -126,10 +128,15 @@ void launch_atom_grad(int n, const int* region, int regions_per_struct, const do
   if (n > 0)
     k_atom_grad<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, region, regions_per_struct, grad, g_atom);
 }
-void launch_seed_rows(int n, const double* v, int C0, double sigma, const double* g_atom,
-                      double* dh, int ldh, hipStream_t s) {
-  if (n > 0) k_seed_rows<<<n, 128, 0, s>>>(n, v, C0, sigma, g_atom, dh, ldh);
+template <typename H>
+void launch_seed_rows(int n, const double* v, int C0, double sigma, const double* g_atom, H* dh,
+                      int ldh, hipStream_t s) {
+  if (n > 0) k_seed_rows<H><<<n, 128, 0, s>>>(n, v, C0, sigma, g_atom, dh, ldh);
 }
+template void launch_seed_rows<double>(int, const double*, int, double, const double*, double*, int,
+                                       hipStream_t);
+template void launch_seed_rows<float>(int, const double*, int, double, const double*, float*, int,
+                                      hipStream_t);
 void launch_readout_wgrad(int C0, const double* u, const double* wr1, const double* wr2,
                           double sigma, double* g_wr1, double* g_wr2, hipStream_t s) {
   k_readout_wgrad<<<1, 256, 0, s>>>(C0, u, wr1, wr2, sigma, g_wr1, g_wr2);

@@ -137,8 +137,9 @@ void launch_wgrad(int64_t rows, int K, int N, const TA* A, RowMap am, const int*
                   double* out, hipStream_t s);
 void launch_atom_grad(int n, const int* region, int regions_per_struct, const double* grad,
                       double* g_atom, hipStream_t s);
-void launch_seed_rows(int n, const double* v, int C0, double sigma, const double* g_atom,
-                      double* dh, int ldh, hipStream_t s);
+template <typename H>
+void launch_seed_rows(int n, const double* v, int C0, double sigma, const double* g_atom, H* dh,
+                      int ldh, hipStream_t s);
 void launch_readout_wgrad(int C0, const double* u, const double* wr1, const double* wr2,
                           double sigma, double* g_wr1, double* g_wr2, hipStream_t s);
 // out_i = pos_i + eps (v_i + U_b pos_i) with b = atom_struct[i] and U[b] row-major 3 x 3
@@ -236,9 +237,9 @@ void launch_readout(int n, const T* h, int ldh, const double* v, int C0, double 
 template <typename T>
 void launch_fill_rows(int n, const double* v, int C0, double scale, T* dh, int ldh,
                       hipStream_t s);
-template <typename T>
+template <typename T, typename H>
 void launch_sender_reduce(int n_rows, const int* sptr, const int* sidx, const T* dxe, int width,
-                          double* dx, hipStream_t s);
+                          H* dx, hipStream_t s);
 template <typename T>
 void launch_ghost_fold(int n_local, const int* gptr, const T* dx_ext, T* dx, int width,
                        hipStream_t s);

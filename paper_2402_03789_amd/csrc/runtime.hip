@@ -850,14 +850,17 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
 // ------------------------------------------------------------------ forward / backward
 // T is the per-edge arithmetic type (float64 in the FP64 form, float32 otherwise).  The
 // node-state chain -- features h, self-connection and gate input y, the gate, the
-// readout and the backward node gradients -- is float64 in every form: the
-// self-connection carries most of each atom's energy through all blocks and is the one
-// place where float32 rounding reaches the per-atom energy at the 1e-6 level.  x (the
+// readout input and the backward node gradients -- is NodeT: float64 in the FP64 and
+// FP32 forms (the self-connection carries most of each atom's energy through all blocks
+// and is the one place where float32 rounding reaches the per-atom energy at the 1e-6
+// level), float32 in the BF16 form, whose bfloat16 operands dominate its error.  x (the
 // sender features that feed the tensor product) and the messages M are type T.
 // S is the storage type of the sender features x, the radial weights w, dE/dw and the
 // per-edge sender gradient rows: T, or bfloat16 in the BF16 form (arithmetic stays in T).
+// Energies, edge gradients, forces, the virial and their reductions stay float64.
 template <typename T, typename S>
 struct Pipe {
+  using NodeT = typename std::conditional<std::is_same<S, bf16_t>::value, float, double>::type;
   sn_ctx* c;
   const sn_model* m;
   hipStream_t s;
@@ -1029,24 +1032,24 @@ struct Pipe {
     const int C0 = m->muls[0];
     // h^(1): embedding rows for locals and ghosts (a ghost's first features come from its species)
     c->mark("embed");
-    double* h = c->get<double>("h_cur", (int64_t)NE * C0);
-    launch_embed<double>(NE, spec_ext, W<double>(c, m->off("embed", {(int)m->species.size(), C0})),
+    NodeT* h = c->get<NodeT>("h_cur", (int64_t)NE * C0);
+    launch_embed<NodeT>(NE, spec_ext, W<NodeT>(c, m->off("embed", {(int)m->species.size(), C0})),
                          C0, h, C0, s);
     for (int t = 0; t < m->T; ++t) {
       const LayerDesc& L = m->layers[t];
       const std::string ts = std::to_string(t);
       c->mark("layer" + ts + ".linear_in");
       S* x = c->get<S>("x" + ts, (int64_t)NE * L.hin.width);
-      double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
+      NodeT* y = c->get<NodeT>("y" + ts, (int64_t)N * L.yl.width);
       const int xrows = (t == 0) ? NE : N;  // block 1: ghosts from their own species
       // Lin1 accumulates in the edge type: x only feeds the tensor product, which runs in it
       {
-        std::vector<GemmDesc<double, T, S>> g;
+        std::vector<GemmDesc<NodeT, T, S>> g;
         for (int l : L.ins)
-          g.push_back(gd<double, T, S>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
+          g.push_back(gd<NodeT, T, S>((int64_t)xrows * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h,
                                        rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l], x,
                                        rows_of(L.hin, l), 1.0, false));
-        gemm_group<double, T, S, T>(g, false);
+        gemm_group<NodeT, T, S, T>(g, false);
       }
       if (t > 0) {
         c->mark("layer" + ts + ".ghost_refresh");
@@ -1054,14 +1057,14 @@ struct Pipe {
       }
       c->mark("layer" + ts + ".linsc");
       {
-        std::vector<GemmDesc<double, double, double>> g;
+        std::vector<GemmDesc<NodeT, NodeT, NodeT>> g;
         for (int l : L.ins)
           if (L.gmul[l] > 0)
-            g.push_back(gd<double, double, double>((int64_t)N * (2 * l + 1), L.gmul[l],
+            g.push_back(gd<NodeT, NodeT, NodeT>((int64_t)N * (2 * l + 1), L.gmul[l],
                                                    L.hin.mul[l], h, rows_of(L.hin, l),
                                                    L.w_linsc[l], L.gmul[l], y, rows_of(L.yl, l),
                                                    1.0, false));
-        gemm_group<double, double, double, double>(g, false);
+        gemm_group<NodeT, NodeT, NodeT, NodeT>(g, false);
       }
       S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("layer" + ts + ".tp");
@@ -1070,26 +1073,26 @@ struct Pipe {
       launch_tp_fwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, M, (T)(1.0 / m->kavg), s);
       c->mark("layer" + ts + ".linear_out");
       {
-        std::vector<GemmDesc<T, T, double>> g;
+        std::vector<GemmDesc<T, T, NodeT>> g;
         for (int l : L.outs) {
           const bool has_sc =
               std::find(L.ins.begin(), L.ins.end(), l) != L.ins.end() && L.gmul[l] > 0;
-          g.push_back(gd<T, T, double>((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M,
+          g.push_back(gd<T, T, NodeT>((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M,
                                        rows_of(L.ml, l), L.w_lin2[l], L.gmul[l], y,
                                        rows_of(L.yl, l), 1.0, has_sc));
         }
-        gemm_group<T, T, double, T>(g, false);
+        gemm_group<T, T, NodeT, T>(g, false);
       }
       // block outputs alternate between two buffers, or stay per block for weight gradients
-      double* hn = c->get<double>(c->fwd_train ? "h_out" + ts : std::string(t % 2 ? "h_a" : "h_b"),
+      NodeT* hn = c->get<NodeT>(c->fwd_train ? "h_out" + ts : std::string(t % 2 ? "h_a" : "h_b"),
                                   (int64_t)N * L.hout.width);
-      launch_gate_fwd<double>(N, L.last, L.yl, L.hout, y, hn, m->act, s);
+      launch_gate_fwd<NodeT>(N, L.last, L.yl, L.hout, y, hn, (NodeT)m->act, s);
       h = hn;
     }
     c->mark("readout");
     double* ae = c->get<double>("atom_e", N);
     const int* spec_loc = c->get<int>("spec_local", N);
-    launch_readout<double>(N, h, m->layers.back().hout.width, c->d_v, C0, m->sigma, c->d_shift,
+    launch_readout<NodeT>(N, h, m->layers.back().hout.width, c->d_v, C0, m->sigma, c->d_shift,
                            spec_loc, ae, s);
     // per-structure energies (eq 1): fixed-order segmented sums
     double* part = c->get<double>("partial_e", c->n_echunk);
@@ -1134,17 +1137,17 @@ struct Pipe {
       max_m = std::max(max_m, L.ml.width);
       max_y = std::max(max_y, L.yl.width);
     }
-    double* dh = c->get<double>("dh_a", (int64_t)N * max_w);
-    double* dh_other = c->get<double>("dh_b", (int64_t)N * max_w);
-    double* dy = c->get<double>("dy", (int64_t)N * max_y);
+    NodeT* dh = c->get<NodeT>("dh_a", (int64_t)N * max_w);
+    NodeT* dh_other = c->get<NodeT>("dh_b", (int64_t)N * max_w);
+    NodeT* dy = c->get<NodeT>("dy", (int64_t)N * max_y);
     T* Gm = c->get<T>("G", (int64_t)N * max_m);
     // dE/dw alternates between two buffers: the MLP adjoint of block t (aux stream) reads
     // one while the tensor-product adjoint of block t-1 writes the other
     S* dw_buf[2] = {c->get<S>("dw_a", 2 * c->NP * max_P), c->get<S>("dw_b", 2 * c->NP * max_P)};
     std::vector<hipEvent_t> mlp_done(m->T, nullptr);
     S* dxe = c->get<S>("dxe", E * max_w);
-    double* dx_ext = c->get<double>("dx_ext", (int64_t)NE * max_w);
-    double* dx = c->get<double>("dx", (int64_t)N * max_w);
+    NodeT* dx_ext = c->get<NodeT>("dx_ext", (int64_t)NE * max_w);
+    NodeT* dx = c->get<NodeT>("dx", (int64_t)N * max_w);
     T* dz2 = c->get<T>("dz2", c->NP * m->hidden);
     T* dY = c->get<T>("dY", E * NY);
     T* drho = c->get<T>("drho", E * m->nb);
@@ -1159,46 +1162,46 @@ struct Pipe {
       // dE/dh^(T+1)_i = sigma g_i (Wr1 Wr2); readout weights from u = sum_i g_i h_i
       const int wlast = m->layers.back().hout.width;
       launch_seed_rows(N, c->d_v, C0, m->sigma, g_atom, dh, wlast, s);
-      const double* hT = c->get<double>("h_out" + std::to_string(m->T - 1), (int64_t)N * wlast);
+      const NodeT* hT = c->get<NodeT>("h_out" + std::to_string(m->T - 1), (int64_t)N * wlast);
       double* u = c->get<double>("tr_u", C0);
-      wgrad<double, double>(N, C0, 1, hT, plain_rows(wlast), g_atom, plain_rows(1), 0, u);
+      wgrad<NodeT, double>(N, C0, 1, hT, plain_rows(wlast), g_atom, plain_rows(1), 0, u);
       const int64_t r0 = m->tensors.at("readout.0").first, r1 = m->tensors.at("readout.1").first;
       launch_readout_wgrad(C0, u, W<double>(c, r0), W<double>(c, r1), m->sigma, gw + r0, gw + r1, s);
     } else {
       // dE/dh^(T+1) = sigma (Wr1 Wr2): the same vector for every atom
-      launch_fill_rows<double>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
+      launch_fill_rows<NodeT>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
     }
     for (int t = m->T - 1; t >= 0; --t) {
       const LayerDesc& L = m->layers[t];
       const std::string ts = std::to_string(t);
       const S* x = c->get<S>("x" + ts, (int64_t)NE * L.hin.width);
-      const double* y = c->get<double>("y" + ts, (int64_t)N * L.yl.width);
+      const NodeT* y = c->get<NodeT>("y" + ts, (int64_t)N * L.yl.width);
       const S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("bwd.layer" + ts + ".linear_out");
-      launch_gate_bwd<double>(N, L.last, L.yl, L.hout, y, dh, dy, m->act, s);
+      launch_gate_bwd<NodeT>(N, L.last, L.yl, L.hout, y, dh, dy, (NodeT)m->act, s);
       // the block's input features (NE rows in block 1, whose ghosts carry their own species)
-      const double* h_in =
-          train ? c->get<double>(t == 0 ? std::string("h_cur") : "h_out" + std::to_string(t - 1),
+      const NodeT* h_in =
+          train ? c->get<NodeT>(t == 0 ? std::string("h_cur") : "h_out" + std::to_string(t - 1),
                                  (int64_t)(t == 0 ? NE : N) * L.hin.width)
                 : nullptr;
       if (train) {
         // Lin2: dW = M^T dy;  Linsc: dW = h^T dy
         const T* Mt = c->get<T>("M" + ts, (int64_t)N * L.ml.width);
         for (int l : L.outs)
-          wgrad<T, double>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], Mt, rows_of(L.ml, l), dy,
+          wgrad<T, NodeT>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], Mt, rows_of(L.ml, l), dy,
                            rows_of(L.yl, l), L.w_lin2[l], gw);
         for (int l : L.ins)
           if (L.gmul[l] > 0)
-            wgrad<double, double>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], h_in,
+            wgrad<NodeT, NodeT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], h_in,
                                   rows_of(L.hin, l), dy, rows_of(L.yl, l), L.w_linsc[l], gw);
       }
       {
-        std::vector<GemmDesc<double, T, T>> g;
+        std::vector<GemmDesc<NodeT, T, T>> g;
         for (int l : L.outs)
-          g.push_back(gd<double, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy,
+          g.push_back(gd<NodeT, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy,
                                        rows_of(L.yl, l), L.w_lin2[l], L.gmul[l], Gm,
                                        rows_of(L.ml, l), 1.0 / m->kavg, false));
-        gemm_group<double, T, T, T>(g, true);
+        gemm_group<NodeT, T, T, T>(g, true);
       }
       S* dw = dw_buf[t % 2];
       if (t + 2 < m->T) {  // dw_buf[t % 2] is free once the MLP adjoint of block t + 2 is done
@@ -1221,47 +1224,47 @@ struct Pipe {
       if (t == 0 && !train) break;
       c->mark("bwd.layer" + ts + ".sender_fold");
       // sender-side sums over every extended row
-      launch_sender_reduce<S>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
+      launch_sender_reduce<S, NodeT>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
       if (t == 0) {
         // block 1 (training): x = Lin1(h^(1)) on every extended row, each ghost from its own
         // species, so nothing folds: dW = h^T dx over all rows, then dE/dh^(1) on all rows
         // (plus the self-connection's share on local rows) feeds the embedding gradient
-        wgrad<double, double>(NE, C0, C0, h_in, rows_of(L.hin, 0), dx_ext, rows_of(L.hin, 0),
+        wgrad<NodeT, NodeT>(NE, C0, C0, h_in, rows_of(L.hin, 0), dx_ext, rows_of(L.hin, 0),
                               L.w_lin1[0], gw);
-        double* dh1 = c->get<double>("tr_dh1", (int64_t)NE * C0);
-        gemm<double, T, double, T>(NE, C0, C0, dx_ext, rows_of(L.hin, 0), L.w_lin1[0], C0, true, dh1,
+        NodeT* dh1 = c->get<NodeT>("tr_dh1", (int64_t)NE * C0);
+        gemm<NodeT, T, NodeT, T>(NE, C0, C0, dx_ext, rows_of(L.hin, 0), L.w_lin1[0], C0, true, dh1,
                                    rows_of(L.hin, 0), T(1), false);
         if (L.gmul[0] > 0)
-          gemm<double, T, double, T>(N, C0, L.gmul[0], dy, rows_of(L.yl, 0), L.w_linsc[0],
+          gemm<NodeT, T, NodeT, T>(N, C0, L.gmul[0], dy, rows_of(L.yl, 0), L.w_linsc[0],
                                      L.gmul[0], true, dh1, rows_of(L.hin, 0), T(1), true);
         const int S_ = (int)m->species.size();
         double* part = c->get<double>("wg_part", wgrad_chunks(NE) * (int64_t)S_ * C0);
-        launch_wgrad<double, double>(NE, S_, C0, nullptr, plain_rows(0), nullptr,
+        launch_wgrad<NodeT, NodeT>(NE, S_, C0, nullptr, plain_rows(0), nullptr,
                                      c->get<int>("spec_ext", NE), dh1, plain_rows(C0), 1.0, part,
                                      gw + m->tensors.at("embed").first, s);
         break;
       }
       // fold ghost rows onto owners
-      launch_ghost_fold<double>(N, gptr, dx_ext, dx, L.hin.width, s);
+      launch_ghost_fold<NodeT>(N, gptr, dx_ext, dx, L.hin.width, s);
       if (train)  // Lin1: dW = h^T dx
         for (int l : L.ins)
-          wgrad<double, double>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h_in,
+          wgrad<NodeT, NodeT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h_in,
                                 rows_of(L.hin, l), dx, rows_of(L.hin, l), L.w_lin1[l], gw);
       c->mark("bwd.layer" + ts + ".linear_in");
       {
         // dh = dx Lin1^T (all degrees), then += dy Linsc^T (all degrees)
-        std::vector<GemmDesc<double, T, double>> g1, g2;
+        std::vector<GemmDesc<NodeT, T, NodeT>> g1, g2;
         for (int l : L.ins) {
-          g1.push_back(gd<double, T, double>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l],
+          g1.push_back(gd<NodeT, T, NodeT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l],
                                              dx, rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l],
                                              dh_other, rows_of(L.hin, l), 1.0, false));
           if (L.gmul[l] > 0)
-            g2.push_back(gd<double, T, double>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l],
+            g2.push_back(gd<NodeT, T, NodeT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l],
                                                dy, rows_of(L.yl, l), L.w_linsc[l], L.gmul[l],
                                                dh_other, rows_of(L.hin, l), 1.0, true));
         }
-        gemm_group<double, T, double, T>(g1, true);
-        gemm_group<double, T, double, T>(g2, true);
+        gemm_group<NodeT, T, NodeT, T>(g1, true);
+        gemm_group<NodeT, T, NodeT, T>(g2, true);
       }
       std::swap(dh, dh_other);
     }
