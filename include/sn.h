@@ -51,9 +51,9 @@ extern "C" {
                       gradients; the forward radial MLP's output layer as sums of products of
                       three-part bfloat16 splits of its float32 operands, float32-level
                       error), edge vectors from float64 positions; the node-state chain
-                      (features, self-connection, gate, readout, node gradients) in float64,
-                      its float64 contractions on the float64 matrix cores; energy and virial
-                      reductions in float64 */
+                      (features, self-connection, gate, readout input) in float64, its
+                      float64 contractions on the float64 matrix cores; node gradients of
+                      the adjoint in float32; energy and virial reductions in float64 */
 #define SN_BF16 2  /* as SN_FP32, but the radial MLP and the channel-mixing linears take
                       bfloat16 operands with float32 accumulation on the matrix cores; sender
                       features, radial weights and per-edge gradients stored in bfloat16;

@@ -61,16 +61,17 @@ __global__ void k_gate_fwd(int n, int last, IrrepLayout yl, IrrepLayout hl, cons
   }
 }
 
-template <typename T>
-__global__ void k_gate_bwd(int n, int last, IrrepLayout yl, IrrepLayout hl, const T* __restrict__ y,
-                           const T* __restrict__ dh, T* __restrict__ dy, T c) {
+// y (the gate input) in the forward node type TY, gradients in TG; arithmetic in TY
+template <typename TY, typename TG>
+__global__ void k_gate_bwd(int n, int last, IrrepLayout yl, IrrepLayout hl, const TY* __restrict__ y,
+                           const TG* __restrict__ dh, TG* __restrict__ dy, TY c) {
   int r = blockIdx.x;
-  const T* yr = y + (int64_t)r * yl.width;
-  const T* dhr = dh + (int64_t)r * hl.width;
-  T* dyr = dy + (int64_t)r * yl.width;
+  const TY* yr = y + (int64_t)r * yl.width;
+  const TG* dhr = dh + (int64_t)r * hl.width;
+  TG* dyr = dy + (int64_t)r * yl.width;
   const int C0 = hl.mul[0];
   for (int k = threadIdx.x; k < C0; k += blockDim.x)
-    dyr[yl.off[0] + k] = dhr[hl.off[0] + k] * act_grad(yr[yl.off[0] + k], c);
+    dyr[yl.off[0] + k] = (TG)((TY)dhr[hl.off[0] + k] * act_grad(yr[yl.off[0] + k], c));
   if (last) return;
   int goff = C0;
   for (int l = 1; l < kNumL; ++l) {
@@ -79,13 +80,14 @@ __global__ void k_gate_bwd(int n, int last, IrrepLayout yl, IrrepLayout hl, cons
     const int nm = 2 * l + 1;
     for (int k = threadIdx.x; k < nm * mul; k += blockDim.x) {
       const int u = k % mul;
-      dyr[yl.off[l] + k] = dhr[hl.off[l] + k] * act(yr[yl.off[0] + goff + u], c);
+      dyr[yl.off[l] + k] = (TG)((TY)dhr[hl.off[l] + k] * act(yr[yl.off[0] + goff + u], c));
     }
     for (int u = threadIdx.x; u < mul; u += blockDim.x) {
-      T s = T(0);
-      for (int m = 0; m < nm; ++m) s += dhr[hl.off[l] + m * mul + u] * yr[yl.off[l] + m * mul + u];
-      const T z = yr[yl.off[0] + goff + u];
-      dyr[yl.off[0] + goff + u] = s * act_grad(z, c);
+      TY s = TY(0);
+      for (int m = 0; m < nm; ++m)
+        s += (TY)dhr[hl.off[l] + m * mul + u] * yr[yl.off[l] + m * mul + u];
+      const TY z = yr[yl.off[0] + goff + u];
+      dyr[yl.off[0] + goff + u] = (TG)(s * act_grad(z, c));
     }
     goff += mul;
   }
@@ -444,10 +446,10 @@ void launch_gate_fwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const T* 
                      hipStream_t s) {
   if (n > 0) k_gate_fwd<T><<<n, 128, 0, s>>>(n, last ? 1 : 0, yl, hl, y, h, c);
 }
-template <typename T>
-void launch_gate_bwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const T* y, const T* dh,
-                     T* dy, T c, hipStream_t s) {
-  if (n > 0) k_gate_bwd<T><<<n, 128, 0, s>>>(n, last ? 1 : 0, yl, hl, y, dh, dy, c);
+template <typename TY, typename TG>
+void launch_gate_bwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const TY* y, const TG* dh,
+                     TG* dy, TY c, hipStream_t s) {
+  if (n > 0) k_gate_bwd<TY, TG><<<n, 128, 0, s>>>(n, last ? 1 : 0, yl, hl, y, dh, dy, c);
 }
 template <typename T>
 void launch_readout(int n, const T* h, int ldh, const double* v, int C0, double sigma,
@@ -503,13 +505,13 @@ void launch_unpermute(int n, const int* order, const double* in_rows, int width,
   template void launch_ghost_refresh<T>(int, int, const int*, T*, int, hipStream_t);              \
   template void launch_gate_fwd<T>(int, bool, IrrepLayout, IrrepLayout, const T*, T*, T,          \
                                    hipStream_t);                                                  \
-  template void launch_gate_bwd<T>(int, bool, IrrepLayout, IrrepLayout, const T*, const T*, T*,   \
-                                   T, hipStream_t);                                               \
+  template void launch_gate_bwd<T, T>(int, bool, IrrepLayout, IrrepLayout, const T*, const T*,    \
+                                      T*, T, hipStream_t);                                        \
   template void launch_readout<T>(int, const T*, int, const double*, int, double, const double*,  \
                                   const int*, double*, hipStream_t);                              \
   template void launch_fill_rows<T>(int, const double*, int, double, T*, int, hipStream_t);       \
-  template void launch_sender_reduce<T, double>(int, const int*, const int*, const T*, int,       \
-                                                double*, hipStream_t);                            \
+  template void launch_sender_reduce<T, T>(int, const int*, const int*, const T*, int, T*,        \
+                                           hipStream_t);                                          \
   template void launch_ghost_fold<T>(int, const int*, const T*, T*, int, hipStream_t);            \
   template void launch_dY_reduce<T>(int64_t, int, int, const T*, T*, bool, hipStream_t);
 SN_INST(float)
@@ -517,6 +519,9 @@ SN_INST(double)
 #undef SN_INST
 // bfloat16 storage of sender features and per-edge sender gradient rows
 template void launch_ghost_refresh<bf16_t>(int, int, const int*, bf16_t*, int, hipStream_t);
+// float64 forward node state with float32 node gradients (FP32 form)
+template void launch_gate_bwd<double, float>(int, bool, IrrepLayout, IrrepLayout, const double*,
+                                             const float*, float*, double, hipStream_t);
 template void launch_sender_reduce<bf16_t, float>(int, const int*, const int*, const bf16_t*, int,
                                                   float*, hipStream_t);
 

@@ -228,9 +228,9 @@ void launch_ghost_refresh(int n_local, int n_ghost, const int* owner, T* x, int 
 template <typename T>
 void launch_gate_fwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const T* y, T* h, T c,
                      hipStream_t s);
-template <typename T>
-void launch_gate_bwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const T* y, const T* dh,
-                     T* dy, T c, hipStream_t s);
+template <typename TY, typename TG>
+void launch_gate_bwd(int n, bool last, IrrepLayout yl, IrrepLayout hl, const TY* y, const TG* dh,
+                     TG* dy, TY c, hipStream_t s);
 template <typename T>
 void launch_readout(int n, const T* h, int ldh, const double* v, int C0, double sigma,
                     const double* shift, const int* spec, double* atom_e, hipStream_t s);

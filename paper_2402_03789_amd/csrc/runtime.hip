@@ -861,6 +861,10 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
 template <typename T, typename S>
 struct Pipe {
   using NodeT = typename std::conditional<std::is_same<S, bf16_t>::value, float, double>::type;
+  // node gradients of the adjoint (dE/dh, dE/dy, the per-sender sums): type T.  They reach
+  // only forces, the virial and weight gradients, whose float32 bounds they meet; the
+  // energies come from the forward chain alone.
+  using GradT = T;
   sn_ctx* c;
   const sn_model* m;
   hipStream_t s;
@@ -1137,17 +1141,17 @@ struct Pipe {
       max_m = std::max(max_m, L.ml.width);
       max_y = std::max(max_y, L.yl.width);
     }
-    NodeT* dh = c->get<NodeT>("dh_a", (int64_t)N * max_w);
-    NodeT* dh_other = c->get<NodeT>("dh_b", (int64_t)N * max_w);
-    NodeT* dy = c->get<NodeT>("dy", (int64_t)N * max_y);
+    GradT* dh = c->get<GradT>("dh_a", (int64_t)N * max_w);
+    GradT* dh_other = c->get<GradT>("dh_b", (int64_t)N * max_w);
+    GradT* dy = c->get<GradT>("dy", (int64_t)N * max_y);
     T* Gm = c->get<T>("G", (int64_t)N * max_m);
     // dE/dw alternates between two buffers: the MLP adjoint of block t (aux stream) reads
     // one while the tensor-product adjoint of block t-1 writes the other
     S* dw_buf[2] = {c->get<S>("dw_a", 2 * c->NP * max_P), c->get<S>("dw_b", 2 * c->NP * max_P)};
     std::vector<hipEvent_t> mlp_done(m->T, nullptr);
     S* dxe = c->get<S>("dxe", E * max_w);
-    NodeT* dx_ext = c->get<NodeT>("dx_ext", (int64_t)NE * max_w);
-    NodeT* dx = c->get<NodeT>("dx", (int64_t)N * max_w);
+    GradT* dx_ext = c->get<GradT>("dx_ext", (int64_t)NE * max_w);
+    GradT* dx = c->get<GradT>("dx", (int64_t)N * max_w);
     T* dz2 = c->get<T>("dz2", c->NP * m->hidden);
     T* dY = c->get<T>("dY", E * NY);
     T* drho = c->get<T>("drho", E * m->nb);
@@ -1169,7 +1173,7 @@ struct Pipe {
       launch_readout_wgrad(C0, u, W<double>(c, r0), W<double>(c, r1), m->sigma, gw + r0, gw + r1, s);
     } else {
       // dE/dh^(T+1) = sigma (Wr1 Wr2): the same vector for every atom
-      launch_fill_rows<NodeT>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
+      launch_fill_rows<GradT>(N, c->d_v, C0, m->sigma, dh, m->layers.back().hout.width, s);
     }
     for (int t = m->T - 1; t >= 0; --t) {
       const LayerDesc& L = m->layers[t];
@@ -1178,7 +1182,7 @@ struct Pipe {
       const NodeT* y = c->get<NodeT>("y" + ts, (int64_t)N * L.yl.width);
       const S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("bwd.layer" + ts + ".linear_out");
-      launch_gate_bwd<NodeT>(N, L.last, L.yl, L.hout, y, dh, dy, (NodeT)m->act, s);
+      launch_gate_bwd<NodeT, GradT>(N, L.last, L.yl, L.hout, y, dh, dy, (NodeT)m->act, s);
       // the block's input features (NE rows in block 1, whose ghosts carry their own species)
       const NodeT* h_in =
           train ? c->get<NodeT>(t == 0 ? std::string("h_cur") : "h_out" + std::to_string(t - 1),
@@ -1188,20 +1192,20 @@ struct Pipe {
         // Lin2: dW = M^T dy;  Linsc: dW = h^T dy
         const T* Mt = c->get<T>("M" + ts, (int64_t)N * L.ml.width);
         for (int l : L.outs)
-          wgrad<T, NodeT>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], Mt, rows_of(L.ml, l), dy,
+          wgrad<T, GradT>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], Mt, rows_of(L.ml, l), dy,
                            rows_of(L.yl, l), L.w_lin2[l], gw);
         for (int l : L.ins)
           if (L.gmul[l] > 0)
-            wgrad<NodeT, NodeT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], h_in,
+            wgrad<NodeT, GradT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l], h_in,
                                   rows_of(L.hin, l), dy, rows_of(L.yl, l), L.w_linsc[l], gw);
       }
       {
-        std::vector<GemmDesc<NodeT, T, T>> g;
+        std::vector<GemmDesc<GradT, T, T>> g;
         for (int l : L.outs)
-          g.push_back(gd<NodeT, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy,
+          g.push_back(gd<GradT, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy,
                                        rows_of(L.yl, l), L.w_lin2[l], L.gmul[l], Gm,
                                        rows_of(L.ml, l), 1.0 / m->kavg, false));
-        gemm_group<NodeT, T, T, T>(g, true);
+        gemm_group<GradT, T, T, T>(g, true);
       }
       S* dw = dw_buf[t % 2];
       if (t + 2 < m->T) {  // dw_buf[t % 2] is free once the MLP adjoint of block t + 2 is done
@@ -1224,47 +1228,47 @@ struct Pipe {
       if (t == 0 && !train) break;
       c->mark("bwd.layer" + ts + ".sender_fold");
       // sender-side sums over every extended row
-      launch_sender_reduce<S, NodeT>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
+      launch_sender_reduce<S, GradT>(NE, sptr, sidx, dxe, L.hin.width, dx_ext, s);
       if (t == 0) {
         // block 1 (training): x = Lin1(h^(1)) on every extended row, each ghost from its own
         // species, so nothing folds: dW = h^T dx over all rows, then dE/dh^(1) on all rows
         // (plus the self-connection's share on local rows) feeds the embedding gradient
-        wgrad<NodeT, NodeT>(NE, C0, C0, h_in, rows_of(L.hin, 0), dx_ext, rows_of(L.hin, 0),
+        wgrad<NodeT, GradT>(NE, C0, C0, h_in, rows_of(L.hin, 0), dx_ext, rows_of(L.hin, 0),
                               L.w_lin1[0], gw);
-        NodeT* dh1 = c->get<NodeT>("tr_dh1", (int64_t)NE * C0);
-        gemm<NodeT, T, NodeT, T>(NE, C0, C0, dx_ext, rows_of(L.hin, 0), L.w_lin1[0], C0, true, dh1,
+        GradT* dh1 = c->get<GradT>("tr_dh1", (int64_t)NE * C0);
+        gemm<GradT, T, GradT, T>(NE, C0, C0, dx_ext, rows_of(L.hin, 0), L.w_lin1[0], C0, true, dh1,
                                    rows_of(L.hin, 0), T(1), false);
         if (L.gmul[0] > 0)
-          gemm<NodeT, T, NodeT, T>(N, C0, L.gmul[0], dy, rows_of(L.yl, 0), L.w_linsc[0],
+          gemm<GradT, T, GradT, T>(N, C0, L.gmul[0], dy, rows_of(L.yl, 0), L.w_linsc[0],
                                      L.gmul[0], true, dh1, rows_of(L.hin, 0), T(1), true);
         const int S_ = (int)m->species.size();
         double* part = c->get<double>("wg_part", wgrad_chunks(NE) * (int64_t)S_ * C0);
-        launch_wgrad<NodeT, NodeT>(NE, S_, C0, nullptr, plain_rows(0), nullptr,
+        launch_wgrad<NodeT, GradT>(NE, S_, C0, nullptr, plain_rows(0), nullptr,
                                      c->get<int>("spec_ext", NE), dh1, plain_rows(C0), 1.0, part,
                                      gw + m->tensors.at("embed").first, s);
         break;
       }
       // fold ghost rows onto owners
-      launch_ghost_fold<NodeT>(N, gptr, dx_ext, dx, L.hin.width, s);
+      launch_ghost_fold<GradT>(N, gptr, dx_ext, dx, L.hin.width, s);
       if (train)  // Lin1: dW = h^T dx
         for (int l : L.ins)
-          wgrad<NodeT, NodeT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h_in,
+          wgrad<NodeT, GradT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l], h_in,
                                 rows_of(L.hin, l), dx, rows_of(L.hin, l), L.w_lin1[l], gw);
       c->mark("bwd.layer" + ts + ".linear_in");
       {
         // dh = dx Lin1^T (all degrees), then += dy Linsc^T (all degrees)
-        std::vector<GemmDesc<NodeT, T, NodeT>> g1, g2;
+        std::vector<GemmDesc<GradT, T, GradT>> g1, g2;
         for (int l : L.ins) {
-          g1.push_back(gd<NodeT, T, NodeT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l],
+          g1.push_back(gd<GradT, T, GradT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.hin.mul[l],
                                              dx, rows_of(L.hin, l), L.w_lin1[l], L.hin.mul[l],
                                              dh_other, rows_of(L.hin, l), 1.0, false));
           if (L.gmul[l] > 0)
-            g2.push_back(gd<NodeT, T, NodeT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l],
+            g2.push_back(gd<GradT, T, GradT>((int64_t)N * (2 * l + 1), L.hin.mul[l], L.gmul[l],
                                                dy, rows_of(L.yl, l), L.w_linsc[l], L.gmul[l],
                                                dh_other, rows_of(L.hin, l), 1.0, true));
         }
-        gemm_group<NodeT, T, NodeT, T>(g1, true);
-        gemm_group<NodeT, T, NodeT, T>(g2, true);
+        gemm_group<GradT, T, GradT, T>(g1, true);
+        gemm_group<GradT, T, GradT, T>(g2, true);
       }
       std::swap(dh, dh_other);
     }
