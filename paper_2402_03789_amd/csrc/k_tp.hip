@@ -300,6 +300,66 @@ __device__ inline void slot_reduce(T (&v)[NV], int cpt, int lane) {
   for (; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o);
 }
 
+// The same transposed reduction for slots of at least 16 lanes, with its exchanges inside
+// 16-lane rows done by DPP lane permutations on the adding instruction (no LDS round
+// trip): the transposed stages pair lanes i and i ^ 15 (row mirror), i ^ 7 (half-row
+// mirror), i ^ 2 and i ^ 1 (quad permutations), in that order, each on the lane-id bit it
+// flips highest (3, 2, 1, 0), so that both lanes of a pair hold the same value group; the
+// four masks span every lane of a row.  Remaining row bits and the cross-row bits of the
+// slot (16, 32) are plain stages on one value.  Afterwards lane l holds the complete sum
+// of value slot_first_value_rows<NV>(l), identical in every row of the slot.
+constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141;
+constexpr int kDppXor2 = 0x4E, kDppXor1 = 0xB1;  // quad_perm [2,3,0,1] and [1,0,3,2]
+template <int CTRL>
+__device__ inline float dpp_get(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_get(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int K>
+struct RowStage;  // stage K: DPP control and the lane-id bit it flips highest
+template <> struct RowStage<0> { static constexpr int ctrl = kDppRowMirror, bit = 8; };
+template <> struct RowStage<1> { static constexpr int ctrl = kDppHalfMirror, bit = 4; };
+template <> struct RowStage<2> { static constexpr int ctrl = kDppXor2, bit = 2; };
+template <> struct RowStage<3> { static constexpr int ctrl = kDppXor1, bit = 1; };
+template <int NV>
+constexpr int log2_nv() { return NV == 1 ? 0 : (NV == 2 ? 1 : (NV == 4 ? 2 : (NV == 8 ? 3 : 4))); }
+template <int NV>
+__device__ inline int slot_first_value_rows(int lane) {
+  int j0 = 0;
+  static_for<log2_nv<NV>()>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    if (lane & RowStage<k>::bit) j0 += NV >> (k + 1);
+  });
+  return j0;
+}
+template <typename T, int NV>
+__device__ inline void slot_reduce_rows(T (&v)[NV], int cpt, int lane) {
+  constexpr int S = log2_nv<NV>();
+  static_for<S>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int H = NV >> (k + 1);
+    const bool hi = (lane & RowStage<k>::bit) != 0;
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      const T send = hi ? v[r] : v[r + H];
+      const T keep = hi ? v[r + H] : v[r];
+      v[r] = keep + dpp_get<RowStage<k>::ctrl>(send);
+    }
+  });
+  static_for<4 - S>([&](auto K) {  // the row bits left: plain stages on the one value
+    constexpr int k = S + decltype(K)::value;
+    v[0] += dpp_get<RowStage<k>::ctrl>(v[0]);
+  });
+  for (int o = 16; o < cpt; o <<= 1) v[0] += __shfl_xor(v[0], o);
+}
+
 // Adjoint of one degree's paths: writes dE/dw (per edge), the per-edge dE/dx rows, and
 // adds this degree's share of dE/dY (set instead when accumulate is 0).
 template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX, int CPT>
@@ -360,9 +420,12 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   // butterfly leaves one complete value per storing lane; narrower slots take a plain
   // butterfly and one storing lane.
   constexpr int NV = NYc <= 1 ? 1 : (NYc <= 2 ? 2 : (NYc <= 4 ? 4 : (NYc <= 8 ? 8 : 16)));
+  // slots of whole 16-lane rows reduce with DPP row exchanges; narrower ones with shuffles
+  const bool rows = cpt >= 16;
   const bool wide = cpt >= NV;
-  const int j0 = wide ? slot_first_value<NV>(uu, cpt) : 0;
-  const bool storer = wide ? (uu & slot_store_mask<NV>(cpt)) == 0 && j0 < NYc : uu == 0;
+  const int j0 = rows ? slot_first_value_rows<NV>(uu) : (wide ? slot_first_value<NV>(uu, cpt) : 0);
+  const bool storer = rows ? uu < 16 && (uu & (16 / NV - 1)) == 0 && j0 < NYc
+                           : (wide ? (uu & slot_store_mask<NV>(cpt)) == 0 && j0 < NYc : uu == 0);
   const int jl = min(j0, NYc - 1);
   using Ops = EdgeOps<T, D1, NP, NYc, KC>;
   edge_pipeline<3, Ops>(
@@ -417,7 +480,10 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
             }
           }
         }
-        if (wide) {
+        if (rows) {
+          slot_reduce_rows<T, NV>(dYl, cpt, lane);
+          if (active && storer) dY[(int64_t)ec * g.NY + j0] = (accumulate ? cur.dyo : T(0)) + dYl[0];
+        } else if (wide) {
           slot_reduce<T, NV>(dYl, cpt, lane);
           if (active && storer) dY[(int64_t)ec * g.NY + j0] = (accumulate ? cur.dyo : T(0)) + dYl[0];
         } else {
