@@ -25,8 +25,10 @@
 //     adjoint streams them in pair order)
 //   dE/dx_s[u, m1] (a per-edge row, reduced over senders by a separate pass)
 //   dE/dY[m2] = sum_{p,u} sum C[m1,m2,m3] x[u,m1] w[p,u] G[p,u,m3]
-// The channel sum of dE/dY runs as shuffles inside each wave; the per-degree
-// kernels add their shares to dE/dY one after another (fixed order).
+// The channel sum of dE/dY runs inside each wave (DPP exchanges within 16-lane rows,
+// shuffles across rows); the per-degree kernels add their shares to dE/dY one after
+// another (fixed order).  Both directions are compiled for slot widths of 64 and 32
+// lanes (fewer registers, so more waves per SIMD) besides the general runtime width.
 #include "kernels.h"
 #include "cg_tables.h"
 
@@ -537,8 +539,7 @@ static void launch_fwd(const TPArgs& a, const T* Y, const S* x, const S* w, T* M
 template <typename T, typename S, int L1, int LSH, int LMX, bool SO>
 static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const S* w, T* M, T inv_k,
                        const T* G, S* dw, S* dxe, T* dY, int acc, hipStream_t s) {
-  // the forward gains from compile-time slot widths; the adjoint, whose per-edge shuffles
-  // share the scalar-load counter, runs faster with the runtime width
+  // compile-time slot widths for the common channel counts
   if (fwd) {
     if (a.d.cpt == 64) launch_fwd<T, S, L1, LSH, LMX, SO, 64>(a, Y, x, w, M, inv_k, s);
     else if (a.d.cpt == 32) launch_fwd<T, S, L1, LSH, LMX, SO, 32>(a, Y, x, w, M, inv_k, s);
@@ -548,10 +549,18 @@ static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const 
   const unsigned grid =
       (unsigned)((((int64_t)a.n_recv << a.split_log) + kRecvPerBlock - 1) / kRecvPerBlock);
   const unsigned block = kWave * kRecvPerBlock;
-  if (dxe)
-    k_tp_bwd<T, S, L1, LSH, LMX, SO, true, 0><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
-  else
-    k_tp_bwd<T, S, L1, LSH, LMX, SO, false, 0><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
+#define SN_TP_BWD(DX, CPT) \
+  k_tp_bwd<T, S, L1, LSH, LMX, SO, DX, CPT><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc)
+  if (dxe) {
+    if (a.d.cpt == 64) SN_TP_BWD(true, 64);
+    else if (a.d.cpt == 32) SN_TP_BWD(true, 32);
+    else SN_TP_BWD(true, 0);
+  } else {
+    if (a.d.cpt == 64) SN_TP_BWD(false, 64);
+    else if (a.d.cpt == 32) SN_TP_BWD(false, 32);
+    else SN_TP_BWD(false, 0);
+  }
+#undef SN_TP_BWD
 }
 
 template <typename T, typename S>
