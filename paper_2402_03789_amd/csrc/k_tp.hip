@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
   }
   using Ops = EdgeOps<T, D1, NP, NYc, KC>;
   if (n_it > 0)
-    edge_pipeline<4, Ops>(
+    edge_pipeline<(CPT == 32 ? 3 : 4), Ops>(
         g, beg, end, EI, ei, n_it,
         [&](int e, const EdgeIdx& ix, Ops& o) {
           load_edge<T, S, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
                            : (wide ? (uu & slot_store_mask<NV>(cpt)) == 0 && j0 < NYc : uu == 0);
   const int jl = min(j0, NYc - 1);
   using Ops = EdgeOps<T, D1, NP, NYc, KC>;
-  edge_pipeline<3, Ops>(
+  edge_pipeline<(CPT == 32 ? 2 : 3), Ops>(
       g, beg, end, EI, ei, n_it,
       [&](int e, const EdgeIdx& ix, Ops& o) {
         load_edge<T, S, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
