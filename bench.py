@@ -586,7 +586,9 @@ def bench_serving(args, count, precision, full):
                      ("single", dict(n_streams=1, max_batch_atoms=1 << 40,
                                      max_batch_structures=1))):
         srv = Server(model, precision=precision, **kw)
-        replay(srv, [(0.0, s) for _, s in warm])  # allocate workspaces, load kernels
+        big = max((s for _, s in warm), key=lambda s: s.n)
+        srv.warmup(big.pos, big.Z, big.cell)  # every worker: workspace and kernels
+        replay(srv, [(0.0, s) for _, s in warm])
         rep = replay(srv, stream)
         summ = latency_summary(rep)
         summ.update(kw)

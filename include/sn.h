@@ -390,6 +390,13 @@ int sn_server_create(const sn_model_t* model, int device, int n_streams, int pre
  * and only the offending request completes with the error.  SN_EHIP when no worker is
  * alive. */
 int sn_server_submit(sn_server_t* server, const sn_request_t* request, uint64_t* ticket);
+/* Evaluate one request once on every worker, in parallel, and return when all are done
+ * (the results are dropped): each worker's workspace is then sized for a structure of
+ * that size and its kernels are loaded, so the first requests of a stream do not pay for
+ * either.  Checked as at submit (SN_EINVAL); SN_EBUSY while another warm-up runs; the
+ * first worker's error otherwise (SN_EHIP when no worker is alive).  Queued requests
+ * wait behind the warm-up of the worker that takes them. */
+int sn_server_warmup(sn_server_t* server, const sn_request_t* request);
 /* Move up to max finished results into out[]; *n_out receives the count.  Waits up to
  * timeout_ms for the first one (0: do not wait, negative: wait without limit). */
 int sn_server_poll(sn_server_t* server, sn_result_t* out, int max, int timeout_ms, int* n_out);

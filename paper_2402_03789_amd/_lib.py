@@ -116,6 +116,7 @@ _SIGS = {
     "sn_server_create": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_size_t, C.c_int64,
                                    C.c_int, C.POINTER(C.c_void_p)]),
     "sn_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "sn_server_warmup": (C.c_int, [C.c_void_p, C.POINTER(Request)]),
     "sn_server_poll": (C.c_int, [C.c_void_p, C.POINTER(Result), C.c_int, C.c_int,
                                  C.POINTER(C.c_int)]),
     "sn_server_pending": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),

@@ -67,12 +67,26 @@ struct sn_server {
   uint64_t next_ticket = 1;
   int live_workers = 0;
   int64_t in_flight = 0;  // requests taken by workers and not yet completed
+  // warm-up: every worker evaluates warm_req once per generation (results dropped)
+  uint64_t warm_gen = 0;
+  std::vector<uint64_t> warm_seen;
+  std::unique_ptr<Request> warm_req;
+  int warm_left = 0;
+  int warm_status = SN_OK;
   std::vector<std::thread> threads;
   std::string err;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
   void worker(int w);
+  void warm_done(int w, int status);  // called with mu held
 };
+
+void sn_server::warm_done(int w, int status) {
+  if (warm_seen[w] == warm_gen) return;
+  warm_seen[w] = warm_gen;
+  if (status != SN_OK && warm_status == SN_OK) warm_status = status;
+  if (--warm_left == 0) cv_done.notify_all();
+}
 
 namespace {
 
@@ -125,7 +139,6 @@ bool valid_request(const sn_server* s, const sn_request_t* q) {
 }  // namespace
 
 void sn_server::worker(int w) {
-  (void)w;
   hipStream_t stream = nullptr;
   sn_ctx_t* ctx = nullptr;
   bool ok = hipSetDevice(device) == hipSuccess &&
@@ -143,8 +156,30 @@ void sn_server::worker(int w) {
   while (ok) {
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+      cv_work.wait(lk, [&] { return stop || !queue.empty() || warm_seen[w] != warm_gen; });
       if (stop) break;
+      if (warm_seen[w] != warm_gen) {
+        // warm-up: allocate this worker's workspace and load its kernels for a request of
+        // this size before traffic arrives
+        const Request* r = warm_req.get();
+        lk.unlock();
+        const int64_t o1[2] = {0, r->n};
+        std::vector<double> e1(1), w1(9), ae1((size_t)r->n), f1(3 * (size_t)r->n);
+        const int st = sn_compute_batch(ctx, 1, o1, r->pos.data(), r->Z.data(), r->cell, e1.data(),
+                                        ae1.data(), f1.data(), w1.data());
+        if (st == SN_OK) {
+          size_t used = 0;
+          sn_ctx_memory(ctx, &used);
+          if (used > high_water) {
+            high_water = used;
+            bytes_per_atom = std::max(1024.0, (double)(used - base) / (double)r->n);
+          }
+        }
+        lk.lock();
+        warm_done(w, st);
+        if (st == SN_EHIP) break;
+        continue;
+      }
       int64_t cap = atom_cap;
       if (slice) {
         const double room = (double)(slice > base ? slice - base : 0) / bytes_per_atom;
@@ -238,6 +273,7 @@ void sn_server::worker(int w) {
   if (stream) (void)hipStreamDestroy(stream);
   std::lock_guard<std::mutex> lk(mu);
   --live_workers;
+  if (warm_left > 0) warm_done(w, SN_EHIP);
   if (live_workers == 0) {
     // nothing can run the remaining requests: complete them with an error
     while (!queue.empty()) {
@@ -277,6 +313,7 @@ int sn_server_create(const sn_model_t* model, int device, int n_streams, int pre
     if (info.species_z[k] >= 0 && info.species_z[k] < 128) s->known_z[info.species_z[k]] = true;
   s->t0 = Clock::now();
   s->live_workers = n_streams;
+  s->warm_seen.assign((size_t)n_streams, 0);
   try {
     for (int w = 0; w < n_streams; ++w) s->threads.emplace_back([p = s.get(), w] { p->worker(w); });
   } catch (const std::exception&) {
@@ -317,6 +354,32 @@ int sn_server_submit(sn_server_t* s, const sn_request_t* req, uint64_t* ticket) 
   }
   s->cv_work.notify_one();
   return SN_OK;
+}
+
+int sn_server_warmup(sn_server_t* s, const sn_request_t* req) {
+  if (!s || !req || req->n <= 0 || !req->pos || !req->Z || !req->cell) return SN_EINVAL;
+  if (!valid_request(s, req)) return SN_EINVAL;
+  auto r = std::make_unique<Request>();
+  r->n = req->n;
+  try {
+    r->pos.assign(req->pos, req->pos + 3 * req->n);
+    r->Z.assign(req->Z, req->Z + req->n);
+  } catch (const std::exception&) {
+    return SN_ENOMEM;
+  }
+  std::memcpy(r->cell, req->cell, sizeof(double) * 9);
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->live_workers == 0) return SN_EHIP;
+  if (s->stop || s->warm_left > 0) return SN_EBUSY;
+  s->warm_req = std::move(r);
+  s->warm_status = SN_OK;
+  ++s->warm_gen;
+  // workers that already exited never see this generation
+  s->warm_left = s->live_workers;
+  s->cv_work.notify_all();
+  s->cv_done.wait(lk, [&] { return s->warm_left <= 0; });
+  s->warm_req.reset();
+  return s->warm_status;
 }
 
 int sn_server_poll(sn_server_t* s, sn_result_t* out, int max, int timeout_ms, int* n_out) {

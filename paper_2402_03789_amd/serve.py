@@ -42,6 +42,15 @@ class Server:
         self._live[t.value] = (ae, f)
         return t.value
 
+    def warmup(self, pos, Z, cell) -> None:
+        """Evaluate one structure once on every worker (results dropped), so that the
+        workers' workspaces and kernels are ready before traffic arrives."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        Z = np.ascontiguousarray(Z, dtype=np.int32)
+        cell = np.ascontiguousarray(cell, dtype=np.float64)
+        req = Request(len(Z), pos.ctypes.data, Z.ctypes.data, cell.ctypes.data, None, None)
+        check(lib().sn_server_warmup(self._h, C.byref(req)))
+
     def poll(self, timeout_ms: int = 0) -> list:
         n = C.c_int()
         check(lib().sn_server_poll(self._h, self._res, len(self._res), int(timeout_ms), C.byref(n)))

@@ -121,3 +121,27 @@ def test_bad_request_fails_alone(model):
         alone = ctx.compute(s.pos, s.Z, s.cell)
         assert res[tk]["energy"] == alone["energy"]
         np.testing.assert_array_equal(res[tk]["forces"], alone["forces"])
+
+
+def test_warmup_every_worker_then_results_unchanged(model):
+    from paper_2402_03789_amd._lib import SNError
+    stream = serving_stream(count=12, seed=23, n_min=8, n_max=400)
+    srv = Server(model, n_streams=3, precision="fp32", max_batch_atoms=2000)
+    big = max((s for _, s in stream), key=lambda s: s.n)
+    log(f"warm-up with {big.n} atoms on 3 workers")
+    srv.warmup(big.pos, big.Z, big.cell)
+    srv.warmup(stream[0][1].pos, stream[0][1].Z, stream[0][1].cell)  # a second round
+    bad_Z = np.array(big.Z, copy=True)
+    bad_Z[0] = 120  # outside the model's species table
+    with pytest.raises(SNError):
+        srv.warmup(big.pos, bad_Z, big.cell)
+    tickets = [srv.submit(s.pos, s.Z, s.cell) for _, s in stream]
+    res = _drain(srv, len(tickets))
+    srv.close()
+    ctx = sn.Context(model, precision="fp32")
+    for tk, (_, s) in zip(tickets, stream):
+        r = res[tk]
+        assert r["status"] == 0
+        alone = ctx.compute(s.pos, s.Z, s.cell)
+        assert r["energy"] == alone["energy"]
+        np.testing.assert_array_equal(r["forces"], alone["forces"])

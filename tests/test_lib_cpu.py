@@ -106,3 +106,26 @@ def test_model_tensor_table_and_huber_helper(tmp_path):
     np.testing.assert_allclose(g, [r[0] / (2 * 12), 0.01 / (2 * 18)], rtol=1e-11)
     with pytest.raises(sn.SNError):
         huber_energy_loss(E, ref, [12, 0], 0.01)
+
+
+def test_server_warmup_without_device_returns_error(tmp_path):
+    """With no usable device every worker exits at start; a warm-up must report that
+    (SN_EHIP) instead of waiting for workers that will never run it."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import paper_2402_03789_amd as sn
+    from paper_2402_03789_amd.serve import Server
+    from paper_2402_03789_amd._lib import SNError, SN_EHIP
+    from gpu_common import write_model
+    from synth import model_spec_small, serving_stream
+    path, _ = write_model(tmp_path, model_spec_small((8, 14)), 5)
+    srv = Server(sn.Model(path), n_streams=3, precision="fp32")
+    _, s = serving_stream(count=1, seed=1, n_min=8, n_max=20)[0]
+    Z = np.where(s.Z % 2 == 0, 8, 14)
+    with pytest.raises(SNError) as e:
+        srv.warmup(s.pos, Z, s.cell)
+    assert e.value.status == SN_EHIP
+    srv.close()
