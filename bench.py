@@ -379,7 +379,7 @@ def _run_form(args, sn, torch, wpath, spec, s, precision, domains, extras):
     flops_tp = sum(e * f for f in _tp_adjoint_flops(spec, cg_nnz)) / len(blocks)
     alu_peak = 78.6 if precision == "fp64" else 157.3
     alu_tf = flops_tp / (tp_ms * 1e-3) / 1e12 if tp_ms > 0 else None
-    tp_src = os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_tp.hip")
+    tp_src = os.path.join(ROOT, "paper_2402_03789_amd", "csrc", "k_tp.h")
     roofline = {"bound": "alu", "kernel": "k_tp_bwd (tensor-product adjoint; one interaction "
                                           "block = its degree launches)",
                 "achieved": alu_tf, "peak": alu_peak, "unit": "TFLOP/s",

@@ -29,6 +29,8 @@
 // shuffles across rows); the per-degree kernels add their shares to dE/dY one after
 // another (fixed order).  Both directions are compiled for slot widths of 64 and 32
 // lanes (fewer registers, so more waves per SIMD) besides the general runtime width.
+#pragma once
+
 #include "kernels.h"
 #include "cg_tables.h"
 
@@ -614,9 +616,5 @@ void launch_tp_bwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* 
   template void launch_tp_bwd<T, S>(const TPLayer&, int, const int*, const int*, const int*,     \
                                     const T*, const S*, const S*, const T*, S*, S*, T*, bool,    \
                                     hipStream_t);
-SN_TP_INST(float, float)
-SN_TP_INST(float, bf16_t)
-SN_TP_INST(double, double)
-#undef SN_TP_INST
 
 }  // namespace sn
