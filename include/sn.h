@@ -56,7 +56,8 @@ extern "C" {
                       the adjoint in float32; energy and virial reductions in float64 */
 #define SN_BF16 2  /* as SN_FP32, but the radial MLP and the channel-mixing linears take
                       bfloat16 operands with float32 accumulation on the matrix cores; sender
-                      features, radial weights and per-edge gradients stored in bfloat16;
+                      features, radial weights, messages and per-edge gradients stored in
+                      bfloat16;
                       tensor product in float32; node-state chain in float32; float64
                       positions, edge gradients, forces, energy and virial reductions */
 

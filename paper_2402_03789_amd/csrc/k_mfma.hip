@@ -25,6 +25,8 @@ constexpr int MT = 64;  // block tile rows / cols
 
 template <typename T>
 __device__ inline float to_float(T v) { return (float)v; }
+template <>
+__device__ inline float to_float<bf16_t>(bf16_t v) { return sload(v); }
 
 // C element update (= v or += v) in the output type
 template <typename TC>
@@ -165,6 +167,13 @@ template <>
 __device__ inline void ld4<float>(const float* p, float (&v)[4]) {
   const floatx4 a = *reinterpret_cast<const floatx4*>(p);
   v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+}
+template <>
+__device__ inline void ld4<bf16_t>(const bf16_t* p, float (&v)[4]) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 a = *reinterpret_cast<const u32x2*>(p);
+  v[0] = __uint_as_float(a[0] << 16); v[1] = __uint_as_float(a[0] & 0xffff0000u);
+  v[2] = __uint_as_float(a[1] << 16); v[3] = __uint_as_float(a[1] & 0xffff0000u);
 }
 template <>
 __device__ inline void ld4<double>(const double* p, float (&v)[4]) {
@@ -471,6 +480,7 @@ SN_MFMA_INST(double, double, float)
 SN_MFMA_INST(double, double, double)
 SN_MFMA_INST(double, float, bf16_t)
 SN_MFMA_INST(float, float, bf16_t)
+SN_MFMA_INST(bf16_t, float, float)
 #undef SN_MFMA_INST
 
 }  // namespace sn

@@ -183,7 +183,7 @@ __device__ inline void edge_pipeline(const TPArgs& g, int beg, int end, int EI, 
 template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, int CPT>
 __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ Y,
                                                  const S* __restrict__ x, const S* __restrict__ w,
-                                                 T* __restrict__ M, T inv_k) {
+                                                 S* __restrict__ M, T inv_k) {
   using PL = PathList<L1, LSH, L3MAX, SO>;
   constexpr int NP = PL::count();
   constexpr int D1 = 2 * L1 + 1;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
       constexpr int oo = PL::ooff(p);
 #pragma unroll
       for (int m3 = 0; m3 < D3; ++m3)
-        M[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u] = acc[c][oo + m3] * inv_k;
+        M[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u] = sstore<S>(acc[c][oo + m3] * inv_k);
     });
   }
 }
@@ -369,7 +369,7 @@ __device__ inline void slot_reduce_rows(T (&v)[NV], int cpt, int lane) {
 template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX, int CPT>
 __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ Y,
                                                  const S* __restrict__ x, const S* __restrict__ w,
-                                                 const T* __restrict__ G, S* __restrict__ dw,
+                                                 const S* __restrict__ G, S* __restrict__ dw,
                                                  S* __restrict__ dxe, T* __restrict__ dY,
                                                  int accumulate) {
   using PL = PathList<L1, LSH, L3MAX, SO>;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
       constexpr int oo = PL::ooff(p);
 #pragma unroll
       for (int m3 = 0; m3 < D3; ++m3)
-        gin[c][oo + m3] = ok ? G[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u] : T(0);
+        gin[c][oo + m3] = ok ? (T)sload(G[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u]) : T(0);
     });
   }
   int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
@@ -533,14 +533,14 @@ static TPArgs make_args(const TPLayer& L, int l1, int n_recv, const int* row_ptr
 }
 
 template <typename T, typename S, int L1, int LSH, int LMX, bool SO, int CPT>
-static void launch_fwd(const TPArgs& a, const T* Y, const S* x, const S* w, T* M, T inv_k,
+static void launch_fwd(const TPArgs& a, const T* Y, const S* x, const S* w, S* M, T inv_k,
                        hipStream_t s) {
   const unsigned grid = (unsigned)((a.n_recv + kRecvPerBlock - 1) / kRecvPerBlock);
   k_tp_fwd<T, S, L1, LSH, LMX, SO, CPT><<<grid, kWave * kRecvPerBlock, 0, s>>>(a, Y, x, w, M, inv_k);
 }
 template <typename T, typename S, int L1, int LSH, int LMX, bool SO>
-static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const S* w, T* M, T inv_k,
-                       const T* G, S* dw, S* dxe, T* dY, int acc, hipStream_t s) {
+static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const S* w, S* M, T inv_k,
+                       const S* G, S* dw, S* dxe, T* dY, int acc, hipStream_t s) {
   // compile-time slot widths for the common channel counts
   if (fwd) {
     if (a.d.cpt == 64) launch_fwd<T, S, L1, LSH, LMX, SO, 64>(a, Y, x, w, M, inv_k, s);
@@ -567,7 +567,7 @@ static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const 
 
 template <typename T, typename S>
 static void run(const TPLayer& L, bool fwd, int n_recv, const int* row_ptr, const int* src,
-                const int* pidx, const T* Y, const S* x, const S* w, T* M, T inv_k, const T* G,
+                const int* pidx, const T* Y, const S* x, const S* w, S* M, T inv_k, const S* G,
                 S* dw, S* dxe, T* dY, bool accumulate, hipStream_t s) {
   if (n_recv <= 0) return;
   bool first = true;
@@ -597,14 +597,14 @@ static void run(const TPLayer& L, bool fwd, int n_recv, const int* row_ptr, cons
 
 template <typename T, typename S>
 void launch_tp_fwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const int* pidx, const T* Y, const S* x, const S* w, T* M, T inv_k,
+                   const int* pidx, const T* Y, const S* x, const S* w, S* M, T inv_k,
                    hipStream_t s) {
   run<T, S>(L, true, n_recv, row_ptr, src, pidx, Y, x, w, M, inv_k, nullptr, nullptr, nullptr,
             nullptr, false, s);
 }
 template <typename T, typename S>
 void launch_tp_bwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const int* pidx, const T* Y, const S* x, const S* w, const T* G, S* dw, S* dxe,
+                   const int* pidx, const T* Y, const S* x, const S* w, const S* G, S* dw, S* dxe,
                    T* dY, bool accumulate, hipStream_t s) {
   run<T, S>(L, false, n_recv, row_ptr, src, pidx, Y, x, w, nullptr, T(0), G, dw, dxe, dY,
             accumulate, s);
@@ -612,9 +612,9 @@ void launch_tp_bwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* 
 
 #define SN_TP_INST(T, S)                                                                       \
   template void launch_tp_fwd<T, S>(const TPLayer&, int, const int*, const int*, const int*,     \
-                                    const T*, const S*, const S*, T*, T, hipStream_t);          \
+                                    const T*, const S*, const S*, S*, T, hipStream_t);          \
   template void launch_tp_bwd<T, S>(const TPLayer&, int, const int*, const int*, const int*,     \
-                                    const T*, const S*, const S*, const T*, S*, S*, T*, bool,    \
+                                    const T*, const S*, const S*, const S*, S*, S*, T*, bool,    \
                                     hipStream_t);
 
 }  // namespace sn

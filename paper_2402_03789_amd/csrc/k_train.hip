@@ -187,6 +187,7 @@ SN_WG_INST(double, double)
 SN_WG_INST(float, double)
 SN_WG_INST(float, float)
 SN_WG_INST(double, float)
+SN_WG_INST(bf16_t, float)
 #undef SN_WG_INST
 
 }  // namespace sn

@@ -195,11 +195,11 @@ struct TPLayer {
 };
 
 // Messages M [n_recv x Dm] of one block; w is indexed by the edge's pair pidx[e] / 2.
-// S is the storage type of x, w, dE/dw and the per-edge dE/dx rows (T, or bf16_t in the
-// bfloat16 form); arithmetic is in T.
+// S is the storage type of x, w, M, dE/dM, dE/dw and the per-edge dE/dx rows (T, or bf16_t
+// in the bfloat16 form); arithmetic is in T.
 template <typename T, typename S>
 void launch_tp_fwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const int* pidx, const T* Y, const S* x, const S* w, T* M, T inv_k,
+                   const int* pidx, const T* Y, const S* x, const S* w, S* M, T inv_k,
                    hipStream_t s);
 // The adjoint of a small graph runs 2^tp_split_log(n_recv) waves per receiver, each over a
 // contiguous slice of its edges (until about 2,048 waves run; at most 8 per receiver).
@@ -216,7 +216,7 @@ inline int tp_split_log(int n_recv) {
 // null), and dE/dY [E x NY] (added to the existing values when accumulate is set).
 template <typename T, typename S>
 void launch_tp_bwd(const TPLayer& L, int n_recv, const int* row_ptr, const int* src,
-                   const int* pidx, const T* Y, const S* x, const S* w, const T* G, S* dw,
+                   const int* pidx, const T* Y, const S* x, const S* w, const S* G, S* dw,
                    S* dxe, T* dY, bool accumulate, hipStream_t s);
 
 // ---------------------------------------------------------------- node-level and reductions

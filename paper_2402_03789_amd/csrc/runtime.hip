@@ -853,10 +853,10 @@ void build_graph(sn_ctx* c, int N, const double* d_pos, const int* d_spec) {
 // readout input and the backward node gradients -- is NodeT: float64 in the FP64 and
 // FP32 forms (the self-connection carries most of each atom's energy through all blocks
 // and is the one place where float32 rounding reaches the per-atom energy at the 1e-6
-// level), float32 in the BF16 form, whose bfloat16 operands dominate its error.  x (the
-// sender features that feed the tensor product) and the messages M are type T.
-// S is the storage type of the sender features x, the radial weights w, dE/dw and the
-// per-edge sender gradient rows: T, or bfloat16 in the BF16 form (arithmetic stays in T).
+// level), float32 in the BF16 form, whose bfloat16 operands dominate its error.
+// S is the storage type of the sender features x that feed the tensor product, the radial
+// weights w, the messages M and their gradients dE/dM, dE/dw and the per-edge sender
+// gradient rows: T, or bfloat16 in the BF16 form (arithmetic stays in T).
 // Energies, edge gradients, forces, the virial and their reductions stay float64.
 template <typename T, typename S>
 struct Pipe {
@@ -1073,19 +1073,19 @@ struct Pipe {
       S* w = c->get<S>("w" + ts, c->NP * L.P);
       c->mark("layer" + ts + ".tp");
       HIPCHK(hipStreamWaitEvent(s, w_ready[t], 0));
-      T* M = c->get<T>(c->fwd_train ? "M" + ts : std::string("M"), (int64_t)N * L.ml.width);
+      S* M = c->get<S>(c->fwd_train ? "M" + ts : std::string("M"), (int64_t)N * L.ml.width);
       launch_tp_fwd<T, S>(L.tp, N, row_ptr, src, pidx, Y, x, w, M, (T)(1.0 / m->kavg), s);
       c->mark("layer" + ts + ".linear_out");
       {
-        std::vector<GemmDesc<T, T, NodeT>> g;
+        std::vector<GemmDesc<S, T, NodeT>> g;
         for (int l : L.outs) {
           const bool has_sc =
               std::find(L.ins.begin(), L.ins.end(), l) != L.ins.end() && L.gmul[l] > 0;
-          g.push_back(gd<T, T, NodeT>((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M,
+          g.push_back(gd<S, T, NodeT>((int64_t)N * (2 * l + 1), L.gmul[l], L.mid[l], M,
                                        rows_of(L.ml, l), L.w_lin2[l], L.gmul[l], y,
                                        rows_of(L.yl, l), 1.0, has_sc));
         }
-        gemm_group<T, T, NodeT, T>(g, false);
+        gemm_group<S, T, NodeT, T>(g, false);
       }
       // block outputs alternate between two buffers, or stay per block for weight gradients
       NodeT* hn = c->get<NodeT>(c->fwd_train ? "h_out" + ts : std::string(t % 2 ? "h_a" : "h_b"),
@@ -1144,7 +1144,7 @@ struct Pipe {
     GradT* dh = c->get<GradT>("dh_a", (int64_t)N * max_w);
     GradT* dh_other = c->get<GradT>("dh_b", (int64_t)N * max_w);
     GradT* dy = c->get<GradT>("dy", (int64_t)N * max_y);
-    T* Gm = c->get<T>("G", (int64_t)N * max_m);
+    S* Gm = c->get<S>("G", (int64_t)N * max_m);
     // dE/dw alternates between two buffers: the MLP adjoint of block t (aux stream) reads
     // one while the tensor-product adjoint of block t-1 writes the other
     S* dw_buf[2] = {c->get<S>("dw_a", 2 * c->NP * max_P), c->get<S>("dw_b", 2 * c->NP * max_P)};
@@ -1190,9 +1190,9 @@ struct Pipe {
                 : nullptr;
       if (train) {
         // Lin2: dW = M^T dy;  Linsc: dW = h^T dy
-        const T* Mt = c->get<T>("M" + ts, (int64_t)N * L.ml.width);
+        const S* Mt = c->get<S>("M" + ts, (int64_t)N * L.ml.width);
         for (int l : L.outs)
-          wgrad<T, GradT>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], Mt, rows_of(L.ml, l), dy,
+          wgrad<S, GradT>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], Mt, rows_of(L.ml, l), dy,
                            rows_of(L.yl, l), L.w_lin2[l], gw);
         for (int l : L.ins)
           if (L.gmul[l] > 0)
@@ -1200,12 +1200,12 @@ struct Pipe {
                                   rows_of(L.hin, l), dy, rows_of(L.yl, l), L.w_linsc[l], gw);
       }
       {
-        std::vector<GemmDesc<GradT, T, T>> g;
+        std::vector<GemmDesc<GradT, T, S>> g;
         for (int l : L.outs)
-          g.push_back(gd<GradT, T, T>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy,
+          g.push_back(gd<GradT, T, S>((int64_t)N * (2 * l + 1), L.mid[l], L.gmul[l], dy,
                                        rows_of(L.yl, l), L.w_lin2[l], L.gmul[l], Gm,
                                        rows_of(L.ml, l), 1.0 / m->kavg, false));
-        gemm_group<GradT, T, T, T>(g, true);
+        gemm_group<GradT, T, S, T>(g, true);
       }
       S* dw = dw_buf[t % 2];
       if (t + 2 < m->T) {  // dw_buf[t % 2] is free once the MLP adjoint of block t + 2 is done
