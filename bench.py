@@ -905,6 +905,7 @@ def bench_md(args):
     dt = time.perf_counter() - t1
     e1 = md.conserved_energy()
     n, g, e = ctx.graph_size()
+    e_eval, _ = ctx.evaluated_edges()  # the list compacted to the pairs inside r_c
     workload = {"sio2_192": "SiO2 192 atoms, 2.2 g/cm^3, periodic cubic 14.26 A",
                 "sio2_24k": "SiO2 24,000 atoms (8,000 Si + 16,000 O), 2.2 g/cm^3, periodic "
                             "cubic 71.32 A",
@@ -921,7 +922,8 @@ def bench_md(args):
             "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
             "data": "synthetic",
             "config": {"workload": f"{workload}; dt 1 fs, {ens}, skin {args.md_skin:g} A, {reb}",
-                       "n_atoms": n, "n_ghost": g, "n_edges": e, "precision": args.precision,
+                       "n_atoms": n, "n_ghost": g, "n_edges": e,
+                       "n_edges_evaluated_last_step": e_eval, "precision": args.precision,
                        "graph_replay": bool(args.capture), "thermostat": args.thermostat,
                        "rebuild": args.md_rebuild},
             "rebuilds_timed": md.rebuilds - r0, "temperature_K": md.temperature(),

@@ -288,6 +288,19 @@ int sn_huber_energy_loss(int B, const double* energy, const double* ref, const i
  * and its derivative vanish beyond r_cut. */
 int sn_ctx_set_graph_reuse(sn_ctx_t* ctx, int reuse);
 
+/* Evaluation of lists built with a skin (default on).  A list built out to r_cut + skin
+ * also holds pairs farther apart than r_cut, whose contributions the envelope makes exact
+ * zeros (paper section 5.1: the cutoff function and its derivative vanish at r_cut).  With
+ * compaction on, every forward call (the build and each later call that keeps the list)
+ * first compacts the list on the device to the pairs inside r_cut at the current
+ * positions (both edges of a pair together, order preserved) and evaluates only those.
+ * Results equal those of the whole list up to the grouping of floating-point sums (a
+ * degree narrower than a wave deals a receiver's edges to lane groups by position, and
+ * reductions are chunked by list length); they stay deterministic, and a structure's
+ * result is the same alone and in a batch.  Not combined with graph replay
+ * (sn_ctx_set_capture on at the build turns it off for that list). */
+int sn_ctx_set_edge_compaction(sn_ctx_t* ctx, int on);
+
 /* Spatial decomposition on one device (paper section 3.1, Fig 3): split every structure of
  * later calls into nx x ny x nz subdomains, the fractional boxes [i/nx, (i+1)/nx) x ... of its
  * cell.  Each subdomain owns the atoms inside its box and gets its own ghost shell of width
@@ -408,16 +421,21 @@ int sn_server_pending(sn_server_t* server, int64_t* queued, int64_t* running);
 void sn_server_free(sn_server_t* server);
 
 /* ---- inspection (tests and benchmarks) ---------------------------------------------
- * After a compute/forward, the graph sizes: local atoms, ghosts, directed edges. */
+ * After a compute/forward, the graph sizes: local atoms, ghosts, directed edges of the
+ * built list (out to r_cut + skin). */
 int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, int64_t* n_edge);
 
-/* Undirected edge pairs of the last graph (the radial MLP runs once per pair). */
+/* Directed edges and undirected pairs the last forward evaluated (the built list, or its
+ * compaction to the pairs inside r_cut; see sn_ctx_set_edge_compaction). */
+int sn_ctx_evaluated_edges(const sn_ctx_t* ctx, int64_t* n_edge, int64_t* n_pair);
+
+/* Undirected edge pairs of the last evaluated graph (the radial MLP runs once per pair). */
 int sn_ctx_pair_count(const sn_ctx_t* ctx, int64_t* n_pairs);
 
 /* Device bytes currently held by the context's workspace and weights. */
 int sn_ctx_memory(const sn_ctx_t* ctx, size_t* bytes);
 
-/* The last graph in the caller's atom order: recv[E], send_owner[E] (owner atom of
+/* The last built graph in the caller's atom order: recv[E], send_owner[E] (owner atom of
  * the sender), shift[E*3] (integer image shift of the sender), and ghost_owner[G],
  * ghost_shift[G*3].  Host buffers sized from sn_ctx_graph_size; any may be NULL. */
 int sn_ctx_graph(const sn_ctx_t* ctx, int32_t* recv, int32_t* send_owner, int32_t* shift,

@@ -265,6 +265,16 @@ class Context:
         """Replay reused-neighbour-list evaluations from a recorded HIP graph."""
         check(lib().sn_ctx_set_capture(self._h, 1 if on else 0), self._h)
 
+    def set_edge_compaction(self, on: bool):
+        """Evaluate lists built with a skin over their pairs inside r_c only (default on)."""
+        check(lib().sn_ctx_set_edge_compaction(self._h, 1 if on else 0))
+
+    def evaluated_edges(self):
+        """(directed edges, pairs) the last forward evaluated."""
+        e, p = C.c_int64(), C.c_int64()
+        check(lib().sn_ctx_evaluated_edges(self._h, C.byref(e), C.byref(p)))
+        return e.value, p.value
+
     def set_graph_reuse(self, reuse: bool):
         check(lib().sn_ctx_set_graph_reuse(self._h, 1 if reuse else 0))
 

@@ -100,6 +100,8 @@ _SIGS = {
                                        C.POINTER(C.c_double), C.c_void_p]),
     "sn_ctx_graph_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64)]),
+    "sn_ctx_evaluated_edges": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "sn_ctx_set_edge_compaction": (C.c_int, [C.c_void_p, C.c_int]),
     "sn_ctx_pair_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "sn_ctx_set_graph_reuse": (C.c_int, [C.c_void_p, C.c_int]),
     "sn_ctx_set_domains": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),

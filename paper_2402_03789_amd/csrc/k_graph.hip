@@ -504,4 +504,102 @@ void launch_pairs(int64_t E, int n_local, const int* recv, const int* src, const
   k_pairs<<<g, 256, 0, s>>>(E, rev, flag, fscan, pidx, pe1, pe2);
 }
 
+// ------------------------------------------------------------------ active-pair compaction
+// A list built out to r_c + skin holds pairs whose atoms are now (or were at the build)
+// farther apart than r_c.  The envelope vanishes there, so such an edge's radial weights,
+// messages, sender gradients and edge gradient are exact zeros: the pairs inside r_c,
+// compacted in order, give the same messages, energies and forces up to the grouping of
+// floating-point sums.  A pair stays when either of its edges has r / r_c below 1 + 1e-12
+// (the slack covers a last-bit difference from the edge-basis kernel's own distance).
+
+__device__ inline bool edge_inside(const double* __restrict__ pos_ext, int i, int s, double r_cut) {
+  const double d0 = pos_ext[3 * s] - pos_ext[3 * i];
+  const double d1 = pos_ext[3 * s + 1] - pos_ext[3 * i + 1];
+  const double d2 = pos_ext[3 * s + 2] - pos_ext[3 * i + 2];
+  return sqrt(d0 * d0 + d1 * d1 + d2 * d2) / r_cut < 1.0 + 1e-12;
+}
+
+__global__ void k_pair_active(int64_t np, const int* __restrict__ pe1, const int* __restrict__ pe2,
+                              const int* __restrict__ recv, const int* __restrict__ src,
+                              const double* __restrict__ pos_ext, double r_cut,
+                              int* __restrict__ active) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int e1 = pe1[p], e2 = pe2[p];
+  bool in = edge_inside(pos_ext, recv[e1], src[e1], r_cut);
+  if (!in && e2 >= 0) in = edge_inside(pos_ext, recv[e2], src[e2], r_cut);
+  active[p] = in ? 1 : 0;
+}
+
+// keep[e] for every edge, and keep_s[k] for every entry of the sender list
+__global__ void k_edge_keep(int64_t E, const int* __restrict__ pidx, const int* __restrict__ active,
+                            const int* __restrict__ send_idx, int* __restrict__ keep,
+                            int* __restrict__ keep_s) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  keep[e] = active[pidx[e] >> 1];
+  keep_s[e] = active[pidx[send_idx[e]] >> 1];
+}
+
+__global__ void k_compact_edges(int64_t E, const int* __restrict__ keep, const int* __restrict__ escan,
+                                const int* __restrict__ pscan, const int* __restrict__ src,
+                                const int* __restrict__ recv, const int* __restrict__ pidx,
+                                const int* __restrict__ send_idx, const int* __restrict__ keep_s,
+                                const int* __restrict__ sscan, int* __restrict__ src_o,
+                                int* __restrict__ recv_o, int* __restrict__ pidx_o,
+                                int* __restrict__ send_idx_o) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  if (keep[e]) {
+    const int ne = escan[e], q = pidx[e];
+    src_o[ne] = src[e];
+    recv_o[ne] = recv[e];
+    pidx_o[ne] = 2 * pscan[q >> 1] + (q & 1);
+  }
+  if (keep_s[e]) send_idx_o[sscan[e]] = escan[send_idx[e]];
+}
+
+__global__ void k_compact_pairs(int64_t np, const int* __restrict__ active, const int* __restrict__ pscan,
+                                const int* __restrict__ escan, const int* __restrict__ pe1,
+                                const int* __restrict__ pe2, int* __restrict__ pe1_o,
+                                int* __restrict__ pe2_o) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np || !active[p]) return;
+  const int q = pscan[p];
+  pe1_o[q] = escan[pe1[p]];
+  pe2_o[q] = pe2[p] >= 0 ? escan[pe2[p]] : -1;
+}
+
+// out[k] = scan[in[k]] for k <= n (segment offsets of the compacted arrays)
+__global__ void k_remap_offsets(int n, const int* __restrict__ in, const int* __restrict__ scan,
+                                int* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k <= n) out[k] = scan[in[k]];
+}
+
+void launch_compact_active(const CompactIn& a, const CompactOut& o, CompactScratch& t,
+                           hipStream_t s) {
+  const unsigned gp = (unsigned)((a.np + 255) / 256), ge = (unsigned)((a.E + 255) / 256);
+  if (a.np > 0)
+    k_pair_active<<<gp, 256, 0, s>>>(a.np, a.pe1, a.pe2, a.recv, a.src, a.pos_ext, a.r_cut,
+                                     t.active);
+  scan_exclusive(t.active, t.pscan, a.np, t.tmp, s);
+  if (a.E > 0) k_edge_keep<<<ge, 256, 0, s>>>(a.E, a.pidx, t.active, a.send_idx, t.keep, t.keep_s);
+  scan_exclusive(t.keep, t.escan, a.E, t.tmp, s);
+  scan_exclusive(t.keep_s, t.sscan, a.E, t.tmp, s);
+  if (a.E > 0)
+    k_compact_edges<<<ge, 256, 0, s>>>(a.E, t.keep, t.escan, t.pscan, a.src, a.recv, a.pidx,
+                                       a.send_idx, t.keep_s, t.sscan, o.src, o.recv, o.pidx,
+                                       o.send_idx);
+  if (a.np > 0)
+    k_compact_pairs<<<gp, 256, 0, s>>>(a.np, t.active, t.pscan, t.escan, a.pe1, a.pe2, o.pe1,
+                                       o.pe2);
+  k_remap_offsets<<<(unsigned)((a.n_local + 1 + 255) / 256), 256, 0, s>>>(a.n_local, a.row_ptr,
+                                                                           t.escan, o.row_ptr);
+  k_remap_offsets<<<(unsigned)((a.n_ext + 1 + 255) / 256), 256, 0, s>>>(a.n_ext, a.send_ptr,
+                                                                         t.sscan, o.send_ptr);
+  k_remap_offsets<<<(unsigned)((a.n_struct + 1 + 255) / 256), 256, 0, s>>>(a.n_struct, a.edge_off,
+                                                                            t.escan, o.edge_off);
+}
+
 }  // namespace sn

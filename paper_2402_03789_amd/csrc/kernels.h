@@ -55,6 +55,28 @@ void launch_edge_fill(int n, const double* pos_ext, const double* frac_ext, cons
                       const StructParams* sp, const int* cell_start, const int* cell_items,
                       double rc2, const int* row_ptr, int* src, int* recv, hipStream_t s);
 
+// Compaction of a list built out to r_c + skin to the pairs now inside r_c (both edges of a
+// pair kept or dropped together; order preserved), for evaluating a kept list: the edge
+// arrays, the pair table, the receiver and sender offsets and the per-structure edge
+// offsets are rewritten into `CompactOut`.  The compacted counts are escan[E] (edges) and
+// pscan[np] (pairs).  Scratch arrays hold np + 1 (active, pscan) or E + 1 ints; tmp
+// scan_tmp_ints(max(E, np) + 1).
+struct CompactIn {
+  int64_t E, np;
+  int n_local, n_ext, n_struct;
+  const int *row_ptr, *src, *recv, *pidx, *pe1, *pe2, *send_ptr, *send_idx, *edge_off;
+  const double* pos_ext;
+  double r_cut;
+};
+struct CompactOut {
+  int *row_ptr, *src, *recv, *pidx, *pe1, *pe2, *send_ptr, *send_idx, *edge_off;
+};
+struct CompactScratch {
+  int *active, *pscan, *keep, *escan, *keep_s, *sscan, *tmp;
+};
+void launch_compact_active(const CompactIn& in, const CompactOut& out, CompactScratch& t,
+                           hipStream_t s);
+
 // Reverse-edge map and undirected pairs: rev[e] (-1 if none), pidx[e] (pair of each edge),
 // pe1[p] (canonical edge of pair p, the lower id) and pe2[p] (its reverse or -1).  The
 // number of pairs is fscan[E].  tmp is scan scratch.

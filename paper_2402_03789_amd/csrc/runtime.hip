@@ -320,6 +320,13 @@ struct sn_ctx {
   std::vector<StructParams> sp;    // per-structure geometry (host copy)
   int nbins = 0;
   int n_echunk = 0, n_vchunk = 0;
+  // A list built out to r_c + skin is evaluated over its pairs inside r_c only: after every
+  // position refresh the built list (kept as full_*) is compacted into the arrays the
+  // evaluation reads (see launch_compact_active).
+  bool compact = true;           // enabled (sn_ctx_set_edge_compaction)
+  bool compacted = false;        // the current graph is a compaction of the built list
+  int64_t E_built = 0, NP_built = 0;
+  std::vector<int> vchunk_host, vfirst_host;  // host copies of the virial chunk table
   bool pending = false;
   bool train = false;       // forwards keep every block's inputs and messages (weight gradients)
   bool fwd_train = false;   // the pending forward kept them
@@ -722,6 +729,75 @@ __global__ void k_gather_offsets(int B, const int* __restrict__ row_ptr, const i
                                  int* __restrict__ eoff) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b <= B) eoff[b] = row_ptr[aoff[b]];
+}
+
+// The built list's arrays, kept under full_* while compacted copies are evaluated.
+const char* const kListArrays[] = {"row_ptr", "src", "recv", "pidx", "pair_e1", "pair_e2",
+                                   "send_ptr", "send_idx", "struct_edge_off"};
+int64_t list_array_len(const sn_ctx* c, int k) {
+  const int64_t N = c->N, NE = c->N + c->G;
+  switch (k) {
+    case 0: return N + 1;
+    case 4: case 5: return c->NP;
+    case 6: return NE + 1;
+    case 8: return c->B + 1;
+    default: return c->E;
+  }
+}
+void keep_built_list(sn_ctx* c) {
+  for (int k = 0; k < 9; ++k) {
+    const int64_t n = list_array_len(c, k);
+    const std::string name = kListArrays[k];
+    int* dst = c->get<int>("full_" + name, n);
+    const int* src = c->get<int>(name, n);
+    if (n > 0)
+      HIPCHK(hipMemcpyAsync(dst, src, sizeof(int) * n, hipMemcpyDeviceToDevice, c->stream));
+  }
+  c->E_built = c->E;
+  c->NP_built = c->NP;
+}
+
+// Compact the built list to the pairs inside r_c at the current positions (pos_ext) and
+// make the compacted list the one the evaluation reads.
+void compact_list(sn_ctx* c) {
+  hipStream_t s = c->stream;
+  const int N = c->N, NE = N + c->G, B = c->B;
+  const int64_t E = c->E_built, NPr = c->NP_built;
+  auto full = [&](const char* name, int64_t n) { return c->get<int>(std::string("full_") + name, n); };
+  CompactIn a{E, NPr, N, NE, B,
+              full("row_ptr", N + 1), full("src", E), full("recv", E), full("pidx", E),
+              full("pair_e1", NPr), full("pair_e2", NPr), full("send_ptr", NE + 1),
+              full("send_idx", E), full("struct_edge_off", B + 1),
+              c->get<double>("pos_ext", 3 * (int64_t)NE), c->m->rc};
+  CompactOut o{c->get<int>("row_ptr", N + 1), c->get<int>("src", E), c->get<int>("recv", E),
+               c->get<int>("pidx", E), c->get<int>("pair_e1", E), c->get<int>("pair_e2", E),
+               c->get<int>("send_ptr", NE + 1), c->get<int>("send_idx", E),
+               c->get<int>("struct_edge_off", B + 1)};
+  CompactScratch t{c->get<int>("cmp_active", NPr + 1), c->get<int>("cmp_pscan", NPr + 1),
+                   c->get<int>("cmp_keep", E + 1), c->get<int>("cmp_escan", E + 1),
+                   c->get<int>("cmp_keep_s", E + 1), c->get<int>("cmp_sscan", E + 1),
+                   c->get<int>("cmp_tmp", (int64_t)scan_tmp_ints(std::max(E, NPr) + 1))};
+  launch_compact_active(a, o, t, s);
+  std::vector<int> h((size_t)B + 3);
+  HIPCHK(hipMemcpyAsync(h.data(), o.edge_off, sizeof(int) * (B + 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&h[B + 1], t.escan + E, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&h[B + 2], t.pscan + NPr, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->E = h[B + 1];
+  c->NP = h[B + 2];
+  c->edge_off.assign(h.begin(), h.begin() + B + 1);
+  SegChunks vc = make_chunks(c->edge_off, 16384);
+  c->vchunk_host.swap(vc.chunk);
+  c->vfirst_host.swap(vc.first);
+  c->n_vchunk = (int)(c->vchunk_host.size() / 3);
+  // from host vectors that live in the context until the next compaction, which waits for
+  // this copy before it writes them
+  HIPCHK(hipMemcpyAsync(c->get<int>("vchunks", 3 * c->n_vchunk), c->vchunk_host.data(),
+                        sizeof(int) * c->vchunk_host.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->get<int>("vfirst", B + 1), c->vfirst_host.data(), sizeof(int) * (B + 1),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipGetLastError());
+  c->compacted = true;
 }
 
 template <typename T>
@@ -1469,6 +1545,7 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
                                c->get<int>("sid_ext", c->N + c->G),
                                c->get<StructParams>("struct_params", c->R),
                                c->get<double>("pos_ext", 3 * (int64_t)(c->N + c->G)), c->stream);
+      if (c->compacted) compact_list(c);
       Pipe<T, S> p(c);
       p.forward(d_energy, d_atom_energy);
     };
@@ -1477,7 +1554,7 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
     sn_ctx::Replay& r = c->rp_fwd;
     // replay once an eager run on this graph has sized every buffer (not in training mode,
     // whose forwards keep other buffers)
-    if (c->capture && !c->train && c->reuse_runs >= 1) {
+    if (c->capture && !c->train && !c->compacted && c->reuse_runs >= 1) {
       if (!replay_hit(r, c->graph_version, d_pos, d_energy, d_atom_energy)) {
         if (r.exec) (void)hipGraphExecDestroy(r.exec);
         r.exec = nullptr;
@@ -1502,6 +1579,13 @@ void forward_impl(sn_ctx* c, int B, const int64_t* offsets, const double* d_pos,
   build_graph<T>(c, (int)n, d_pos, d_spec);
   launch_wrap_offsets((int)n, c->get<int>("order", n), d_pos, c->get<double>("pos_ext", 3 * n),
                       c->get<double>("wrap_off", 3 * n), c->stream);
+  // a list with a skin is evaluated over its pairs inside r_c (not with graph replay, whose
+  // recorded launches need fixed sizes)
+  c->compacted = false;
+  if (c->compact && c->skin > 0 && !c->capture) {
+    keep_built_list(c);
+    compact_list(c);
+  }
   c->graph_cells.assign(cells, cells + 9 * B);
   c->have_graph = true;
   Pipe<T, S> p(c);
@@ -1519,7 +1603,7 @@ void backward_impl(sn_ctx* c, const double* d_grad, double* d_forces, double* d_
   };
   c->pending = false;
   sn_ctx::Replay& r = c->rp_bwd;
-  if (!d_wgrad && c->capture && c->last_fwd_reused && c->reuse_runs >= 1) {
+  if (!d_wgrad && c->capture && !c->compacted && c->last_fwd_reused && c->reuse_runs >= 1) {
     if (!replay_hit(r, c->graph_version, d_forces, d_virial, d_grad)) {
       if (r.exec) (void)hipGraphExecDestroy(r.exec);
       r.exec = nullptr;
@@ -2100,7 +2184,20 @@ int sn_ctx_graph_size(const sn_ctx_t* ctx, int64_t* n_local, int64_t* n_ghost, i
   if (!ctx) return SN_EINVAL;
   if (n_local) *n_local = ctx->N;
   if (n_ghost) *n_ghost = ctx->G;
+  if (n_edge) *n_edge = ctx->compacted ? ctx->E_built : ctx->E;
+  return SN_OK;
+}
+
+int sn_ctx_evaluated_edges(const sn_ctx_t* ctx, int64_t* n_edge, int64_t* n_pair) {
+  if (!ctx) return SN_EINVAL;
   if (n_edge) *n_edge = ctx->E;
+  if (n_pair) *n_pair = ctx->NP;
+  return SN_OK;
+}
+
+int sn_ctx_set_edge_compaction(sn_ctx_t* ctx, int on) {
+  if (!ctx) return SN_EINVAL;
+  ctx->compact = on != 0;
   return SN_OK;
 }
 
@@ -2181,7 +2278,9 @@ int sn_ctx_graph(const sn_ctx_t* cctx, int32_t* recv, int32_t* send_owner, int32
   }
   return guarded(ctx, [&] {
     const int N = ctx->N, G = ctx->G;
-    const int64_t E = ctx->E;
+    // the built list (of which the evaluated one may be a compaction)
+    const int64_t E = ctx->compacted ? ctx->E_built : ctx->E;
+    const std::string pre = ctx->compacted ? "full_" : "";
     hipStream_t s = ctx->stream;
     std::vector<int> order(N), owner(G), gsh(3 * (size_t)G), src(E), rcv(E);
     HIPCHK(hipMemcpyAsync(order.data(), ctx->get<int>("order", N), sizeof(int) * N,
@@ -2193,9 +2292,9 @@ int sn_ctx_graph(const sn_ctx_t* cctx, int32_t* recv, int32_t* send_owner, int32
                             sizeof(int) * 3 * G, hipMemcpyDeviceToHost, s));
     }
     if (E) {
-      HIPCHK(hipMemcpyAsync(src.data(), ctx->get<int>("src", E), sizeof(int) * E,
+      HIPCHK(hipMemcpyAsync(src.data(), ctx->get<int>(pre + "src", E), sizeof(int) * E,
                             hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(rcv.data(), ctx->get<int>("recv", E), sizeof(int) * E,
+      HIPCHK(hipMemcpyAsync(rcv.data(), ctx->get<int>(pre + "recv", E), sizeof(int) * E,
                             hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));

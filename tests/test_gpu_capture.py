@@ -40,6 +40,7 @@ def test_replays_equal_eager(model, precision):
     cap.set_graph_reuse(True)
     cap.set_capture(True)
     ref = sn.Context(model, precision=precision, skin=1.0)
+    ref.set_edge_compaction(False)  # replay evaluates the whole list; so does the reference
     ref.set_graph_reuse(True)
     pos_c = torch.tensor(s.pos, device=dev)
     pos_r = torch.tensor(s.pos, device=dev)
@@ -70,6 +71,7 @@ def test_md_trajectory_same_with_replay(model):
     runs = []
     for capture in (False, True):
         ctx = sn.Context(model, precision="fp64", skin=1.0)
+        ctx.set_edge_compaction(False)  # replay evaluates the whole list; so does the eager run
         md = VelocityVerlet(ctx, s.pos, s.Z, s.cell, s.masses(), dt=0.5, rebuild_every=10,
                             temperature=600.0, seed=3, capture=capture)
         md.run(25)
