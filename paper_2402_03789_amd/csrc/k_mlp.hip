@@ -247,38 +247,57 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
 #pragma unroll
     for (int s = 0; s < HID / 4; ++s) za[s] = Z[r * ZP + 4 * s + q];
   }
+  // Wc panels in flight: a ring of RING register sets, RING - 1 panels ahead of the one
+  // being multiplied (a panel's eight MFMAs per wave take far less than the L2 round trip
+  // of the next panel's loads).  Panel pan0 + k travels in ring slot k % RING; the loop is
+  // unrolled by RING so the slots are fixed registers.
+  constexpr int RING = 3;
+  PanelRegs<BF16> ring[RING];
+  const int count = pan1 - pan0;
+  static_for<RING - 1>([&](auto J) {
+    constexpr int k = decltype(J)::value + 1;
+    fetch_panel<BF16>(Wcp, pan0 + k, npan, tid, ring[k % RING]);
+  });
   int buf = 0;
-  for (int n0 = pan0 * HID; n0 < min(P, pan1 * HID); n0 += HID) {
-    fetch_panel<BF16>(Wcp, n0 / HID + 1, npan, tid, pr);  // in flight during the MFMAs
-    __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
+  auto step = [&](int jj, auto SLOT) {
+    constexpr int sc = decltype(SLOT)::value, sn = (sc + 1) % RING;
+    // slot sc held panel jj, staged into LDS by the previous step: reuse it for panel
+    // jj + RING (loads past the last panel read the last one again and are never used)
+    fetch_panel<BF16>(Wcp, pan0 + jj + RING, npan, tid, ring[sc]);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
     const float* sf = sW[buf];
     const __bf16* sh = reinterpret_cast<const __bf16*>(sW[buf]);
+    const int n0 = (pan0 + jj) * HID;
     // the transposed product w^T = Wc^T z2^T: lane (r, q) receives weights of pair r only.
     // float32: row i of tile t is panel column 16 t + i, so acc[t] = w[pair r][n0 + 16 t +
     // 4 q + 0..3] (the A rows read from LDS stay bank-conflict free); bfloat16: row i of
     // tile t is column 16 (i / 4) + 4 t + i % 4, so acc[0..3][0..3] = w[pair r][n0 + 16 q +
     // 0..15], sixteen consecutive values for two 16-byte stores
     zero4(acc);
-    if (BF16) {
-      const int ca = 16 * (r >> 2) + (r & 3);
+    if (jj < count) {
+      if (BF16) {
+        const int ca = 16 * (r >> 2) + (r & 3);
 #pragma unroll
-      for (int s = 0; s < HID / 32; ++s)
+        for (int s = 0; s < HID / 32; ++s)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sh[(ca + 4 * t) * BP + 32 * s + 8 * q]);
-          acc[t] = mfma32(a, zh[s], acc[t]);
-        }
-    } else {
+          for (int t = 0; t < 4; ++t) {
+            const bf16x8 a =
+                *reinterpret_cast<const bf16x8*>(&sh[(ca + 4 * t) * BP + 32 * s + 8 * q]);
+            acc[t] = mfma32(a, zh[s], acc[t]);
+          }
+      } else {
 #pragma unroll
-      for (int s = 0; s < HID / 4; ++s)
+        for (int s = 0; s < HID / 4; ++s)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = mfma4(sf[(4 * s + q) * WP + 16 * t + r], za[s], acc[t]);
+          for (int t = 0; t < 4; ++t)
+            acc[t] = mfma4(sf[(4 * s + q) * WP + 16 * t + r], za[s], acc[t]);
+      }
     }
-    // staged unconditionally (the panel past the last is never read): a conditional store
+    // staged unconditionally (a panel past the last is never read): a conditional store
     // would let the compiler sink the panel loads into the branch, after the MFMAs
-    store_panel<BF16>(pr, tid, reinterpret_cast<WPan<BF16>*>(sW[buf ^ 1]), BF16 ? BP : WP);
+    store_panel<BF16>(ring[sn], tid, reinterpret_cast<WPan<BF16>*>(sW[buf ^ 1]), BF16 ? BP : WP);
     const int64_t p = p0 + wave * 16 + r;
-    if (p < np) {
+    if (jj < count && p < np) {
       if constexpr (BF16) {  // two 16-byte stores of eight bfloat16 values
         const int c0 = n0 + 16 * q;
 #pragma unroll
@@ -304,6 +323,9 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
     }
     __syncthreads();
     buf ^= 1;
+  };
+  for (int j = 0; j < count; j += RING) {
+    static_for<RING>([&](auto J) { step(j + decltype(J)::value, J); });
   }
 }
 
