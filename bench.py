@@ -204,7 +204,7 @@ def main():
     ap.add_argument("--sizes", default="4608,12960",
                     help="paper_models: atom counts (multiples of 3)")
     ap.add_argument("--serve-requests", type=int, default=None,
-                    help="requests of the serving stream to replay: default 400 beside the "
+                    help="requests of the serving stream to replay: default 1,000 beside the "
                          "headline line (0 to skip), 2,000 for --workload serving")
     ap.add_argument("--serve-streams", type=int, default=3)
     ap.add_argument("--serve-high-rate", type=float, default=5000.0,
@@ -285,7 +285,7 @@ def main():
     cpu = None if args.no_cpu_baseline else _cpu_baseline(args, spec, weights)
 
     serving = None
-    count = 400 if args.serve_requests is None else args.serve_requests
+    count = 1000 if args.serve_requests is None else args.serve_requests
     if count > 0:
         torch.cuda.empty_cache()
         serving = bench_serving(args, count, args.precision, full=False)
