@@ -207,7 +207,10 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   __shared__ float sWa[NBAS * HID];
   __shared__ float sRho[EB * (NBAS + 1)];
   __shared__ float sZ[4][16 * ZP];
-  __shared__ __attribute__((aligned(16))) float sW[2][HID * WP];  // Wb, then Wc panels
+  // two Wc panel stages (float32 [k][n] of stride WP, or bfloat16 of stride BP); the second
+  // one holds Wb for the hidden layers first (float32, or bfloat16 B^T rows).  Sized for
+  // the form, the bfloat16 kernel's LDS (about 40 KB) admits four blocks per CU.
+  __shared__ __attribute__((aligned(16))) float sW[2][BF16 ? HID * BP / 2 : HID * WP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
   // output panels of this block: all of them, or (few pairs) one of gridDim.y panel groups;
@@ -216,8 +219,8 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   const int ppg = (npan + gridDim.y - 1) / gridDim.y;
   const int pan0 = blockIdx.y * ppg, pan1 = min(npan, pan0 + ppg);
   if (pan0 >= pan1) return;
-  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sW[1], sRho);
-  __shared__ __attribute__((aligned(16))) __bf16 sWbT[BF16 ? HID * BP : 8];
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, BF16 ? nullptr : sW[1], sRho);
+  __bf16* sWbT = reinterpret_cast<__bf16*>(sW[1]);
   if (BF16) stage_wb_bf16(Wb, sWbT, nullptr);
   PanelRegs<BF16> pr;
   fetch_panel<BF16>(Wcp, pan0, npan, tid, pr);
