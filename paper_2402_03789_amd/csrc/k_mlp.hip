@@ -299,24 +299,38 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
     // staged unconditionally (a panel past the last is never read): a conditional store
     // would let the compiler sink the panel loads into the branch, after the MFMAs
     store_panel<BF16>(ring[sn], tid, reinterpret_cast<WPan<BF16>*>(sW[buf ^ 1]), BF16 ? BP : WP);
-    const int64_t p = p0 + wave * 16 + r;
-    if (jj < count && p < np) {
-      if constexpr (BF16) {  // two 16-byte stores of eight bfloat16 values
-        const int c0 = n0 + 16 * q;
+    if constexpr (BF16) {
+      // through the wave's LDS tile (free once z2 is in registers): a 16-byte store then
+      // writes eight whole 128-byte row segments instead of pieces of sixteen rows.  LDS
+      // operations of one wave complete in order; the empty asm statements keep the
+      // compiler from moving the tile's reads across its writes.
+      if (jj < count) {
+        __bf16* Zb = reinterpret_cast<__bf16*>(Z);  // rows of 2 ZP bfloat16 values
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          if (c0 + 8 * h < P) {  // P is a multiple of 8
-            u32x4 v;
+          u32x4 v;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int t = 2 * h + (e >> 1), rr = 2 * (e & 1);
-              v[e] = (uint32_t)sstore<bf16_t>(acc[t][rr]).u |
-                     ((uint32_t)sstore<bf16_t>(acc[t][rr + 1]).u << 16);
-            }
-            *reinterpret_cast<u32x4*>(&w[p * P + c0 + 8 * h]) = v;
+          for (int e = 0; e < 4; ++e) {
+            const int t = 2 * h + (e >> 1), rr = 2 * (e & 1);
+            v[e] = (uint32_t)sstore<bf16_t>(acc[t][rr]).u |
+                   ((uint32_t)sstore<bf16_t>(acc[t][rr + 1]).u << 16);
           }
+          *reinterpret_cast<u32x4*>(Zb + r * 2 * ZP + 16 * q + 8 * h) = v;
         }
-      } else {
+        __asm__ volatile("" ::: "memory");
+        const int cb = 8 * (lane & 7);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int rr = 8 * k + (lane >> 3);
+          const u32x4 v = *reinterpret_cast<const u32x4*>(Zb + rr * 2 * ZP + cb);
+          const int64_t p = p0 + wave * 16 + rr;
+          if (p < np && n0 + cb < P) *reinterpret_cast<u32x4*>(&w[p * P + n0 + cb]) = v;  // P % 8 == 0
+        }
+        __asm__ volatile("" ::: "memory");
+      }
+    } else {
+      const int64_t p = p0 + wave * 16 + r;
+      if (jj < count && p < np) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int col = n0 + 16 * t + 4 * q;
@@ -366,26 +380,30 @@ __device__ inline void split3(float v, __bf16& h0, __bf16& h1, __bf16& h2) {
   h2 = __float2bfloat16(r1 - (float)h1);
 }
 
+// One LDS stage for the split panels (two barriers per panel): the hidden layers' Wb, Wa
+// and rho live in the stage until the first panel replaces them, so a block takes 44 KB
+// and three blocks share a CU.  Outputs leave through the wave's LDS tile, so each store
+// writes four whole 256-byte row segments instead of sixteen rows' scattered pieces.
 __global__ __launch_bounds__(256) void k_mlp_fused_fwd_split(int64_t np, const int* __restrict__ pe1,
                                                               const float* __restrict__ rho,
                                                               const float* __restrict__ Wa,
                                                               const float* __restrict__ Wb,
                                                               const bf16_t* __restrict__ Wc3, int P,
                                                               float c, float* __restrict__ w) {
-  __shared__ float sWa[NBAS * HID];
-  __shared__ float sRho[EB * (NBAS + 1)];
+  constexpr int kStage = 3 * HID * BP;  // bfloat16 elements of a split-panel stage
   __shared__ float sZ[4][16 * ZP];
-  // two split-panel stages; the second one holds Wb (k-major, float32) until the hidden
-  // layers are done
-  __shared__ __attribute__((aligned(16))) __bf16 sS[2][3 * HID * BP];
-  static_assert(sizeof(float) * HID * WP <= sizeof(__bf16) * 3 * HID * BP, "Wb fits a stage");
+  __shared__ __attribute__((aligned(16))) __bf16 sS[kStage];
+  static_assert(sizeof(float) * (HID * WP + NBAS * HID + EB * (NBAS + 1)) <= sizeof(__bf16) * kStage,
+                "the hidden layers' operands fit the stage");
+  float* sWb = reinterpret_cast<float*>(sS);
+  float* sWa = sWb + HID * WP;
+  float* sRho = sWa + NBAS * HID;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
   const int npan = (P + HID - 1) / HID;
   const int ppg = (npan + gridDim.y - 1) / gridDim.y;
   const int pan0 = blockIdx.y * ppg, pan1 = min(npan, pan0 + ppg);
   if (pan0 >= pan1) return;
-  float* sWb = reinterpret_cast<float*>(sS[1]);
   stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
   Panel3Regs pr;
   fetch_panel3(Wc3, pan0, npan, tid, pr);
@@ -394,12 +412,12 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd_split(int64_t np, const i
   floatx4 acc[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, acc, lane);
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
-  store_panel3(pr, tid, sS[0]);
   __syncthreads();
   zero4(acc);
   panel_kn(Z, sWb, acc, lane);
-  __syncthreads();
+  __syncthreads();  // every wave is past Wb, Wa and rho: the stage takes the first panel
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  store_panel3(pr, tid, sS);
   __syncthreads();
   // z2 of pair r in three parts: eight consecutive k per lane and 32-wide step
   const int r = lane & 15, q = lane >> 4;
@@ -417,20 +435,20 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd_split(int64_t np, const i
   // w^T = Wc^T z2^T with the bfloat16 form's row order: row i of tile t is panel column
   // 16 (i / 4) + 4 t + i % 4, so acc[t] = w[pair r][n0 + 16 q + 4 t + 0..3]
   const int ca = 16 * (r >> 2) + (r & 3);
-  int buf = 0;
+  // store layout: lane l writes columns 4 (l % 16) .. + 3 of the wave's rows l / 16 + 4 k
+  const int cc = 4 * (lane & 15);
   for (int n0 = pan0 * HID; n0 < min(P, pan1 * HID); n0 += HID) {
     fetch_panel3(Wc3, n0 / HID + 1, npan, tid, pr);  // in flight during the MFMAs
     __builtin_amdgcn_sched_barrier(0);
-    const __bf16* sh = sS[buf];
     zero4(acc);
 #pragma unroll
     for (int st = 0; st < HID / 32; ++st)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int off = (ca + 4 * t) * BP + 32 * st + 8 * q;
-        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sh + off);
-        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sh + HID * BP + off);
-        const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(sh + 2 * HID * BP + off);
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sS + off);
+        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sS + HID * BP + off);
+        const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(sS + 2 * HID * BP + off);
         acc[t] = mfma32(a2, z0[st], acc[t]);  // smaller part products first
         acc[t] = mfma32(a1, z1[st], acc[t]);
         acc[t] = mfma32(a0, z2[st], acc[t]);
@@ -438,17 +456,22 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd_split(int64_t np, const i
         acc[t] = mfma32(a0, z1[st], acc[t]);
         acc[t] = mfma32(a0, z0[st], acc[t]);
       }
-    store_panel3(pr, tid, sS[buf ^ 1]);  // unconditionally, as in the other forms
-    const int64_t p = p0 + wave * 16 + r;
-    if (p < np) {
+    // the wave's tile is its own: LDS operations of one wave complete in order, and the
+    // empty asm statements keep the compiler from moving the tile's reads across its writes
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int col = n0 + 16 * q + 4 * t;
-        if (col < P) *reinterpret_cast<floatx4*>(&w[p * P + col]) = acc[t];  // P % 4 == 0
-      }
+    for (int t = 0; t < 4; ++t) *reinterpret_cast<floatx4*>(&Z[r * ZP + 16 * q + 4 * t]) = acc[t];
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int rr = 4 * k + (lane >> 4);
+      const floatx4 v = *reinterpret_cast<const floatx4*>(&Z[rr * ZP + cc]);
+      const int64_t p = p0 + wave * 16 + rr;
+      if (p < np && n0 + cc < P) *reinterpret_cast<floatx4*>(&w[p * P + n0 + cc]) = v;  // P % 4 == 0
     }
+    __asm__ volatile("" ::: "memory");
+    __syncthreads();  // every wave is done with this panel
+    store_panel3(pr, tid, sS);  // unconditionally, as in the other forms
     __syncthreads();
-    buf ^= 1;
   }
 }
 
@@ -551,7 +574,9 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
   stage_common(np, p0, pe1, rho, Wa, Wb, sWa, BF16 ? nullptr : sWb, sRho);
-  __shared__ __attribute__((aligned(16))) __bf16 sWbT[BF16 ? HID * BP : 8];
+  // bfloat16 copies of Wb: the transposed one (hidden-layer recompute) lives in the second
+  // panel buffer until the panel loop first fills it, which keeps the block at 48 KB of LDS
+  __bf16* sWbT = reinterpret_cast<__bf16*>(sB[1]);
   __shared__ __attribute__((aligned(16))) __bf16 sWbN[BF16 ? HID * BP : 8];
   if (BF16) stage_wb_bf16(Wb, sWbT, sWbN);
   const int r = lane & 15, q = lane >> 4;
@@ -559,9 +584,10 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   const DwRows<BF16> rows(np, p0 + wave * 16, pe2, P, lane);
   const int npan = (P + HID - 1) / HID;
   PanelRegs<BF16> wr;
-  // dE/dw panels in flight: a ring of RING register sets (RING - 1 panels ahead); the
-  // bfloat16 operands are small and the matrix cores fast, so that form looks further ahead
-  constexpr int RING = BF16 ? 6 : 3;
+  // dE/dw panels in flight: a ring of RING register sets (RING - 1 panels ahead).  A deeper
+  // ring in the bfloat16 form costs its third wave per SIMD (164 registers with 3), and the
+  // extra wave hides more than the extra panels did.
+  constexpr int RING = 3;
   DwRegs<BF16> ring[RING];
   fetch_panel<BF16>(Wcp, 0, npan, tid, wr);
   static_for<RING - 1>([&](auto J) {
@@ -576,8 +602,12 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   store_panel<BF16>(wr, tid, reinterpret_cast<WPan<BF16>*>(sB[0]), BF16 ? BP : TP);
   __syncthreads();
   zero4(a2);
-  if (BF16) panel_bf16(Z, sWbT, a2, lane);
-  else panel_kn(Z, sWb, a2, lane);
+  if (BF16) {
+    panel_bf16(Z, sWbT, a2, lane);
+    __syncthreads();  // every wave is done with sWbT before the first panel overwrites it
+  } else {
+    panel_kn(Z, sWb, a2, lane);
+  }
   // dz2 = (dw[e1] + dw[e2]) Wc^T, contraction over the P radial weights in 64-wide panels
   floatx4 g[4];
   zero4(g);
