@@ -691,6 +691,131 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   }
 }
 
+// ------------------------------------------------------------------ backward, split form
+// The FP32 form's adjoint with dz2 = dw Wc^T in three-part bfloat16 arithmetic (the split
+// of the forward above): the pair sums of dE/dw are split as they leave the wave's LDS
+// tile, Wc arrives pre-split as [part][j][c] panels, and the six part products with
+// i + j <= 2 accumulate in float32.  Float32 matrix cores run at a sixteenth of the
+// bfloat16 rate, so six bfloat16 products cost 0.4 of the eight float32 ones they replace.
+// One LDS stage for the split panels (two barriers per panel); the hidden layers stay
+// float32 as in the plain form.
+__global__ __launch_bounds__(256) void k_mlp_fused_bwd_split(int64_t np, const int* __restrict__ pe1,
+                                                             const int* __restrict__ pe2,
+                                                             const float* __restrict__ rho,
+                                                             const float* __restrict__ Wa,
+                                                             const float* __restrict__ Wb,
+                                                             const bf16_t* __restrict__ Wc3, int P,
+                                                             float c, const float* __restrict__ dw,
+                                                             float* __restrict__ drho,
+                                                             int accumulate) {
+  __shared__ float sWa[NBAS * HID];
+  __shared__ float sWb[HID * WP];
+  __shared__ float sRho[EB * (NBAS + 1)];
+  __shared__ float sZ[4][16 * ZP];
+  __shared__ __attribute__((aligned(16))) __bf16 sS[3 * HID * BP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * EB;
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
+  const int r = lane & 15, q = lane >> 4;
+  // dE/dw is pair-major: rows 2p (first edge) and 2p + 1 (its reverse, when present)
+  const DwRows<false> rows(np, p0 + wave * 16, pe2, P, lane);
+  const int npan = (P + HID - 1) / HID;
+  Panel3Regs pr;
+  constexpr int RING = 3;  // dE/dw panels in flight: RING - 1 ahead
+  DwRegs<false> ring[RING];
+  fetch_panel3(Wc3, 0, npan, tid, pr);
+  static_for<RING - 1>([&](auto J) {
+    fetch_dw<false>(dw, rows, P, decltype(J)::value * HID, lane, ring[decltype(J)::value]);
+  });
+  __syncthreads();
+  float* Z = sZ[wave];
+  // recompute a1 and a2 (accumulator layout)
+  floatx4 a1[4], a2[4];
+  first_layer(sRho + wave * 16 * (NBAS + 1), sWa, a1, lane);
+  acc_to_panel(a1, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  store_panel3(pr, tid, sS);
+  __syncthreads();
+  zero4(a2);
+  panel_kn(Z, sWb, a2, lane);
+  // dz2 = (dw[e1] + dw[e2]) Wc^T over 64-wide k panels; g[t][rr] = dz2[pair 4 q + rr][16 t + r]
+  floatx4 g[4];
+  zero4(g);
+  auto step = [&](int jj, auto SLOT) {
+    constexpr int rc = decltype(SLOT)::value, rn = (rc + RING - 1) % RING;
+    const int k0 = jj * HID;
+    fetch_panel3(Wc3, jj + 1, npan, tid, pr);
+    fetch_dw<false>(dw, rows, P, k0 + (RING - 1) * HID, lane, ring[rn]);
+    if (jj < npan) {
+      // the wave's own tile, written and then read: LDS operations of one wave complete in
+      // order, and the empty asm statements keep the compiler's order
+      __asm__ volatile("" ::: "memory");
+      stage_dw<false>(ring[rc], rows, P, k0, lane, Z);
+      __asm__ volatile("" ::: "memory");
+#pragma unroll
+      for (int st = 0; st < HID / 32; ++st) {
+        bf16x8 z0, z1, z2;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 h0, h1, h2;
+          split3(Z[r * ZP + 32 * st + 8 * q + e], h0, h1, h2);
+          z0[e] = h0;
+          z1[e] = h1;
+          z2[e] = h2;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int off = (16 * t + r) * BP + 32 * st + 8 * q;
+          const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(sS + off);
+          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(sS + HID * BP + off);
+          const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(sS + 2 * HID * BP + off);
+          g[t] = mfma32(z2, b0, g[t]);  // smaller part products first
+          g[t] = mfma32(z1, b1, g[t]);
+          g[t] = mfma32(z0, b2, g[t]);
+          g[t] = mfma32(z1, b0, g[t]);
+          g[t] = mfma32(z0, b1, g[t]);
+          g[t] = mfma32(z0, b0, g[t]);
+        }
+      }
+      __asm__ volatile("" ::: "memory");
+    }
+    __syncthreads();  // every wave is done with this panel
+    store_panel3(pr, tid, sS);  // unconditionally (a panel past the last is never read)
+    __syncthreads();
+  };
+  for (int j = 0; j < npan; j += RING) {
+    static_for<RING>([&](auto J) { step(j + decltype(J)::value, J); });
+  }
+  // da2 = dz2 * phi'(a2) -> operand panel;  dz1 = da2 Wb^T
+  acc_to_panel(g, Z, lane, [&](float v, int t, int rr) { return v * dphi(a2[t][rr], c); });
+  __syncthreads();
+  floatx4 d1[4];
+  zero4(d1);
+  panel_kn_T(Z, sWb, d1, lane);
+  __syncthreads();
+  // da1 = dz1 * phi'(a1) -> operand panel;  drho = da1 Wa^T (8 columns, padded to 16)
+  acc_to_panel(d1, Z, lane, [&](float v, int t, int rr) { return v * dphi(a1[t][rr], c); });
+  __syncthreads();
+  floatx4 dr = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < HID / 4; ++s) {
+    const float a = Z[r * ZP + 4 * s + q];
+    const float b = (r < NBAS) ? sWa[r * HID + 4 * s + q] : 0.f;
+    dr = mfma4(a, b, dr);
+  }
+  const int col = lane & 15, rq = (lane >> 4) * 4;
+  if (col < NBAS) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t p = p0 + wave * 16 + rq + rr;
+      if (p < np) {
+        const int64_t o = (int64_t)pe1[p] * NBAS + col;
+        const float v = dr[rr];
+        drho[o] = accumulate ? drho[o] + v : v;
+      }
+    }
+  }
+}
+
 template <typename WS>
 void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
                           const float* Wb, const WS* Wcp, int P, float c, WS* w, hipStream_t s) {
@@ -722,6 +847,15 @@ void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const floa
   constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
   k_mlp_fused_bwd<BF16><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wcp, P, c, dw, drho,
                                              accumulate ? 1 : 0);
+}
+
+void launch_mlp_fused_bwd_split(int64_t np, const int* pe1, const int* pe2, const float* rho,
+                                const float* Wa, const float* Wb, const bf16_t* Wc3, int P, float c,
+                                const float* dw, float* drho, bool accumulate, hipStream_t s) {
+  if (np <= 0) return;
+  const unsigned grid = (unsigned)((np + EB - 1) / EB);
+  k_mlp_fused_bwd_split<<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wc3, P, c, dw, drho,
+                                              accumulate ? 1 : 0);
 }
 
 template void launch_mlp_fused_fwd<float>(int64_t, const int*, const float*, const float*,

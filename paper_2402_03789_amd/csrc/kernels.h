@@ -191,6 +191,11 @@ template <typename WS>
 void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
                           const float* Wa, const float* Wb, const WS* Wcp, int P, float c,
                           const WS* dw, float* drho, bool accumulate, hipStream_t s);
+// FP32 form of the adjoint with dz2 = dw Wc^T in three-part bfloat16 arithmetic: Wc3
+// holds per panel the three parts of every weight, each [j][c] (the forward's are [c][j]).
+void launch_mlp_fused_bwd_split(int64_t np, const int* pe1, const int* pe2, const float* rho,
+                                const float* Wa, const float* Wb, const bf16_t* Wc3, int P, float c,
+                                const float* dw, float* drho, bool accumulate, hipStream_t s);
 
 // ---------------------------------------------------------------- tensor product
 struct TPTask {  // one wave's work: one degree l1, 64 lanes over channels x edges

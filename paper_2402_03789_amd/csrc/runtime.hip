@@ -303,7 +303,7 @@ struct sn_ctx {
   // per block: the radial MLP's output weights as 64-column panels (wc_panels)
   void* d_wpan = nullptr;
   std::vector<const float*> wc_pan;
-  std::vector<const bf16_t*> wc_pan16, wc_panT16, wc_panT3;
+  std::vector<const bf16_t*> wc_pan16, wc_panT16, wc_panT3, wc_pan3;
   size_t weight_bytes = 0;
   double* d_v = nullptr;
   double* d_shift = nullptr;
@@ -515,7 +515,8 @@ const float* W<float>(const sn_ctx* c, int64_t off) {
 
 // The radial MLP's output weights Wc [hidden x P] of every block, rearranged for the fused
 // matrix-core kernels into 64-column panels of 64 x 64 contiguous values, zero past column
-// P: float32 [panel][j][c], bfloat16 [panel][j][c], and bfloat16 [panel][c][j].
+// P: float32 [panel][j][c], bfloat16 [panel][j][c], bfloat16 [panel][c][j], and the three
+// bfloat16 parts of every value (FP32 form) as [panel][part][c][j] and [panel][part][j][c].
 void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
   const sn_model* m = c->m;
   constexpr int H = 64, K = H * H;  // the model's hidden width (checked at load)
@@ -526,7 +527,7 @@ void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
     total += (size_t)((L.P + H - 1) / H) * K;
   }
   std::vector<float> f(total, 0.f);
-  std::vector<bf16_t> h(total), ht(total), h3(3 * total);
+  std::vector<bf16_t> h(total), ht(total), h3(3 * total), h3n(3 * total);
   auto widen = [](bf16_t b) { return __builtin_bit_cast(float, (uint32_t)b.u << 16); };
   for (size_t t = 0; t < m->layers.size(); ++t) {
     const LayerDesc& L = m->layers[t];
@@ -549,24 +550,31 @@ void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
           h3[b3] = x0;
           h3[b3 + K] = x1;
           h3[b3 + 2 * K] = x2;
+          const size_t b3n = 3 * off[t] + (size_t)pan * 3 * K + j * H + q;
+          h3n[b3n] = x0;
+          h3n[b3n + K] = x1;
+          h3n[b3n + 2 * K] = x2;
         }
   }
-  const size_t bytes = total * (sizeof(float) + 5 * sizeof(bf16_t));
+  const size_t bytes = total * (sizeof(float) + 8 * sizeof(bf16_t));
   c->d_wpan = c->weight_alloc(bytes);
   char* d = static_cast<char*>(c->d_wpan);
   float* df = reinterpret_cast<float*>(d);
   bf16_t* dh = reinterpret_cast<bf16_t*>(d + total * sizeof(float));
   bf16_t* dht = dh + total;
   bf16_t* dh3 = dht + total;
+  bf16_t* dh3n = dh3 + 3 * total;
   HIPCHK(hipMemcpy(df, f.data(), total * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dh, h.data(), total * sizeof(bf16_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dht, ht.data(), total * sizeof(bf16_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dh3, h3.data(), 3 * total * sizeof(bf16_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dh3n, h3n.data(), 3 * total * sizeof(bf16_t), hipMemcpyHostToDevice));
   for (size_t t = 0; t < m->layers.size(); ++t) {
     c->wc_pan.push_back(df + off[t]);
     c->wc_pan16.push_back(dh + off[t]);
     c->wc_panT16.push_back(dht + off[t]);
     c->wc_panT3.push_back(dh3 + 3 * off[t]);
+    c->wc_pan3.push_back(dh3n + 3 * off[t]);
   }
   c->weight_bytes += bytes;
 }
@@ -1027,8 +1035,15 @@ struct Pipe {
     const int* pe2 = c->get<int>("pair_e2", c->E);
     if constexpr (std::is_same<T, float>::value) {
       (void)dz2;
-      launch_mlp_fused_bwd<S>(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
-                              wc_panel<S>(L, false), L.P, (float)m->act, dw, drho, true, s);
+      if constexpr (std::is_same<S, float>::value)  // FP32 form: split-bfloat16 dw Wc^T
+        launch_mlp_fused_bwd_split(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]),
+                                   W<float>(c, L.w_mlp[1]),
+                                   c->wc_pan3[(size_t)(&L - m->layers.data())], L.P,
+                                   (float)m->act, dw, drho, true, s);
+      else
+        launch_mlp_fused_bwd<S>(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]),
+                                W<float>(c, L.w_mlp[1]), wc_panel<S>(L, false), L.P,
+                                (float)m->act, dw, drho, true, s);
     } else {
       T* dws = c->get<T>("dw_pair", NPr * L.P);
       launch_pair_sum<T>(NPr, pe1, pe2, dw, L.P, dws, s);
