@@ -51,7 +51,6 @@ constexpr int HID = 64;  // hidden width
 constexpr int NBAS = 8;  // radial features
 constexpr int ZP = 68;   // operand panel stride (floats)
 constexpr int WP = 80;   // k-major weight panel stride (floats)
-constexpr int TP = 68;   // n-major weight panel stride (floats)
 constexpr int BP = 72;   // n-major bf16 panel stride (16-byte aligned rows)
 
 __device__ inline float phi(float z, float c) { return c * z / (1.f + __expf(-z)); }
@@ -158,38 +157,30 @@ __device__ inline void stage_common(int64_t np, int64_t p0, const int* __restric
 }
 
 // Output-layer weights Wc [64 x P] arrive rearranged into 64-column panels, each a
-// contiguous 64 x 64 block (zero past column P): [panel][j][c] (hidden row j, column c) in
-// float32 or bfloat16, or transposed per panel, [panel][c][j], in bfloat16.  A panel is
-// staged into LDS through registers: each of the 256 threads loads 16 bytes per step
-// (four steps in float32, two in bfloat16) while the current panel is being multiplied,
-// and stores them as 16-byte segments of the LDS panel's rows.  Loads past the last panel
-// read the last one again (valid memory; the copy is never used).
-template <bool BF16>
-using WPan = typename std::conditional<BF16, bf16_t, float>::type;
+// contiguous 64 x 64 block of bfloat16 (zero past column P): [panel][j][c] (hidden row j,
+// column c) for the adjoint, transposed per panel, [panel][c][j], for the forward (the
+// FP32 form's three-part copies are described with its kernels).  A panel is staged into
+// LDS through registers: each of the 256 threads loads 16 bytes per step (two steps) while
+// the current panel is being multiplied, and stores them as 16-byte segments of the LDS
+// panel's rows (stride BP).  Loads past the last panel read the last one again (valid
+// memory; the copy is never used).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-template <bool BF16>
 struct PanelRegs {
-  u32x4 v[BF16 ? 2 : 4];
+  u32x4 v[2];
 };
 constexpr int kPanel = HID * HID;  // elements per panel
 
-template <bool BF16>
-__device__ inline void fetch_panel(const WPan<BF16>* __restrict__ pan, int panel, int npan, int tid,
-                                   PanelRegs<BF16>& r) {
-  const WPan<BF16>* src = pan + (int64_t)min(panel, npan - 1) * kPanel;
-  constexpr int PER = BF16 ? 8 : 4;  // elements per 16 bytes
+__device__ inline void fetch_panel(const bf16_t* __restrict__ pan, int panel, int npan, int tid,
+                                   PanelRegs& r) {
+  const bf16_t* src = pan + (int64_t)min(panel, npan - 1) * kPanel;
 #pragma unroll
-  for (int j = 0; j < (BF16 ? 2 : 4); ++j)
-    r.v[j] = *reinterpret_cast<const u32x4*>(src + (tid + 256 * j) * PER);
+  for (int j = 0; j < 2; ++j) r.v[j] = *reinterpret_cast<const u32x4*>(src + (tid + 256 * j) * 8);
 }
-// store into an LDS panel of row stride ld elements (a multiple of 16 bytes)
-template <bool BF16>
-__device__ inline void store_panel(const PanelRegs<BF16>& r, int tid, WPan<BF16>* lds, int ld) {
-  constexpr int PER = BF16 ? 8 : 4;
+__device__ inline void store_panel(const PanelRegs& r, int tid, void* lds) {
 #pragma unroll
-  for (int j = 0; j < (BF16 ? 2 : 4); ++j) {
-    const int i = (tid + 256 * j) * PER;
-    *reinterpret_cast<u32x4*>(lds + (i / HID) * ld + i % HID) = r.v[j];
+  for (int j = 0; j < 2; ++j) {
+    const int i = (tid + 256 * j) * 8;
+    *reinterpret_cast<u32x4*>(reinterpret_cast<__bf16*>(lds) + (i / HID) * BP + i % HID) = r.v[j];
   }
 }
 
@@ -197,20 +188,19 @@ __device__ inline void store_panel(const PanelRegs<BF16>& r, int tid, WPan<BF16>
 template <bool BF16>
 using WStore = typename std::conditional<BF16, bf16_t, float>::type;
 
-template <bool BF16>
+// BF16 form (the FP32 form's output layer is the split kernel below)
 __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __restrict__ pe1,
                                                         const float* __restrict__ rho,
                                                         const float* __restrict__ Wa,
                                                         const float* __restrict__ Wb,
-                                                        const WPan<BF16>* __restrict__ Wcp, int P,
-                                                        float c, WStore<BF16>* __restrict__ w) {
+                                                        const bf16_t* __restrict__ Wcp, int P,
+                                                        float c, bf16_t* __restrict__ w) {
   __shared__ float sWa[NBAS * HID];
   __shared__ float sRho[EB * (NBAS + 1)];
   __shared__ float sZ[4][16 * ZP];
-  // two Wc panel stages (float32 [k][n] of stride WP, or bfloat16 of stride BP); the second
-  // one holds Wb for the hidden layers first (float32, or bfloat16 B^T rows).  Sized for
-  // the form, the bfloat16 kernel's LDS (about 40 KB) admits four blocks per CU.
-  __shared__ __attribute__((aligned(16))) float sW[2][BF16 ? HID * BP / 2 : HID * WP];
+  // two bfloat16 Wc panel stages of row stride BP; the second one holds Wb (bfloat16 B^T
+  // rows) for the hidden layers first.  About 40 KB of LDS: four blocks per CU.
+  __shared__ __attribute__((aligned(16))) float sW[2][HID * BP / 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
   // output panels of this block: all of them, or (few pairs) one of gridDim.y panel groups;
@@ -219,124 +209,94 @@ __global__ __launch_bounds__(256) void k_mlp_fused_fwd(int64_t np, const int* __
   const int ppg = (npan + gridDim.y - 1) / gridDim.y;
   const int pan0 = blockIdx.y * ppg, pan1 = min(npan, pan0 + ppg);
   if (pan0 >= pan1) return;
-  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, BF16 ? nullptr : sW[1], sRho);
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, nullptr, sRho);
   __bf16* sWbT = reinterpret_cast<__bf16*>(sW[1]);
-  if (BF16) stage_wb_bf16(Wb, sWbT, nullptr);
-  PanelRegs<BF16> pr;
-  fetch_panel<BF16>(Wcp, pan0, npan, tid, pr);
+  stage_wb_bf16(Wb, sWbT, nullptr);
+  PanelRegs pr;
+  fetch_panel(Wcp, pan0, npan, tid, pr);
   __syncthreads();
   float* Z = sZ[wave];
   floatx4 acc[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, acc, lane);
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
-  store_panel<BF16>(pr, tid, reinterpret_cast<WPan<BF16>*>(sW[0]), BF16 ? BP : WP);
+  store_panel(pr, tid, sW[0]);
   __syncthreads();
   zero4(acc);
-  if (BF16) panel_bf16(Z, sWbT, acc, lane);
-  else panel_kn(Z, sW[1], acc, lane);
+  panel_bf16(Z, sWbT, acc, lane);
   __syncthreads();
   acc_to_panel(acc, Z, lane, [&](float v, int, int) { return phi(v, c); });
   __syncthreads();
   // z2 operand fragments, kept in registers for every output panel
   const int r = lane & 15, q = lane >> 4;
-  float za[HID / 4];
   bf16x8 zh[HID / 32];
-  if (BF16) {
 #pragma unroll
-    for (int s = 0; s < HID / 32; ++s)
+  for (int s = 0; s < HID / 32; ++s)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) zh[s][e] = __float2bfloat16(Z[r * ZP + 32 * s + 8 * q + e]);
-  } else {
-#pragma unroll
-    for (int s = 0; s < HID / 4; ++s) za[s] = Z[r * ZP + 4 * s + q];
-  }
+    for (int e = 0; e < 8; ++e) zh[s][e] = __float2bfloat16(Z[r * ZP + 32 * s + 8 * q + e]);
   // Wc panels in flight: a ring of RING register sets, RING - 1 panels ahead of the one
   // being multiplied (a panel's eight MFMAs per wave take far less than the L2 round trip
   // of the next panel's loads).  Panel pan0 + k travels in ring slot k % RING; the loop is
   // unrolled by RING so the slots are fixed registers.
   constexpr int RING = 3;
-  PanelRegs<BF16> ring[RING];
+  PanelRegs ring[RING];
   const int count = pan1 - pan0;
   static_for<RING - 1>([&](auto J) {
     constexpr int k = decltype(J)::value + 1;
-    fetch_panel<BF16>(Wcp, pan0 + k, npan, tid, ring[k % RING]);
+    fetch_panel(Wcp, pan0 + k, npan, tid, ring[k % RING]);
   });
   int buf = 0;
   auto step = [&](int jj, auto SLOT) {
     constexpr int sc = decltype(SLOT)::value, sn = (sc + 1) % RING;
     // slot sc held panel jj, staged into LDS by the previous step: reuse it for panel
     // jj + RING (loads past the last panel read the last one again and are never used)
-    fetch_panel<BF16>(Wcp, pan0 + jj + RING, npan, tid, ring[sc]);
+    fetch_panel(Wcp, pan0 + jj + RING, npan, tid, ring[sc]);
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
-    const float* sf = sW[buf];
     const __bf16* sh = reinterpret_cast<const __bf16*>(sW[buf]);
     const int n0 = (pan0 + jj) * HID;
-    // the transposed product w^T = Wc^T z2^T: lane (r, q) receives weights of pair r only.
-    // float32: row i of tile t is panel column 16 t + i, so acc[t] = w[pair r][n0 + 16 t +
-    // 4 q + 0..3] (the A rows read from LDS stay bank-conflict free); bfloat16: row i of
-    // tile t is column 16 (i / 4) + 4 t + i % 4, so acc[0..3][0..3] = w[pair r][n0 + 16 q +
-    // 0..15], sixteen consecutive values for two 16-byte stores
+    // the transposed product w^T = Wc^T z2^T: lane (r, q) receives weights of pair r only;
+    // row i of tile t is panel column 16 (i / 4) + 4 t + i % 4, so acc[0..3][0..3] =
+    // w[pair r][n0 + 16 q + 0..15]
     zero4(acc);
     if (jj < count) {
-      if (BF16) {
-        const int ca = 16 * (r >> 2) + (r & 3);
+      const int ca = 16 * (r >> 2) + (r & 3);
 #pragma unroll
-        for (int s = 0; s < HID / 32; ++s)
+      for (int s = 0; s < HID / 32; ++s)
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const bf16x8 a =
-                *reinterpret_cast<const bf16x8*>(&sh[(ca + 4 * t) * BP + 32 * s + 8 * q]);
-            acc[t] = mfma32(a, zh[s], acc[t]);
-          }
-      } else {
-#pragma unroll
-        for (int s = 0; s < HID / 4; ++s)
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            acc[t] = mfma4(sf[(4 * s + q) * WP + 16 * t + r], za[s], acc[t]);
-      }
+        for (int t = 0; t < 4; ++t) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sh[(ca + 4 * t) * BP + 32 * s + 8 * q]);
+          acc[t] = mfma32(a, zh[s], acc[t]);
+        }
     }
     // staged unconditionally (a panel past the last is never read): a conditional store
     // would let the compiler sink the panel loads into the branch, after the MFMAs
-    store_panel<BF16>(ring[sn], tid, reinterpret_cast<WPan<BF16>*>(sW[buf ^ 1]), BF16 ? BP : WP);
-    if constexpr (BF16) {
-      // through the wave's LDS tile (free once z2 is in registers): a 16-byte store then
-      // writes eight whole 128-byte row segments instead of pieces of sixteen rows.  LDS
-      // operations of one wave complete in order; the empty asm statements keep the
-      // compiler from moving the tile's reads across its writes.
-      if (jj < count) {
-        __bf16* Zb = reinterpret_cast<__bf16*>(Z);  // rows of 2 ZP bfloat16 values
+    store_panel(ring[sn], tid, sW[buf ^ 1]);
+    // out through the wave's LDS tile (free once z2 is in registers): a 16-byte store then
+    // writes eight whole 128-byte row segments instead of pieces of sixteen rows.  LDS
+    // operations of one wave complete in order; the empty asm statements keep the compiler
+    // from moving the tile's reads across its writes.
+    if (jj < count) {
+      __bf16* Zb = reinterpret_cast<__bf16*>(Z);  // rows of 2 ZP bfloat16 values
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          u32x4 v;
+      for (int h = 0; h < 2; ++h) {
+        u32x4 v;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int t = 2 * h + (e >> 1), rr = 2 * (e & 1);
-            v[e] = (uint32_t)sstore<bf16_t>(acc[t][rr]).u |
-                   ((uint32_t)sstore<bf16_t>(acc[t][rr + 1]).u << 16);
-          }
-          *reinterpret_cast<u32x4*>(Zb + r * 2 * ZP + 16 * q + 8 * h) = v;
+        for (int e = 0; e < 4; ++e) {
+          const int t = 2 * h + (e >> 1), rr = 2 * (e & 1);
+          v[e] = (uint32_t)sstore<bf16_t>(acc[t][rr]).u |
+                 ((uint32_t)sstore<bf16_t>(acc[t][rr + 1]).u << 16);
         }
-        __asm__ volatile("" ::: "memory");
-        const int cb = 8 * (lane & 7);
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const int rr = 8 * k + (lane >> 3);
-          const u32x4 v = *reinterpret_cast<const u32x4*>(Zb + rr * 2 * ZP + cb);
-          const int64_t p = p0 + wave * 16 + rr;
-          if (p < np && n0 + cb < P) *reinterpret_cast<u32x4*>(&w[p * P + n0 + cb]) = v;  // P % 8 == 0
-        }
-        __asm__ volatile("" ::: "memory");
+        *reinterpret_cast<u32x4*>(Zb + r * 2 * ZP + 16 * q + 8 * h) = v;
       }
-    } else {
-      const int64_t p = p0 + wave * 16 + r;
-      if (jj < count && p < np) {
+      __asm__ volatile("" ::: "memory");
+      const int cb = 8 * (lane & 7);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int col = n0 + 16 * t + 4 * q;
-          if (col < P) *reinterpret_cast<floatx4*>(&w[p * P + col]) = acc[t];  // P % 4 == 0
-        }
+      for (int k = 0; k < 2; ++k) {
+        const int rr = 8 * k + (lane >> 3);
+        const u32x4 v = *reinterpret_cast<const u32x4*>(Zb + rr * 2 * ZP + cb);
+        const int64_t p = p0 + wave * 16 + rr;
+        if (p < np && n0 + cb < P) *reinterpret_cast<u32x4*>(&w[p * P + n0 + cb]) = v;  // P % 8 == 0
       }
+      __asm__ volatile("" ::: "memory");
     }
     __syncthreads();
     buf ^= 1;
@@ -556,42 +516,41 @@ __device__ inline void stage_dw(const DwRegs<BF16>& d, const DwRows<BF16>& rows,
 }
 
 // ------------------------------------------------------------------ backward
-template <bool BF16>
+// BF16 form (the FP32 form's is the split kernel below)
 __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __restrict__ pe1,
                                                         const int* __restrict__ pe2,
                                                         const float* __restrict__ rho,
                                                         const float* __restrict__ Wa,
                                                         const float* __restrict__ Wb,
-                                                        const WPan<BF16>* __restrict__ Wcp, int P,
-                                                        float c, const WStore<BF16>* __restrict__ dw,
+                                                        const bf16_t* __restrict__ Wcp, int P,
+                                                        float c, const bf16_t* __restrict__ dw,
                                                         float* __restrict__ drho, int accumulate) {
   __shared__ float sWa[NBAS * HID];
-  __shared__ float sWb[BF16 ? 4 : HID * WP];  // float32 form only (bfloat16 copies below)
   __shared__ float sRho[EB * (NBAS + 1)];
   __shared__ float sZ[4][16 * ZP];
-  // Wc[j][k-panel]: float32 rows of stride TP, or bfloat16 rows of stride BP
-  __shared__ __attribute__((aligned(16))) float sB[2][BF16 ? HID * BP / 2 : HID * TP];
+  // Wc[j][k-panel]: bfloat16 rows of stride BP
+  __shared__ __attribute__((aligned(16))) float sB[2][HID * BP / 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
-  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, BF16 ? nullptr : sWb, sRho);
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, nullptr, sRho);
   // bfloat16 copies of Wb: the transposed one (hidden-layer recompute) lives in the second
   // panel buffer until the panel loop first fills it, which keeps the block at 48 KB of LDS
   __bf16* sWbT = reinterpret_cast<__bf16*>(sB[1]);
-  __shared__ __attribute__((aligned(16))) __bf16 sWbN[BF16 ? HID * BP : 8];
-  if (BF16) stage_wb_bf16(Wb, sWbT, sWbN);
+  __shared__ __attribute__((aligned(16))) __bf16 sWbN[HID * BP];
+  stage_wb_bf16(Wb, sWbT, sWbN);
   const int r = lane & 15, q = lane >> 4;
   // dE/dw is pair-major: rows 2p (first edge) and 2p + 1 (its reverse, when present)
-  const DwRows<BF16> rows(np, p0 + wave * 16, pe2, P, lane);
+  const DwRows<true> rows(np, p0 + wave * 16, pe2, P, lane);
   const int npan = (P + HID - 1) / HID;
-  PanelRegs<BF16> wr;
+  PanelRegs wr;
   // dE/dw panels in flight: a ring of RING register sets (RING - 1 panels ahead).  A deeper
-  // ring in the bfloat16 form costs its third wave per SIMD (164 registers with 3), and the
-  // extra wave hides more than the extra panels did.
+  // ring costs the third wave per SIMD (164 registers with 3), and the extra wave hides
+  // more than the extra panels did.
   constexpr int RING = 3;
-  DwRegs<BF16> ring[RING];
-  fetch_panel<BF16>(Wcp, 0, npan, tid, wr);
+  DwRegs<true> ring[RING];
+  fetch_panel(Wcp, 0, npan, tid, wr);
   static_for<RING - 1>([&](auto J) {
-    fetch_dw<BF16>(dw, rows, P, decltype(J)::value * HID, lane, ring[decltype(J)::value]);
+    fetch_dw<true>(dw, rows, P, decltype(J)::value * HID, lane, ring[decltype(J)::value]);
   });
   __syncthreads();
   float* Z = sZ[wave];
@@ -599,15 +558,11 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   floatx4 a1[4], a2[4];
   first_layer(sRho + wave * 16 * (NBAS + 1), sWa, a1, lane);
   acc_to_panel(a1, Z, lane, [&](float v, int, int) { return phi(v, c); });
-  store_panel<BF16>(wr, tid, reinterpret_cast<WPan<BF16>*>(sB[0]), BF16 ? BP : TP);
+  store_panel(wr, tid, sB[0]);
   __syncthreads();
   zero4(a2);
-  if (BF16) {
-    panel_bf16(Z, sWbT, a2, lane);
-    __syncthreads();  // every wave is done with sWbT before the first panel overwrites it
-  } else {
-    panel_kn(Z, sWb, a2, lane);
-  }
+  panel_bf16(Z, sWbT, a2, lane);
+  __syncthreads();  // every wave is done with sWbT before the first panel overwrites it
   // dz2 = (dw[e1] + dw[e2]) Wc^T, contraction over the P radial weights in 64-wide panels
   floatx4 g[4];
   zero4(g);
@@ -618,41 +573,26 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   int buf = 0;
   auto step = [&](int jj, auto SLOT) {
     constexpr int rc = decltype(SLOT)::value, rn = (rc + RING - 1) % RING;
-    const DwRegs<BF16>& cur = ring[rc];
+    const DwRegs<true>& cur = ring[rc];
     const int k0 = jj * HID;
-    fetch_panel<BF16>(Wcp, jj + 1, npan, tid, wr);
-    fetch_dw<BF16>(dw, rows, P, k0 + (RING - 1) * HID, lane, ring[rn]);
+    fetch_panel(Wcp, jj + 1, npan, tid, wr);
+    fetch_dw<true>(dw, rows, P, k0 + (RING - 1) * HID, lane, ring[rn]);
     if (jj < npan) {
       // the pairs' summed dE/dw through the wave's LDS tile into the operand layout
-      stage_dw<BF16>(cur, rows, P, k0, lane, Z);
-      if constexpr (BF16) {
-        const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
-        const __bf16* zh = reinterpret_cast<const __bf16*>(Z);
+      stage_dw<true>(cur, rows, P, k0, lane, Z);
+      const __bf16* sh = reinterpret_cast<const __bf16*>(sB[buf]);
+      const __bf16* zh = reinterpret_cast<const __bf16*>(Z);
 #pragma unroll
-        for (int s = 0; s < HID / 32; ++s) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&zh[r * BP + 32 * s + 8 * q]);
+      for (int s = 0; s < HID / 32; ++s) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&zh[r * BP + 32 * s + 8 * q]);
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
-            g[t] = mfma32(a, b, g[t]);
-          }
-        }
-      } else {
-        const float* sf = sB[buf];
-#pragma unroll
-        for (int u = 0; u < HID / 16; ++u) {
-          const floatx4 av = *reinterpret_cast<const floatx4*>(&Z[r * ZP + 16 * u + 4 * q]);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const floatx4 bv =
-                *reinterpret_cast<const floatx4*>(&sf[(t * 16 + r) * TP + 16 * u + 4 * q]);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) g[t] = mfma4(av[s], bv[s], g[t]);
-          }
+        for (int t = 0; t < 4; ++t) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sh[(t * 16 + r) * BP + 32 * s + 8 * q]);
+          g[t] = mfma32(a, b, g[t]);
         }
       }
     }
-    store_panel<BF16>(wr, tid, reinterpret_cast<WPan<BF16>*>(sB[buf ^ 1]), BF16 ? BP : TP);
+    store_panel(wr, tid, sB[buf ^ 1]);
     __syncthreads();
     buf ^= 1;
   };
@@ -664,8 +604,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
   __syncthreads();
   floatx4 d1[4];
   zero4(d1);
-  if (BF16) panel_bf16(Z, sWbN, d1, lane);
-  else panel_kn_T(Z, sWb, d1, lane);
+  panel_bf16(Z, sWbN, d1, lane);
   __syncthreads();
   // da1 = dz1 * phi'(a1) -> operand panel;  drho = da1 Wa^T (8 columns, padded to 16)
   acc_to_panel(d1, Z, lane, [&](float v, int t, int rr) { return v * dphi(a1[t][rr], c); });
@@ -697,9 +636,12 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd(int64_t np, const int* __
 // tile, Wc arrives pre-split as [part][j][c] panels, and the six part products with
 // i + j <= 2 accumulate in float32.  Float32 matrix cores run at a sixteenth of the
 // bfloat16 rate, so six bfloat16 products cost 0.4 of the eight float32 ones they replace.
-// One LDS stage for the split panels (two barriers per panel); the hidden layers stay
-// float32 as in the plain form.
-__global__ __launch_bounds__(256) void k_mlp_fused_bwd_split(int64_t np, const int* __restrict__ pe1,
+// One LDS stage for the split panels (two barriers per panel).  The hidden layers stay
+// float32 and run after the panel loop: their operands (Wb, Wa, rho) then take the stage's
+// memory and a1, a2 are recomputed there, so a block holds 44 KB of LDS and no hidden
+// activations during the loop: three blocks per CU, with the registers bounded to match
+// (168, no spills, two dE/dw panels ahead).
+__global__ __launch_bounds__(256, 3) void k_mlp_fused_bwd_split(int64_t np, const int* __restrict__ pe1,
                                                              const int* __restrict__ pe2,
                                                              const float* __restrict__ rho,
                                                              const float* __restrict__ Wa,
@@ -708,14 +650,13 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd_split(int64_t np, const i
                                                              float c, const float* __restrict__ dw,
                                                              float* __restrict__ drho,
                                                              int accumulate) {
-  __shared__ float sWa[NBAS * HID];
-  __shared__ float sWb[HID * WP];
-  __shared__ float sRho[EB * (NBAS + 1)];
+  constexpr int kStage = 3 * HID * BP;  // bfloat16 elements of a split-panel stage
   __shared__ float sZ[4][16 * ZP];
-  __shared__ __attribute__((aligned(16))) __bf16 sS[3 * HID * BP];
+  __shared__ __attribute__((aligned(16))) __bf16 sS[kStage];
+  static_assert(sizeof(float) * (HID * WP + NBAS * HID + EB * (NBAS + 1)) <= sizeof(__bf16) * kStage,
+                "the hidden layers' operands fit the stage");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t p0 = (int64_t)blockIdx.x * EB;
-  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
   const int r = lane & 15, q = lane >> 4;
   // dE/dw is pair-major: rows 2p (first edge) and 2p + 1 (its reverse, when present)
   const DwRows<false> rows(np, p0 + wave * 16, pe2, P, lane);
@@ -727,16 +668,9 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd_split(int64_t np, const i
   static_for<RING - 1>([&](auto J) {
     fetch_dw<false>(dw, rows, P, decltype(J)::value * HID, lane, ring[decltype(J)::value]);
   });
-  __syncthreads();
-  float* Z = sZ[wave];
-  // recompute a1 and a2 (accumulator layout)
-  floatx4 a1[4], a2[4];
-  first_layer(sRho + wave * 16 * (NBAS + 1), sWa, a1, lane);
-  acc_to_panel(a1, Z, lane, [&](float v, int, int) { return phi(v, c); });
   store_panel3(pr, tid, sS);
   __syncthreads();
-  zero4(a2);
-  panel_kn(Z, sWb, a2, lane);
+  float* Z = sZ[wave];
   // dz2 = (dw[e1] + dw[e2]) Wc^T over 64-wide k panels; g[t][rr] = dz2[pair 4 q + rr][16 t + r]
   floatx4 g[4];
   zero4(g);
@@ -785,6 +719,20 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd_split(int64_t np, const i
   for (int j = 0; j < npan; j += RING) {
     static_for<RING>([&](auto J) { step(j + decltype(J)::value, J); });
   }
+  // the hidden layers' operands into the stage (every wave is past the last panel)
+  float* sWb = reinterpret_cast<float*>(sS);
+  float* sWa = sWb + HID * WP;
+  float* sRho = sWa + NBAS * HID;
+  stage_common(np, p0, pe1, rho, Wa, Wb, sWa, sWb, sRho);
+  __syncthreads();
+  // recompute a1 and a2 (accumulator layout)
+  floatx4 a1[4], a2[4];
+  first_layer(sRho + wave * 16 * (NBAS + 1), sWa, a1, lane);
+  acc_to_panel(a1, Z, lane, [&](float v, int, int) { return phi(v, c); });
+  __syncthreads();
+  zero4(a2);
+  panel_kn(Z, sWb, a2, lane);
+  __syncthreads();
   // da2 = dz2 * phi'(a2) -> operand panel;  dz1 = da2 Wb^T
   acc_to_panel(g, Z, lane, [&](float v, int t, int rr) { return v * dphi(a2[t][rr], c); });
   __syncthreads();
@@ -816,16 +764,15 @@ __global__ __launch_bounds__(256) void k_mlp_fused_bwd_split(int64_t np, const i
   }
 }
 
-template <typename WS>
 void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
-                          const float* Wb, const WS* Wcp, int P, float c, WS* w, hipStream_t s) {
+                          const float* Wb, const bf16_t* Wcp, int P, float c, bf16_t* w,
+                          hipStream_t s) {
   if (np <= 0) return;
   const unsigned grid = (unsigned)((np + EB - 1) / EB);
   // few pairs: split the output panels over blocks until about 512 blocks run
   const int npan = (P + HID - 1) / HID;
   const unsigned groups = (unsigned)std::max(1, std::min<int>(npan, (int)((512 + grid - 1) / grid)));
-  constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
-  k_mlp_fused_fwd<BF16><<<dim3(grid, groups), 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wcp, P, c, w);
+  k_mlp_fused_fwd<<<dim3(grid, groups), 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wcp, P, c, w);
 }
 
 void launch_mlp_fused_fwd_split(int64_t np, const int* pe1, const float* rho, const float* Wa,
@@ -838,15 +785,13 @@ void launch_mlp_fused_fwd_split(int64_t np, const int* pe1, const float* rho, co
   k_mlp_fused_fwd_split<<<dim3(grid, groups), 256, 0, s>>>(np, pe1, rho, Wa, Wb, Wc3, P, c, w);
 }
 
-template <typename WS>
 void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
-                          const float* Wa, const float* Wb, const WS* Wcp, int P, float c,
-                          const WS* dw, float* drho, bool accumulate, hipStream_t s) {
+                          const float* Wa, const float* Wb, const bf16_t* Wcp, int P, float c,
+                          const bf16_t* dw, float* drho, bool accumulate, hipStream_t s) {
   if (np <= 0) return;
   const unsigned grid = (unsigned)((np + EB - 1) / EB);
-  constexpr bool BF16 = std::is_same<WS, bf16_t>::value;
-  k_mlp_fused_bwd<BF16><<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wcp, P, c, dw, drho,
-                                             accumulate ? 1 : 0);
+  k_mlp_fused_bwd<<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wcp, P, c, dw, drho,
+                                       accumulate ? 1 : 0);
 }
 
 void launch_mlp_fused_bwd_split(int64_t np, const int* pe1, const int* pe2, const float* rho,
@@ -857,18 +802,5 @@ void launch_mlp_fused_bwd_split(int64_t np, const int* pe1, const int* pe2, cons
   k_mlp_fused_bwd_split<<<grid, 256, 0, s>>>(np, pe1, pe2, rho, Wa, Wb, Wc3, P, c, dw, drho,
                                               accumulate ? 1 : 0);
 }
-
-template void launch_mlp_fused_fwd<float>(int64_t, const int*, const float*, const float*,
-                                          const float*, const float*, int, float, float*,
-                                          hipStream_t);
-template void launch_mlp_fused_fwd<bf16_t>(int64_t, const int*, const float*, const float*,
-                                           const float*, const bf16_t*, int, float, bf16_t*,
-                                           hipStream_t);
-template void launch_mlp_fused_bwd<float>(int64_t, const int*, const int*, const float*,
-                                          const float*, const float*, const float*, int, float,
-                                          const float*, float*, bool, hipStream_t);
-template void launch_mlp_fused_bwd<bf16_t>(int64_t, const int*, const int*, const float*,
-                                           const float*, const float*, const bf16_t*, int, float,
-                                           const bf16_t*, float*, bool, hipStream_t);
 
 }  // namespace sn

@@ -170,29 +170,26 @@ void launch_perturb(int64_t n, const double* pos, const double* v, const double*
 void launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);
 void launch_fill_f64(int64_t n, double v, double* y, hipStream_t s);
 
-// Fused radial MLP (hidden layers + output layer) on the matrix cores.  WS = float: float32
-// operands and storage; WS = bf16_t: bfloat16 operands for the two P-wide contractions and
-// bfloat16 storage of w and dE/dw.  Both run over undirected pairs: pair p takes rho of
-// edge pe1[p]; the backward sums the pair-major dE/dw rows 2p and 2p+1 (the latter absent
-// when pe2[p] < 0) and adds drho into row pe1[p].  P must be a multiple of 8.
-// The output weights Wc [64 x P] come as 64-column panels, each 64 x 64 contiguous and
-// zero past column P (see wc_panels): [panel][j][c] for the backward and for the float32
-// forward, [panel][c][j] for the bfloat16 forward.
-template <typename WS>
+// Fused radial MLP (hidden layers + output layer) on the matrix cores, over undirected
+// pairs: pair p takes rho of edge pe1[p]; the backward sums the pair-major dE/dw rows 2p
+// and 2p+1 (the latter absent when pe2[p] < 0) and adds drho into row pe1[p].  P must be
+// a multiple of 8.  The output weights Wc [64 x P] come as 64-column panels, each 64 x 64
+// contiguous and zero past column P (see wc_panels).
+// BF16 form: bfloat16 operands for the two P-wide contractions and bfloat16 storage of w
+// and dE/dw; Wcp is [panel][c][j] for the forward, [panel][j][c] for the backward.
 void launch_mlp_fused_fwd(int64_t np, const int* pe1, const float* rho, const float* Wa,
-                          const float* Wb, const WS* Wcp, int P, float c, WS* w, hipStream_t s);
-// FP32 form of the forward with the output layer in three-part bfloat16 arithmetic
-// (float32-level results): Wc3 holds per panel the three bfloat16 parts x0, x1, x2 of every
-// weight (x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1)), each [c][j].
+                          const float* Wb, const bf16_t* Wcp, int P, float c, bf16_t* w,
+                          hipStream_t s);
+void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
+                          const float* Wa, const float* Wb, const bf16_t* Wcp, int P, float c,
+                          const bf16_t* dw, float* drho, bool accumulate, hipStream_t s);
+// FP32 form: float32 storage, the P-wide contractions in three-part bfloat16 arithmetic
+// (float32-level results).  Wc3 holds per panel the three bfloat16 parts x0, x1, x2 of
+// every weight (x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1)): each [c][j] for
+// the forward, each [j][c] for the backward.
 void launch_mlp_fused_fwd_split(int64_t np, const int* pe1, const float* rho, const float* Wa,
                                 const float* Wb, const bf16_t* Wc3, int P, float c, float* w,
                                 hipStream_t s);
-template <typename WS>
-void launch_mlp_fused_bwd(int64_t np, const int* pe1, const int* pe2, const float* rho,
-                          const float* Wa, const float* Wb, const WS* Wcp, int P, float c,
-                          const WS* dw, float* drho, bool accumulate, hipStream_t s);
-// FP32 form of the adjoint with dz2 = dw Wc^T in three-part bfloat16 arithmetic: Wc3
-// holds per panel the three parts of every weight, each [j][c] (the forward's are [c][j]).
 void launch_mlp_fused_bwd_split(int64_t np, const int* pe1, const int* pe2, const float* rho,
                                 const float* Wa, const float* Wb, const bf16_t* Wc3, int P, float c,
                                 const float* dw, float* drho, bool accumulate, hipStream_t s);

@@ -302,7 +302,6 @@ struct sn_ctx {
   void* d_w32 = nullptr;
   // per block: the radial MLP's output weights as 64-column panels (wc_panels)
   void* d_wpan = nullptr;
-  std::vector<const float*> wc_pan;
   std::vector<const bf16_t*> wc_pan16, wc_panT16, wc_panT3, wc_pan3;
   size_t weight_bytes = 0;
   double* d_v = nullptr;
@@ -515,8 +514,8 @@ const float* W<float>(const sn_ctx* c, int64_t off) {
 
 // The radial MLP's output weights Wc [hidden x P] of every block, rearranged for the fused
 // matrix-core kernels into 64-column panels of 64 x 64 contiguous values, zero past column
-// P: float32 [panel][j][c], bfloat16 [panel][j][c], bfloat16 [panel][c][j], and the three
-// bfloat16 parts of every value (FP32 form) as [panel][part][c][j] and [panel][part][j][c].
+// P: bfloat16 [panel][j][c] and [panel][c][j] (BF16 form), and the three bfloat16 parts of
+// every value (FP32 form) as [panel][part][c][j] and [panel][part][j][c].
 void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
   const sn_model* m = c->m;
   constexpr int H = 64, K = H * H;  // the model's hidden width (checked at load)
@@ -526,7 +525,6 @@ void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
     off.push_back(total);
     total += (size_t)((L.P + H - 1) / H) * K;
   }
-  std::vector<float> f(total, 0.f);
   std::vector<bf16_t> h(total), ht(total), h3(3 * total), h3n(3 * total);
   auto widen = [](bf16_t b) { return __builtin_bit_cast(float, (uint32_t)b.u << 16); };
   for (size_t t = 0; t < m->layers.size(); ++t) {
@@ -538,10 +536,9 @@ void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
           const int col = pan * H + q;
           const float v = col < L.P ? wc[(size_t)j * L.P + col] : 0.f;
           const size_t b = off[t] + (size_t)pan * K;
-          f[b + j * H + q] = v;
           h[b + j * H + q] = sstore<bf16_t>(v);
           ht[b + q * H + j] = sstore<bf16_t>(v);
-          // three bfloat16 parts of v (each remainder is exact in float32), each [c][j]
+          // three bfloat16 parts of v (each remainder is exact in float32), [c][j] and [j][c]
           const bf16_t x0 = sstore<bf16_t>(v);
           const float r1 = v - widen(x0);
           const bf16_t x1 = sstore<bf16_t>(r1);
@@ -556,21 +553,17 @@ void wc_panels(sn_ctx* c, const std::vector<float>& w32) {
           h3n[b3n + 2 * K] = x2;
         }
   }
-  const size_t bytes = total * (sizeof(float) + 8 * sizeof(bf16_t));
+  const size_t bytes = total * 8 * sizeof(bf16_t);
   c->d_wpan = c->weight_alloc(bytes);
-  char* d = static_cast<char*>(c->d_wpan);
-  float* df = reinterpret_cast<float*>(d);
-  bf16_t* dh = reinterpret_cast<bf16_t*>(d + total * sizeof(float));
+  bf16_t* dh = static_cast<bf16_t*>(c->d_wpan);
   bf16_t* dht = dh + total;
   bf16_t* dh3 = dht + total;
   bf16_t* dh3n = dh3 + 3 * total;
-  HIPCHK(hipMemcpy(df, f.data(), total * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dh, h.data(), total * sizeof(bf16_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dht, ht.data(), total * sizeof(bf16_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dh3, h3.data(), 3 * total * sizeof(bf16_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dh3n, h3n.data(), 3 * total * sizeof(bf16_t), hipMemcpyHostToDevice));
   for (size_t t = 0; t < m->layers.size(); ++t) {
-    c->wc_pan.push_back(df + off[t]);
     c->wc_pan16.push_back(dh + off[t]);
     c->wc_panT16.push_back(dht + off[t]);
     c->wc_panT3.push_back(dh3 + 3 * off[t]);
@@ -998,13 +991,11 @@ struct Pipe {
       launch_gemm_group<TA, TB, TC, TACC>(n, d.data(), bt, false, s);
   }
 
-  // panels of block L's output weights for the fused kernels (the transposed bfloat16
-  // copy for the bfloat16 forward)
-  template <typename WS>
-  const WS* wc_panel(const LayerDesc& L, bool fwd) const {
+  // bfloat16 panels of block L's output weights for the fused kernels: [c][j] for the
+  // forward, [j][c] for the adjoint
+  const bf16_t* wc_panel(const LayerDesc& L, bool fwd) const {
     const size_t t = (size_t)(&L - m->layers.data());
-    if constexpr (std::is_same<WS, bf16_t>::value) return fwd ? c->wc_panT16[t] : c->wc_pan16[t];
-    else return c->wc_pan[t];
+    return fwd ? c->wc_panT16[t] : c->wc_pan16[t];
   }
 
   // radial MLP over undirected pairs: fused matrix-core kernels for float32 storage,
@@ -1019,8 +1010,8 @@ struct Pipe {
                                    c->wc_panT3[(size_t)(&L - m->layers.data())], L.P,
                                    (float)m->act, w, s);
       else
-        launch_mlp_fused_fwd<S>(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
-                                wc_panel<S>(L, true), L.P, (float)m->act, w, s);
+        launch_mlp_fused_fwd(NPr, pe1, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
+                             wc_panel(L, true), L.P, (float)m->act, w, s);
     } else {
       T* z2 = c->get<T>("z2", NPr * m->hidden);
       launch_mlp_hidden_fwd<T>(NPr, pe1, rho, m->nb, m->hidden, W<T>(c, L.w_mlp[0]),
@@ -1041,9 +1032,8 @@ struct Pipe {
                                    c->wc_pan3[(size_t)(&L - m->layers.data())], L.P,
                                    (float)m->act, dw, drho, true, s);
       else
-        launch_mlp_fused_bwd<S>(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]),
-                                W<float>(c, L.w_mlp[1]), wc_panel<S>(L, false), L.P,
-                                (float)m->act, dw, drho, true, s);
+        launch_mlp_fused_bwd(NPr, pe1, pe2, rho, W<float>(c, L.w_mlp[0]), W<float>(c, L.w_mlp[1]),
+                             wc_panel(L, false), L.P, (float)m->act, dw, drho, true, s);
     } else {
       T* dws = c->get<T>("dw_pair", NPr * L.P);
       launch_pair_sum<T>(NPr, pe1, pe2, dw, L.P, dws, s);

@@ -53,12 +53,16 @@ def stats(d, steps, out, cmd, blocks=5):
               "most of which is the benchmark's copy-rate measurement outside the timed steps)", "",
               f"Per interaction block (sum over the kernel's instantiations per step / {blocks} "
               "blocks):", ""]
-    # (the FP32 form's radial-MLP forward is the non-template k_mlp_fused_fwd_split)
     for k in ("k_tp_bwd", "k_tp_fwd", "k_mlp_fused_bwd", "k_mlp_fused_fwd"):
-        t = sum(float(r["TotalDurationNs"]) for r in rows
-                if f"::{k}<" in r["Name"] or f"::{k}_split(" in r["Name"])
+        t = sum(float(r["TotalDurationNs"]) for r in rows if _is_kernel(r["Name"], k))
         lines.append(f"- `{k}`: {t / 1e3 / steps / blocks:.1f} us")
     open(out, "w").write("\n".join(lines) + "\n")
+
+
+def _is_kernel(name, k):
+    """Whether a demangled kernel name is kernel k: any instantiation of the template k, the
+    plain function k, or its FP32 split form k_split."""
+    return f"::{k}<" in name or f"::{k}(" in name or f"::{k}_split(" in name
 
 
 def traffic(fetch_dir, write_dir, kernel, source, precision, out, cmd):
@@ -76,12 +80,12 @@ def traffic(fetch_dir, write_dir, kernel, source, precision, out, cmd):
     cf = calib(f_rows, "FETCH_SIZE") / (256 * 1024)
     cw = calib(w_rows, "WRITE_SIZE") / (256 * 1024)
     kernel, _, unit = kernel.partition("@")
-    fk = [float(r["Counter_Value"]) for r in f_rows if f"::{kernel}<" in r["Kernel_Name"]]
-    wk = [float(r["Counter_Value"]) for r in w_rows if f"::{kernel}<" in r["Kernel_Name"]]
+    fk = [float(r["Counter_Value"]) for r in f_rows if _is_kernel(r["Kernel_Name"], kernel)]
+    wk = [float(r["Counter_Value"]) for r in w_rows if _is_kernel(r["Kernel_Name"], kernel)]
     nf = nw = len(fk)
     if unit:
-        nf = sum(1 for r in f_rows if f"::{unit}<" in r["Kernel_Name"])
-        nw = sum(1 for r in w_rows if f"::{unit}<" in r["Kernel_Name"])
+        nf = sum(1 for r in f_rows if _is_kernel(r["Kernel_Name"], unit))
+        nw = sum(1 for r in w_rows if _is_kernel(r["Kernel_Name"], unit))
     fetch = sum(fk) / nf / cf * 1024
     write = sum(wk) / nw / cw * 1024
     rec = {"kernel": kernel, "per": f"dispatch of {unit}" if unit else "dispatch",

@@ -47,7 +47,7 @@ def test_traffic_calibrates_on_the_copy_before_the_library(tmp_path):
     fetch = [(1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 128 * MiB),
              (2, "void sn::k_tp_bwd<float, float, 1, 2, 2, false, true, 0>(...)", "FETCH_SIZE", 50 * MiB),
              (3, "void sn::k_tp_bwd<float, float, 2, 2, 2, false, true, 0>(...)", "FETCH_SIZE", 30 * MiB),
-             (4, "void sn::k_mlp_fused_bwd<false>(...)", "FETCH_SIZE", 10 * MiB),
+             (4, "sn::k_mlp_fused_bwd_split(long, int const*)", "FETCH_SIZE", 10 * MiB),
              (5, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 512 * MiB)]
     write = [(d, k, "WRITE_SIZE", v * 2 if "copy" in k else v) for d, k, _, v in fetch]
     _write_counters(tmp_path / "f", fetch)
@@ -65,12 +65,13 @@ def test_traffic_calibrates_on_the_copy_before_the_library(tmp_path):
     assert rec["write_bytes_per_launch"] == pytest.approx(80 * 2 ** 20)
 
 
-def test_stats_counts_the_split_forward_per_block(tmp_path):
+def test_stats_counts_split_and_plain_kernels_per_block(tmp_path):
     from paper_2402_03789_amd import profile_summary as ps
     d = tmp_path / "trace"
     d.mkdir()
     cols = ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"]
     rows = [("void sn::k_mlp_fused_fwd_split(long, int const*)", 15, 7.5e6, 5e5, 40.0),
+            ("sn::k_mlp_fused_bwd(long, int const*)", 15, 3e6, 2e5, 10.0),
             ("void sn::k_tp_bwd<float, float, 0, 2, 2, false, true, 0>(...)", 15, 1.5e7, 1e6, 60.0)]
     with open(d / "run_kernel_stats.csv", "w", newline="") as f:
         w = csv.writer(f)
@@ -80,6 +81,7 @@ def test_stats_counts_the_split_forward_per_block(tmp_path):
     ps.stats(str(d), 3.0, str(out), "cmd")
     text = out.read_text()
     assert "- `k_mlp_fused_fwd`: 500.0 us" in text   # 7.5 ms / 3 steps / 5 blocks
+    assert "- `k_mlp_fused_bwd`: 200.0 us" in text   # the plain (non-template) kernel
     assert "- `k_tp_bwd`: 1000.0 us" in text
 
 
