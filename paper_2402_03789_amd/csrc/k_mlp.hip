@@ -1,4 +1,6 @@
-// Fused radial MLP on the matrix cores (float32 and bfloat16 forms).
+// Fused radial MLP on the matrix cores: the BF16 form with bfloat16 operands and storage,
+// the FP32 form with float32 storage and its two P-wide contractions in three-part
+// bfloat16 arithmetic (float32-level results; the split kernels below).
 //
 // Per undirected edge pair (paper section 5.1, "learnable radial functions"
 // of the 8 Bessel features; the weights depend only on the distance, so an
@@ -16,9 +18,10 @@
 // the accumulator layout into the operand layout); weight panels are staged
 // in LDS once per block and shared by the four waves.  The output layer is
 // computed transposed (w^T = Wc^T z2^T), so a lane's accumulators hold
-// consecutive weights of one pair and go to memory as 16-byte stores.  The
-// adjoint reads dE/dw row-coalesced and turns it into the operand layout
-// through the wave's LDS panel.
+// consecutive weights of one pair; they leave through the wave's LDS panel so
+// that each 16-byte store instruction writes whole row segments.  The adjoint
+// reads dE/dw row-coalesced and turns it into the operand layout through the
+// wave's LDS panel.
 //
 // MFMA layouts (lane l, 16 x 16 tiles):
 //   f32 16x16x4  : a = A[l%16][4s + l/16],     b = B[4s + l/16][l%16]
