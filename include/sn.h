@@ -298,7 +298,8 @@ int sn_ctx_set_graph_reuse(sn_ctx_t* ctx, int reuse);
  * degree narrower than a wave deals a receiver's edges to lane groups by position, and
  * reductions are chunked by list length); they stay deterministic, and a structure's
  * result is the same alone and in a batch.  Not combined with graph replay
- * (sn_ctx_set_capture on at the build turns it off for that list). */
+ * (sn_ctx_set_capture on at the build turns it off for that list).  The setting takes
+ * effect at the next list build; a kept list goes on as it was built. */
 int sn_ctx_set_edge_compaction(sn_ctx_t* ctx, int on);
 
 /* Spatial decomposition on one device (paper section 3.1, Fig 3): split every structure of

@@ -266,7 +266,8 @@ class Context:
         check(lib().sn_ctx_set_capture(self._h, 1 if on else 0), self._h)
 
     def set_edge_compaction(self, on: bool):
-        """Evaluate lists built with a skin over their pairs inside r_c only (default on)."""
+        """Evaluate lists built with a skin over their pairs inside r_c only (default on);
+        takes effect at the next list build."""
         check(lib().sn_ctx_set_edge_compaction(self._h, 1 if on else 0))
 
     def evaluated_edges(self):
