@@ -35,6 +35,7 @@
 #include "cg_tables.h"
 
 #include <stdexcept>
+#include <type_traits>
 #include <utility>
 
 namespace sn {
@@ -75,6 +76,43 @@ __device__ inline void static_for_impl(F&& f, std::integer_sequence<int, I...>) 
 template <int N, class F>
 __device__ inline void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Two consecutive channels of one row as one access, for lanes that own a channel pair
+// (PAIR kernels: 2 u, 2 u + 1 on lane slot u).  The row offsets are even, so the access is
+// aligned to its size.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ inline void ld2(const float* p, T& a, T& b) {
+  const f32x2 v = *reinterpret_cast<const f32x2*>(p);
+  a = (T)v[0];
+  b = (T)v[1];
+}
+template <typename T>
+__device__ inline void ld2(const double* p, T& a, T& b) {
+  const f64x2 v = *reinterpret_cast<const f64x2*>(p);
+  a = (T)v[0];
+  b = (T)v[1];
+}
+template <typename T>
+__device__ inline void ld2(const bf16_t* p, T& a, T& b) {
+  const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+  a = (T)__uint_as_float(v << 16);
+  b = (T)__uint_as_float(v & 0xffff0000u);
+}
+template <typename T>
+__device__ inline void st2(float* p, T a, T b) {
+  *reinterpret_cast<f32x2*>(p) = f32x2{sstore<float>(a), sstore<float>(b)};
+}
+template <typename T>
+__device__ inline void st2(double* p, T a, T b) {
+  *reinterpret_cast<f64x2*>(p) = f64x2{sstore<double>(a), sstore<double>(b)};
+}
+template <typename T>
+__device__ inline void st2(bf16_t* p, T a, T b) {
+  *reinterpret_cast<uint32_t*>(p) =
+      (uint32_t)sstore<bf16_t>(a).u | ((uint32_t)sstore<bf16_t>(b).u << 16);
 }
 
 // Per-degree arguments of one interaction block.
@@ -130,7 +168,7 @@ struct EdgeIdx {
   int s, p;
 };
 
-template <typename T, typename S, int D1, int NP, int NYc, int KC>
+template <typename T, typename S, int D1, int NP, int NYc, int KC, bool PAIR = false>
 __device__ inline void load_edge(const TPArgs& g, const TPDeg& a, const int (&uc)[KC], int64_t e,
                                  const EdgeIdx& ix, const T* __restrict__ Y, const S* __restrict__ x,
                                  const S* __restrict__ w, EdgeOps<T, D1, NP, NYc, KC>& o) {
@@ -138,6 +176,14 @@ __device__ inline void load_edge(const TPArgs& g, const TPDeg& a, const int (&uc
   for (int q = 0; q < NYc; ++q) o.Y[q] = Y[e * g.NY + q];
   const int64_t wrow = (int64_t)(ix.p >> 1) * g.P + a.woff;
   const int64_t xrow = (int64_t)ix.s * g.Dx + a.xoff;
+  if constexpr (PAIR) {  // uc[1] = uc[0] + 1
+#pragma unroll
+    for (int m1 = 0; m1 < D1; ++m1) ld2(&x[xrow + m1 * a.mul + uc[0]], o.x[0][m1], o.x[1][m1]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) ld2(&w[wrow + p * a.mul + uc[0]], o.w[0][p], o.w[1][p]);
+    o.p = ix.p;
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
 #pragma unroll
@@ -180,7 +226,7 @@ __device__ inline void edge_pipeline(const TPArgs& g, int beg, int end, int EI, 
   }
 }
 
-template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, int CPT>
+template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, int CPT, bool PAIR = false>
 __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ Y,
                                                  const S* __restrict__ x, const S* __restrict__ w,
                                                  S* __restrict__ M, T inv_k) {
@@ -205,20 +251,21 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
     for (int q = 0; q < NO; ++q) acc[c][q] = T(0);
   const int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
   const int n_it = (end - beg + EI - 1) / EI;
+  static_assert(!PAIR || KC == 2, "channel pairs need two channels per lane");
   int uc[KC];
   bool ok[KC];
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
-    const int u = uu + c * cpt;
+    const int u = PAIR ? 2 * uu + c : uu + c * cpt;
     ok[c] = c < a.cpl && u < a.mul;
-    uc[c] = ok[c] ? u : 0;
+    uc[c] = ok[c] ? u : (PAIR ? c : 0);
   }
   using Ops = EdgeOps<T, D1, NP, NYc, KC>;
   if (n_it > 0)
     edge_pipeline<(CPT == 32 ? 3 : 4), Ops>(
         g, beg, end, EI, ei, n_it,
         [&](int e, const EdgeIdx& ix, Ops& o) {
-          load_edge<T, S, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
+          load_edge<T, S, D1, NP, NYc, KC, PAIR>(g, a, uc, e, ix, Y, x, w, o);
         },
         [&](int k, const Ops& cur) {
           const bool active = beg + k * EI + ei < end;
@@ -243,6 +290,20 @@ __global__ __launch_bounds__(256) void k_tp_fwd(TPArgs g, const T* __restrict__ 
       for (int q = 0; q < NO; ++q) acc[c][q] += __shfl_xor(acc[c][q], off);
   }
   if (ei != 0) return;
+  if constexpr (PAIR) {
+    if (2 * uu >= a.mul) return;  // both channels of the pair or neither (mul is even)
+    const int u = 2 * uu;
+    static_for<NP>([&](auto P) {
+      constexpr int p = decltype(P)::value;
+      constexpr int D3 = 2 * PL::l3(p) + 1;
+      constexpr int oo = PL::ooff(p);
+#pragma unroll
+      for (int m3 = 0; m3 < D3; ++m3)
+        st2(&M[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u], acc[0][oo + m3] * inv_k,
+            acc[1][oo + m3] * inv_k);
+    });
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
     const int u = uu + c * cpt;
@@ -366,7 +427,8 @@ __device__ inline void slot_reduce_rows(T (&v)[NV], int cpt, int lane) {
 
 // Adjoint of one degree's paths: writes dE/dw (per edge), the per-edge dE/dx rows, and
 // adds this degree's share of dE/dY (set instead when accumulate is 0).
-template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX, int CPT>
+template <typename T, typename S, int L1, int LSH, int L3MAX, bool SO, bool WRITE_DX, int CPT,
+          bool PAIR = false>
 __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ Y,
                                                  const S* __restrict__ x, const S* __restrict__ w,
                                                  const S* __restrict__ G, S* __restrict__ dw,
@@ -390,19 +452,37 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   // lanes per edge slot: a compile-time 64 or 32 for the common widths (a 64-lane slot makes
   // every edge index wave-uniform), else the runtime value
   const int cpt = CPT ? CPT : a.cpt, EI = kWave / cpt, ei = lane / cpt, uu = lane % cpt;
+  static_assert(!PAIR || KC == 2, "channel pairs need two channels per lane");
   T gin[KC][NO];
-#pragma unroll
-  for (int c = 0; c < KC; ++c) {
-    const int u = uu + c * cpt;
-    const bool ok = c < a.cpl && u < a.mul;
+  if constexpr (PAIR) {
+    const bool ok = 2 * uu < a.mul;  // both channels of the pair or neither (mul is even)
+    const int u = ok ? 2 * uu : 0;
     static_for<NP>([&](auto P) {
       constexpr int p = decltype(P)::value;
       constexpr int D3 = 2 * PL::l3(p) + 1;
       constexpr int oo = PL::ooff(p);
 #pragma unroll
-      for (int m3 = 0; m3 < D3; ++m3)
-        gin[c][oo + m3] = ok ? (T)sload(G[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u]) : T(0);
+      for (int m3 = 0; m3 < D3; ++m3) {
+        T g0, g1;
+        ld2(&G[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u], g0, g1);
+        gin[0][oo + m3] = ok ? g0 : T(0);
+        gin[1][oo + m3] = ok ? g1 : T(0);
+      }
     });
+  } else {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const int u = uu + c * cpt;
+      const bool ok = c < a.cpl && u < a.mul;
+      static_for<NP>([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        constexpr int D3 = 2 * PL::l3(p) + 1;
+        constexpr int oo = PL::ooff(p);
+#pragma unroll
+        for (int m3 = 0; m3 < D3; ++m3)
+          gin[c][oo + m3] = ok ? (T)sload(G[(int64_t)i * g.Dm + a.mo[p] + m3 * a.mw[p] + u]) : T(0);
+      });
+    }
   }
   int beg = g.row_ptr[i], end = g.row_ptr[i + 1];
   if (g.split_log) {
@@ -416,8 +496,8 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   int uc[KC];
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
-    const int u = uu + c * cpt;
-    uc[c] = (c < a.cpl && u < a.mul) ? u : 0;
+    const int u = PAIR ? 2 * uu + c : uu + c * cpt;
+    uc[c] = (c < a.cpl && u < a.mul) ? u : (PAIR ? c : 0);
   }
   // dE/dY: NV = NYc rounded up to a power of two values per lane, reduced per edge slot.
   // With at least NV lanes per slot (every degree of at least NV channels) the transposed
@@ -435,7 +515,7 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
   edge_pipeline<(CPT == 32 ? 2 : 3), Ops>(
       g, beg, end, EI, ei, n_it,
       [&](int e, const EdgeIdx& ix, Ops& o) {
-        load_edge<T, S, D1, NP, NYc, KC>(g, a, uc, e, ix, Y, x, w, o);
+        load_edge<T, S, D1, NP, NYc, KC, PAIR>(g, a, uc, e, ix, Y, x, w, o);
         o.dyo = dY[(int64_t)e * g.NY + jl];  // earlier share of this edge's dE/dY
       },
       [&](int k, const Ops& cur) {
@@ -447,9 +527,12 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
         if (active) {
           const int64_t e = ec;
           const int64_t drow = (int64_t)cur.p * g.P + a.woff;  // pair-major dE/dw row
+          // PAIR: the pair's dE/dw and dxe values are kept and stored together below
+          T dwp[PAIR ? 2 : 1][PAIR ? NP : 1];
+          T dxp[PAIR ? 2 : 1][PAIR ? D1 : 1];
 #pragma unroll
           for (int c = 0; c < KC; ++c) {
-            const int u = uu + c * cpt;
+            const int u = PAIR ? 2 * uu + c : uu + c * cpt;
             if (c >= a.cpl || u >= a.mul) break;
             const T* xv = cur.x[c];
             T dxv[D1];
@@ -471,16 +554,32 @@ __global__ __launch_bounds__(256) void k_tp_bwd(TPArgs g, const T* __restrict__ 
                 dwv += gi * t[m3];
                 gg[m3] = wv * gi;
               }
-              dw[drow + p * a.mul + u] = sstore<S>(dwv);
+              if constexpr (PAIR) dwp[c][p] = dwv;
+              else dw[drow + p * a.mul + u] = sstore<S>(dwv);
               CG<L1, l2, l3>::each([&](int m1, int m2, int m3, double cc) {
                 if (WRITE_DX) dxv[m1] += T(cc) * (cur.Y[l2 * l2 + m2] * gg[m3]);
                 dYl[l2 * l2 + m2] += T(cc) * (xv[m1] * gg[m3]);
               });
             });
-            if (WRITE_DX) {
+            if constexpr (PAIR) {
+#pragma unroll
+              for (int m1 = 0; m1 < D1; ++m1) dxp[c][m1] = dxv[m1];
+            } else if (WRITE_DX) {
 #pragma unroll
               for (int m1 = 0; m1 < D1; ++m1)
                 dxe[e * g.Dx + a.xoff + m1 * a.mul + u] = sstore<S>(dxv[m1]);
+            }
+          }
+          if constexpr (PAIR) {
+            if (2 * uu < a.mul) {  // both channels of the pair (mul is even)
+              const int u = 2 * uu;
+#pragma unroll
+              for (int p = 0; p < NP; ++p) st2(&dw[drow + p * a.mul + u], dwp[0][p], dwp[1][p]);
+              if (WRITE_DX) {
+#pragma unroll
+                for (int m1 = 0; m1 < D1; ++m1)
+                  st2(&dxe[e * g.Dx + a.xoff + m1 * a.mul + u], dxp[0][m1], dxp[1][m1]);
+              }
             }
           }
         }
@@ -532,17 +631,38 @@ static TPArgs make_args(const TPLayer& L, int l1, int n_recv, const int* row_ptr
   return a;
 }
 
-template <typename T, typename S, int L1, int LSH, int LMX, bool SO, int CPT>
+template <typename T, typename S, int L1, int LSH, int LMX, bool SO, int CPT, bool PAIR = false>
 static void launch_fwd(const TPArgs& a, const T* Y, const S* x, const S* w, S* M, T inv_k,
                        hipStream_t s) {
   const unsigned grid = (unsigned)((a.n_recv + kRecvPerBlock - 1) / kRecvPerBlock);
-  k_tp_fwd<T, S, L1, LSH, LMX, SO, CPT><<<grid, kWave * kRecvPerBlock, 0, s>>>(a, Y, x, w, M, inv_k);
+  k_tp_fwd<T, S, L1, LSH, LMX, SO, CPT, PAIR>
+      <<<grid, kWave * kRecvPerBlock, 0, s>>>(a, Y, x, w, M, inv_k);
+}
+
+// Channel pairs (two adjacent channels per lane, one 2-wide access per value) for a degree
+// whose 65..128 channels take two per lane anyway, when every row offset is even.
+static bool pairable(const TPArgs& a) {
+  if (a.d.cpl != 2 || a.d.mul % 2 || a.d.xoff % 2 || a.d.woff % 2 || a.Dx % 2 || a.P % 2 ||
+      a.Dm % 2)
+    return false;
+  for (int p = 0; p < kMaxPathsL1; ++p)
+    if (a.d.mo[p] % 2 || a.d.mw[p] % 2) return false;
+  return true;
 }
 template <typename T, typename S, int L1, int LSH, int LMX, bool SO>
 static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const S* w, S* M, T inv_k,
                        const S* G, S* dw, S* dxe, T* dY, int acc, hipStream_t s) {
   // compile-time slot widths for the common channel counts
+  // (not in the FP64 form: its paired kernels would need scratch registers)
+  constexpr bool kPairs = CPL<L1>::value == 2 && !std::is_same<T, double>::value;
+  const bool pair = kPairs && a.d.cpt == 64 && pairable(a);
   if (fwd) {
+    if constexpr (kPairs) {
+      if (pair) {
+        launch_fwd<T, S, L1, LSH, LMX, SO, 64, true>(a, Y, x, w, M, inv_k, s);
+        return;
+      }
+    }
     if (a.d.cpt == 64) launch_fwd<T, S, L1, LSH, LMX, SO, 64>(a, Y, x, w, M, inv_k, s);
     else if (a.d.cpt == 32) launch_fwd<T, S, L1, LSH, LMX, SO, 32>(a, Y, x, w, M, inv_k, s);
     else launch_fwd<T, S, L1, LSH, LMX, SO, 0>(a, Y, x, w, M, inv_k, s);
@@ -553,6 +673,17 @@ static void launch_one(bool fwd, const TPArgs& a, const T* Y, const S* x, const 
   const unsigned block = kWave * kRecvPerBlock;
 #define SN_TP_BWD(DX, CPT) \
   k_tp_bwd<T, S, L1, LSH, LMX, SO, DX, CPT><<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc)
+  if constexpr (kPairs) {
+    if (pair) {
+      if (dxe)
+        k_tp_bwd<T, S, L1, LSH, LMX, SO, true, 64, true>
+            <<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
+      else
+        k_tp_bwd<T, S, L1, LSH, LMX, SO, false, 64, true>
+            <<<grid, block, 0, s>>>(a, Y, x, w, G, dw, dxe, dY, acc);
+      return;
+    }
+  }
   if (dxe) {
     if (a.d.cpt == 64) SN_TP_BWD(true, 64);
     else if (a.d.cpt == 32) SN_TP_BWD(true, 32);
