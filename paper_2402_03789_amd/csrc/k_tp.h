@@ -11,7 +11,8 @@
 // gets its own register budget), one 64-lane wavefront per receiver and one
 // wave per block (measured faster than two or four per block: the waves of a
 // launch are placed one by one).  A wave covers the degree's channels with lanes (two
-// channels per lane for a 128-channel scalar block); a degree with fewer than
+// channels per lane for a 128-channel scalar block: the adjacent pair 2u, 2u + 1, so every
+// value moves as one 2-wide access, where the row offsets allow); a degree with fewer than
 // 64 channels processes 64/cpt edges at once (lanes = channel x edge slot) and
 // combines the slots with cross-lane shuffles at the end.  The radial weights
 // are read through the edge's pair index (an edge and its reverse share them).  Every receiver's
